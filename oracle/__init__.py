@@ -1,0 +1,115 @@
+"""CPU oracle for string sorting (test infrastructure only).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The HIP library never calls it, links
+it or loads it, and the two share no code.
+
+``sort`` returns the unique permutation that orders the strings by unsigned
+lexicographic byte order up to their terminator, equal strings by ascending
+input index, plus the LCP array of that order (Bingmann & Sanders, Section 2,
+definitions of the input, of lcp and of D).  The C source implements multikey
+quicksort (Section 2.1) and an explicit LCP pass; see ``s5_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "s5_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "_s5_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/_s5_oracle.so``."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.oracle_sort.argtypes = [P, P, ctypes.c_uint32, P, P]
+        lib.oracle_sort.restype = ctypes.c_int
+        lib.oracle_sort_batched.argtypes = [P, P, P, ctypes.c_uint32, P, P]
+        lib.oracle_sort_batched.restype = ctypes.c_int
+        lib.oracle_dist_prefix.argtypes = [P, P, P, P, ctypes.c_uint64]
+        lib.oracle_dist_prefix.restype = ctypes.c_uint64
+        lib.oracle_lcp.argtypes = [P, P, P, ctypes.c_uint64, P]
+        lib.oracle_lcp.restype = None
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _check(chars, offsets):
+    chars = np.ascontiguousarray(chars, dtype=np.uint8)
+    offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+    if offsets.size >= 2**32:
+        raise ValueError("at most 2^32 - 1 strings")
+    return chars, offsets
+
+
+def sort(chars: np.ndarray, offsets: np.ndarray):
+    """Return ``(perm, lcp)`` as uint32 arrays for the strings at ``offsets``."""
+    chars, offsets = _check(chars, offsets)
+    n = offsets.size
+    perm = np.empty(n, dtype=np.uint32)
+    lcp = np.empty(n, dtype=np.uint32)
+    if n and _load().oracle_sort(_ptr(chars), _ptr(offsets), n, _ptr(perm), _ptr(lcp)):
+        raise MemoryError("oracle_sort ran out of memory")
+    return perm, lcp
+
+
+def sort_batched(chars: np.ndarray, offsets: np.ndarray, set_begin: np.ndarray):
+    """Sort every set ``[set_begin[s], set_begin[s+1])`` on its own.
+
+    ``perm`` holds set-local indices and ``lcp`` is 0 at every set's first slot.
+    """
+    chars, offsets = _check(chars, offsets)
+    set_begin = np.ascontiguousarray(set_begin, dtype=np.uint64)
+    n = offsets.size
+    perm = np.empty(n, dtype=np.uint32)
+    lcp = np.empty(n, dtype=np.uint32)
+    ns = set_begin.size - 1
+    if ns > 0 and _load().oracle_sort_batched(
+            _ptr(chars), _ptr(offsets), _ptr(set_begin), ns, _ptr(perm), _ptr(lcp)):
+        raise ValueError("oracle_sort_batched failed (bad set_begin or no memory)")
+    return perm, lcp
+
+
+def lcp_of(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray) -> np.ndarray:
+    """Explicit LCP pass over any given order ``perm``."""
+    chars, offsets = _check(chars, offsets)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    lcp = np.empty(perm.size, dtype=np.uint32)
+    if perm.size:
+        _load().oracle_lcp(_ptr(chars), _ptr(offsets), _ptr(perm), perm.size, _ptr(lcp))
+    return lcp
+
+
+def dist_prefix(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray,
+                lcp: np.ndarray) -> int:
+    """Distinguishing prefix size D of the set, terminators counted."""
+    chars, offsets = _check(chars, offsets)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    lcp = np.ascontiguousarray(lcp, dtype=np.uint32)
+    if perm.size == 0:
+        return 0
+    return int(_load().oracle_dist_prefix(_ptr(chars), _ptr(offsets), _ptr(perm),
+                                          _ptr(lcp), perm.size))
