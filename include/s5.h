@@ -1,0 +1,154 @@
+/*
+ * s5.h -- super scalar string sample sort (S^5) on one MI355X (gfx950).
+ *
+ * Problem (Bingmann & Sanders, "Parallel String Sample Sort", Section 2,
+ * "Preliminaries"): n zero-terminated strings over the alphabet {1..255},
+ * given as one arena of bytes plus the start offset of every string (the
+ * paper's array of string pointers).  Output: the permutation that lists the
+ * strings in lexicographic order of their unsigned bytes, and the LCP array of
+ * that order, lcp[i] = lcp(x[i-1], x[i]).  The method is S^5 (Section 3.1):
+ * splitter sampling, a ternary splitter tree with equality buckets over 8-byte
+ * big-endian key prefixes, classification, counting, prefix sum and
+ * out-of-place redistribution, recursing on the buckets.
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named chars, offsets, set_begin, out_perm, out_lcp and
+ *     workspace are DEVICE pointers; cfg and host_out are HOST pointers.
+ *   - chars: the arena.  Each string runs from chars[offsets[i]] to its first
+ *     0 byte.  Strings may overlap (e.g. all suffixes of one text) and offsets
+ *     need not be increasing.  The library only reads aligned 8-byte words that
+ *     contain at least one byte of some string, so it never touches memory
+ *     outside the arena's pages.  No string may be 2^31 bytes or longer.
+ *   - out_perm[i]: input index of the i-th smallest string; equal strings are
+ *     listed by ascending input index, which makes the output unique.
+ *   - out_lcp[0] = 0; out_lcp[i] = number of equal leading bytes of strings
+ *     out_perm[i-1] and out_perm[i], not counting the terminator.
+ *   - Every call is ordered on `stream` (a hipStream_t of the caller's HIP
+ *     runtime; 0 = the null stream).  Sorting waits on `stream` between
+ *     recursion levels, so a call returns when its results are complete on
+ *     the device side of `stream`.
+ *   - The caller owns every input, output and user workspace; the library
+ *     owns only its internal workspace pool, freed by s5_release().
+ *   - Inputs are never written.  Outputs may not alias inputs.
+ *   - Errors are returned as status codes (never thrown across this ABI).
+ */
+#ifndef S5_H
+#define S5_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define S5_OK 0
+#define S5_ERR_INVALID (-1) /* NULL pointer with n > 0, bad config or bad set table */
+#define S5_ERR_NOMEM (-2)   /* workspace missing/too small or allocation failed */
+#define S5_ERR_HIP (-3)     /* HIP runtime error */
+#define S5_ERR_DEVICE (-4)  /* device status word set (a device-side capacity check failed) */
+
+/* splitter_mode */
+#define S5_SPLIT_SAMPLED 0u /* splitters from a pseudo-random sample (Section 3.1) */
+#define S5_SPLIT_LEARNED 1u /* splitters proposed by a small learned CDF model */
+
+/* Tuning knobs.  A NULL config, or a 0 in any field, selects the default.
+ * No choice here changes the output, only the speed. */
+typedef struct s5_config {
+    uint32_t splitters;      /* most splitters per distribution pass, v = 2^d - 1,
+                                7 <= v <= 1023 (Section 3.1 "Implementation
+                                Details"; default 255) */
+    uint32_t oversample;     /* oversampling factor alpha (Section 2.3; default 2) */
+    uint32_t unroll;         /* interleaved tree descents per lane: 1, 2, 4 or 8
+                                (Section 3.1; default 4) */
+    uint32_t tile;           /* minimum strings per classification unit, a
+                                multiple of 64 (default 1024) */
+    uint32_t base_threshold; /* buckets of at most this many strings are finished
+                                by the LDS base-case sorter (Section 3.1
+                                "Parallelization", the size-classed sub-algorithms;
+                                64 <= T <= 4096, default 2048) */
+    uint32_t splitter_mode;  /* S5_SPLIT_SAMPLED or S5_SPLIT_LEARNED */
+    float imbalance_bound;   /* learned mode: fall back to sampled splitters when a
+                                range bucket exceeds this many times the ideal
+                                size (default 4) */
+    uint64_t seed;           /* sampling / training seed; the output never depends on it */
+} s5_config;
+
+/* Counters of the last completed sort on a stream. */
+typedef struct s5_stats {
+    uint32_t passes;        /* distribution levels run */
+    uint32_t fallbacks;     /* learned-splitter passes replaced by sampled splitters */
+    uint64_t moved_M;       /* strings moved by distribution passes, summed over passes */
+    uint64_t max_bucket;    /* largest bucket produced by the first pass */
+    double entropy_bits;    /* sum_i (|b_i|/n) log2(n/|b_i|) over the first pass's
+                               buckets (appendix A, "Adaptivity") */
+    size_t workspace_bytes; /* device workspace the sort used */
+    uint64_t base_items;    /* buckets finished by the base-case sorter */
+    uint64_t segments;      /* segments distributed, summed over passes */
+} s5_stats;
+
+/* Sort n strings.  perm and lcp as described above.  Uses the internal
+ * workspace pool of the current device (grown on demand).
+ * Returns S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP or S5_ERR_DEVICE. */
+int s5_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* out_perm,
+            uint32_t* out_lcp, hipStream_t stream);
+
+/* As s5_sort with explicit tuning and, optionally, a caller workspace of
+ * workspace_bytes >= s5_workspace_bytes(n, cfg) (NULL = internal pool).
+ * chars_len (bytes in the arena; 0 = unknown) is only used for argument checks. */
+int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
+               uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg, void* workspace,
+               size_t workspace_bytes, hipStream_t stream);
+
+/* Device workspace bytes that a sort of n strings with cfg needs. */
+size_t s5_workspace_bytes(uint32_t n, const s5_config* cfg);
+
+/* Sort num_sets independent sets in one call.  Set s holds the strings
+ * offsets[set_begin[s] .. set_begin[s+1]); set_begin (num_sets+1 entries,
+ * DEVICE memory, non-decreasing, set_begin[0] = 0) fixes where each set's
+ * results go: out_perm holds set-local indices and out_lcp is 0 at every
+ * set's first slot.  n = set_begin[num_sets] < 2^32. */
+int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                    const uint64_t* set_begin, uint32_t num_sets, uint32_t* out_perm,
+                    uint32_t* out_lcp, const s5_config* cfg, hipStream_t stream);
+
+/* Copy the counters of the last sort finished on `stream` to host_out.
+ * Synchronizes `stream`; returns S5_ERR_DEVICE if that sort's device status
+ * word reported a failure. */
+int s5_stats_get(hipStream_t stream, s5_stats* host_out);
+
+/* Human-readable text for a status code (static storage). */
+const char* s5_strerror(int status);
+
+/* Free the internal workspace pools of every device. */
+void s5_release(void);
+
+
+/* ---- building blocks ------------------------------------------------------
+ * The two primitives below are the first steps of every distribution pass,
+ * exported for callers that drive their own recursion and for step-level
+ * checks.  Same conventions as above. */
+
+/* out_keys[i] = the 8 bytes of string i that start at byte `depth`, packed
+ * big-endian (first byte most significant) and zero from the terminator on,
+ * so unsigned key order is lexicographic order of those bytes (Section 2.2,
+ * caching of characters and super-alphabets; Section 3.1, w = 8 characters per
+ * machine word).  Requires depth <= length of every string. */
+int s5_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t depth,
+                   uint64_t* out_keys, hipStream_t stream);
+
+/* Ternary classification against v = 2^d - 1 splitters, 1 <= v <= 1023,
+ * given in sorted (non-decreasing) order in DEVICE memory (Section 3.1 and
+ * Figure 1): with j = number of splitters smaller than the key, the bucket is
+ * 2j + 1 if splitter j equals the key, else 2j.  Buckets 0..2v. */
+int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
+                uint16_t* out_bucket, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S5_H */

@@ -1,0 +1,430 @@
+// Host orchestrator and C-ABI of the S^5 library (declared in include/s5.h).
+//
+// One call runs the recursion of string sample sort (Section 3.1) level by
+// level: every pass distributes all segments larger than the base threshold
+// at once; the device plans the next pass (appending work items with atomic
+// counters) and the host reads back one small counter block per pass to size
+// the next launches.  Buckets at or below the base threshold collect in one
+// list that the LDS base-case sorter finishes after the last pass, and a final
+// kernel completes the LCPs at bucket boundaries.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+
+#include "../../include/s5.h"
+#include "s5_internal.h"
+
+namespace s5 {
+void launch_init_keys(const uint8_t*, const uint64_t*, uint32_t, uint64_t*, uint32_t*, hipStream_t);
+void launch_prefix_keys(const uint8_t*, const uint64_t*, uint32_t, uint32_t, uint64_t*, hipStream_t);
+void launch_plan_roots(const uint64_t*, uint32_t, uint32_t, uint32_t*, uint32_t*, const PlanCtx&,
+                       hipStream_t);
+void launch_sample_tree(uint32_t, const LSeg*, const uint64_t*, uint32_t, uint32_t, uint64_t,
+                        uint64_t*, uint64_t*, uint8_t*, uint32_t*, uint32_t*, hipStream_t);
+void launch_classify(uint32_t, uint32_t, const LSeg*, const uint32_t*, const uint64_t*,
+                     const uint64_t*, const uint64_t*, uint16_t*, uint32_t*, uint32_t, uint32_t,
+                     hipStream_t);
+void launch_colscan(uint32_t, uint32_t, const LSeg*, const uint32_t*, uint32_t*, uint32_t*,
+                    hipStream_t);
+void launch_bucket_plan(uint32_t, const LSeg*, uint32_t*, uint32_t*, const uint64_t*,
+                        const uint8_t*, const PlanCtx&, uint32_t, hipStream_t);
+void launch_scatter(uint32_t, uint32_t, const LSeg*, const uint32_t*, const uint16_t*,
+                    const uint64_t*, const uint32_t*, uint64_t*, uint32_t*, const uint32_t*,
+                    const uint32_t*, const uint32_t*, const uint64_t*, const uint8_t*,
+                    const uint8_t*, const uint64_t*, uint32_t*, uint32_t*, uint32_t, uint32_t,
+                    hipStream_t);
+void launch_base_sort(uint32_t, const Seg*, const uint64_t*, const uint64_t*, const uint32_t*,
+                      const uint32_t*, const uint8_t*, const uint64_t*, uint32_t*, uint32_t*,
+                      uint32_t, hipStream_t);
+void launch_lcp_fix(const uint8_t*, const uint64_t*, const uint64_t*, uint32_t, uint32_t,
+                    const uint32_t*, uint32_t*, hipStream_t);
+void launch_classify_plain(const uint64_t*, uint32_t, const uint64_t*, uint32_t, uint32_t,
+                           uint64_t*, uint64_t*, uint16_t*, hipStream_t);
+}  // namespace s5
+
+using namespace s5;
+
+namespace {
+
+struct Cfg {
+    uint32_t dmax, alpha, unroll, unit_min, T, mode;
+    float beta;
+    uint64_t seed;
+};
+
+int resolve_cfg(const s5_config* c, Cfg* o) {
+    s5_config z;
+    memset(&z, 0, sizeof z);
+    if (!c) c = &z;
+    uint32_t v = c->splitters ? c->splitters : 255u;
+    uint32_t d = 0;
+    while (((1u << (d + 1)) - 1) <= v && d < 31) ++d;  // largest d with 2^d - 1 <= v
+    if (v < 7 || v > 1023 || ((1u << d) - 1) != v) return S5_ERR_INVALID;
+    o->dmax = d;
+    o->alpha = c->oversample ? c->oversample : 2u;
+    if (o->alpha < 1 || o->alpha > 4) return S5_ERR_INVALID;
+    o->unroll = c->unroll ? c->unroll : 4u;
+    if (o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8) return S5_ERR_INVALID;
+    o->unit_min = c->tile ? c->tile : 1024u;
+    if (o->unit_min % 64 || o->unit_min > (1u << 20)) return S5_ERR_INVALID;
+    o->T = c->base_threshold ? c->base_threshold : 2048u;
+    if (o->T < 64 || o->T > 4096) return S5_ERR_INVALID;
+    o->mode = c->splitter_mode;
+    if (o->mode != S5_SPLIT_SAMPLED && o->mode != S5_SPLIT_LEARNED) return S5_ERR_INVALID;
+    o->beta = c->imbalance_bound > 0 ? c->imbalance_bound : 4.0f;
+    o->seed = c->seed;
+    return S5_OK;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace regions (byte offsets into one device allocation).
+struct Layout {
+    size_t key[2], idx[2], bid, lseg[2], unit_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
+        bstart, base_list, counters[2], glob, total;
+    Caps caps;
+};
+
+Layout make_layout(uint64_t n, const Cfg& c) {
+    Layout L;
+    const uint64_t kmax = (2ull << c.dmax) - 1;
+    Caps cp;
+    uint64_t large = n / (c.T + 1) + 2;
+    uint64_t units = n / c.unit_min + kWaves * large + kWaves;
+    uint64_t chunks = units / kChunkRows + large + 1;
+    // sum over segments of 2^d < 4 |S| / T (plus the d >= 1 floor)
+    uint64_t tree = 4 * n / c.T + 2 * large + 2;
+    cp.large = (uint32_t)large;
+    cp.units = (uint32_t)std::min<uint64_t>(units, 0xFFFFFFFFull);
+    cp.chunks = (uint32_t)chunks;
+    cp.tree = (uint32_t)tree;
+    cp.bstart = (uint32_t)(2 * tree + large + 2);
+    cp.base = (uint32_t)(n / 2 + 2);
+    // sum over segments of units x k: units_s <= |S|/unit_min + 4 and
+    // k_s <= max(3, min(kmax, 8 |S| / T))
+    const uint64_t ksum = 3 * large + 8 * n / c.T + kmax;
+    cp.cm = (unsigned long long)(kmax * (n / c.unit_min + 1) + 4 * ksum);
+    cp.cs = (unsigned long long)(cp.cm / kChunkRows + ksum);
+    size_t p = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = p;
+        p = align_up(p + bytes);
+        return o;
+    };
+    for (int b = 0; b < 2; ++b) L.key[b] = take(n * 8);
+    for (int b = 0; b < 2; ++b) L.idx[b] = take(n * 4);
+    L.bid = take(n * 2);
+    for (int b = 0; b < 2; ++b) L.lseg[b] = take((size_t)cp.large * sizeof(LSeg));
+    L.unit_tab = take((size_t)cp.units * 4);
+    L.chunk_tab = take((size_t)cp.chunks * 4);
+    L.tree_lo = take((size_t)cp.tree * 8);
+    L.tree_in = take((size_t)cp.tree * 8);
+    L.tree_lcp = take((size_t)cp.tree);
+    L.cm = take((size_t)cp.cm * 4);
+    L.cs = take((size_t)cp.cs * 4);
+    L.bstart = take((size_t)cp.bstart * 4);
+    L.base_list = take((size_t)cp.base * sizeof(Seg));
+    for (int b = 0; b < 2; ++b) L.counters[b] = take(sizeof(Counters));
+    L.glob = take(sizeof(Globals));
+    L.total = p;
+    L.caps = cp;
+    return L;
+}
+
+struct DevPool {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    void* host = nullptr;  // pinned readback block
+};
+
+std::mutex g_mu;
+std::unordered_map<int, DevPool> g_pools;
+struct StreamRecord {
+    s5_stats stats;
+    int status;
+};
+std::unordered_map<hipStream_t, StreamRecord> g_last;
+
+#define S5_HIP(call)                                   \
+    do {                                               \
+        hipError_t e_ = (call);                        \
+        if (e_ != hipSuccess) return S5_ERR_HIP;       \
+    } while (0)
+
+// Get the pool of the current device with at least `bytes`.
+int pool_get(size_t bytes, DevPool** out) {
+    int dev = 0;
+    S5_HIP(hipGetDevice(&dev));
+    DevPool& P = g_pools[dev];
+    if (!P.host) S5_HIP(hipHostMalloc(&P.host, 4096, hipHostMallocDefault));
+    if (P.bytes < bytes) {
+        if (P.ptr) {
+            S5_HIP(hipDeviceSynchronize());
+            S5_HIP(hipFree(P.ptr));
+            P.ptr = nullptr;
+            P.bytes = 0;
+        }
+        if (hipMalloc(&P.ptr, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return S5_ERR_NOMEM;
+        }
+        P.bytes = bytes;
+    }
+    *out = &P;
+    return S5_OK;
+}
+
+struct SortArgs {
+    const uint8_t* chars;
+    const uint64_t* offsets;
+    const uint64_t* set_begin;  // device, or null for a single set
+    uint32_t num_sets, n;
+    uint32_t* perm;
+    uint32_t* lcp;
+};
+
+// The whole sort on one workspace.  `host` is a pinned block of >= 4 KiB.
+int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* host,
+             hipStream_t st, s5_stats* stats) {
+    memset(stats, 0, sizeof *stats);
+    const Layout L = make_layout(a.n, c);
+    if (ws_bytes < L.total) return S5_ERR_NOMEM;
+    stats->workspace_bytes = L.total;
+    char* W = (char*)ws;
+    uint64_t* key[2] = {(uint64_t*)(W + L.key[0]), (uint64_t*)(W + L.key[1])};
+    uint32_t* idx[2] = {(uint32_t*)(W + L.idx[0]), (uint32_t*)(W + L.idx[1])};
+    uint16_t* bid = (uint16_t*)(W + L.bid);
+    LSeg* lseg[2] = {(LSeg*)(W + L.lseg[0]), (LSeg*)(W + L.lseg[1])};
+    uint32_t* unit_tab = (uint32_t*)(W + L.unit_tab);
+    uint32_t* chunk_tab = (uint32_t*)(W + L.chunk_tab);
+    uint64_t* tree_lo = (uint64_t*)(W + L.tree_lo);
+    uint64_t* tree_in = (uint64_t*)(W + L.tree_in);
+    uint8_t* tree_lcp = (uint8_t*)(W + L.tree_lcp);
+    uint32_t* cm = (uint32_t*)(W + L.cm);
+    uint32_t* cs = (uint32_t*)(W + L.cs);
+    uint32_t* bstart = (uint32_t*)(W + L.bstart);
+    Seg* base_list = (Seg*)(W + L.base_list);
+    Counters* cnt[2] = {(Counters*)(W + L.counters[0]), (Counters*)(W + L.counters[1])};
+    Globals* glob = (Globals*)(W + L.glob);
+    Counters* hc = (Counters*)host;
+    Globals* hg = (Globals*)((char*)host + 512);
+
+    auto ctx_for = [&](int next) {
+        PlanCtx x;
+        x.lseg = lseg[next];
+        x.cnt = cnt[next];
+        x.base_list = base_list;
+        x.glob = glob;
+        x.caps = L.caps;
+        x.T = c.T;
+        x.d_max = c.dmax;
+        x.unit_min = c.unit_min;
+        return x;
+    };
+    auto readback = [&](int which) -> int {
+        S5_HIP(hipMemcpyAsync(hc, cnt[which], sizeof(Counters), hipMemcpyDeviceToHost, st));
+        S5_HIP(hipMemcpyAsync(hg, glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+        S5_HIP(hipStreamSynchronize(st));
+        return hg->status ? S5_ERR_DEVICE : S5_OK;
+    };
+
+    S5_HIP(hipMemsetAsync(cnt[0], 0, sizeof(Counters), st));
+    S5_HIP(hipMemsetAsync(glob, 0, sizeof(Globals), st));
+    launch_init_keys(a.chars, a.offsets, a.n, key[0], idx[0], st);
+    launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, ctx_for(0), st);
+    S5_HIP(hipGetLastError());
+    int rc = readback(0);
+    if (rc) return rc;
+
+    int cur = 0;  // lseg / counters index of the pass about to run
+    int buf = 0;  // work buffer holding the pass's input
+    uint32_t level = 0;
+    while (hc->n_large > 0) {
+        const Counters now = *hc;
+        const uint32_t kmax = now.kmax, vmax = (kmax - 1) / 2;
+        const int nxt = cur ^ 1;
+        S5_HIP(hipMemsetAsync(cnt[nxt], 0, sizeof(Counters), st));
+        launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
+                           tree_in, tree_lcp, unit_tab, chunk_tab, st);
+        launch_classify(now.units, c.unroll, lseg[cur], unit_tab, key[buf], tree_lo, tree_in, bid,
+                        cm, vmax, kmax, st);
+        launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st);
+        launch_bucket_plan(now.n_large, lseg[cur], cs, bstart, tree_in, tree_lcp, ctx_for(nxt),
+                           (uint32_t)(buf ^ 1), st);
+        launch_scatter(now.units, c.unroll, lseg[cur], unit_tab, bid, key[buf], idx[buf],
+                       key[buf ^ 1], idx[buf ^ 1], cm, cs, bstart, tree_in, tree_lcp, a.chars,
+                       a.offsets, a.perm, a.lcp, vmax, kmax, st);
+        S5_HIP(hipGetLastError());
+        rc = readback(nxt);
+        if (rc) return rc;
+        stats->moved_M += now.moved;
+        stats->segments += now.n_large;
+        if (level == 0) {
+            stats->max_bucket = hc->max_bucket;
+            stats->entropy_bits = now.moved ? hc->entropy_sum / (double)now.moved : 0.0;
+        }
+        ++level;
+        cur = nxt;
+        buf ^= 1;
+    }
+    stats->passes = level;
+    const uint32_t n_base = hg->n_base;
+    stats->base_items = n_base;
+    launch_base_sort(n_base, base_list, key[0], key[1], idx[0], idx[1], a.chars, a.offsets, a.perm,
+                     a.lcp, c.T, st);
+    launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, st);
+    S5_HIP(hipGetLastError());
+    S5_HIP(hipMemcpyAsync(hg, glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+    S5_HIP(hipStreamSynchronize(st));
+    return hg->status ? S5_ERR_DEVICE : S5_OK;
+}
+
+int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_bytes,
+                hipStream_t st) {
+    Cfg c;
+    int rc = resolve_cfg(cfg, &c);
+    if (rc) return rc;
+    if (a.n == 0) {
+        std::lock_guard<std::mutex> g(g_mu);
+        StreamRecord& r = g_last[st];
+        memset(&r.stats, 0, sizeof r.stats);
+        r.status = S5_OK;
+        return S5_OK;
+    }
+    std::lock_guard<std::mutex> g(g_mu);
+    const size_t need = make_layout(a.n, c).total;
+    void* host = nullptr;
+    if (!ws) {
+        DevPool* P = nullptr;
+        rc = pool_get(need, &P);
+        if (rc) return rc;
+        ws = P->ptr;
+        ws_bytes = P->bytes;
+        host = P->host;
+    } else {
+        DevPool* P = nullptr;
+        rc = pool_get(0, &P);
+        if (rc) return rc;
+        host = P->host;
+    }
+    s5_stats stats;
+    rc = run_sort(a, c, ws, ws_bytes, host, st, &stats);
+    StreamRecord& r = g_last[st];
+    r.stats = stats;
+    r.status = rc;
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
+               uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg, void* workspace,
+               size_t workspace_bytes, hipStream_t stream) {
+    (void)chars_len;
+    if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
+    if (n == 0xFFFFFFFFu) return S5_ERR_INVALID;
+    SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp};
+    return sort_common(a, cfg, workspace, workspace_bytes, stream);
+}
+
+int s5_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* out_perm,
+            uint32_t* out_lcp, hipStream_t stream) {
+    return s5_sort_ex(chars, 0, offsets, n, out_perm, out_lcp, nullptr, nullptr, 0, stream);
+}
+
+size_t s5_workspace_bytes(uint32_t n, const s5_config* cfg) {
+    Cfg c;
+    if (resolve_cfg(cfg, &c)) return 0;
+    return make_layout(n, c).total;
+}
+
+int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                    const uint64_t* set_begin, uint32_t num_sets, uint32_t* out_perm,
+                    uint32_t* out_lcp, const s5_config* cfg, hipStream_t stream) {
+    (void)chars_len;
+    if (num_sets == 0) return S5_OK;
+    if (!set_begin) return S5_ERR_INVALID;
+    uint64_t ends[2];
+    if (hipMemcpyAsync(ends, set_begin, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipMemcpyAsync(ends + 1, set_begin + num_sets, 8, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+        return S5_ERR_HIP;
+    if (ends[0] != 0 || ends[1] >= 0xFFFFFFFFull) return S5_ERR_INVALID;
+    const uint32_t n = (uint32_t)ends[1];
+    if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
+    SortArgs a{chars, offsets, set_begin, num_sets, n, out_perm, out_lcp};
+    return sort_common(a, cfg, nullptr, 0, stream);
+}
+
+int s5_stats_get(hipStream_t stream, s5_stats* host_out) {
+    if (!host_out) return S5_ERR_INVALID;
+    if (hipStreamSynchronize(stream) != hipSuccess) return S5_ERR_HIP;
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_last.find(stream);
+    if (it == g_last.end()) {
+        memset(host_out, 0, sizeof *host_out);
+        return S5_OK;
+    }
+    *host_out = it->second.stats;
+    return it->second.status == S5_ERR_DEVICE ? S5_ERR_DEVICE : S5_OK;
+}
+
+const char* s5_strerror(int status) {
+    switch (status) {
+        case S5_OK: return "success";
+        case S5_ERR_INVALID: return "invalid argument";
+        case S5_ERR_NOMEM: return "workspace missing, too small, or device allocation failed";
+        case S5_ERR_HIP: return "HIP runtime error";
+        case S5_ERR_DEVICE: return "device-side capacity check failed";
+        default: return "unknown status";
+    }
+}
+
+void s5_release(void) {
+    std::lock_guard<std::mutex> g(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto& kv : g_pools) {
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+        if (kv.second.ptr) (void)hipFree(kv.second.ptr);
+        if (kv.second.host) (void)hipHostFree(kv.second.host);
+    }
+    g_pools.clear();
+    (void)hipSetDevice(cur);
+}
+
+int s5_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t depth,
+                   uint64_t* out_keys, hipStream_t stream) {
+    if (n > 0 && (!chars || !offsets || !out_keys)) return S5_ERR_INVALID;
+    launch_prefix_keys(chars, offsets, n, depth, out_keys, stream);
+    return hipGetLastError() == hipSuccess ? S5_OK : S5_ERR_HIP;
+}
+
+int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
+                uint16_t* out_bucket, hipStream_t stream) {
+    uint32_t d = 0;
+    while (d < 11 && ((1u << d) - 1) < v) ++d;
+    if (v < 1 || v > 1023 || ((1u << d) - 1) != v || !splitters) return S5_ERR_INVALID;
+    if (n > 0 && (!keys || !out_bucket)) return S5_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    DevPool* P = nullptr;
+    int rc = pool_get((size_t)(v + 1) * 16, &P);
+    if (rc) return rc;
+    uint64_t* tlo = (uint64_t*)P->ptr;
+    uint64_t* tin = tlo + (v + 1);
+    launch_classify_plain(keys, n, splitters, v, d, tlo, tin, out_bucket, stream);
+    if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
+    // the pool may be reused by the next call: finish before returning
+    return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;
+}
+
+}  // extern "C"

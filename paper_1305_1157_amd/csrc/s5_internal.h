@@ -1,0 +1,82 @@
+// Internal definitions shared by the S^5 kernels (s5_kernels.hip) and the
+// host orchestrator (s5_host.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace s5 {
+
+// A distribution pass works on "units": contiguous runs of a segment that one
+// wavefront classifies and scatters.  Four units form one workgroup ("tile")
+// and always belong to the same segment.
+constexpr int kWG = 256;                 // threads per tile workgroup
+constexpr int kWaves = kWG / 64;         // units per tile
+constexpr uint32_t kMaxUnits = 4096;     // units per segment, at most
+constexpr uint32_t kChunkRows = 64;      // count-matrix rows per column-scan chunk
+constexpr int kDMax = 10;                // tree depth limit: v <= 1023 splitters
+constexpr uint32_t kLcpFlag = 0x80000000u;  // out_lcp entry still to be completed
+constexpr uint32_t kBufBit = 0x80000000u;   // work-buffer bit packed into a depth
+
+// status-word bits (device side capacity checks)
+constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrUnitCap = 4u, kErrCmCap = 8u,
+                   kErrTreeCap = 16u;
+
+// A bucket that still has to be sorted.
+struct Seg {
+    uint32_t begin;  // first position in the work arrays
+    uint32_t size;   // number of strings
+    uint32_t depth;  // common prefix length of all its strings (bit 31: work buffer for base items)
+    uint32_t base;   // first index of the set the strings belong to
+};
+
+// A segment distributed in the current pass, with its per-pass storage.
+struct LSeg {
+    uint32_t begin, size, depth, base;
+    uint32_t d, v, k, unit_len;     // tree depth, splitters (2^d-1), buckets (2v+1), strings per unit
+    uint32_t units, unit_base;      // units (a multiple of kWaves) and first unit id
+    uint32_t chunks, chunk_base;    // column-scan chunks and first chunk id
+    uint32_t tree_base, bstart_base;
+    uint32_t pad0, pad1;
+    unsigned long long cm_base;     // units x k count matrix (row-major)
+    unsigned long long cs_base;     // chunks x k chunk sums / prefixes
+};
+
+// Counters written by one planning step and read back by the host.
+struct Counters {
+    uint32_t n_large, units, chunks, tree;
+    uint32_t bstart, kmax, pad0, pad1;
+    unsigned long long cm, cs;
+    unsigned long long moved;       // strings in the planned large segments
+    unsigned long long max_bucket;  // largest bucket seen by the planning step
+    double entropy_sum;             // sum over buckets of |b| log2(|S|/|b|)
+    unsigned long long planned;     // strings in buckets of size >= 2 planned
+};
+
+// Device-global state that survives the whole sort.
+struct Globals {
+    uint32_t n_base;   // base-case items appended so far
+    uint32_t status;   // error bits
+    uint32_t pad0, pad1;
+};
+
+// Capacities of the per-pass storage.
+struct Caps {
+    uint32_t large, units, chunks, tree, bstart, base;
+    unsigned long long cm, cs;
+};
+
+// Everything a planning step needs to append work.
+struct PlanCtx {
+    LSeg* lseg;           // next pass's segment list
+    Counters* cnt;        // next pass's counters
+    Seg* base_list;       // base-case items (all passes)
+    Globals* glob;
+    Caps caps;
+    uint32_t T;           // base threshold
+    uint32_t d_max;       // tree depth limit for this sort
+    uint32_t unit_min;    // minimum strings per unit
+};
+
+}  // namespace s5

@@ -1,0 +1,116 @@
+// Word-level helpers of S^5, usable on the device and on the host (the host
+// side serves CPU checks of these helpers).  Keys are the next w = 8 bytes of
+// a string packed big-endian, zero from the terminator on (Section 2.2,
+// caching of characters and super-alphabets; Section 3.1, w characters per
+// machine word), so unsigned 64-bit order is lexicographic byte order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace s5 {
+
+#define S5_HD __host__ __device__ __forceinline__
+
+// High bit of each byte set iff that byte of x is zero (exact, no false hits).
+S5_HD uint64_t zero_byte_mask(uint64_t x) {
+    const uint64_t L7 = 0x7F7F7F7F7F7F7F7Full;
+    uint64_t t = ((x & L7) + L7) | x;
+    return ~(t | L7);
+}
+S5_HD bool has_zero(uint64_t x) { return zero_byte_mask(x) != 0; }
+// number of leading (most significant) nonzero bytes
+S5_HD uint32_t nz_bytes(uint64_t x) {
+    uint64_t z = zero_byte_mask(x);
+    return z ? (uint32_t)(__builtin_clzll((unsigned long long)z) >> 3) : 8u;
+}
+// zero every byte from the first zero byte (most significant first) on
+S5_HD uint64_t clip_at_zero(uint64_t k) {
+    uint64_t z = zero_byte_mask(k);
+    if (z == 0) return k;
+    uint32_t q = (uint32_t)__builtin_clzll((unsigned long long)z) >> 3;
+    return q == 0 ? 0ull : (k & (~0ull << (64 - 8 * q)));
+}
+// common leading bytes of two keys that are zero from their terminator on
+S5_HD uint32_t lcp8(uint64_t a, uint64_t b) {
+    return a == b ? nz_bytes(a) : (uint32_t)(__builtin_clzll((unsigned long long)(a ^ b)) >> 3);
+}
+
+// The 8 bytes at chars[pos..pos+8) as a big-endian key, zero from the first
+// 0 byte on.  Reads the aligned word holding chars[pos] and, only when the
+// string continues past that word, the next aligned word; both hold at least
+// one byte of the string, so no read leaves the string's own words.
+S5_HD uint64_t load_key(const uint8_t* chars, uint64_t pos) {
+    uintptr_t a = (uintptr_t)(chars + pos);
+    const uint64_t* w = (const uint64_t*)(a & ~(uintptr_t)7);
+    uint32_t sh = (uint32_t)(a & 7) * 8;
+    uint64_t k = __builtin_bswap64(w[0]) << sh;
+    if (sh) {
+        uint64_t valid = ~0ull << sh;
+        if ((zero_byte_mask(k) & valid) == 0) k |= __builtin_bswap64(w[1]) >> (64 - sh);
+    }
+    return clip_at_zero(k);
+}
+
+S5_HD uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// heap index (1-based level order) of the in-order splitter j in a tree of depth d
+S5_HD uint32_t inorder_node(uint32_t j, uint32_t d) {
+    uint32_t t = j + 1;
+    uint32_t L = d - 1 - (uint32_t)__builtin_ctz(t);
+    return (1u << L) + (t >> (d - L));
+}
+
+// U interleaved branch-free descents followed by one equality test each
+// (Section 3.1: the "unrolled" variant that only uses <= comparisons on the
+// way down).  t: level order, t[1..v]; tin: in order, tin[0..v).
+template <int U>
+S5_HD void classify_u(const uint64_t* t, const uint64_t* tin, uint32_t d,
+                                           uint32_t v, const uint64_t (&key)[U],
+                                           uint32_t (&b)[U]) {
+    uint32_t i[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) i[q] = 1;
+    for (uint32_t L = 0; L < d; ++L) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) i[q] = 2 * i[q] + (key[q] > t[i[q]] ? 1u : 0u);
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        uint32_t j = i[q] - (v + 1);
+        bool eq = (j < v) && (tin[j] == key[q]);
+        b[q] = 2 * j + (eq ? 1u : 0u);
+    }
+}
+
+// One step of the recursive splitter selection (Section 3.1): for the sorted
+// sample range smp[a..b), a < b, the node takes the middle sample x; its left
+// child recurses on smp[a..lo) and its right child on smp[hi..b), where
+// [lo, hi) is the run of samples equal to x.
+S5_HD void select_node(const uint64_t* smp, uint32_t a, uint32_t b, uint64_t* x, uint32_t* lo,
+                       uint32_t* hi) {
+    uint32_t mid = (a + b) >> 1;
+    uint64_t m = smp[mid];
+    uint32_t l = a, h = mid;  // first index in [a, mid] with smp >= m
+    while (l < h) {
+        uint32_t md = (l + h) >> 1;
+        if (smp[md] < m) l = md + 1; else h = md;
+    }
+    *lo = l;
+    l = mid + 1;
+    h = b;  // first index in (mid, b] with smp > m
+    while (l < h) {
+        uint32_t md = (l + h) >> 1;
+        if (smp[md] <= m) l = md + 1; else h = md;
+    }
+    *hi = l;
+    *x = m;
+}
+
+#undef S5_HD
+
+}  // namespace s5

@@ -1,0 +1,187 @@
+"""Python binding of the S^5 C-ABI (``include/s5.h``): argument marshalling only.
+
+Device memory and streams come from PyTorch; every step of the sort runs in the
+HIP kernels of ``libs5.so``.  There is no fallback: if the library is missing
+or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime that libs5.so must share)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libs5.so")
+
+S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP, S5_ERR_DEVICE = 0, -1, -2, -3, -4
+SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
+
+EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched", "s5_stats_get",
+           "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify")
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("splitters", ctypes.c_uint32), ("oversample", ctypes.c_uint32),
+                ("unroll", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("base_threshold", ctypes.c_uint32), ("splitter_mode", ctypes.c_uint32),
+                ("imbalance_bound", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_uint32), ("fallbacks", ctypes.c_uint32),
+                ("moved_M", ctypes.c_uint64), ("max_bucket", ctypes.c_uint64),
+                ("entropy_bits", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
+                ("base_items", ctypes.c_uint64), ("segments", ctypes.c_uint64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class S5Error(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load ``libs5.so`` (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise S5Error(f"S^5 HIP library not built: {path} is missing "
+                      "(run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+    lib.s5_sort.argtypes = [P, P, U32, P, P, P]
+    lib.s5_sort_ex.argtypes = [P, U64, P, U32, P, P, ctypes.POINTER(Config), P, ctypes.c_size_t, P]
+    lib.s5_workspace_bytes.argtypes = [U32, ctypes.POINTER(Config)]
+    lib.s5_workspace_bytes.restype = ctypes.c_size_t
+    lib.s5_sort_batched.argtypes = [P, U64, P, P, U32, P, P, ctypes.POINTER(Config), P]
+    lib.s5_stats_get.argtypes = [P, ctypes.POINTER(Stats)]
+    lib.s5_strerror.argtypes = [ctypes.c_int]
+    lib.s5_strerror.restype = ctypes.c_char_p
+    lib.s5_release.argtypes = []
+    lib.s5_release.restype = None
+    lib.s5_prefix_keys.argtypes = [P, P, U32, U32, P, P]
+    lib.s5_classify.argtypes = [P, U32, P, U32, P, P]
+    for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_stats_get", "s5_prefix_keys",
+              "s5_classify"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != S5_OK:
+        raise S5Error(f"S^5 call failed: {load().s5_strerror(rc).decode()} ({rc})")
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_config(splitters=0, oversample=0, unroll=0, tile=0, base_threshold=0,
+                splitter_mode=SPLIT_SAMPLED, imbalance_bound=0.0, seed=0) -> Config:
+    return Config(splitters, oversample, unroll, tile, base_threshold, splitter_mode,
+                  imbalance_bound, seed)
+
+
+def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,
+         out_perm: torch.Tensor | None = None, out_lcp: torch.Tensor | None = None,
+         workspace: torch.Tensor | None = None, stream=None):
+    """Sort the strings at ``offsets`` (uint64) in the arena ``chars`` (uint8).
+
+    Returns ``(perm, lcp)`` as uint32 device tensors.
+    """
+    lib = load()
+    n = offsets.numel()
+    dev = offsets.device
+    if out_perm is None:
+        out_perm = torch.empty(n, dtype=torch.uint32, device=dev)
+    if out_lcp is None:
+        out_lcp = torch.empty(n, dtype=torch.uint32, device=dev)
+    ws, wsb = None, 0
+    if workspace is not None:
+        ws, wsb = _dev(workspace, torch.uint8, "workspace"), workspace.numel()
+    rc = lib.s5_sort_ex(_dev(chars, torch.uint8, "chars"), chars.numel(),
+                        _dev(offsets, torch.uint64, "offsets"), n,
+                        _dev(out_perm, torch.uint32, "out_perm"),
+                        _dev(out_lcp, torch.uint32, "out_lcp"),
+                        ctypes.byref(cfg) if cfg is not None else None, ws, wsb, _stream(stream))
+    _check(rc)
+    return out_perm, out_lcp
+
+
+def sort_plain(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tensor,
+               out_lcp: torch.Tensor, stream=None):
+    """The 6-argument entry point ``s5_sort`` (internal workspace pool, defaults)."""
+    _check(load().s5_sort(_dev(chars, torch.uint8, "chars"),
+                          _dev(offsets, torch.uint64, "offsets"), offsets.numel(),
+                          _dev(out_perm, torch.uint32, "out_perm"),
+                          _dev(out_lcp, torch.uint32, "out_lcp"), _stream(stream)))
+    return out_perm, out_lcp
+
+
+def sort_batched(chars: torch.Tensor, offsets: torch.Tensor, set_begin: torch.Tensor,
+                 cfg: Config | None = None, stream=None):
+    """Sort every set ``offsets[set_begin[s]:set_begin[s+1]]`` on its own.
+
+    Returns set-local ``perm`` and ``lcp`` (0 at each set's first slot)."""
+    lib = load()
+    n = offsets.numel()
+    perm = torch.empty(n, dtype=torch.uint32, device=offsets.device)
+    lcp = torch.empty(n, dtype=torch.uint32, device=offsets.device)
+    rc = lib.s5_sort_batched(_dev(chars, torch.uint8, "chars"), chars.numel(),
+                             _dev(offsets, torch.uint64, "offsets"),
+                             _dev(set_begin, torch.uint64, "set_begin"), set_begin.numel() - 1,
+                             _dev(perm, torch.uint32, "out_perm"), _dev(lcp, torch.uint32, "out_lcp"),
+                             ctypes.byref(cfg) if cfg is not None else None, _stream(stream))
+    _check(rc)
+    return perm, lcp
+
+
+def workspace_bytes(n: int, cfg: Config | None = None) -> int:
+    return int(load().s5_workspace_bytes(n, ctypes.byref(cfg) if cfg is not None else None))
+
+
+def stats(stream=None) -> dict:
+    st = Stats()
+    rc = load().s5_stats_get(_stream(stream), ctypes.byref(st))
+    _check(rc)
+    return st.as_dict()
+
+
+def prefix_keys(chars: torch.Tensor, offsets: torch.Tensor, depth: int = 0, stream=None):
+    """uint64 keys: the 8 bytes of every string at ``depth``, big-endian, zero-padded."""
+    n = offsets.numel()
+    keys = torch.empty(n, dtype=torch.uint64, device=offsets.device)
+    _check(load().s5_prefix_keys(_dev(chars, torch.uint8, "chars"),
+                                 _dev(offsets, torch.uint64, "offsets"), n, depth,
+                                 _dev(keys, torch.uint64, "keys"), _stream(stream)))
+    return keys
+
+
+def classify(keys: torch.Tensor, splitters: torch.Tensor, stream=None):
+    """Ternary bucket (uint16) of every key against sorted splitters (2^d - 1 of them)."""
+    n = keys.numel()
+    out = torch.empty(n, dtype=torch.uint16, device=keys.device)
+    _check(load().s5_classify(_dev(keys, torch.uint64, "keys"), n,
+                              _dev(splitters, torch.uint64, "splitters"), splitters.numel(),
+                              _dev(out, torch.uint16, "out"), _stream(stream)))
+    return out
+
+
+def release():
+    load().s5_release()

@@ -1,0 +1,239 @@
+// CPU checks of the library's word-level helpers (s5_word.h), compiled for the
+// host.  Every check compares a helper with a plain byte-level definition.
+// Usage: word_helpers_test <fig1 golden file>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <sys/mman.h>
+#include <unistd.h>
+
+#include <algorithm>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "s5_word.h"
+
+using namespace s5;
+
+static int failures = 0;
+#define CHECK(cond, ...)                                \
+    do {                                                \
+        if (!(cond)) {                                  \
+            if (failures < 20) {                        \
+                printf("FAIL %s:%d: ", __FILE__, __LINE__); \
+                printf(__VA_ARGS__);                    \
+                printf("\n");                           \
+            }                                           \
+            ++failures;                                 \
+        }                                               \
+    } while (0)
+
+// byte-level definition of the key of s at depth
+static uint64_t ref_key(const uint8_t* s) {
+    uint64_t k = 0;
+    bool ended = false;
+    for (int i = 0; i < 8; ++i) {
+        uint8_t c = ended ? 0 : s[i];
+        if (c == 0) ended = true;
+        k = (k << 8) | c;
+    }
+    return k;
+}
+static uint32_t ref_lcp(const uint8_t* a, const uint8_t* b) {
+    uint32_t k = 0;
+    while (k < 8 && a[k] == b[k] && a[k] != 0) ++k;
+    return k;
+}
+
+static void test_load_key_guarded(std::mt19937_64& rng) {
+    // strings that end right before an inaccessible page: any read past the
+    // string's last aligned word would fault
+    long pg = sysconf(_SC_PAGESIZE);
+    uint8_t* mem = (uint8_t*)mmap(nullptr, 2 * pg, PROT_READ | PROT_WRITE,
+                                  MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+    CHECK(mem != MAP_FAILED, "mmap");
+    mprotect(mem + pg, pg, PROT_NONE);
+    for (int len = 0; len <= 40; ++len) {
+        uint8_t* s = mem + pg - (len + 1);
+        for (int i = 0; i < len; ++i) s[i] = (uint8_t)(1 + rng() % 255);
+        s[len] = 0;
+        for (int dep = 0; dep <= len; ++dep) {
+            uint64_t got = load_key(mem, (uint64_t)(s - mem) + dep);
+            uint8_t tmp[8];
+            for (int i = 0; i < 8; ++i) tmp[i] = dep + i <= len ? s[dep + i] : 0;
+            CHECK(got == ref_key(tmp), "guarded len %d depth %d", len, dep);
+        }
+    }
+    munmap(mem, 2 * pg);
+}
+
+static void test_load_key_random(std::mt19937_64& rng) {
+    std::vector<uint8_t> arena(1 << 16, 0);
+    size_t p = 3;  // deliberately unaligned start
+    std::vector<std::pair<size_t, int>> strs;
+    while (p + 40 < arena.size()) {
+        int len = rng() % 30;
+        for (int i = 0; i < len; ++i) {
+            uint8_t c = (rng() % 4 == 0) ? (uint8_t)(0x80 + rng() % 128) : (uint8_t)(1 + rng() % 127);
+            arena[p + i] = c;
+        }
+        arena[p + len] = 0;
+        strs.push_back({p, len});
+        p += len + 1;
+    }
+    for (auto& sl : strs)
+        for (int dep = 0; dep <= sl.second; ++dep) {
+            const uint8_t* s = arena.data() + sl.first + dep;
+            uint64_t got = load_key(arena.data(), sl.first + dep);
+            CHECK(got == ref_key(s), "random key at %zu depth %d", sl.first, dep);
+        }
+    // lcp8 and nz_bytes against byte loops
+    for (size_t t = 1; t < strs.size(); ++t) {
+        const uint8_t* a = arena.data() + strs[t - 1].first;
+        const uint8_t* b = arena.data() + strs[t].first;
+        CHECK(lcp8(ref_key(a), ref_key(b)) == ref_lcp(a, b), "lcp8 %zu", t);
+        CHECK(lcp8(ref_key(a), ref_key(a)) == ref_lcp(a, a), "lcp8 self %zu", t);
+        CHECK(nz_bytes(ref_key(a)) == std::min<uint32_t>(8, (uint32_t)strlen((const char*)a)),
+              "nz %zu", t);
+    }
+    // key order equals byte order (memcmp on the zero-padded 8 bytes)
+    for (int t = 0; t < 20000; ++t) {
+        uint8_t a[8], b[8];
+        for (int i = 0; i < 8; ++i) {
+            a[i] = (uint8_t)(rng() % 3 == 0 ? 0 : rng());
+            b[i] = (uint8_t)(rng() % 3 == 0 ? 0 : rng());
+        }
+        for (int i = 0; i < 8; ++i) if (a[i] == 0) for (int j = i; j < 8; ++j) a[j] = 0;
+        for (int i = 0; i < 8; ++i) if (b[i] == 0) for (int j = i; j < 8; ++j) b[j] = 0;
+        int c = memcmp(a, b, 8);
+        uint64_t ka = ref_key(a), kb = ref_key(b);
+        CHECK((c < 0) == (ka < kb) && (c == 0) == (ka == kb), "order");
+        CHECK(clip_at_zero(ka) == ka, "clip idempotent");
+    }
+}
+
+// in-order traversal of a perfect tree with heap indices 1..2^d-1
+static void inorder(uint32_t i, uint32_t v, std::vector<uint32_t>& out) {
+    if (i > v) return;
+    inorder(2 * i, v, out);
+    out.push_back(i);
+    inorder(2 * i + 1, v, out);
+}
+
+static void test_inorder_map() {
+    for (uint32_t d = 1; d <= 10; ++d) {
+        uint32_t v = (1u << d) - 1;
+        std::vector<uint32_t> ord;
+        inorder(1, v, ord);
+        for (uint32_t j = 0; j < v; ++j) CHECK(inorder_node(j, d) == ord[j], "d %u j %u", d, j);
+    }
+}
+
+// Build a tree from a sorted sample exactly as the device does, level by level.
+static void build_tree(const std::vector<uint64_t>& smp, uint32_t d, std::vector<uint64_t>& t,
+                       std::vector<uint64_t>& tin) {
+    uint32_t v = (1u << d) - 1;
+    t.assign(v + 1, 0);
+    std::vector<uint32_t> ra(v + 1), rb(v + 1);
+    ra[1] = 0;
+    rb[1] = (uint32_t)smp.size();
+    for (uint32_t L = 0; L < d; ++L)
+        for (uint32_t i = 1u << L; i < (2u << L); ++i) {
+            uint32_t a = ra[i], b = rb[i], lo = 0, hi = 0;
+            uint64_t x;
+            if (a < b) select_node(smp.data(), a, b, &x, &lo, &hi);
+            else x = t[i >> 1];
+            t[i] = x;
+            if (L + 1 < d) {
+                ra[2 * i] = a < b ? a : 0; rb[2 * i] = a < b ? lo : 0;
+                ra[2 * i + 1] = a < b ? hi : 0; rb[2 * i + 1] = a < b ? b : 0;
+            }
+        }
+    tin.assign(v + 1, 0);
+    for (uint32_t j = 0; j < v; ++j) tin[j] = t[inorder_node(j, d)];
+}
+
+static void test_tree_and_classify(std::mt19937_64& rng) {
+    for (int rep = 0; rep < 300; ++rep) {
+        uint32_t d = 1 + rng() % 10, v = (1u << d) - 1;
+        uint32_t m = 1 + rng() % (4 * (v + 1));
+        uint32_t distinct = 1 + rng() % (2 * m);
+        std::vector<uint64_t> pool(distinct);
+        for (auto& x : pool) x = rng() >> (rng() % 64);
+        std::vector<uint64_t> smp(m);
+        for (auto& x : smp) x = pool[rng() % distinct];
+        std::sort(smp.begin(), smp.end());
+        std::vector<uint64_t> t, tin;
+        build_tree(smp, d, t, tin);
+        for (uint32_t j = 1; j < v; ++j) CHECK(tin[j - 1] <= tin[j], "in-order sorted d %u", d);
+        for (int probe = 0; probe < 200; ++probe) {
+            uint64_t key[4];
+            for (auto& k : key) k = (rng() % 2) ? pool[rng() % distinct] + (rng() % 3) - 1 : rng();
+            uint32_t b[4];
+            classify_u<4>(t.data(), tin.data(), d, v, key, b);
+            for (int q = 0; q < 4; ++q) {
+                uint32_t j = (uint32_t)(std::lower_bound(tin.begin(), tin.begin() + v, key[q]) -
+                                        tin.begin());
+                uint32_t want = 2 * j + (j < v && tin[j] == key[q]);
+                CHECK(b[q] == want, "classify d %u key %llx got %u want %u", d,
+                      (unsigned long long)key[q], b[q], want);
+            }
+        }
+    }
+}
+
+static void test_fig1(const char* path) {
+    FILE* f = fopen(path, "r");
+    CHECK(f != nullptr, "open %s", path);
+    if (!f) return;
+    char line[256];
+    std::vector<uint64_t> spl, lvl;
+    std::vector<std::pair<uint64_t, uint32_t>> probes;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        char tag[32];
+        if (sscanf(line, "%31s", tag) != 1) continue;
+        const char* p = line + strlen(tag);
+        if (!strcmp(tag, "splitters") || !strcmp(tag, "level_order")) {
+            unsigned long long x;
+            int used;
+            while (sscanf(p, " %llx%n", &x, &used) == 1) {
+                (!strcmp(tag, "splitters") ? spl : lvl).push_back(x);
+                p += used;
+            }
+        } else if (!strcmp(tag, "probe")) {
+            unsigned long long x;
+            unsigned b;
+            if (sscanf(p, " %llx %u", &x, &b) == 2) probes.push_back({x, b});
+        }
+    }
+    fclose(f);
+    CHECK(spl.size() == 3 && lvl.size() == 3 && probes.size() >= 7, "fixture shape");
+    if (spl.size() != 3 || lvl.size() != 3) return;
+    std::vector<uint64_t> t, tin;
+    build_tree(spl, 2, t, tin);
+    for (int i = 0; i < 3; ++i) CHECK(t[i + 1] == lvl[i], "fig1 level order %d", i);
+    for (auto& pr : probes) {
+        uint64_t key[1] = {pr.first};
+        uint32_t b[1];
+        classify_u<1>(t.data(), tin.data(), 2, 3, key, b);
+        CHECK(b[0] == pr.second, "fig1 probe %llx got %u want %u", (unsigned long long)pr.first,
+              b[0], pr.second);
+    }
+}
+
+int main(int argc, char** argv) {
+    std::mt19937_64 rng(12345);
+    test_load_key_guarded(rng);
+    test_load_key_random(rng);
+    test_inorder_map();
+    test_tree_and_classify(rng);
+    if (argc > 1) test_fig1(argv[1]);
+    if (failures) {
+        printf("%d failures\n", failures);
+        return 1;
+    }
+    printf("OK\n");
+    return 0;
+}

@@ -1,0 +1,57 @@
+"""C-ABI checks that need no GPU: the library loads and exports every entry
+point that ``include/*.h`` declares; host-only calls behave as documented."""
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(s5_[a-z_]+)\s*\(",
+                             text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1305_1157_amd import s5
+    if not os.path.exists(s5.LIB_PATH):
+        from paper_1305_1157_amd import build
+        build.build()
+    return s5.load()
+
+
+def test_every_declared_symbol_exported(lib):
+    names = declared_functions()
+    assert {"s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_workspace_bytes", "s5_stats_get",
+            "s5_strerror", "s5_release"} <= names
+    for name in names:
+        assert hasattr(lib, name), f"{name} not exported"
+
+
+def test_strerror(lib):
+    for rc in (0, -1, -2, -3, -4):
+        assert lib.s5_strerror(rc)
+    assert lib.s5_strerror(-99) == b"unknown status"
+
+
+def test_workspace_bytes(lib):
+    from paper_1305_1157_amd import s5
+    small = s5.workspace_bytes(1000)
+    big = s5.workspace_bytes(1_000_000)
+    assert 0 < small < big
+    # about 26 B/string of work arrays plus bounded per-pass storage
+    assert 26 * 1_000_000 < big < 64 * 1_000_000
+    # invalid configurations are rejected (0 bytes)
+    assert s5.workspace_bytes(1000, s5.make_config(splitters=100)) == 0
+    assert s5.workspace_bytes(1000, s5.make_config(base_threshold=8192)) == 0
+    assert s5.workspace_bytes(1000, s5.make_config(unroll=3)) == 0
+    assert s5.workspace_bytes(1000, s5.make_config(splitters=1023, unroll=8)) > 0

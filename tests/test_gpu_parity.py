@@ -1,0 +1,168 @@
+"""Parity of the HIP S^5 path with the CPU oracle (bit-exact perm and LCP)."""
+import random
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from gpu_util import assert_parity, gpu_sort, strings_parity, to_dev  # noqa: E402
+from paper_1305_1157_amd import gen, s5  # noqa: E402
+
+# configurations that force many passes, tiny trees and every unroll variant
+CFGS = {
+    "default": None,
+    "tiny_T_v7": s5.make_config(splitters=7, base_threshold=64, tile=64),
+    "v1023_u8": s5.make_config(splitters=1023, unroll=8, base_threshold=4096),
+    "v31_u1_T128": s5.make_config(splitters=31, unroll=1, base_threshold=128, tile=128),
+    "v63_u2_a4": s5.make_config(splitters=63, unroll=2, oversample=4, base_threshold=256),
+}
+
+
+def test_prefix_keys_vs_bytes():
+    rng = random.Random(3)
+    strings = [bytes(rng.choice([1, 0x41, 0x7F, 0x80, 0xFE, 0xFF]) for _ in range(rng.randint(0, 30)))
+               for _ in range(3000)]
+    chars, offs = gen.from_strings(strings)
+    raw = chars.tobytes()
+    for depth in (0, 1, 5):
+        sel = [i for i, s in enumerate(strings) if len(s) >= depth]
+        o = offs[sel] + depth
+        keys = s5.prefix_keys(to_dev(chars), to_dev(o), 0).cpu().numpy()
+        for j, i in enumerate(sel):
+            b = raw[o[j]:o[j] + 8].split(b"\x00")[0][:8]
+            want = int.from_bytes(b.ljust(8, b"\x00"), "big")
+            assert int(keys[j]) == want, (depth, i)
+
+
+def test_classify_vs_searchsorted():
+    rng = np.random.default_rng(5)
+    for v in (1, 3, 7, 255, 1023):
+        spl = np.sort(rng.integers(0, 2**63, size=v, dtype=np.uint64))
+        if v > 3:
+            spl[v // 2] = spl[v // 2 - 1]  # a duplicate splitter
+        keys = np.concatenate([rng.integers(0, 2**63, size=5000, dtype=np.uint64), spl,
+                               np.array([0, 2**64 - 1], dtype=np.uint64)])
+        got = s5.classify(to_dev(keys), to_dev(spl)).cpu().numpy().astype(np.int64)
+        j = np.searchsorted(spl, keys, side="left")
+        eq = (j < v) & (spl[np.minimum(j, v - 1)] == keys)
+        want = 2 * j + eq
+        assert np.array_equal(got, want), v
+
+
+def test_fig1_tree():
+    spl = np.array([0x6161610000000000, 0x6D6D6D0000000000, 0x7878780000000000], dtype=np.uint64)
+    keys = np.array([0, 0x6161600000000000, 0x6161610000000000, 0x6161610000000001,
+                     0x6A00000000000000, 0x6D6D6D0000000000, 0x6D6D6D6100000000,
+                     0x7878780000000000, 0x7878780100000000, 2**64 - 1], dtype=np.uint64)
+    got = s5.classify(to_dev(keys), to_dev(spl)).cpu().numpy().tolist()
+    assert got == [0, 0, 1, 2, 2, 3, 4, 5, 6, 6]
+
+
+EDGE = {
+    "one": [b"abc"],
+    "two_equal": [b"x", b"x"],
+    "two": [b"b", b"a"],
+    "all_empty": [b""] * 5000,
+    "all_equal": [b"same string here"] * 7000,
+    "key_boundary": [b"k" * L for L in (7, 8, 9, 15, 16, 17, 0, 1)] * 700,
+    "prefixes_of_each_other": [b"q" * (i % 97) for i in range(9000)],
+    "high_bytes": [bytes([0x80 + (i * 7) % 128, 0xFF, 0x01 + i % 3]) for i in range(6000)],
+    "long_shared_prefix": [b"p" * 1000 + bytes([65 + (i * 31) % 26, 65 + i % 26]) for i in range(5000)],
+    "giant_eq_bucket_plus_tiny": [b"giant" if i % 4 else bytes([97 + i % 26]) * (1 + i % 13)
+                                  for i in range(40000)],
+}
+
+
+@pytest.mark.parametrize("name", sorted(EDGE))
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7"])
+def test_edge_cases(name, cfg):
+    strings_parity(EDGE[name], CFGS[cfg], label=f"{name}/{cfg}")
+
+
+def test_empty_input():
+    perm, lcp = gpu_sort(np.zeros(8, np.uint8), np.zeros(0, np.uint64))
+    assert perm.size == 0 and lcp.size == 0
+
+
+def test_suffixes_overlapping_offsets():
+    rng = random.Random(11)
+    text = bytes(rng.choice(b"abab" b"c") for _ in range(30000))
+    chars = np.frombuffer(text + b"\x00", dtype=np.uint8).copy()
+    offs = np.arange(len(text), dtype=np.uint64)
+    for cfg in ("default", "tiny_T_v7"):
+        assert_parity(chars, offs, CFGS[cfg], label=f"suffixes/{cfg}")
+
+
+def test_many_copies_of_one_string():
+    chars, offs = gen.from_strings([b"copy-me"])
+    offs = np.zeros(1 << 20, dtype=np.uint64)
+    st = assert_parity(chars, offs, None, label="2^20 copies")
+    assert st["passes"] >= 1
+
+
+@pytest.mark.parametrize("name,n", [("random_1M", 200_000), ("url_10M", 200_000),
+                                    ("dna_16M", 100_000), ("words_50M", 300_000)])
+@pytest.mark.parametrize("cfg", sorted(CFGS))
+def test_workloads(name, n, cfg):
+    chars, offs = gen.workload(name, n)
+    assert_parity(chars, offs, CFGS[cfg], label=f"{name}[{n}]/{cfg}")
+
+
+def test_random_1M_full():
+    chars, offs = gen.workload("random_1M")
+    st = assert_parity(chars, offs, None, label="random_1M full")
+    assert st["passes"] >= 1 and st["moved_M"] >= 1_000_000
+
+
+def test_output_independent_of_seed():
+    chars, offs = gen.workload("words_50M", 100_000)
+    a = gpu_sort(chars, offs, s5.make_config(seed=1, base_threshold=128))
+    b = gpu_sort(chars, offs, s5.make_config(seed=99, base_threshold=128))
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_six_argument_entry_point():
+    chars, offs = gen.workload("random_1M", 50_000)
+    dc, do = to_dev(chars), to_dev(offs)
+    perm = torch.empty(offs.size, dtype=torch.uint32, device=dc.device)
+    lcp = torch.empty(offs.size, dtype=torch.uint32, device=dc.device)
+    s5.sort_plain(dc, do, perm, lcp)
+    torch.cuda.synchronize()
+    rp, rl = oracle.sort(chars, offs)
+    assert np.array_equal(perm.cpu().numpy(), rp) and np.array_equal(lcp.cpu().numpy(), rl)
+
+
+def test_user_workspace():
+    chars, offs = gen.workload("url_10M", 30_000)
+    cfg = s5.make_config(base_threshold=256)
+    ws = torch.empty(s5.workspace_bytes(offs.size, cfg), dtype=torch.uint8, device="cuda")
+    perm, lcp = s5.sort(to_dev(chars), to_dev(offs), cfg=cfg, workspace=ws)
+    torch.cuda.synchronize()
+    rp, rl = oracle.sort(chars, offs)
+    assert np.array_equal(perm.cpu().numpy(), rp) and np.array_equal(lcp.cpu().numpy(), rl)
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(s5.S5Error):
+        s5.sort(to_dev(chars), to_dev(offs), cfg=cfg, workspace=small)
+
+
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7"])
+def test_batched_small(cfg):
+    chars, offs, sb = gen.batched(60, 1, 5000, kinds=("random", "url", "dna", "words"), seed=7)
+    # include empty sets and single-string sets
+    sizes = np.diff(sb).astype(np.int64)
+    sizes[3] = 0
+    sizes[5] = 1
+    sb2 = np.zeros(sizes.size + 1, dtype=np.uint64)
+    np.cumsum(sizes, out=sb2[1:])
+    offs2 = np.concatenate([offs[int(sb[s]):int(sb[s]) + int(sizes[s])] for s in range(sizes.size)])
+    perm, lcp = s5.sort_batched(to_dev(chars), to_dev(offs2), to_dev(sb2), cfg=CFGS[cfg])
+    torch.cuda.synchronize()
+    rp, rl = oracle.sort_batched(chars, offs2, sb2)
+    assert np.array_equal(perm.cpu().numpy(), rp)
+    assert np.array_equal(lcp.cpu().numpy(), rl)
