@@ -15,8 +15,10 @@
 #include <algorithm>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 #include "../../include/s5.h"
+#include "../../include/s5_profile.h"
 #include "s5_internal.h"
 
 namespace s5 {
@@ -179,6 +181,74 @@ int pool_get(size_t bytes, DevPool** out) {
     return S5_OK;
 }
 
+
+// ---- per-kernel event timing (s5_profile.h) --------------------------------
+enum KId { K_INIT, K_ROOTS, K_SAMPLE, K_CLASSIFY, K_COLSCAN, K_PLAN, K_SCATTER, K_BASE, K_LCPFIX,
+           K_COUNT };
+const char* const kKName[K_COUNT] = {"init_keys", "plan_roots", "sample_tree", "classify",
+                                     "colscan",   "bucket_plan", "scatter",    "base_sort",
+                                     "lcp_fix"};
+// algorithmic bytes per string processed: init reads an offset and 8 key bytes
+// and writes key + index; classify reads a key and writes a bucket id; a
+// redistribution pass reads and writes (key, index); the base case reads
+// (key, index) and writes perm + lcp; the LCP completion reads one lcp word
+const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4};
+struct ProfAcc {
+    uint64_t launches = 0, items = 0;
+    double ms = 0, bytes = 0;
+};
+struct Pending {
+    int k;
+    hipEvent_t a, b;
+    uint64_t items;
+};
+bool g_prof_on = false;
+ProfAcc g_prof[K_COUNT];
+std::vector<hipEvent_t> g_event_pool;
+std::vector<Pending> g_pending;
+
+hipEvent_t prof_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch `fn` on `st`, bracketed by events when profiling is on.
+template <class F>
+void timed(int k, uint64_t items, hipStream_t st, F&& fn) {
+    if (!g_prof_on) {
+        fn();
+        return;
+    }
+    hipEvent_t a = prof_event(), b = prof_event();
+    if (a) (void)hipEventRecord(a, st);
+    fn();
+    if (b) (void)hipEventRecord(b, st);
+    if (a && b) g_pending.push_back({k, a, b, items});
+}
+
+// After the stream has been synchronized: fold pending events into totals.
+void prof_collect() {
+    for (auto& p : g_pending) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ProfAcc& A = g_prof[p.k];
+            A.launches += 1;
+            A.items += p.items;
+            A.ms += ms;
+            A.bytes += kKBytes[p.k] * (double)p.items;
+        }
+        g_event_pool.push_back(p.a);
+        g_event_pool.push_back(p.b);
+    }
+    g_pending.clear();
+}
+
 struct SortArgs {
     const uint8_t* chars;
     const uint64_t* offsets;
@@ -235,11 +305,16 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
 
     S5_HIP(hipMemsetAsync(cnt[0], 0, sizeof(Counters), st));
     S5_HIP(hipMemsetAsync(glob, 0, sizeof(Globals), st));
-    launch_init_keys(a.chars, a.offsets, a.n, key[0], idx[0], st);
-    launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, ctx_for(0), st);
+    timed(K_INIT, a.n, st, [&] { launch_init_keys(a.chars, a.offsets, a.n, key[0], idx[0], st); });
+    timed(K_ROOTS, a.num_sets, st, [&] {
+        launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, ctx_for(0), st);
+    });
     S5_HIP(hipGetLastError());
     int rc = readback(0);
-    if (rc) return rc;
+    if (rc) {
+        prof_collect();
+        return rc;
+    }
 
     int cur = 0;  // lseg / counters index of the pass about to run
     int buf = 0;  // work buffer holding the pass's input
@@ -249,19 +324,31 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         const uint32_t kmax = now.kmax, vmax = (kmax - 1) / 2;
         const int nxt = cur ^ 1;
         S5_HIP(hipMemsetAsync(cnt[nxt], 0, sizeof(Counters), st));
-        launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
-                           tree_in, tree_lcp, unit_tab, chunk_tab, st);
-        launch_classify(now.units, c.unroll, lseg[cur], unit_tab, key[buf], tree_lo, tree_in, bid,
-                        cm, vmax, kmax, st);
-        launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st);
-        launch_bucket_plan(now.n_large, lseg[cur], cs, bstart, tree_in, tree_lcp, ctx_for(nxt),
-                           (uint32_t)(buf ^ 1), st);
-        launch_scatter(now.units, c.unroll, lseg[cur], unit_tab, bid, key[buf], idx[buf],
-                       key[buf ^ 1], idx[buf ^ 1], cm, cs, bstart, tree_in, tree_lcp, a.chars,
-                       a.offsets, a.perm, a.lcp, vmax, kmax, st);
+        timed(K_SAMPLE, now.n_large, st, [&] {
+            launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
+                               tree_in, tree_lcp, unit_tab, chunk_tab, st);
+        });
+        timed(K_CLASSIFY, now.moved, st, [&] {
+            launch_classify(now.units, c.unroll, lseg[cur], unit_tab, key[buf], tree_lo, tree_in,
+                            bid, cm, vmax, kmax, st);
+        });
+        timed(K_COLSCAN, now.moved, st,
+              [&] { launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st); });
+        timed(K_PLAN, now.moved, st, [&] {
+            launch_bucket_plan(now.n_large, lseg[cur], cs, bstart, tree_in, tree_lcp, ctx_for(nxt),
+                               (uint32_t)(buf ^ 1), st);
+        });
+        timed(K_SCATTER, now.moved, st, [&] {
+            launch_scatter(now.units, c.unroll, lseg[cur], unit_tab, bid, key[buf], idx[buf],
+                           key[buf ^ 1], idx[buf ^ 1], cm, cs, bstart, tree_in, tree_lcp, a.chars,
+                           a.offsets, a.perm, a.lcp, vmax, kmax, st);
+        });
         S5_HIP(hipGetLastError());
         rc = readback(nxt);
-        if (rc) return rc;
+        if (rc) {
+            prof_collect();
+            return rc;
+        }
         stats->moved_M += now.moved;
         stats->segments += now.n_large;
         if (level == 0) {
@@ -275,12 +362,17 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
     stats->passes = level;
     const uint32_t n_base = hg->n_base;
     stats->base_items = n_base;
-    launch_base_sort(n_base, base_list, key[0], key[1], idx[0], idx[1], a.chars, a.offsets, a.perm,
-                     a.lcp, c.T, st);
-    launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, st);
+    timed(K_BASE, hg->base_elems, st, [&] {
+        launch_base_sort(n_base, base_list, key[0], key[1], idx[0], idx[1], a.chars, a.offsets,
+                         a.perm, a.lcp, c.T, st);
+    });
+    timed(K_LCPFIX, a.n, st, [&] {
+        launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, st);
+    });
     S5_HIP(hipGetLastError());
     S5_HIP(hipMemcpyAsync(hg, glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
     S5_HIP(hipStreamSynchronize(st));
+    prof_collect();
     return hg->status ? S5_ERR_DEVICE : S5_OK;
 }
 
@@ -425,6 +517,35 @@ int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uin
     if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
     // the pool may be reused by the next call: finish before returning
     return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;
+}
+
+
+int s5_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_prof_on = on != 0;
+    for (auto& A : g_prof) A = ProfAcc();
+    return S5_OK;
+}
+
+int s5_profile_read(s5_kernel_profile* out, uint32_t max, uint32_t* count) {
+    if (!out || !count) return S5_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    uint32_t c = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (!g_prof[k].launches) continue;
+        if (c < max) {
+            s5_kernel_profile& p = out[c];
+            memset(&p, 0, sizeof p);
+            strncpy(p.name, kKName[k], sizeof p.name - 1);
+            p.launches = g_prof[k].launches;
+            p.total_ms = g_prof[k].ms;
+            p.items = g_prof[k].items;
+            p.alg_bytes = g_prof[k].bytes;
+        }
+        ++c;
+    }
+    *count = c;
+    return S5_OK;
 }
 
 }  // extern "C"

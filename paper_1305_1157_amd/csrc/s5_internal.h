@@ -58,7 +58,7 @@ struct Counters {
 struct Globals {
     uint32_t n_base;   // base-case items appended so far
     uint32_t status;   // error bits
-    uint32_t pad0, pad1;
+    unsigned long long base_elems;  // strings in those items
 };
 
 // Capacities of the per-pass storage.

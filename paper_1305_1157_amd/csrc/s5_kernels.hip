@@ -94,6 +94,7 @@ __device__ void plan_segment(uint32_t begin, uint32_t size, uint32_t depth, uint
         s.depth = depth | (buf ? kBufBit : 0u);
         s.base = base;
         c.base_list[slot] = s;
+        atomicAdd(&c.glob->base_elems, (unsigned long long)size);
         return;
     }
     // a large segment: sized tree and units for the next distribution pass

@@ -18,7 +18,8 @@ S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP, S5_ERR_DEVICE = 0, -1, -2, -3, 
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched", "s5_stats_get",
-           "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify")
+           "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
+           "s5_profile_read")
 
 
 class Config(ctypes.Structure):
@@ -36,6 +37,12 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("items", ctypes.c_uint64),
+                ("alg_bytes", ctypes.c_double)]
 
 
 class S5Error(RuntimeError):
@@ -67,8 +74,10 @@ def load(path: str = LIB_PATH):
     lib.s5_release.restype = None
     lib.s5_prefix_keys.argtypes = [P, P, U32, U32, P, P]
     lib.s5_classify.argtypes = [P, U32, P, U32, P, P]
+    lib.s5_profile_enable.argtypes = [ctypes.c_int]
+    lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
     for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_stats_get", "s5_prefix_keys",
-              "s5_classify"):
+              "s5_classify", "s5_profile_enable", "s5_profile_read"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -185,3 +194,21 @@ def classify(keys: torch.Tensor, splitters: torch.Tensor, stream=None):
 
 def release():
     load().s5_release()
+
+
+def profile_enable(on: bool = True):
+    """Turn per-kernel HIP-event timing on or off (clears the accumulators)."""
+    _check(load().s5_profile_enable(1 if on else 0))
+
+
+def profile_read() -> dict:
+    """Per-kernel totals since the last ``profile_enable``: name -> dict."""
+    arr = (KernelProfile * 32)()
+    cnt = ctypes.c_uint32(0)
+    _check(load().s5_profile_read(arr, 32, ctypes.byref(cnt)))
+    out = {}
+    for i in range(min(cnt.value, 32)):
+        e = arr[i]
+        out[e.name.decode()] = {"launches": e.launches, "total_ms": e.total_ms,
+                                "items": e.items, "alg_bytes": e.alg_bytes}
+    return out
