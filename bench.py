@@ -145,7 +145,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "n": n,
                    "arena_bytes": int(chars.size), "D": D, "variant": "plain S^5, sampled splitters",
-                   "splitters_max": 255, "base_threshold": 2048},
+                   "splitters_max": 255, "base_threshold": 1024},
         "hbm": {"B_min_bytes": b_min, "B_alg_bytes": b_alg, "moved_M": st["moved_M"],
                 "passes": st["passes"], "B_min_GBps": b_min / sec / 1e9,
                 "B_alg_GBps": b_alg / sec / 1e9,

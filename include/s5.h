@@ -69,7 +69,7 @@ typedef struct s5_config {
     uint32_t base_threshold; /* buckets of at most this many strings are finished
                                 by the LDS base-case sorter (Section 3.1
                                 "Parallelization", the size-classed sub-algorithms;
-                                64 <= T <= 4096, default 2048) */
+                                64 <= T <= 2048, default 1024) */
     uint32_t splitter_mode;  /* S5_SPLIT_SAMPLED or S5_SPLIT_LEARNED */
     float imbalance_bound;   /* learned mode: fall back to sampled splitters when a
                                 range bucket exceeds this many times the ideal

@@ -27,7 +27,8 @@ void launch_prefix_keys(const uint8_t*, const uint64_t*, uint32_t, uint32_t, uin
 void launch_plan_roots(const uint64_t*, uint32_t, uint32_t, uint32_t*, uint32_t*, const PlanCtx&,
                        hipStream_t);
 void launch_sample_tree(uint32_t, const LSeg*, const uint64_t*, uint32_t, uint32_t, uint64_t,
-                        uint64_t*, uint64_t*, uint8_t*, uint32_t*, uint32_t*, hipStream_t);
+                        uint64_t*, uint64_t*, uint8_t*, uint32_t*, uint32_t*, Counters*,
+                        hipStream_t);
 void launch_classify(uint32_t, uint32_t, const LSeg*, const uint32_t*, const uint64_t*,
                      const uint64_t*, const uint64_t*, uint16_t*, uint32_t*, uint32_t, uint32_t,
                      hipStream_t);
@@ -40,9 +41,9 @@ void launch_scatter(uint32_t, uint32_t, const LSeg*, const uint32_t*, const uint
                     const uint32_t*, const uint32_t*, const uint64_t*, const uint8_t*,
                     const uint8_t*, const uint64_t*, uint32_t*, uint32_t*, uint32_t, uint32_t,
                     hipStream_t);
-void launch_base_sort(uint32_t, const Seg*, const uint64_t*, const uint64_t*, const uint32_t*,
-                      const uint32_t*, const uint8_t*, const uint64_t*, uint32_t*, uint32_t*,
-                      uint32_t, hipStream_t);
+void launch_base_sort(const uint32_t*, Seg* const*, const uint64_t*, const uint64_t*,
+                      const uint32_t*, const uint32_t*, const uint8_t*, const uint64_t*, uint32_t*,
+                      uint32_t*, uint32_t, hipStream_t);
 void launch_lcp_fix(const uint8_t*, const uint64_t*, const uint64_t*, uint32_t, uint32_t,
                     const uint32_t*, uint32_t*, hipStream_t);
 void launch_classify_plain(const uint64_t*, uint32_t, const uint64_t*, uint32_t, uint32_t,
@@ -74,8 +75,8 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     if (o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8) return S5_ERR_INVALID;
     o->unit_min = c->tile ? c->tile : 1024u;
     if (o->unit_min % 64 || o->unit_min > (1u << 20)) return S5_ERR_INVALID;
-    o->T = c->base_threshold ? c->base_threshold : 2048u;
-    if (o->T < 64 || o->T > 4096) return S5_ERR_INVALID;
+    o->T = c->base_threshold ? c->base_threshold : 1024u;
+    if (o->T < 64 || o->T > 2048) return S5_ERR_INVALID;
     o->mode = c->splitter_mode;
     if (o->mode != S5_SPLIT_SAMPLED && o->mode != S5_SPLIT_LEARNED) return S5_ERR_INVALID;
     o->beta = c->imbalance_bound > 0 ? c->imbalance_bound : 4.0f;
@@ -106,7 +107,10 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     cp.chunks = (uint32_t)chunks;
     cp.tree = (uint32_t)tree;
     cp.bstart = (uint32_t)(2 * tree + large + 2);
-    cp.base = (uint32_t)(n / 2 + 2);
+    // every base item holds >= 2 strings, and > 64 / > 512 in the larger classes
+    cp.base[0] = (uint32_t)(n / 2 + 2);
+    cp.base[1] = (uint32_t)(n / (kBaseWave + 1) + 2);
+    cp.base[2] = (uint32_t)(n / (kBaseMid + 1) + 2);
     // sum over segments of units x k: units_s <= |S|/unit_min + 4 and
     // k_s <= max(3, min(kmax, 8 |S| / T))
     const uint64_t ksum = 3 * large + 8 * n / c.T + kmax;
@@ -130,9 +134,12 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     L.cm = take((size_t)cp.cm * 4);
     L.cs = take((size_t)cp.cs * 4);
     L.bstart = take((size_t)cp.bstart * 4);
-    L.base_list = take((size_t)cp.base * sizeof(Seg));
-    for (int b = 0; b < 2; ++b) L.counters[b] = take(sizeof(Counters));
-    L.glob = take(sizeof(Globals));
+    L.base_list = take((size_t)(cp.base[0] + cp.base[1] + cp.base[2]) * sizeof(Seg));
+    // [counters 0 | globals | counters 1] back to back: one copy reads a pass's
+    // counters together with the globals
+    L.counters[0] = take(sizeof(Counters) + sizeof(Globals) + sizeof(Counters));
+    L.glob = L.counters[0] + sizeof(Counters);
+    L.counters[1] = L.glob + sizeof(Globals);
     L.total = p;
     L.caps = cp;
     return L;
@@ -278,17 +285,20 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
     uint32_t* cm = (uint32_t*)(W + L.cm);
     uint32_t* cs = (uint32_t*)(W + L.cs);
     uint32_t* bstart = (uint32_t*)(W + L.bstart);
-    Seg* base_list = (Seg*)(W + L.base_list);
+    Seg* base_list[kBaseClasses];
+    base_list[0] = (Seg*)(W + L.base_list);
+    base_list[1] = base_list[0] + L.caps.base[0];
+    base_list[2] = base_list[1] + L.caps.base[1];
     Counters* cnt[2] = {(Counters*)(W + L.counters[0]), (Counters*)(W + L.counters[1])};
     Globals* glob = (Globals*)(W + L.glob);
-    Counters* hc = (Counters*)host;
-    Globals* hg = (Globals*)((char*)host + 512);
+    Counters* hc = (Counters*)((char*)host + 1024);
+    Globals* hg = (Globals*)((char*)host + 2048);
 
     auto ctx_for = [&](int next) {
         PlanCtx x;
         x.lseg = lseg[next];
         x.cnt = cnt[next];
-        x.base_list = base_list;
+        for (int q = 0; q < kBaseClasses; ++q) x.base_list[q] = base_list[q];
         x.glob = glob;
         x.caps = L.caps;
         x.T = c.T;
@@ -297,14 +307,17 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         return x;
     };
     auto readback = [&](int which) -> int {
-        S5_HIP(hipMemcpyAsync(hc, cnt[which], sizeof(Counters), hipMemcpyDeviceToHost, st));
-        S5_HIP(hipMemcpyAsync(hg, glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+        char* src = which == 0 ? (char*)cnt[0] : (char*)glob;
+        S5_HIP(hipMemcpyAsync(host, src, sizeof(Counters) + sizeof(Globals), hipMemcpyDeviceToHost,
+                              st));
         S5_HIP(hipStreamSynchronize(st));
+        const char* hb = (const char*)host;
+        memcpy(hc, which == 0 ? hb : hb + sizeof(Globals), sizeof(Counters));
+        memcpy(hg, which == 0 ? hb + sizeof(Counters) : hb, sizeof(Globals));
         return hg->status ? S5_ERR_DEVICE : S5_OK;
     };
 
-    S5_HIP(hipMemsetAsync(cnt[0], 0, sizeof(Counters), st));
-    S5_HIP(hipMemsetAsync(glob, 0, sizeof(Globals), st));
+    S5_HIP(hipMemsetAsync(cnt[0], 0, 2 * sizeof(Counters) + sizeof(Globals), st));
     timed(K_INIT, a.n, st, [&] { launch_init_keys(a.chars, a.offsets, a.n, key[0], idx[0], st); });
     timed(K_ROOTS, a.num_sets, st, [&] {
         launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, ctx_for(0), st);
@@ -323,10 +336,9 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         const Counters now = *hc;
         const uint32_t kmax = now.kmax, vmax = (kmax - 1) / 2;
         const int nxt = cur ^ 1;
-        S5_HIP(hipMemsetAsync(cnt[nxt], 0, sizeof(Counters), st));
         timed(K_SAMPLE, now.n_large, st, [&] {
             launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
-                               tree_in, tree_lcp, unit_tab, chunk_tab, st);
+                               tree_in, tree_lcp, unit_tab, chunk_tab, cnt[nxt], st);
         });
         timed(K_CLASSIFY, now.moved, st, [&] {
             launch_classify(now.units, c.unroll, lseg[cur], unit_tab, key[buf], tree_lo, tree_in,
@@ -360,8 +372,9 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         buf ^= 1;
     }
     stats->passes = level;
-    const uint32_t n_base = hg->n_base;
-    stats->base_items = n_base;
+    uint32_t n_base[kBaseClasses];
+    for (int q = 0; q < kBaseClasses; ++q) n_base[q] = hg->n_base[q];
+    stats->base_items = (uint64_t)n_base[0] + n_base[1] + n_base[2];
     timed(K_BASE, hg->base_elems, st, [&] {
         launch_base_sort(n_base, base_list, key[0], key[1], idx[0], idx[1], a.chars, a.offsets,
                          a.perm, a.lcp, c.T, st);

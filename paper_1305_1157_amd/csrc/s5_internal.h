@@ -55,15 +55,23 @@ struct Counters {
 };
 
 // Device-global state that survives the whole sort.
+// Base-case items go to one of three lists by size: <= 64 strings (one
+// wavefront each), <= 512, and <= T (one workgroup each).
+constexpr int kBaseClasses = 3;
+constexpr uint32_t kBaseWave = 64, kBaseMid = 512;
+__host__ __device__ inline int base_class(uint32_t size) {
+    return size <= kBaseWave ? 0 : (size <= kBaseMid ? 1 : 2);
+}
+
 struct Globals {
-    uint32_t n_base;   // base-case items appended so far
-    uint32_t status;   // error bits
+    uint32_t n_base[kBaseClasses];  // base-case items appended so far, per class
+    uint32_t status;                // error bits
     unsigned long long base_elems;  // strings in those items
 };
 
 // Capacities of the per-pass storage.
 struct Caps {
-    uint32_t large, units, chunks, tree, bstart, base;
+    uint32_t large, units, chunks, tree, bstart, base[kBaseClasses];
     unsigned long long cm, cs;
 };
 
@@ -71,7 +79,7 @@ struct Caps {
 struct PlanCtx {
     LSeg* lseg;           // next pass's segment list
     Counters* cnt;        // next pass's counters
-    Seg* base_list;       // base-case items (all passes)
+    Seg* base_list[kBaseClasses];  // base-case items (all passes), per size class
     Globals* glob;
     Caps caps;
     uint32_t T;           // base threshold

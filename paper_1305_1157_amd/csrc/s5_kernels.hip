@@ -78,56 +78,103 @@ __device__ uint32_t block_exclusive_scan(const uint32_t* cnt, uint32_t* out, uin
 }
 
 // ---------------------------------------------------------------------------
-// planning: decide what happens to a bucket of >= 2 strings
+// planning: decide what happens to every bucket of >= 2 strings.  A block
+// first tallies its requests in LDS, then takes one global allocation per
+// counter, then hands out the slots from LDS counters (no contention on the
+// global counters beyond one atomic per counter and block).
 
-__device__ void plan_segment(uint32_t begin, uint32_t size, uint32_t depth, uint32_t base,
-                             uint32_t buf, const PlanCtx& c) {
+struct PlanTally {
+    uint32_t n_base[kBaseClasses], n_large, units, chunks, tree, bstart, kmax, err;
+    unsigned long long cm, cs, moved, base_elems;
+};
+
+// tree depth and units of a large segment of `size` strings
+__device__ __forceinline__ void seg_shape(uint32_t size, const PlanCtx& c, uint32_t& d,
+                                          uint32_t& ulen, uint32_t& units, uint32_t& chunks) {
+    d = 1;
+    while (d < c.d_max && ((uint64_t)c.T << d) < 2ull * size) ++d;  // 2^d * T/2 >= size
+    ulen = (uint32_t)(((uint64_t)size + kMaxUnits - 1) / kMaxUnits);
+    ulen = (ulen + 63u) & ~63u;
+    if (ulen < c.unit_min) ulen = c.unit_min;
+    units = (uint32_t)(((uint64_t)size + ulen - 1) / ulen);
+    units = (units + kWaves - 1) / kWaves * kWaves;
+    chunks = (units + kChunkRows - 1) / kChunkRows;
+}
+
+// Phase 1 for one request (begin, size >= 2, depth).
+__device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, PlanTally* T) {
     if (size <= c.T) {
-        uint32_t slot = atomicAdd(&c.glob->n_base, 1u);
-        if (slot >= c.caps.base) {
-            atomicOr(&c.glob->status, kErrBaseCap);
-            return;
-        }
+        atomicAdd(&T->n_base[base_class(size)], 1u);
+        atomicAdd(&T->base_elems, (unsigned long long)size);
+        return;
+    }
+    uint32_t d, ulen, units, chunks;
+    seg_shape(size, c, d, ulen, units, chunks);
+    const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
+    atomicAdd(&T->n_large, 1u);
+    atomicAdd(&T->units, units);
+    atomicAdd(&T->chunks, chunks);
+    atomicAdd(&T->tree, v + 1);
+    atomicAdd(&T->bstart, k + 1);
+    atomicAdd(&T->cm, (unsigned long long)units * k);
+    atomicAdd(&T->cs, (unsigned long long)chunks * k);
+    atomicAdd(&T->moved, (unsigned long long)size);
+    atomicMax(&T->kmax, k);
+}
+
+// Phase 2, one thread: turn block totals into global bases (stored back into T).
+__device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
+    uint32_t err = 0;
+    if (T->base_elems) atomicAdd(&c.glob->base_elems, T->base_elems);
+    for (int q = 0; q < kBaseClasses; ++q) {
+        if (!T->n_base[q]) continue;
+        uint32_t b0 = atomicAdd(&c.glob->n_base[q], T->n_base[q]);
+        if (b0 + T->n_base[q] > c.caps.base[q]) err |= kErrBaseCap;
+        T->n_base[q] = b0;
+    }
+    if (T->n_large) {
+        uint32_t l0 = atomicAdd(&c.cnt->n_large, T->n_large);
+        uint32_t u0 = atomicAdd(&c.cnt->units, T->units);
+        uint32_t h0 = atomicAdd(&c.cnt->chunks, T->chunks);
+        uint32_t t0 = atomicAdd(&c.cnt->tree, T->tree);
+        uint32_t s0 = atomicAdd(&c.cnt->bstart, T->bstart);
+        unsigned long long m0 = atomicAdd(&c.cnt->cm, T->cm);
+        unsigned long long q0 = atomicAdd(&c.cnt->cs, T->cs);
+        atomicAdd(&c.cnt->moved, T->moved);
+        atomicMax(&c.cnt->kmax, T->kmax);
+        if (l0 + T->n_large > c.caps.large) err |= kErrLargeCap;
+        if (u0 + T->units > c.caps.units || h0 + T->chunks > c.caps.chunks) err |= kErrUnitCap;
+        if (m0 + T->cm > c.caps.cm || q0 + T->cs > c.caps.cs) err |= kErrCmCap;
+        if (t0 + T->tree > c.caps.tree || s0 + T->bstart > c.caps.bstart) err |= kErrTreeCap;
+        T->n_large = l0;
+        T->units = u0;
+        T->chunks = h0;
+        T->tree = t0;
+        T->bstart = s0;
+        T->cm = m0;
+        T->cs = q0;
+    }
+    if (err) atomicOr(&c.glob->status, err);
+    T->err = err;
+}
+
+// Phase 3 for one request: take slots from the LDS counters and write the record.
+__device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_t base,
+                          uint32_t buf, const PlanCtx& c, PlanTally* T) {
+    if (size <= c.T) {
+        const int q = base_class(size);
+        uint32_t slot = atomicAdd(&T->n_base[q], 1u);
         Seg s;
         s.begin = begin;
         s.size = size;
         s.depth = depth | (buf ? kBufBit : 0u);
         s.base = base;
-        c.base_list[slot] = s;
-        atomicAdd(&c.glob->base_elems, (unsigned long long)size);
+        c.base_list[q][slot] = s;
         return;
     }
-    // a large segment: sized tree and units for the next distribution pass
-    uint32_t d = 1;
-    while (d < c.d_max && ((uint64_t)c.T << d) < 2ull * size) ++d;  // 2^d * T/2 >= size
-    uint32_t v = (1u << d) - 1, k = 2 * v + 1;
-    uint32_t ulen = (uint32_t)(((uint64_t)size + kMaxUnits - 1) / kMaxUnits);
-    ulen = (ulen + 63u) & ~63u;
-    if (ulen < c.unit_min) ulen = c.unit_min;
-    uint32_t units = (uint32_t)(((uint64_t)size + ulen - 1) / ulen);
-    units = (units + kWaves - 1) / kWaves * kWaves;
-    uint32_t chunks = (units + kChunkRows - 1) / kChunkRows;
-
-    uint32_t slot = atomicAdd(&c.cnt->n_large, 1u);
-    uint32_t ub = atomicAdd(&c.cnt->units, units);
-    uint32_t cb = atomicAdd(&c.cnt->chunks, chunks);
-    uint32_t tb = atomicAdd(&c.cnt->tree, v + 1);
-    uint32_t bb = atomicAdd(&c.cnt->bstart, k + 1);
-    unsigned long long cmb = atomicAdd(&c.cnt->cm, (unsigned long long)units * k);
-    unsigned long long csb = atomicAdd(&c.cnt->cs, (unsigned long long)chunks * k);
-    atomicAdd(&c.cnt->moved, (unsigned long long)size);
-    atomicMax(&c.cnt->kmax, k);
-    uint32_t err = 0;
-    if (slot >= c.caps.large) err |= kErrLargeCap;
-    if (ub + units > c.caps.units || cb + chunks > c.caps.chunks) err |= kErrUnitCap;
-    if (cmb + (unsigned long long)units * k > c.caps.cm ||
-        csb + (unsigned long long)chunks * k > c.caps.cs)
-        err |= kErrCmCap;
-    if (tb + v + 1 > c.caps.tree || bb + k + 1 > c.caps.bstart) err |= kErrTreeCap;
-    if (err) {
-        atomicOr(&c.glob->status, err);
-        return;
-    }
+    uint32_t d, ulen, units, chunks;
+    seg_shape(size, c, d, ulen, units, chunks);
+    const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
     LSeg g;
     g.begin = begin;
     g.size = size;
@@ -138,15 +185,23 @@ __device__ void plan_segment(uint32_t begin, uint32_t size, uint32_t depth, uint
     g.k = k;
     g.unit_len = ulen;
     g.units = units;
-    g.unit_base = ub;
+    g.unit_base = atomicAdd(&T->units, units);
     g.chunks = chunks;
-    g.chunk_base = cb;
-    g.tree_base = tb;
-    g.bstart_base = bb;
+    g.chunk_base = atomicAdd(&T->chunks, chunks);
+    g.tree_base = atomicAdd(&T->tree, v + 1);
+    g.bstart_base = atomicAdd(&T->bstart, k + 1);
     g.pad0 = g.pad1 = 0;
-    g.cm_base = cmb;
-    g.cs_base = csb;
-    c.lseg[slot] = g;
+    g.cm_base = atomicAdd(&T->cm, (unsigned long long)units * k);
+    g.cs_base = atomicAdd(&T->cs, (unsigned long long)chunks * k);
+    c.lseg[atomicAdd(&T->n_large, 1u)] = g;
+}
+
+__device__ __forceinline__ void tally_clear(PlanTally* T) {
+    if (threadIdx.x == 0) {
+        T->n_base[0] = T->n_base[1] = T->n_base[2] = 0;
+        T->n_large = T->units = T->chunks = T->tree = T->bstart = T->kmax = T->err = 0;
+        T->cm = T->cs = T->moved = T->base_elems = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -171,17 +226,26 @@ __global__ __launch_bounds__(256) void k_prefix_keys(const uint8_t* chars, const
 __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, uint32_t num_sets,
                                                     uint32_t n, uint32_t* out_perm,
                                                     uint32_t* out_lcp, PlanCtx ctx) {
-    uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= num_sets) return;
-    uint32_t b = set_begin ? (uint32_t)set_begin[s] : 0u;
-    uint32_t e = set_begin ? (uint32_t)set_begin[s + 1] : n;
-    if (e <= b) return;
-    out_lcp[b] = 0;
-    if (e - b == 1) {
-        out_perm[b] = 0;
-        return;
+    __shared__ PlanTally T;
+    tally_clear(&T);
+    __syncthreads();
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t b = 0, e = 0;
+    if (s < num_sets) {
+        b = set_begin ? (uint32_t)set_begin[s] : 0u;
+        e = set_begin ? (uint32_t)set_begin[s + 1] : n;
+        if (e > b) {
+            out_lcp[b] = 0;
+            if (e - b == 1) out_perm[b] = 0;
+        }
     }
-    plan_segment(b, e - b, 0, b, 0, ctx);
+    const bool req = e > b + 1;
+    if (req) plan_tally(e - b, ctx, &T);
+    __syncthreads();
+    if (threadIdx.x == 0) plan_allocate(ctx, &T);
+    __syncthreads();
+    if (T.err) return;
+    if (req) plan_emit(b, e - b, 0, b, 0, ctx, &T);
 }
 
 // ---------------------------------------------------------------------------
@@ -191,8 +255,10 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
                                                      uint32_t alpha, uint64_t seed,
                                                      uint64_t* tree_lo, uint64_t* tree_in,
                                                      uint8_t* tree_lcp, uint32_t* unit_tab,
-                                                     uint32_t* chunk_tab) {
+                                                     uint32_t* chunk_tab, Counters* next_cnt) {
     extern __shared__ uint64_t smp[];  // sample, padded to a power of two
+    // the next pass's counters are planned later in this pass: clear them here
+    if (blockIdx.x == 0 && threadIdx.x < sizeof(Counters) / 4) ((uint32_t*)next_cnt)[threadIdx.x] = 0;
     __shared__ uint32_t ra[1u << kDMax], rb[1u << kDMax];
     __shared__ uint64_t t[1u << kDMax];
     const uint32_t slot = blockIdx.x;
@@ -384,6 +450,8 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
     uint32_t* bs = bstart + g.bstart_base;
     double ent = 0.0;
     unsigned long long mx = 0;
+    __shared__ PlanTally T;
+    tally_clear(&T);
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
         const uint32_t s0 = st[b];
         bs[b] = s0;
@@ -392,21 +460,53 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
         if (sz == 0) continue;
         ent += (double)sz * log2((double)g.size / (double)sz);
         if (sz > mx) mx = sz;
-        if (sz < 2) continue;  // single strings are finished by the scatter
-        const uint32_t j = b >> 1;
-        uint32_t nd;
-        if (b & 1u) {
-            uint64_t x = tree_in[g.tree_base + j];
-            if (has_zero(x)) continue;  // all strings identical: finished by the scatter
-            nd = g.depth + 8;
-        } else {
-            nd = g.depth + ((j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j]);
-        }
-        plan_segment(g.begin + s0, sz, nd, g.base, next_buf, ctx);
     }
     if (threadIdx.x == 0) bs[k] = g.size;
-    atomicMax(&ctx.cnt->max_bucket, mx);
-    if (ent != 0.0) atomicAdd(&ctx.cnt->entropy_sum, ent);
+    // block-reduce the statistics, then one atomic each per block
+    __shared__ double s_ent;
+    __shared__ unsigned long long s_mx;
+    if (threadIdx.x == 0) {
+        s_ent = 0.0;
+        s_mx = 0;
+    }
+    __syncthreads();
+    for (uint32_t o = 32; o > 0; o >>= 1) {
+        ent += __shfl_xor(ent, (int)o);
+        const unsigned long long om = __shfl_xor(mx, (int)o);
+        mx = om > mx ? om : mx;
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&s_ent, ent);
+        atomicMax(&s_mx, mx);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_mx) atomicMax(&ctx.cnt->max_bucket, s_mx);
+        if (s_ent != 0.0) atomicAdd(&ctx.cnt->entropy_sum, s_ent);
+    }
+    // new depth of bucket b, or 0xFFFFFFFF if it needs no further sorting
+    // (empty, a single string, or an equality bucket whose splitter ends the
+    // strings: all its strings are identical and the scatter finishes them)
+    auto next_depth = [&](uint32_t b) -> uint32_t {
+        const uint32_t sz = tot[b];
+        if (sz < 2) return 0xFFFFFFFFu;
+        const uint32_t j = b >> 1;
+        if (b & 1u) {
+            if (has_zero(tree_in[g.tree_base + j])) return 0xFFFFFFFFu;
+            return g.depth + 8;
+        }
+        return g.depth + ((j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j]);
+    };
+    for (uint32_t b = threadIdx.x; b < k; b += kWG)
+        if (next_depth(b) != 0xFFFFFFFFu) plan_tally(tot[b], ctx, &T);
+    __syncthreads();
+    if (threadIdx.x == 0) plan_allocate(ctx, &T);
+    __syncthreads();
+    if (T.err) return;
+    for (uint32_t b = threadIdx.x; b < k; b += kWG) {
+        const uint32_t nd = next_depth(b);
+        if (nd != 0xFFFFFFFFu) plan_emit(g.begin + st[b], tot[b], nd, g.base, next_buf, ctx, &T);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -494,117 +594,352 @@ __global__ __launch_bounds__(256) void k_scatter(
 }
 
 // ---------------------------------------------------------------------------
-// K8: base case in LDS.  Sorts a bucket of <= T strings by (key, index);
-// equal keys without a terminator are refreshed 8 bytes deeper and sorted
-// again inside their run (multikey refinement, Section 2.1), until every
-// neighbouring pair is decided.  Emits perm and the LCPs inside the bucket.
+// K8: base case.  A bucket of n <= T strings that share `depth` leading
+// bytes is finished on chip:
+//   1. sort by (key, local index); local index order is input order, because
+//      every distribution pass is stable;
+//   2. neighbours with different keys, or equal keys that hold the
+//      terminator, are decided: their LCP is depth + common key bytes;
+//   3. maximal runs of undecided neighbours ("groups") are re-keyed 8 bytes
+//      deeper and only their members are sorted again, by (group, key, local
+//      index) -- the multikey refinement of Section 2.1 -- until every
+//      neighbouring pair is decided.
+// Buckets of <= 64 strings are finished by one wavefront each, entirely in
+// registers (shuffle bitonic network, ballots for the groups).  Larger buckets
+// use a workgroup and LDS; once <= 64 strings remain undecided, wavefront 0
+// finishes them the same way without further workgroup barriers.
 
-__device__ __forceinline__ bool less3(uint16_t ga, uint64_t ka, uint32_t ia, uint16_t gb,
-                                      uint64_t kb, uint32_t ib) {
-    if (ga != gb) return ga < gb;
-    if (ka != kb) return ka < kb;
-    return ia < ib;
+// (group, key, local index) order of two packed elements; a = group << 16 | local
+__device__ __forceinline__ bool elem_less(uint64_t k1, uint32_t a1, uint64_t k2, uint32_t a2) {
+    uint32_t g1 = a1 >> 16, g2 = a2 >> 16;
+    if (g1 != g2) return g1 < g2;
+    if (k1 != k2) return k1 < k2;
+    return (a1 & 0xFFFFu) < (a2 & 0xFFFFu);
 }
 
-__global__ __launch_bounds__(256) void k_base_sort(const Seg* items, const uint64_t* key0,
-                                                   const uint64_t* key1, const uint32_t* idx0,
-                                                   const uint32_t* idx1, const uint8_t* chars,
-                                                   const uint64_t* offsets, uint32_t* out_perm,
-                                                   uint32_t* out_lcp, uint32_t pmax) {
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
+    uint32_t lo = __shfl_up((uint32_t)v, d), hi = __shfl_up((uint32_t)(v >> 32), d);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of one element per lane over the wavefront.
+__device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& a) {
+    const uint32_t lane = lane_id();
+    for (uint32_t kk = 2; kk <= 64; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            const uint64_t pk = shfl_xor64(k, (int)j);
+            const uint32_t pa = __shfl_xor(a, (int)j);
+            const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
+            const bool pl = elem_less(pk, pa, k, a);
+            if (keep_min ? pl : !pl) {
+                k = pk;
+                a = pa;
+            }
+        }
+    }
+}
+
+// Rounds of decide / re-key / sort inside one wavefront.  Lane r owns output
+// position pos; lanes are sorted by (group, key, local index) and padding
+// lanes (valid == false) are last.  Returns the final packed element of the lane.
+__device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, uint32_t pos,
+                                const uint32_t* iin, const uint8_t* chars,
+                                const uint64_t* offsets, uint32_t* olcp) {
+    const uint32_t lane = lane_id();
+    const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    for (;;) {
+        const uint64_t kp = shfl_up64(k, 1);
+        const uint32_t ap = __shfl_up(a, 1);
+        bool und = false;
+        if (valid && lane > 0 && (ap >> 16) == (a >> 16)) {
+            if (kp == k && !has_zero(k))
+                und = true;
+            else
+                olcp[pos] = h + lcp8(kp, k);
+        }
+        const uint64_t U = __ballot(und);
+        if (!U) break;
+        const bool member = ((U >> lane) & 1ull) || (lane < 63 && ((U >> (lane + 1)) & 1ull));
+        const uint32_t st = 63u - (uint32_t)__builtin_clzll((unsigned long long)(~U & upto));
+        h += 8;
+        if (member) {
+            k = load_key(chars, offsets[iin[a & 0xFFFFu]] + h);
+            a = (st << 16) | (a & 0xFFFFu);
+        } else if (valid) {
+            a = (lane << 16) | (a & 0xFFFFu);
+        }
+        wave_sort(k, a);
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_items,
+                                                   const uint64_t* key0, const uint64_t* key1,
+                                                   const uint32_t* idx0, const uint32_t* idx1,
+                                                   const uint8_t* chars, const uint64_t* offsets,
+                                                   uint32_t* out_perm, uint32_t* out_lcp) {
+    const uint32_t lane = lane_id();
+    const uint32_t item = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (item >= n_items) return;  // uniform per wavefront
+    const Seg it = items[item];
+    const uint32_t buf = it.depth >> 31;
+    const uint32_t h = it.depth & ~kBufBit;
+    const uint32_t n = it.size;
+    const uint64_t* kin = (buf ? key1 : key0) + it.begin;
+    const uint32_t* iin = (buf ? idx1 : idx0) + it.begin;
+    const bool valid = lane < n;
+    uint64_t k = valid ? kin[lane] : ~0ull;
+    uint32_t a = valid ? lane : 0xFFFFFFFFu;
+    wave_sort(k, a);
+    const uint32_t fa = wave_rounds(k, a, valid, h, lane, iin, chars, offsets, out_lcp + it.begin);
+    if (valid) out_perm[it.begin + lane] = iin[fa & 0xFFFFu] - it.base;
+}
+
+template <int E, int J>
+__device__ __forceinline__ void cex_local(uint64_t (&k)[E], uint32_t (&a)[E], uint32_t t,
+                                          uint32_t kk) {
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        if ((s & J) == 0) {
+            const int s2 = s | J;
+            const bool up = (((uint32_t)(t * E + s)) & kk) == 0;
+            if (elem_less(k[s2], a[s2], k[s], a[s]) == up) {
+                uint64_t tk = k[s]; k[s] = k[s2]; k[s2] = tk;
+                uint32_t ta = a[s]; a[s] = a[s2]; a[s2] = ta;
+            }
+        }
+    }
+}
+
+// Sort SK/SA[0..P) ascending, P a power of two, P / E <= kWG.  All threads call.
+// Each thread holds E consecutive elements in registers; only stages whose
+// partner lives in another thread exchange through LDS.
+template <int E>
+__device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
+    const uint32_t t = threadIdx.x;
+    const bool act = t * E < P;
+    uint64_t k[E];
+    uint32_t a[E];
+#pragma unroll
+    for (int s = 0; s < E; ++s) {
+        k[s] = act ? SK[t * E + s] : 0ull;
+        a[s] = act ? SA[t * E + s] : 0u;
+    }
+    for (uint32_t kk = 2; kk <= P; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            if (j >= (uint32_t)E) {
+                // exchange through LDS; slot s of thread t lives at t*E + ((s + t) mod E)
+                // so that the lanes of one access hit distinct banks
+                __syncthreads();
+                if (act) {
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        SK[t * E + ((s + t) & (E - 1))] = k[s];
+                        SA[t * E + ((s + t) & (E - 1))] = a[s];
+                    }
+                }
+                __syncthreads();
+                if (act) {
+                    const uint32_t tp = t ^ (j / E);
+#pragma unroll
+                    for (int s = 0; s < E; ++s) {
+                        const uint64_t pk = SK[tp * E + ((s + tp) & (E - 1))];
+                        const uint32_t pa = SA[tp * E + ((s + tp) & (E - 1))];
+                        const uint32_t e = t * E + s;
+                        const bool keep_min = ((e & j) == 0) == ((e & kk) == 0);
+                        const bool pl = elem_less(pk, pa, k[s], a[s]);
+                        if (keep_min ? pl : !pl) {
+                            k[s] = pk;
+                            a[s] = pa;
+                        }
+                    }
+                }
+            } else if (act) {
+                if constexpr (E >= 2) { if (j == 1) cex_local<E, 1>(k, a, t, kk); }
+                if constexpr (E >= 4) { if (j == 2) cex_local<E, 2>(k, a, t, kk); }
+                if constexpr (E >= 8) { if (j == 4) cex_local<E, 4>(k, a, t, kk); }
+                if constexpr (E >= 16) { if (j == 8) cex_local<E, 8>(k, a, t, kk); }
+            }
+        }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            SK[t * E + s] = k[s];
+            SA[t * E + s] = a[s];
+        }
+    }
+    __syncthreads();
+}
+
+// P <= EMAX * kWG; only the instantiations up to EMAX are compiled into a kernel,
+// so small-bucket kernels keep a small register footprint.
+template <int EMAX>
+__device__ void sort_pow2(uint64_t* SK, uint32_t* SA, uint32_t P) {
+    if (P <= (uint32_t)kWG) block_bitonic<1>(SK, SA, P);
+    else if constexpr (EMAX >= 2) {
+        if (P <= 2u * kWG) block_bitonic<2>(SK, SA, P);
+        else if constexpr (EMAX >= 4) {
+            if (P <= 4u * kWG) block_bitonic<4>(SK, SA, P);
+            else if constexpr (EMAX >= 8) block_bitonic<8>(SK, SA, P);
+        }
+    }
+}
+
+// Exclusive block scans of two per-thread values at once: running maximum of
+// `mx` and running sum of `ad` (in thread order).  `wl` holds 2 * kWaves
+// words.  Returns the block-wide sum of `ad`.
+__device__ uint32_t block_scan_max_add(uint32_t& mx, uint32_t& ad, uint32_t* wl) {
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t im = mx, ia = ad;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t xm = __shfl_up(im, o), xa = __shfl_up(ia, o);
+        if (lane >= o) {
+            im = xm > im ? xm : im;
+            ia += xa;
+        }
+    }
+    if (lane == 63) {
+        wl[w] = im;
+        wl[kWaves + w] = ia;
+    }
+    __syncthreads();
+    uint32_t pm = 0, pa = 0, total = 0;
+    for (uint32_t q = 0; q < (uint32_t)kWaves; ++q) {
+        if (q < w) {
+            pm = wl[q] > pm ? wl[q] : pm;
+            pa += wl[kWaves + q];
+        }
+        total += wl[kWaves + q];
+    }
+    uint32_t em = __shfl_up(im, 1), ea = __shfl_up(ia, 1);
+    if (lane == 0) em = ea = 0;
+    mx = em > pm ? em : pm;
+    ad = pa + ea;
+    __syncthreads();
+    return total;
+}
+
+template <int EMAX>
+__global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint64_t* key0,
+                                                    const uint64_t* key1, const uint32_t* idx0,
+                                                    const uint32_t* idx1, const uint8_t* chars,
+                                                    const uint64_t* offsets, uint32_t* out_perm,
+                                                    uint32_t* out_lcp, uint32_t pmax) {
     extern __shared__ uint64_t dyn[];
-    uint64_t* K = dyn;                         // pmax
-    uint32_t* I = (uint32_t*)(K + pmax);       // pmax
-    uint32_t* L = I + pmax;                    // pmax
-    uint16_t* G = (uint16_t*)(L + pmax);       // pmax
-    uint8_t* Ur = (uint8_t*)(G + pmax);        // pmax
-    __shared__ uint32_t tmp[kWG + 1];
+    uint64_t* K = dyn;                          // pmax keys, by position
+    uint64_t* SK = K + pmax;                    // pmax keys, compacted members
+    uint32_t* A = (uint32_t*)(SK + pmax);       // pmax packed group | local, by position
+    uint32_t* SA = A + pmax;                    // pmax compacted members
+    uint16_t* ST = (uint16_t*)(SA + pmax);      // pmax group start of each position
+    uint16_t* POS = ST + pmax;                  // pmax position of each compacted member
+    uint8_t* F = (uint8_t*)(POS + pmax);        // pmax: pair (i-1, i) undecided
+    __shared__ uint32_t wl[2 * kWaves];
     const Seg it = items[blockIdx.x];
     const uint32_t buf = it.depth >> 31;
     uint32_t h = it.depth & ~kBufBit;
     const uint32_t n = it.size;
     uint32_t P = 1;
     while (P < n) P <<= 1;
-    const uint64_t* kin = buf ? key1 : key0;
-    const uint32_t* iin = buf ? idx1 : idx0;
+    const uint64_t* kin = (buf ? key1 : key0) + it.begin;
+    const uint32_t* iin = (buf ? idx1 : idx0) + it.begin;
+    uint32_t* olcp = out_lcp + it.begin;
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < P; i += kWG) {
-        if (i < n) {
-            K[i] = kin[it.begin + i];
-            I[i] = iin[it.begin + i];
-            G[i] = 0;
-        } else {
-            K[i] = ~0ull;
-            I[i] = ~0u;
-            G[i] = 0xFFFF;
-        }
-        L[i] = 0;
-        Ur[i] = 0;
+        K[i] = i < n ? kin[i] : ~0ull;
+        A[i] = i < n ? i : 0xFFFFFFFFu;
     }
     __syncthreads();
-    for (;;) {
-        for (uint32_t kk = 2; kk <= P; kk <<= 1) {
-            for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-                for (uint32_t i = tid; i < P / 2; i += kWG) {
-                    uint32_t lo = 2 * i - (i & (j - 1)), hi = lo + j;
-                    bool up = (lo & kk) == 0;
-                    uint16_t ga = G[lo], gb = G[hi];
-                    uint64_t ka = K[lo], kb = K[hi];
-                    uint32_t ia = I[lo], ib = I[hi];
-                    if (less3(gb, kb, ib, ga, ka, ia) == up) {
-                        G[lo] = gb; G[hi] = ga;
-                        K[lo] = kb; K[hi] = ka;
-                        I[lo] = ib; I[hi] = ia;
-                    }
-                }
-                __syncthreads();
+    sort_pow2<EMAX>(K, A, P);
+    // each thread owns positions [c0, c1)
+    const uint32_t per = (n + kWG - 1) / kWG;
+    const uint32_t c0 = tid * per < n ? tid * per : n;
+    const uint32_t c1 = c0 + per < n ? c0 + per : n;
+    int any = 0;
+    for (uint32_t i = c0; i < c1; ++i) {
+        uint8_t un = 0;
+        if (i > 0) {
+            const uint64_t x = K[i - 1], y = K[i];
+            if (x == y && !has_zero(y))
+                un = 1;
+            else
+                olcp[i] = h + lcp8(x, y);
+        }
+        F[i] = un;
+        any |= un;
+    }
+    any = __syncthreads_or(any);
+    while (any) {
+        // group start of every position (running max of decided positions) and
+        // the rank of every group member among all members
+        uint32_t mx = 0, cnt = 0;
+        for (uint32_t i = c0; i < c1; ++i) {
+            if (!F[i]) mx = i;
+            cnt += (F[i] || (i + 1 < n && F[i + 1])) ? 1u : 0u;
+        }
+        const uint32_t m = block_scan_max_add(mx, cnt, wl);
+        uint32_t run = mx, r = cnt;
+        for (uint32_t i = c0; i < c1; ++i) {
+            if (!F[i]) run = i;
+            if (F[i] || (i + 1 < n && F[i + 1])) {
+                POS[r] = (uint16_t)i;
+                SK[r] = K[i];
+                SA[r] = (run << 16) | (A[i] & 0xFFFFu);
+                ++r;
             }
         }
-        int any = 0;
-        for (uint32_t i = tid; i < n; i += kWG) {
-            uint8_t un = 0;
-            if (i > 0 && G[i] == G[i - 1]) {
-                if (K[i] == K[i - 1] && !has_zero(K[i]))
-                    un = 1;
-                else
-                    L[i] = h + lcp8(K[i - 1], K[i]);
+        __syncthreads();
+        if (m <= 64) {
+            // few undecided strings left: wavefront 0 finishes them in registers
+            if (tid < 64) {
+                const bool valid = tid < m;
+                const uint32_t pos = valid ? POS[tid] : 0u;
+                const uint32_t fa = wave_rounds(valid ? SK[tid] : ~0ull, valid ? SA[tid] : 0xFFFFFFFFu,
+                                                valid, h, pos, iin, chars, offsets, olcp);
+                if (valid) A[pos] = fa;
             }
-            Ur[i] = un;
-            any |= un;
+            __syncthreads();
+            break;
+        }
+        // re-key the members 8 bytes deeper and sort them by (group, key, local index)
+        h += 8;
+        uint32_t Pm = 1;
+        while (Pm < m) Pm <<= 1;
+        for (uint32_t q = tid; q < Pm; q += kWG) {
+            if (q < m) {
+                SK[q] = load_key(chars, offsets[iin[SA[q] & 0xFFFFu]] + h);
+            } else {
+                SK[q] = ~0ull;
+                SA[q] = 0xFFFFFFFFu;
+            }
+        }
+        __syncthreads();
+        sort_pow2<EMAX>(SK, SA, Pm);
+        for (uint32_t q = tid; q < m; q += kWG) {
+            const uint32_t i = POS[q];
+            K[i] = SK[q];
+            A[i] = SA[q];
+        }
+        __syncthreads();
+        any = 0;
+        for (uint32_t i = c0; i < c1; ++i) {
+            if (!F[i]) continue;
+            const uint64_t x = K[i - 1], y = K[i];
+            if (x == y && !has_zero(y)) {
+                any = 1;
+            } else {
+                F[i] = 0;
+                olcp[i] = h + lcp8(x, y);
+            }
         }
         any = __syncthreads_or(any);
-        if (!any) break;
-        // run starts: st(i) = max_{j <= i, pair (j-1, j) decided} j
-        const uint32_t per = (n + kWG - 1) / kWG;
-        const uint32_t b0 = tid * per;
-        uint32_t mxv = 0;
-        for (uint32_t i = b0; i < b0 + per && i < n; ++i)
-            if (!Ur[i]) mxv = i;
-        tmp[tid] = mxv;
-        __syncthreads();
-        for (uint32_t off = 1; off < (uint32_t)kWG; off <<= 1) {
-            uint32_t x = tid >= off ? tmp[tid - off] : 0u;
-            __syncthreads();
-            if (x > tmp[tid]) tmp[tid] = x;
-            __syncthreads();
-        }
-        uint32_t runst = tid ? tmp[tid - 1] : 0u;
-        for (uint32_t i = b0; i < b0 + per && i < n; ++i) {
-            if (!Ur[i]) runst = i;
-            bool active = Ur[i] || (i + 1 < n && Ur[i + 1]);
-            if (active) {
-                G[i] = (uint16_t)runst;
-                K[i] = load_key(chars, offsets[I[i]] + h + 8);
-            } else {
-                G[i] = (uint16_t)i;
-            }
-        }
-        h += 8;
-        __syncthreads();
     }
-    for (uint32_t i = tid; i < n; i += kWG) {
-        out_perm[it.begin + i] = I[i] - it.base;
-        if (i) out_lcp[it.begin + i] = L[i];
-    }
+    for (uint32_t i = tid; i < n; i += kWG) out_perm[it.begin + i] = iin[A[i] & 0xFFFFu] - it.base;
 }
 
 // ---------------------------------------------------------------------------
@@ -724,11 +1059,11 @@ void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
 void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_in,
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
                         uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* unit_tab,
-                        uint32_t* chunk_tab, hipStream_t st) {
+                        uint32_t* chunk_tab, Counters* next_cnt, hipStream_t st) {
     uint32_t m = alpha * (vmax + 1) - 1, P = 1;
     while (P < m) P <<= 1;
     S5_LAUNCH(k_sample_tree, dim3(n_large), dim3(kWG), (size_t)P * 8, st, lseg, key_in, alpha,
-              seed, tree_lo, tree_in, tree_lcp, unit_tab, chunk_tab);
+              seed, tree_lo, tree_in, tree_lcp, unit_tab, chunk_tab, next_cnt);
 }
 
 void launch_classify(uint32_t units, uint32_t unroll, const LSeg* lseg, const uint32_t* unit_tab,
@@ -766,9 +1101,9 @@ void launch_scatter(uint32_t units, uint32_t unroll, const LSeg* lseg, const uin
     size_t lds = (size_t)(vmax + 1) * 8 + (size_t)(kmax + 1) * 4 + (size_t)kWaves * kmax * 4 +
                  (size_t)(vmax + 1);
     dim3 grid(units / kWaves);
-#define S5_SC(Uv)                                                                            \
-    S5_LAUNCH(k_scatter<Uv>, grid, dim3(kWG), lds, st, lseg, unit_tab, bid, key_in, idx_in,   \
-              key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,  \
+#define S5_SC(Uv)                                                                             \
+    S5_LAUNCH(k_scatter<Uv>, grid, dim3(kWG), lds, st, lseg, unit_tab, bid, key_in, idx_in,    \
+              key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,   \
               out_lcp, vmax, kmax)
     switch (unroll) {
         case 1: S5_SC(1); break;
@@ -779,16 +1114,24 @@ void launch_scatter(uint32_t units, uint32_t unroll, const LSeg* lseg, const uin
 #undef S5_SC
 }
 
-void launch_base_sort(uint32_t n_items, const Seg* items, const uint64_t* key0,
+void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
                       const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                       uint32_t* out_lcp, uint32_t T, hipStream_t st) {
-    if (!n_items) return;
-    uint32_t P = 1;
-    while (P < T) P <<= 1;
-    size_t lds = (size_t)P * (8 + 4 + 4 + 2 + 1);
-    S5_LAUNCH(k_base_sort, dim3(n_items), dim3(kWG), lds, st, items, key0, key1, idx0, idx1,
-              chars, offsets, out_perm, out_lcp, P);
+    if (n_items[0])
+        S5_LAUNCH(k_base_wave, dim3((n_items[0] + kWaves - 1) / kWaves), dim3(kWG), 0, st,
+                  items[0], n_items[0], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp);
+    uint32_t PT = 1;
+    while (PT < T) PT <<= 1;
+    const size_t per = 8 + 8 + 4 + 4 + 2 + 2 + 1;
+    if (n_items[1]) {
+        const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
+        S5_LAUNCH(k_base_block<kBaseMid / kWG>, dim3(n_items[1]), dim3(kWG), per * P, st, items[1],
+                  key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P);
+    }
+    if (n_items[2])
+        S5_LAUNCH(k_base_block<8>, dim3(n_items[2]), dim3(kWG), per * PT, st, items[2], key0, key1,
+                  idx0, idx1, chars, offsets, out_perm, out_lcp, PT);
 }
 
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,

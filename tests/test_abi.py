@@ -52,6 +52,6 @@ def test_workspace_bytes(lib):
     assert 26 * 1_000_000 < big < 64 * 1_000_000
     # invalid configurations are rejected (0 bytes)
     assert s5.workspace_bytes(1000, s5.make_config(splitters=100)) == 0
-    assert s5.workspace_bytes(1000, s5.make_config(base_threshold=8192)) == 0
+    assert s5.workspace_bytes(1000, s5.make_config(base_threshold=4096)) == 0
     assert s5.workspace_bytes(1000, s5.make_config(unroll=3)) == 0
     assert s5.workspace_bytes(1000, s5.make_config(splitters=1023, unroll=8)) > 0

@@ -18,7 +18,7 @@ from paper_1305_1157_amd import gen, s5  # noqa: E402
 CFGS = {
     "default": None,
     "tiny_T_v7": s5.make_config(splitters=7, base_threshold=64, tile=64),
-    "v1023_u8": s5.make_config(splitters=1023, unroll=8, base_threshold=4096),
+    "v1023_u8": s5.make_config(splitters=1023, unroll=8, base_threshold=2048),
     "v31_u1_T128": s5.make_config(splitters=31, unroll=1, base_threshold=128, tile=128),
     "v63_u2_a4": s5.make_config(splitters=63, unroll=2, oversample=4, base_threshold=256),
 }
@@ -79,8 +79,27 @@ EDGE = {
 }
 
 
+def _dup_groups(seed, n_distinct, max_rep, length):
+    """Long strings over a 2-letter alphabet, each repeated 1..max_rep times, shuffled:
+    groups that stay undecided for many 8-byte rounds."""
+    rng = random.Random(seed)
+    base = [bytes(rng.choice(b"AC") for _ in range(length)) for _ in range(n_distinct)]
+    out = [s for s in base for _ in range(rng.randint(1, max_rep))]
+    rng.shuffle(out)
+    return out
+
+
+EDGE.update({
+    "dup_groups_long": _dup_groups(1, 400, 20, 120),
+    "dup_pairs_dna_like": _dup_groups(2, 3000, 2, 100),
+    "bucket_sizes_64_65_512_513": [bytes([65 + g]) + bytes([97 + (i * 7919) % 26]) * 12
+                                   for g, size in enumerate((64, 65, 512, 513, 2, 3, 4096))
+                                   for i in range(size)],
+})
+
+
 @pytest.mark.parametrize("name", sorted(EDGE))
-@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7"])
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "v1023_u8"])
 def test_edge_cases(name, cfg):
     strings_parity(EDGE[name], CFGS[cfg], label=f"{name}/{cfg}")
 
