@@ -64,8 +64,9 @@ typedef struct s5_config {
     uint32_t oversample;     /* oversampling factor alpha (Section 2.3; default 2) */
     uint32_t unroll;         /* interleaved tree descents per lane: 1, 2, 4 or 8
                                 (Section 3.1; default 4) */
-    uint32_t tile;           /* minimum strings per classification unit, a
-                                multiple of 64 (default 1024) */
+    uint32_t tile;           /* minimum strings per tile (the range one workgroup
+                                classifies and redistributes), a multiple of 64
+                                (default 2048) */
     uint32_t base_threshold; /* buckets of at most this many strings are finished
                                 by the LDS base-case sorter (Section 3.1
                                 "Parallelization", the size-classed sub-algorithms;

@@ -55,7 +55,7 @@ using namespace s5;
 namespace {
 
 struct Cfg {
-    uint32_t dmax, alpha, unroll, unit_min, T, mode;
+    uint32_t dmax, alpha, unroll, tile_min, T, mode;
     float beta;
     uint64_t seed;
 };
@@ -73,8 +73,8 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     if (o->alpha < 1 || o->alpha > 4) return S5_ERR_INVALID;
     o->unroll = c->unroll ? c->unroll : 4u;
     if (o->unroll != 1 && o->unroll != 2 && o->unroll != 4 && o->unroll != 8) return S5_ERR_INVALID;
-    o->unit_min = c->tile ? c->tile : 1024u;
-    if (o->unit_min % 64 || o->unit_min > (1u << 20)) return S5_ERR_INVALID;
+    o->tile_min = c->tile ? c->tile : 2048u;
+    if (o->tile_min % 64 || o->tile_min > (1u << 20)) return S5_ERR_INVALID;
     o->T = c->base_threshold ? c->base_threshold : 1024u;
     if (o->T < 64 || o->T > 2048) return S5_ERR_INVALID;
     o->mode = c->splitter_mode;
@@ -88,7 +88,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
-    size_t key[2], idx[2], bid, lseg[2], unit_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
+    size_t key[2], idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
         bstart, base_list, counters[2], glob, total;
     Caps caps;
 };
@@ -98,12 +98,13 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     const uint64_t kmax = (2ull << c.dmax) - 1;
     Caps cp;
     uint64_t large = n / (c.T + 1) + 2;
-    uint64_t units = n / c.unit_min + kWaves * large + kWaves;
-    uint64_t chunks = units / kChunkRows + large + 1;
+    // tiles of a segment: ceil(|S| / tile_len) with tile_len >= tile_min
+    uint64_t tiles = n / c.tile_min + large + 1;
+    uint64_t chunks = tiles / kChunkRows + large + 1;
     // sum over segments of 2^d < 4 |S| / T (plus the d >= 1 floor)
     uint64_t tree = 4 * n / c.T + 2 * large + 2;
     cp.large = (uint32_t)large;
-    cp.units = (uint32_t)std::min<uint64_t>(units, 0xFFFFFFFFull);
+    cp.tiles = (uint32_t)std::min<uint64_t>(tiles, 0xFFFFFFFFull);
     cp.chunks = (uint32_t)chunks;
     cp.tree = (uint32_t)tree;
     cp.bstart = (uint32_t)(2 * tree + large + 2);
@@ -111,10 +112,10 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     cp.base[0] = (uint32_t)(n / 2 + 2);
     cp.base[1] = (uint32_t)(n / (kBaseWave + 1) + 2);
     cp.base[2] = (uint32_t)(n / (kBaseMid + 1) + 2);
-    // sum over segments of units x k: units_s <= |S|/unit_min + 4 and
+    // sum over segments of tiles x k: tiles_s <= |S|/tile_min + 1 and
     // k_s <= max(3, min(kmax, 8 |S| / T))
     const uint64_t ksum = 3 * large + 8 * n / c.T + kmax;
-    cp.cm = (unsigned long long)(kmax * (n / c.unit_min + 1) + 4 * ksum);
+    cp.cm = (unsigned long long)(kmax * (n / c.tile_min + 1) + 4 * ksum);
     cp.cs = (unsigned long long)(cp.cm / kChunkRows + ksum);
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -126,7 +127,7 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     for (int b = 0; b < 2; ++b) L.idx[b] = take(n * 4);
     L.bid = take(n * 2);
     for (int b = 0; b < 2; ++b) L.lseg[b] = take((size_t)cp.large * sizeof(LSeg));
-    L.unit_tab = take((size_t)cp.units * 4);
+    L.tile_tab = take((size_t)cp.tiles * 4);
     L.chunk_tab = take((size_t)cp.chunks * 4);
     L.tree_lo = take((size_t)cp.tree * 8);
     L.tree_in = take((size_t)cp.tree * 8);
@@ -277,7 +278,7 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
     uint32_t* idx[2] = {(uint32_t*)(W + L.idx[0]), (uint32_t*)(W + L.idx[1])};
     uint16_t* bid = (uint16_t*)(W + L.bid);
     LSeg* lseg[2] = {(LSeg*)(W + L.lseg[0]), (LSeg*)(W + L.lseg[1])};
-    uint32_t* unit_tab = (uint32_t*)(W + L.unit_tab);
+    uint32_t* tile_tab = (uint32_t*)(W + L.tile_tab);
     uint32_t* chunk_tab = (uint32_t*)(W + L.chunk_tab);
     uint64_t* tree_lo = (uint64_t*)(W + L.tree_lo);
     uint64_t* tree_in = (uint64_t*)(W + L.tree_in);
@@ -303,7 +304,7 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         x.caps = L.caps;
         x.T = c.T;
         x.d_max = c.dmax;
-        x.unit_min = c.unit_min;
+        x.tile_min = c.tile_min;
         return x;
     };
     auto readback = [&](int which) -> int {
@@ -338,10 +339,10 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         const int nxt = cur ^ 1;
         timed(K_SAMPLE, now.n_large, st, [&] {
             launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
-                               tree_in, tree_lcp, unit_tab, chunk_tab, cnt[nxt], st);
+                               tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
         });
         timed(K_CLASSIFY, now.moved, st, [&] {
-            launch_classify(now.units, c.unroll, lseg[cur], unit_tab, key[buf], tree_lo, tree_in,
+            launch_classify(now.tiles, c.unroll, lseg[cur], tile_tab, key[buf], tree_lo, tree_in,
                             bid, cm, vmax, kmax, st);
         });
         timed(K_COLSCAN, now.moved, st,
@@ -351,7 +352,7 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
                                (uint32_t)(buf ^ 1), st);
         });
         timed(K_SCATTER, now.moved, st, [&] {
-            launch_scatter(now.units, c.unroll, lseg[cur], unit_tab, bid, key[buf], idx[buf],
+            launch_scatter(now.tiles, c.unroll, lseg[cur], tile_tab, bid, key[buf], idx[buf],
                            key[buf ^ 1], idx[buf ^ 1], cm, cs, bstart, tree_in, tree_lcp, a.chars,
                            a.offsets, a.perm, a.lcp, vmax, kmax, st);
         });

@@ -8,19 +8,20 @@
 
 namespace s5 {
 
-// A distribution pass works on "units": contiguous runs of a segment that one
-// wavefront classifies and scatters.  Four units form one workgroup ("tile")
-// and always belong to the same segment.
-constexpr int kWG = 256;                 // threads per tile workgroup
-constexpr int kWaves = kWG / 64;         // units per tile
-constexpr uint32_t kMaxUnits = 4096;     // units per segment, at most
+// A distribution pass works on "tiles": contiguous runs of a segment that one
+// workgroup classifies and redistributes; each tile owns one row of bucket
+// counts.  The redistribution stages sub-tiles of kSubTile strings in LDS.
+constexpr int kWG = 256;                 // threads per workgroup
+constexpr int kWaves = kWG / 64;         // wavefronts per workgroup
+constexpr uint32_t kMaxTiles = 1024;     // tiles per segment, at most
+constexpr uint32_t kSubTile = 2048;      // strings staged at once by the redistribution
 constexpr uint32_t kChunkRows = 64;      // count-matrix rows per column-scan chunk
 constexpr int kDMax = 10;                // tree depth limit: v <= 1023 splitters
 constexpr uint32_t kLcpFlag = 0x80000000u;  // out_lcp entry still to be completed
 constexpr uint32_t kBufBit = 0x80000000u;   // work-buffer bit packed into a depth
 
 // status-word bits (device side capacity checks)
-constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrUnitCap = 4u, kErrCmCap = 8u,
+constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrTileCap = 4u, kErrCmCap = 8u,
                    kErrTreeCap = 16u;
 
 // A bucket that still has to be sorted.
@@ -34,18 +35,18 @@ struct Seg {
 // A segment distributed in the current pass, with its per-pass storage.
 struct LSeg {
     uint32_t begin, size, depth, base;
-    uint32_t d, v, k, unit_len;     // tree depth, splitters (2^d-1), buckets (2v+1), strings per unit
-    uint32_t units, unit_base;      // units (a multiple of kWaves) and first unit id
+    uint32_t d, v, k, tile_len;     // tree depth, splitters (2^d-1), buckets (2v+1), strings per tile
+    uint32_t tiles, tile_base;      // tiles and first tile id
     uint32_t chunks, chunk_base;    // column-scan chunks and first chunk id
     uint32_t tree_base, bstart_base;
     uint32_t pad0, pad1;
-    unsigned long long cm_base;     // units x k count matrix (row-major)
+    unsigned long long cm_base;     // tiles x k count matrix (row-major)
     unsigned long long cs_base;     // chunks x k chunk sums / prefixes
 };
 
 // Counters written by one planning step and read back by the host.
 struct Counters {
-    uint32_t n_large, units, chunks, tree;
+    uint32_t n_large, tiles, chunks, tree;
     uint32_t bstart, kmax, pad0, pad1;
     unsigned long long cm, cs;
     unsigned long long moved;       // strings in the planned large segments
@@ -71,7 +72,7 @@ struct Globals {
 
 // Capacities of the per-pass storage.
 struct Caps {
-    uint32_t large, units, chunks, tree, bstart, base[kBaseClasses];
+    uint32_t large, tiles, chunks, tree, bstart, base[kBaseClasses];
     unsigned long long cm, cs;
 };
 
@@ -84,7 +85,7 @@ struct PlanCtx {
     Caps caps;
     uint32_t T;           // base threshold
     uint32_t d_max;       // tree depth limit for this sort
-    uint32_t unit_min;    // minimum strings per unit
+    uint32_t tile_min;    // minimum strings per tile
 };
 
 }  // namespace s5

@@ -84,21 +84,20 @@ __device__ uint32_t block_exclusive_scan(const uint32_t* cnt, uint32_t* out, uin
 // global counters beyond one atomic per counter and block).
 
 struct PlanTally {
-    uint32_t n_base[kBaseClasses], n_large, units, chunks, tree, bstart, kmax, err;
+    uint32_t n_base[kBaseClasses], n_large, tiles, chunks, tree, bstart, kmax, err;
     unsigned long long cm, cs, moved, base_elems;
 };
 
-// tree depth and units of a large segment of `size` strings
+// tree depth and tiles of a large segment of `size` strings
 __device__ __forceinline__ void seg_shape(uint32_t size, const PlanCtx& c, uint32_t& d,
-                                          uint32_t& ulen, uint32_t& units, uint32_t& chunks) {
+                                          uint32_t& ulen, uint32_t& tiles, uint32_t& chunks) {
     d = 1;
     while (d < c.d_max && ((uint64_t)c.T << d) < 2ull * size) ++d;  // 2^d * T/2 >= size
-    ulen = (uint32_t)(((uint64_t)size + kMaxUnits - 1) / kMaxUnits);
+    ulen = (uint32_t)(((uint64_t)size + kMaxTiles - 1) / kMaxTiles);
     ulen = (ulen + 63u) & ~63u;
-    if (ulen < c.unit_min) ulen = c.unit_min;
-    units = (uint32_t)(((uint64_t)size + ulen - 1) / ulen);
-    units = (units + kWaves - 1) / kWaves * kWaves;
-    chunks = (units + kChunkRows - 1) / kChunkRows;
+    if (ulen < c.tile_min) ulen = c.tile_min;
+    tiles = (uint32_t)(((uint64_t)size + ulen - 1) / ulen);
+    chunks = (tiles + kChunkRows - 1) / kChunkRows;
 }
 
 // Phase 1 for one request (begin, size >= 2, depth).
@@ -108,15 +107,15 @@ __device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, Plan
         atomicAdd(&T->base_elems, (unsigned long long)size);
         return;
     }
-    uint32_t d, ulen, units, chunks;
-    seg_shape(size, c, d, ulen, units, chunks);
+    uint32_t d, ulen, tiles, chunks;
+    seg_shape(size, c, d, ulen, tiles, chunks);
     const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
     atomicAdd(&T->n_large, 1u);
-    atomicAdd(&T->units, units);
+    atomicAdd(&T->tiles, tiles);
     atomicAdd(&T->chunks, chunks);
     atomicAdd(&T->tree, v + 1);
     atomicAdd(&T->bstart, k + 1);
-    atomicAdd(&T->cm, (unsigned long long)units * k);
+    atomicAdd(&T->cm, (unsigned long long)tiles * k);
     atomicAdd(&T->cs, (unsigned long long)chunks * k);
     atomicAdd(&T->moved, (unsigned long long)size);
     atomicMax(&T->kmax, k);
@@ -134,7 +133,7 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
     }
     if (T->n_large) {
         uint32_t l0 = atomicAdd(&c.cnt->n_large, T->n_large);
-        uint32_t u0 = atomicAdd(&c.cnt->units, T->units);
+        uint32_t u0 = atomicAdd(&c.cnt->tiles, T->tiles);
         uint32_t h0 = atomicAdd(&c.cnt->chunks, T->chunks);
         uint32_t t0 = atomicAdd(&c.cnt->tree, T->tree);
         uint32_t s0 = atomicAdd(&c.cnt->bstart, T->bstart);
@@ -143,11 +142,11 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
         atomicAdd(&c.cnt->moved, T->moved);
         atomicMax(&c.cnt->kmax, T->kmax);
         if (l0 + T->n_large > c.caps.large) err |= kErrLargeCap;
-        if (u0 + T->units > c.caps.units || h0 + T->chunks > c.caps.chunks) err |= kErrUnitCap;
+        if (u0 + T->tiles > c.caps.tiles || h0 + T->chunks > c.caps.chunks) err |= kErrTileCap;
         if (m0 + T->cm > c.caps.cm || q0 + T->cs > c.caps.cs) err |= kErrCmCap;
         if (t0 + T->tree > c.caps.tree || s0 + T->bstart > c.caps.bstart) err |= kErrTreeCap;
         T->n_large = l0;
-        T->units = u0;
+        T->tiles = u0;
         T->chunks = h0;
         T->tree = t0;
         T->bstart = s0;
@@ -172,8 +171,8 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
         c.base_list[q][slot] = s;
         return;
     }
-    uint32_t d, ulen, units, chunks;
-    seg_shape(size, c, d, ulen, units, chunks);
+    uint32_t d, ulen, tiles, chunks;
+    seg_shape(size, c, d, ulen, tiles, chunks);
     const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
     LSeg g;
     g.begin = begin;
@@ -183,15 +182,15 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
     g.d = d;
     g.v = v;
     g.k = k;
-    g.unit_len = ulen;
-    g.units = units;
-    g.unit_base = atomicAdd(&T->units, units);
+    g.tile_len = ulen;
+    g.tiles = tiles;
+    g.tile_base = atomicAdd(&T->tiles, tiles);
     g.chunks = chunks;
     g.chunk_base = atomicAdd(&T->chunks, chunks);
     g.tree_base = atomicAdd(&T->tree, v + 1);
     g.bstart_base = atomicAdd(&T->bstart, k + 1);
     g.pad0 = g.pad1 = 0;
-    g.cm_base = atomicAdd(&T->cm, (unsigned long long)units * k);
+    g.cm_base = atomicAdd(&T->cm, (unsigned long long)tiles * k);
     g.cs_base = atomicAdd(&T->cs, (unsigned long long)chunks * k);
     c.lseg[atomicAdd(&T->n_large, 1u)] = g;
 }
@@ -199,7 +198,7 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
 __device__ __forceinline__ void tally_clear(PlanTally* T) {
     if (threadIdx.x == 0) {
         T->n_base[0] = T->n_base[1] = T->n_base[2] = 0;
-        T->n_large = T->units = T->chunks = T->tree = T->bstart = T->kmax = T->err = 0;
+        T->n_large = T->tiles = T->chunks = T->tree = T->bstart = T->kmax = T->err = 0;
         T->cm = T->cs = T->moved = T->base_elems = 0;
     }
 }
@@ -254,7 +253,7 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
 __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uint64_t* key_in,
                                                      uint32_t alpha, uint64_t seed,
                                                      uint64_t* tree_lo, uint64_t* tree_in,
-                                                     uint8_t* tree_lcp, uint32_t* unit_tab,
+                                                     uint8_t* tree_lcp, uint32_t* tile_tab,
                                                      uint32_t* chunk_tab, Counters* next_cnt) {
     extern __shared__ uint64_t smp[];  // sample, padded to a power of two
     // the next pass's counters are planned later in this pass: clear them here
@@ -341,64 +340,75 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
             lcp_out[i] = 0;
         }
     }
-    for (uint32_t u = tid; u < g.units; u += kWG) unit_tab[g.unit_base + u] = slot;
+    for (uint32_t u = tid; u < g.tiles; u += kWG) tile_tab[g.tile_base + u] = slot;
     for (uint32_t c = tid; c < g.chunks; c += kWG) chunk_tab[g.chunk_base + c] = slot;
 }
 
 // ---------------------------------------------------------------------------
-// K3: classification + per-unit histograms
+// K3: classification + per-tile histogram.  The workgroup walks its tile in
+// steps of kWG * U strings; every wavefront classifies U chunks of 64 coalesced
+// keys at once and counts them in its own LDS histogram (ballot match, the
+// lowest lane of each group adds).  The per-wavefront histograms are summed
+// into the tile's row of the count matrix.
 
 template <int U>
-__global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32_t* unit_tab,
+__global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32_t* tile_tab,
                                                   const uint64_t* key_in, const uint64_t* tree_lo,
                                                   const uint64_t* tree_in, uint16_t* bid,
                                                   uint32_t* cm, uint32_t vmax, uint32_t kmax) {
     extern __shared__ uint64_t dyn[];
     uint64_t* t = dyn;
     uint64_t* tin = t + (vmax + 1);
-    uint32_t* hist = (uint32_t*)(tin + (vmax + 1));
-    const uint32_t unit0 = blockIdx.x * kWaves;
-    const uint32_t slot = unit_tab[unit0];
-    const LSeg g = lseg[slot];
+    uint32_t* hist = (uint32_t*)(tin + (vmax + 1));  // kWaves * kmax
+    const uint32_t tile = blockIdx.x;
+    const LSeg g = lseg[tile_tab[tile]];
     for (uint32_t i = threadIdx.x; i <= g.v; i += kWG) {
         t[i] = tree_lo[g.tree_base + i];
         tin[i] = tree_in[g.tree_base + i];
     }
+    for (uint32_t b = threadIdx.x; b < g.k; b += kWG) {
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) hist[q * kmax + b] = 0;
+    }
+    __syncthreads();
     const uint32_t w = threadIdx.x >> 6, lane = lane_id();
     uint32_t* h = hist + w * kmax;
-    for (uint32_t b = lane; b < g.k; b += 64) h[b] = 0;
-    __syncthreads();
-    const uint32_t u = unit0 + w - g.unit_base;
-    const uint64_t ub = (uint64_t)u * g.unit_len;
-    const uint32_t start = g.begin + (uint32_t)(ub < g.size ? ub : g.size);
-    const uint32_t end = g.begin + (uint32_t)(ub + g.unit_len < g.size ? ub + g.unit_len : g.size);
+    const uint32_t row = tile - g.tile_base;
+    const uint64_t tb = (uint64_t)row * g.tile_len;
+    const uint32_t start = g.begin + (uint32_t)(tb < g.size ? tb : g.size);
+    const uint32_t end = g.begin + (uint32_t)(tb + g.tile_len < g.size ? tb + g.tile_len : g.size);
     const uint32_t nbits = g.d + 1;
-    for (uint32_t c = start; c < end; c += 64 * U) {
+    for (uint32_t c = start + w * 64 * U; c < end; c += kWG * U) {
         uint64_t kk[U];
         uint32_t b[U];
         bool valid[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            uint32_t pos = c + q * 64 + lane;
+            const uint32_t pos = c + q * 64 + lane;
             valid[q] = pos < end;
             kk[q] = valid[q] ? key_in[pos] : 0ull;
         }
         classify_u<U>(t, tin, g.d, g.v, kk, b);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            uint32_t pos = c + q * 64 + lane;
+            const uint32_t pos = c + q * 64 + lane;
             if (valid[q]) bid[pos] = (uint16_t)b[q];
-            uint64_t act = __ballot(valid[q]);
+            const uint64_t act = __ballot(valid[q]);
             if (act) {
-                uint64_t m = match_bucket(b[q], nbits, act);
+                const uint64_t m = match_bucket(b[q], nbits, act);
                 if (valid[q] && lane == (uint32_t)(__ffsll((long long)m) - 1))
                     h[b[q]] += (uint32_t)__popcll(m);
             }
         }
     }
     __syncthreads();
-    uint32_t* row = cm + g.cm_base + (uint64_t)u * g.k;
-    for (uint32_t b = lane; b < g.k; b += 64) row[b] = h[b];
+    uint32_t* out = cm + g.cm_base + (uint64_t)row * g.k;
+    for (uint32_t b = threadIdx.x; b < g.k; b += kWG) {
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kWaves; ++q) s += hist[q * kmax + b];
+        out[b] = s;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -412,7 +422,7 @@ __global__ __launch_bounds__(256) void k_colscan(const LSeg* lseg, const uint32_
     if (b >= g.k) return;
     const uint32_t c = cg - g.chunk_base;
     const uint32_t r0 = c * kChunkRows;
-    const uint32_t r1 = r0 + kChunkRows < g.units ? r0 + kChunkRows : g.units;
+    const uint32_t r1 = r0 + kChunkRows < g.tiles ? r0 + kChunkRows : g.tiles;
     uint32_t run = 0;
     uint32_t* col = cm + g.cm_base + b;
     for (uint32_t r = r0; r < r1; ++r) {
@@ -510,86 +520,209 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
 }
 
 // ---------------------------------------------------------------------------
-// K5: stable scatter; key refresh for the next depth; finished buckets
+// K5: stable redistribution (Section 3.1, out-of-place into the second work
+// array).  A tile is processed in sub-tiles of kSubTile strings:
+//   A. every wavefront loads its 512 strings (8 chunks of 64, in order),
+//      refreshes the keys of buckets whose depth grows (shift when the key
+//      holds the terminator, else an 8-byte gather from the arena), and ranks
+//      them by bucket with ballots into its own LDS counters;
+//   B. per bucket: prefix over the wavefronts and the bucket's start inside the
+//      sub-tile (block-wide scan over the buckets);
+//   C. every string is staged in LDS at its rank in bucket order;
+//   D. consecutive threads write consecutive staged strings, i.e. contiguous
+//      runs per bucket, to their final places.  Buckets that need no further
+//      sorting write the output permutation (and the LCPs inside an equality
+//      bucket of identical strings) directly; every bucket start gets its
+//      boundary depth flagged in out_lcp.
+constexpr uint32_t kPerWave = kSubTile / kWaves;  // strings per wavefront per sub-tile
+constexpr int kChunks = (int)(kPerWave / 64);     // chunks of 64 per wavefront
 
-template <int U>
+// per-bucket byte: mode in bits 4..5, depth increase (0..8) in bits 0..3
+constexpr uint32_t kModeLive = 0, kModeSingle = 1, kModeIdentical = 2;
+
+// exclusive block-wide sum of one value per thread; `wl` holds kWaves words
+__device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    uint32_t inc = v;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const uint32_t x = __shfl_up(inc, o);
+        if (lane >= o) inc += x;
+    }
+    if (lane == 63) wl[w] = inc;
+    __syncthreads();
+    uint32_t pre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+        if ((uint32_t)q < w) pre += wl[q];
+        tot += wl[q];
+    }
+    *total = tot;
+    __syncthreads();
+    return pre + inc - v;
+}
+
 __global__ __launch_bounds__(256) void k_scatter(
-    const LSeg* lseg, const uint32_t* unit_tab, const uint16_t* bid, const uint64_t* key_in,
+    const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
     const uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm,
     const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp,
     uint32_t vmax, uint32_t kmax) {
     extern __shared__ uint64_t dyn[];
-    uint64_t* tin = dyn;                                   // vmax + 1
-    uint32_t* bst = (uint32_t*)(tin + (vmax + 1));         // kmax + 1
-    uint32_t* run = bst + (kmax + 1);                      // kWaves * kmax
-    uint8_t* lcpx = (uint8_t*)(run + kWaves * kmax);       // vmax + 1
-    const uint32_t unit0 = blockIdx.x * kWaves;
-    const uint32_t slot = unit_tab[unit0];
-    const LSeg g = lseg[slot];
-    for (uint32_t i = threadIdx.x; i <= g.v; i += kWG) {
-        tin[i] = tree_in[g.tree_base + i];
-        lcpx[i] = tree_lcp[g.tree_base + i];
-    }
-    for (uint32_t b = threadIdx.x; b <= g.k; b += kWG) bst[b] = bstart[g.bstart_base + b];
-    const uint32_t w = threadIdx.x >> 6, lane = lane_id();
-    const uint32_t u = unit0 + w - g.unit_base;
-    const uint32_t c = u / kChunkRows;
-    uint32_t* r = run + w * kmax;
-    for (uint32_t b = lane; b < g.k; b += 64)
-        r[b] = cs[g.cs_base + (uint64_t)c * g.k + b] + cm[g.cm_base + (uint64_t)u * g.k + b];
-    __syncthreads();
-    const uint64_t ub = (uint64_t)u * g.unit_len;
-    const uint32_t start = g.begin + (uint32_t)(ub < g.size ? ub : g.size);
-    const uint32_t end = g.begin + (uint32_t)(ub + g.unit_len < g.size ? ub + g.unit_len : g.size);
-    const uint32_t nbits = g.d + 1;
-    const uint64_t ltmask = (1ull << lane) - 1ull;
-    for (uint32_t cpos = start; cpos < end; cpos += 64 * U) {
-        uint32_t b[U], id[U];
-        uint64_t kk[U];
-        bool valid[U];
+    uint64_t* SK = dyn;                                   // kSubTile staged keys
+    uint32_t* SI = (uint32_t*)(SK + kSubTile);            // kSubTile staged indices
+    uint32_t* base = SI + kSubTile;                       // kmax: next slot of each bucket
+    uint32_t* bst = base + kmax;                          // kmax: bucket starts in the segment
+    uint16_t* SB = (uint16_t*)(bst + kmax);               // kSubTile staged buckets
+    uint16_t* whist = SB + kSubTile;                      // kWaves * kmax per-wave counts
+    uint16_t* tstart = whist + kWaves * kmax;             // kmax + 1: starts in the sub-tile
+    uint8_t* binfo = (uint8_t*)(tstart + (kmax + 1));     // kmax: mode | depth increase
+    uint8_t* ident = binfo + kmax;                        // kmax: LCP inside identical buckets
+    __shared__ uint32_t wl[kWaves];
+    (void)vmax;
+
+    const uint32_t tile = blockIdx.x;
+    const LSeg g = lseg[tile_tab[tile]];
+    const uint32_t k = g.k, tid = threadIdx.x;
+    const uint32_t row = tile - g.tile_base, chunk = row / kChunkRows;
+    for (uint32_t b = tid; b < k; b += kWG) {
+        const uint32_t s0 = bstart[g.bstart_base + b], s1 = bstart[g.bstart_base + b + 1];
+        bst[b] = s0;
+        base[b] = cs[g.cs_base + (uint64_t)chunk * k + b] + cm[g.cm_base + (uint64_t)row * k + b];
+        const uint32_t j = b >> 1;
+        uint32_t info;
+        if (s1 - s0 == 1) {
+            info = kModeSingle << 4;
+        } else if (b & 1u) {
+            const uint64_t x = tree_in[g.tree_base + j];
+            if (has_zero(x)) {
+                info = kModeIdentical << 4;
+                ident[b] = (uint8_t)nz_bytes(x);
+            } else {
+                info = 8;
+            }
+        } else {
+            info = (j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j];
+        }
+        binfo[b] = (uint8_t)info;
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            uint32_t pos = cpos + q * 64 + lane;
-            valid[q] = pos < end;
-            b[q] = valid[q] ? bid[pos] : 0u;
-            kk[q] = valid[q] ? key_in[pos] : 0ull;
-            id[q] = valid[q] ? idx_in[pos] : 0u;
+        for (int q = 0; q < kWaves; ++q) whist[q * kmax + b] = 0;
+    }
+    __syncthreads();
+
+    const uint32_t w = tid >> 6, lane = lane_id();
+    uint16_t* wh = whist + w * kmax;
+    const uint64_t ltmask = (1ull << lane) - 1ull;
+    const uint32_t nbits = g.d + 1;
+    const uint64_t tb = (uint64_t)row * g.tile_len;
+    const uint32_t start = g.begin + (uint32_t)(tb < g.size ? tb : g.size);
+    const uint32_t end = g.begin + (uint32_t)(tb + g.tile_len < g.size ? tb + g.tile_len : g.size);
+    const uint32_t per = (k + kWG - 1) / kWG;  // buckets per thread in phase B (<= 8)
+    const uint32_t b0 = tid * per;
+
+    for (uint32_t sub = start; sub < end; sub += kSubTile) {
+        const uint32_t se = sub + kSubTile < end ? sub + kSubTile : end;
+        const uint32_t pw = sub + w * kPerWave + lane;
+        // A: load, refresh, rank inside the wavefront
+        uint64_t nk[kChunks];
+        uint32_t id[kChunks], bb[kChunks];
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const uint32_t p = pw + c * 64;
+            const bool valid = p < se;
+            bb[c] = valid ? bid[p] : 0xFFFFu;
+            nk[c] = valid ? key_in[p] : 0ull;
+            id[c] = valid ? idx_in[p] : 0u;
         }
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            uint64_t act = __ballot(valid[q]);
+        for (int c = 0; c < kChunks; ++c) {
+            if (bb[c] == 0xFFFFu) continue;
+            const uint32_t info = binfo[bb[c]];
+            const uint32_t delta = info & 15u;
+            if ((info >> 4) != kModeLive || delta == 0) continue;
+            if (delta < 8 && has_zero(nk[c]))
+                nk[c] <<= 8 * delta;
+            else
+                nk[c] = load_key(chars, offsets[id[c]] + g.depth + delta);
+        }
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            const bool valid = bb[c] != 0xFFFFu;
+            const uint64_t act = __ballot(valid);
             if (!act) break;
-            uint64_t m = match_bucket(b[q], nbits, act);
-            uint32_t old = valid[q] ? r[b[q]] : 0u;
-            if (valid[q] && lane == (uint32_t)(__ffsll((long long)m) - 1))
-                r[b[q]] = old + (uint32_t)__popcll(m);
-            if (!valid[q]) continue;
-            const uint32_t dr = old + (uint32_t)__popcll(m & ltmask);
-            const uint32_t dest = g.begin + dr;
-            const uint32_t bb = b[q];
-            const uint32_t s0 = bst[bb], size = bst[bb + 1] - s0;
-            if (dr == s0 && dr != 0) out_lcp[dest] = kLcpFlag | g.depth;
-            const uint32_t j = bb >> 1;
-            const bool odd = bb & 1u;
-            if (size == 1) {
-                out_perm[dest] = id[q] - g.base;
-            } else if (odd && has_zero(tin[j])) {
-                out_perm[dest] = id[q] - g.base;
-                if (dr != s0) out_lcp[dest] = g.depth + nz_bytes(tin[j]);
-            } else {
-                uint32_t delta = odd ? 8u : ((j == 0 || j == g.v) ? 0u : (uint32_t)lcpx[j]);
-                uint64_t nk = kk[q];
-                if (delta) {
-                    if (has_zero(nk) && delta < 8)
-                        nk = nk << (8 * delta);
-                    else
-                        nk = load_key(chars, offsets[id[q]] + g.depth + delta);
+            const uint32_t b = valid ? bb[c] : 0u;
+            const uint64_t m = match_bucket(b, nbits, act);
+            const uint32_t old = valid ? wh[b] : 0u;
+            if (valid && lane == (uint32_t)(__ffsll((long long)m) - 1))
+                wh[b] = (uint16_t)(old + (uint32_t)__popcll(m));
+            bb[c] = valid ? ((b << 16) | (old + (uint32_t)__popcll(m & ltmask))) : 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        // B: prefix over wavefronts per bucket, then bucket starts inside the sub-tile
+        uint32_t tot[8];
+        uint32_t mysum = 0;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t b = b0 + e;
+            tot[e] = 0;
+            if ((uint32_t)e < per && b < k) {
+                uint32_t r = 0;
+#pragma unroll
+                for (int q = 0; q < kWaves; ++q) {
+                    const uint32_t x = whist[q * kmax + b];
+                    whist[q * kmax + b] = (uint16_t)r;
+                    r += x;
                 }
-                key_out[dest] = nk;
-                idx_out[dest] = id[q];
+                tot[e] = r;
+                mysum += r;
             }
         }
+        uint32_t nsub;
+        uint32_t run = block_excl_add(mysum, wl, &nsub);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t b = b0 + e;
+            if ((uint32_t)e < per && b < k) {
+                tstart[b] = (uint16_t)run;
+                run += tot[e];
+            }
+        }
+        if (tid == 0) tstart[k] = (uint16_t)nsub;
+        __syncthreads();
+        // C: stage in bucket order
+#pragma unroll
+        for (int c = 0; c < kChunks; ++c) {
+            if (bb[c] == 0xFFFFFFFFu) continue;
+            const uint32_t b = bb[c] >> 16;
+            const uint32_t s = (uint32_t)tstart[b] + whist[w * kmax + b] + (bb[c] & 0xFFFFu);
+            SK[s] = nk[c];
+            SI[s] = id[c];
+            SB[s] = (uint16_t)b;
+        }
+        __syncthreads();
+        // D: write contiguous runs
+        for (uint32_t s = tid; s < nsub; s += kWG) {
+            const uint32_t b = SB[s];
+            const uint32_t dr = base[b] + s - tstart[b];
+            const uint32_t dest = g.begin + dr;
+            const uint32_t s0 = bst[b];
+            if (dr == s0 && dr != 0) out_lcp[dest] = kLcpFlag | g.depth;
+            const uint32_t mode = binfo[b] >> 4;
+            if (mode == kModeLive) {
+                key_out[dest] = SK[s];
+                idx_out[dest] = SI[s];
+            } else {
+                out_perm[dest] = SI[s] - g.base;
+                if (mode == kModeIdentical && dr != s0) out_lcp[dest] = g.depth + ident[b];
+            }
+        }
+        __syncthreads();
+        // E: advance the tile's bucket bases, clear the counters
+        for (uint32_t b = tid; b < k; b += kWG) {
+            base[b] += (uint32_t)tstart[b + 1] - tstart[b];
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) whist[q * kmax + b] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -910,10 +1043,29 @@ __global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint
         h += 8;
         uint32_t Pm = 1;
         while (Pm < m) Pm <<= 1;
-        for (uint32_t q = tid; q < Pm; q += kWG) {
-            if (q < m) {
-                SK[q] = load_key(chars, offsets[iin[SA[q] & 0xFFFFu]] + h);
-            } else {
+        {
+            // up to pmax / kWG members per thread: all their gathers in flight at once
+            constexpr int G = EMAX;
+            uint64_t pos[G], nkey[G];
+            uint32_t gi[G];
+            bool need[G];
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const uint32_t q = tid + e * kWG;
+                need[e] = q < m;
+                gi[e] = iin[need[e] ? (SA[q] & 0xFFFFu) : 0u];
+            }
+#pragma unroll
+            for (int e = 0; e < G; ++e) pos[e] = offsets[gi[e]];
+#pragma unroll
+            for (int e = 0; e < G; ++e) pos[e] += h;
+            load_keys<G>(chars, pos, need, nkey);
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const uint32_t q = tid + e * kWG;
+                if (q < m) SK[q] = nkey[e];
+            }
+            for (uint32_t q = m + tid; q < Pm; q += kWG) {
                 SK[q] = ~0ull;
                 SA[q] = 0xFFFFFFFFu;
             }
@@ -1058,24 +1210,24 @@ void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
 
 void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_in,
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
-                        uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* unit_tab,
+                        uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* tile_tab,
                         uint32_t* chunk_tab, Counters* next_cnt, hipStream_t st) {
     uint32_t m = alpha * (vmax + 1) - 1, P = 1;
     while (P < m) P <<= 1;
     S5_LAUNCH(k_sample_tree, dim3(n_large), dim3(kWG), (size_t)P * 8, st, lseg, key_in, alpha,
-              seed, tree_lo, tree_in, tree_lcp, unit_tab, chunk_tab, next_cnt);
+              seed, tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, next_cnt);
 }
 
-void launch_classify(uint32_t units, uint32_t unroll, const LSeg* lseg, const uint32_t* unit_tab,
+void launch_classify(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
                      const uint64_t* key_in, const uint64_t* tree_lo, const uint64_t* tree_in,
                      uint16_t* bid, uint32_t* cm, uint32_t vmax, uint32_t kmax, hipStream_t st) {
     size_t lds = (size_t)(vmax + 1) * 16 + (size_t)kWaves * kmax * 4;
-    dim3 grid(units / kWaves);
+    dim3 grid(tiles);
     switch (unroll) {
-        case 1: S5_LAUNCH(k_classify<1>, grid, dim3(kWG), lds, st, lseg, unit_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
-        case 2: S5_LAUNCH(k_classify<2>, grid, dim3(kWG), lds, st, lseg, unit_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
-        case 8: S5_LAUNCH(k_classify<8>, grid, dim3(kWG), lds, st, lseg, unit_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
-        default: S5_LAUNCH(k_classify<4>, grid, dim3(kWG), lds, st, lseg, unit_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
+        case 1: S5_LAUNCH(k_classify<1>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
+        case 2: S5_LAUNCH(k_classify<2>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
+        case 8: S5_LAUNCH(k_classify<8>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
+        default: S5_LAUNCH(k_classify<4>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
     }
 }
 
@@ -1092,26 +1244,18 @@ void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32
               ctx, next_buf);
 }
 
-void launch_scatter(uint32_t units, uint32_t unroll, const LSeg* lseg, const uint32_t* unit_tab,
+void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
                     const uint16_t* bid, const uint64_t* key_in, const uint32_t* idx_in,
                     uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs,
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, hipStream_t st) {
-    size_t lds = (size_t)(vmax + 1) * 8 + (size_t)(kmax + 1) * 4 + (size_t)kWaves * kmax * 4 +
-                 (size_t)(vmax + 1);
-    dim3 grid(units / kWaves);
-#define S5_SC(Uv)                                                                             \
-    S5_LAUNCH(k_scatter<Uv>, grid, dim3(kWG), lds, st, lseg, unit_tab, bid, key_in, idx_in,    \
-              key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,   \
-              out_lcp, vmax, kmax)
-    switch (unroll) {
-        case 1: S5_SC(1); break;
-        case 2: S5_SC(2); break;
-        case 8: S5_SC(8); break;
-        default: S5_SC(4); break;
-    }
-#undef S5_SC
+    (void)unroll;
+    const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
+                       (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
+    S5_LAUNCH(k_scatter, dim3(tiles), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in, idx_in,
+              key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,
+              out_lcp, vmax, kmax);
 }
 
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
@@ -1129,9 +1273,14 @@ void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t
         S5_LAUNCH(k_base_block<kBaseMid / kWG>, dim3(n_items[1]), dim3(kWG), per * P, st, items[1],
                   key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P);
     }
-    if (n_items[2])
-        S5_LAUNCH(k_base_block<8>, dim3(n_items[2]), dim3(kWG), per * PT, st, items[2], key0, key1,
-                  idx0, idx1, chars, offsets, out_perm, out_lcp, PT);
+    if (n_items[2]) {
+        if (PT <= 4u * kWG)
+            S5_LAUNCH(k_base_block<4>, dim3(n_items[2]), dim3(kWG), per * PT, st, items[2], key0,
+                      key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT);
+        else
+            S5_LAUNCH(k_base_block<8>, dim3(n_items[2]), dim3(kWG), per * PT, st, items[2], key0,
+                      key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT);
+    }
 }
 
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,

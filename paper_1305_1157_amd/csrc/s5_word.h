@@ -111,6 +111,40 @@ S5_HD void select_node(const uint64_t* smp, uint32_t a, uint32_t b, uint64_t* x,
     *x = m;
 }
 
+// Keys at chars[pos[c]] for every c with need[c], like load_key, for N
+// strings at once: all first words are loaded before any is inspected, then
+// all second words, so a thread has N gathers in flight instead of one.  Lanes
+// with need[c] == false read the aligned word holding chars[0] instead (always
+// a word of the arena) and leave out[c] unchanged.
+template <int N>
+S5_HD void load_keys(const uint8_t* chars, const uint64_t (&pos)[N], const bool (&need)[N],
+                     uint64_t (&out)[N]) {
+    const uint64_t* safe = (const uint64_t*)((uintptr_t)chars & ~(uintptr_t)7);
+    const uint64_t* w[N];
+    uint32_t sh[N];
+    uint64_t k[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        const uintptr_t a = (uintptr_t)(chars + pos[c]);
+        w[c] = need[c] ? (const uint64_t*)(a & ~(uintptr_t)7) : safe;
+        sh[c] = need[c] ? (uint32_t)(a & 7) * 8 : 0u;
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) k[c] = __builtin_bswap64(*w[c]) << sh[c];
+    bool more[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+        more[c] = sh[c] != 0 && (zero_byte_mask(k[c]) & (~0ull << sh[c])) == 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+        const uint64_t w1 = *(more[c] ? w[c] + 1 : w[c]);
+        if (more[c]) k[c] |= __builtin_bswap64(w1) >> (64 - sh[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+        if (need[c]) out[c] = clip_at_zero(k[c]);
+}
+
 #undef S5_HD
 
 }  // namespace s5

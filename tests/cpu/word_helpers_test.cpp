@@ -63,6 +63,13 @@ static void test_load_key_guarded(std::mt19937_64& rng) {
             uint8_t tmp[8];
             for (int i = 0; i < 8; ++i) tmp[i] = dep + i <= len ? s[dep + i] : 0;
             CHECK(got == ref_key(tmp), "guarded len %d depth %d", len, dep);
+            // batched form: mixed need flags, untouched outputs where not needed
+            uint64_t pos[4], out[4] = {1, 2, 3, 4};
+            bool need[4] = {true, false, true, false};
+            for (int c = 0; c < 4; ++c) pos[c] = (uint64_t)(s - mem) + dep;
+            load_keys<4>(mem, pos, need, out);
+            CHECK(out[0] == ref_key(tmp) && out[2] == ref_key(tmp) && out[1] == 2 && out[3] == 4,
+                  "load_keys len %d depth %d", len, dep);
         }
     }
     munmap(mem, 2 * pg);

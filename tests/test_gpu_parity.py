@@ -18,6 +18,8 @@ from paper_1305_1157_amd import gen, s5  # noqa: E402
 CFGS = {
     "default": None,
     "tiny_T_v7": s5.make_config(splitters=7, base_threshold=64, tile=64),
+    "v255_tile2048": s5.make_config(tile=2048),
+    "v511_tile_big": s5.make_config(splitters=511, tile=65536),
     "v1023_u8": s5.make_config(splitters=1023, unroll=8, base_threshold=2048),
     "v31_u1_T128": s5.make_config(splitters=31, unroll=1, base_threshold=128, tile=128),
     "v63_u2_a4": s5.make_config(splitters=63, unroll=2, oversample=4, base_threshold=256),
