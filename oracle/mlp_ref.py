@@ -1,0 +1,172 @@
+"""Reference (fp64, NumPy) for the learned splitter proposal -- test infrastructure only.
+
+Only ``tests/`` may use this module; the HIP library shares no code with it.
+
+The paper suggests adapting S^5 to the input by inspecting the sample and
+measures what a set of splitters gains by the entropy of the bucket sizes
+(appendix A, "Adaptivity").  The learned proposal here models the sample's
+distribution function with a small network and places splitters at its
+quantiles; classification stays the exact key comparison of Section 3.1, so the
+sort's output never depends on the model.
+
+Model (fixed by the build, see the design notes): 8 input features, the key's
+bytes divided by 255 (most significant byte first); two hidden layers of 32
+ReLU units; one sigmoid output, the estimated CDF.  1377 parameters in this
+order: W1 (32x8, row major), b1 (32), W2 (32x32), b2 (32), w3 (32), b3 (1).
+
+Initialisation draws uniform numbers from splitmix64 (Steele, Lea and Flood,
+2014) used as a counter-based generator: u_i = top 24 bits of
+splitmix64(seed + i + 1) / 2^24, parameter i gets (2 u_i - 1) * a_i with
+a = sqrt(6 / fan_in) for W1, W2 and 0.1 * sqrt(6 / 32) for w3; biases start at 0.
+
+Training: full-batch mean squared error against the empirical CDF of the sorted
+sample, t_i = (i + 0.5) / m, optimised with Adam (Kingma and Ba, 2015).
+
+Proposal: F_i = running maximum of the model over the sorted sample (a monotone
+CDF); splitter j (1 <= j <= v) is the sample key at the first i with
+F_i >= j / (v + 1), or the last sample key if there is none.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+N_PARAMS = 1377
+H = 32
+SLICES = {  # name -> (offset, shape)
+    "W1": (0, (H, 8)),
+    "b1": (256, (H,)),
+    "W2": (288, (H, H)),
+    "b2": (1312, (H,)),
+    "w3": (1344, (H,)),
+    "b3": (1376, (1,)),
+}
+MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x: int) -> int:
+    """One output of splitmix64 for state x (the state advance is included)."""
+    z = (x + 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def init_params(seed: int) -> np.ndarray:
+    p = np.zeros(N_PARAMS, dtype=np.float64)
+    bounds = np.zeros(N_PARAMS)
+    bounds[0:256] = np.sqrt(6.0 / 8)
+    bounds[288:1312] = np.sqrt(6.0 / H)
+    bounds[1344:1376] = 0.1 * np.sqrt(6.0 / H)
+    for i in range(N_PARAMS):
+        if bounds[i] == 0:
+            continue
+        u = (splitmix64((seed + i + 1) & MASK64) >> 40) / float(1 << 24)
+        p[i] = (2.0 * u - 1.0) * bounds[i]
+    return p
+
+
+def unpack(p: np.ndarray):
+    return {k: p[o:o + int(np.prod(s))].reshape(s) for k, (o, s) in SLICES.items()}
+
+
+def features(keys: np.ndarray) -> np.ndarray:
+    """(n, 8) features: bytes of the big-endian 64-bit keys / 255."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    shifts = np.arange(56, -8, -8, dtype=np.uint64)
+    return ((keys[:, None] >> shifts[None, :]) & np.uint64(0xFF)).astype(np.float64) / 255.0
+
+
+def forward(p: np.ndarray, x: np.ndarray):
+    q = unpack(p)
+    z1 = x @ q["W1"].T + q["b1"]
+    h1 = np.maximum(z1, 0.0)
+    z2 = h1 @ q["W2"].T + q["b2"]
+    h2 = np.maximum(z2, 0.0)
+    z3 = h2 @ q["w3"] + q["b3"][0]
+    y = 1.0 / (1.0 + np.exp(-z3))
+    return y, (x, z1, h1, z2, h2, y)
+
+
+def loss(p: np.ndarray, x: np.ndarray, t: np.ndarray) -> float:
+    y, _ = forward(p, x)
+    return float(np.mean((y - t) ** 2))
+
+
+def grad(p: np.ndarray, x: np.ndarray, t: np.ndarray) -> np.ndarray:
+    """Gradient of the mean squared error by backpropagation."""
+    q = unpack(p)
+    y, (x, z1, h1, z2, h2, _) = forward(p, x)
+    m = x.shape[0]
+    d3 = (2.0 / m) * (y - t) * y * (1.0 - y)          # dL/dz3, (m,)
+    g = np.zeros_like(p)
+    gq = unpack(g)
+    gq["w3"][:] = d3 @ h2
+    gq["b3"][0] = d3.sum()
+    d2 = np.outer(d3, q["w3"]) * (z2 > 0)              # dL/dz2, (m, 32)
+    gq["W2"][:] = d2.T @ h1
+    gq["b2"][:] = d2.sum(axis=0)
+    d1 = (d2 @ q["W2"]) * (z1 > 0)                     # dL/dz1, (m, 32)
+    gq["W1"][:] = d1.T @ x
+    gq["b1"][:] = d1.sum(axis=0)
+    return g
+
+
+def adam_step(p, g, m1, m2, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (step counts from 1); returns new (p, m1, m2)."""
+    m1 = b1 * m1 + (1 - b1) * g
+    m2 = b2 * m2 + (1 - b2) * g * g
+    mh = m1 / (1 - b1 ** step)
+    vh = m2 / (1 - b2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m1, m2
+
+
+def cdf_targets(m: int) -> np.ndarray:
+    return (np.arange(m, dtype=np.float64) + 0.5) / m
+
+
+def train(sorted_keys: np.ndarray, steps: int, lr: float, seed: int):
+    """Full-batch Adam on the empirical CDF of a sorted sample; returns
+    (params, losses) with losses[s] the loss before step s+1 and a final one."""
+    x = features(sorted_keys)
+    t = cdf_targets(len(sorted_keys))
+    p = init_params(seed)
+    m1 = np.zeros_like(p)
+    m2 = np.zeros_like(p)
+    losses = []
+    for s in range(1, steps + 1):
+        losses.append(loss(p, x, t))
+        p, m1, m2 = adam_step(p, grad(p, x, t), m1, m2, s, lr)
+    losses.append(loss(p, x, t))
+    return p, np.array(losses)
+
+
+def quantile_splitters(cdf: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
+    """v splitters from CDF values over the sorted sample: running maximum, then
+    for each j the sample key at the first index whose value reaches j/(v+1)."""
+    f = np.maximum.accumulate(np.asarray(cdf, dtype=np.float64))
+    q = np.arange(1, v + 1, dtype=np.float64) / (v + 1)
+    idx = np.searchsorted(f, q, side="left")
+    idx = np.minimum(idx, len(sorted_keys) - 1)
+    return np.asarray(sorted_keys, dtype=np.uint64)[idx]
+
+
+def propose(p: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
+    """v splitters (sorted, may repeat) at the quantiles j/(v+1) of the model's
+    monotone CDF over the sorted sample."""
+    y, _ = forward(p, features(sorted_keys))
+    return quantile_splitters(y, sorted_keys, v)
+
+
+def imbalanced(bucket_sizes: np.ndarray, v: int, size: int, beta: float) -> bool:
+    """True if some range bucket (even index) holds more than beta times the
+    ideal share |S| / (v + 1): the learned splitters are then replaced by
+    sampled ones."""
+    return bool(np.max(np.asarray(bucket_sizes)[0::2]) > beta * size / (v + 1))
+
+
+def entropy_bits(bucket_sizes: np.ndarray) -> float:
+    """sum_i (|b_i| / n) log2(n / |b_i|) over non-empty buckets (appendix A)."""
+    b = np.asarray(bucket_sizes, dtype=np.float64)
+    b = b[b > 0]
+    n = b.sum()
+    return float(np.sum(b / n * np.log2(n / b)))

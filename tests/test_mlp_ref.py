@@ -1,0 +1,100 @@
+"""Pins of the fp64 reference for the learned splitter proposal (CPU only).
+
+* splitmix64 against the generator's published first outputs;
+* backpropagation against central finite differences (a closed form);
+* forward / Adam / quantile selection against closed forms;
+* entropy of bucket sizes against log2(k) for k equal buckets.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_splitmix64_published_outputs():
+    vals = [int(l, 16) for l in open(os.path.join(GOLDEN, "splitmix64.txt"))
+            if l.strip() and not l.startswith("#")]
+    state = 0
+    for v in vals:
+        assert mlp_ref.splitmix64(state) == v
+        state = (state + 0x9E3779B97F4A7C15) & mlp_ref.MASK64
+
+
+def test_init_params_ranges():
+    p = mlp_ref.init_params(7)
+    q = mlp_ref.unpack(p)
+    assert p.shape == (1377,)
+    assert np.all(q["b1"] == 0) and np.all(q["b2"] == 0) and q["b3"][0] == 0
+    assert np.abs(q["W1"]).max() <= np.sqrt(6 / 8) and np.abs(q["W2"]).max() <= np.sqrt(6 / 32)
+    assert np.abs(q["w3"]).max() <= 0.1 * np.sqrt(6 / 32)
+    assert not np.array_equal(p, mlp_ref.init_params(8))
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_grad_vs_finite_differences(seed):
+    rng = np.random.default_rng(seed)
+    keys = np.sort(rng.integers(0, 2**63, size=24, dtype=np.uint64))
+    x = mlp_ref.features(keys)
+    t = mlp_ref.cdf_targets(len(keys))
+    p = mlp_ref.init_params(seed) + rng.normal(0, 0.05, size=1377)
+    g = mlp_ref.grad(p, x, t)
+    idx = rng.choice(1377, size=60, replace=False)
+    idx = np.concatenate([idx, [1376, 1344, 288, 0]])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(1377)
+        e[i] = h
+        fd = (mlp_ref.loss(p + e, x, t) - mlp_ref.loss(p - e, x, t)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 + 1e-4 * abs(fd), (i, fd, g[i])
+
+
+def test_forward_closed_forms():
+    x = mlp_ref.features(np.array([0, 2**64 - 1, 12345], dtype=np.uint64))
+    assert np.allclose(x[1], 1.0) and np.allclose(x[0], 0.0)
+    p = np.zeros(1377)
+    y, _ = mlp_ref.forward(p, x)
+    assert np.allclose(y, 0.5)
+    p[1376] = 2.0
+    y, _ = mlp_ref.forward(p, x)
+    assert np.allclose(y, 1 / (1 + np.exp(-2.0)))
+
+
+def test_adam_first_step_is_signed_lr():
+    rng = np.random.default_rng(0)
+    p = rng.normal(size=1377)
+    g = rng.normal(size=1377)
+    p1, _, _ = mlp_ref.adam_step(p, g, np.zeros(1377), np.zeros(1377), 1, 0.01)
+    # bias-corrected moments of the first step are g and g^2
+    assert np.allclose(p1 - p, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-9, atol=1e-12)
+
+
+def test_quantile_splitters_closed_form():
+    m, v = 1000, 15
+    keys = np.arange(m, dtype=np.uint64) * np.uint64(3)
+    spl = mlp_ref.quantile_splitters(mlp_ref.cdf_targets(m), keys, v)
+    want = [keys[int(np.ceil(j * m / (v + 1) - 0.5))] for j in range(1, v + 1)]
+    assert spl.tolist() == [int(w) for w in want]
+    # a non-monotone CDF is made monotone first; a constant CDF maps every
+    # splitter to the first key reaching the quantile, or to the last key
+    cdf = np.full(m, 0.2)
+    spl = mlp_ref.quantile_splitters(cdf, keys, v)
+    assert np.all(spl[: 3] == keys[0]) and np.all(spl[3:] == keys[-1])
+
+
+def test_training_lowers_loss():
+    rng = np.random.default_rng(4)
+    keys = np.sort(rng.integers(0, 2**63, size=512, dtype=np.uint64))
+    p, losses = mlp_ref.train(keys, steps=40, lr=0.02, seed=3)
+    assert losses[-1] < 0.25 * losses[0]
+
+
+def test_entropy_and_imbalance():
+    assert mlp_ref.entropy_bits(np.full(64, 10)) == pytest.approx(6.0)
+    assert mlp_ref.entropy_bits(np.array([0, 50, 0])) == 0.0
+    sizes = np.array([10, 0, 10, 0, 100])
+    assert mlp_ref.imbalanced(sizes, v=2, size=120, beta=2.0)
+    assert not mlp_ref.imbalanced(sizes, v=2, size=120, beta=3.0)
