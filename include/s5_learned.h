@@ -1,0 +1,57 @@
+/*
+ * s5_learned.h -- the learned splitter model of the S^5 library as building
+ * blocks (device pointers, stream-ordered, same conventions as s5.h).
+ *
+ * The paper proposes adapting string sample sort to its input by inspecting
+ * the sample (appendix A, "Adaptivity").  With splitter_mode =
+ * S5_SPLIT_LEARNED, s5_sort_ex models the distribution function of every
+ * segment of >= 65536 strings with a small network trained on 4096 sampled
+ * keys and places the splitters at its quantiles; classification remains the
+ * exact comparison of Section 3.1, so the output never depends on the model.
+ * The calls below expose the same model, training and evaluation code.
+ *
+ * Model: features = the key's 8 bytes / 255 (most significant first) after
+ * dropping the `shift` leading bytes that the whole training sample shares
+ * (shift = common leading bytes of its smallest and largest key, at most 7);
+ * two hidden layers of 32 ReLU units; sigmoid output.  Parameters (1377 floats):
+ * W1 (32x8, row major), b1 (32), W2 (32x32), b2 (32), w3 (32), b3 (1).
+ * Initial weights: splitmix64 as a counter-based generator, parameter i gets
+ * (2u - 1) * a with u = top 24 bits of splitmix64(seed + i + 1) / 2^24 and
+ * a = sqrt(6/8) (W1), sqrt(6/32) (W2), 0.1 sqrt(6/32) (w3), biases 0.
+ * Training: full-batch mean squared error against the empirical CDF
+ * t_i = (i + 0.5)/m of the sorted keys, Adam (beta1 0.9, beta2 0.999,
+ * eps 1e-8), one update per step.
+ */
+#ifndef S5_LEARNED_H
+#define S5_LEARNED_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Train from the initial weights of `seed` on m sorted keys (64 <= m <= 4096,
+ * m a multiple of 64) for `steps` Adam steps of learning rate lr; the 1377
+ * final parameters go to out_params.  Returns S5_OK or S5_ERR_INVALID. */
+int s5_mlp_train(const uint64_t* sorted_keys, uint32_t m, uint32_t steps, float lr,
+                 uint64_t seed, float* out_params, hipStream_t stream);
+
+/* Gradient of the mean squared error at `params` over m sorted keys (same
+ * constraints on m, features shifted as in training) into out_grad (1377
+ * floats). */
+int s5_mlp_grad(const float* params, const uint64_t* sorted_keys, uint32_t m, float* out_grad,
+                hipStream_t stream);
+
+/* Model output (estimated CDF) for n keys into out (n floats); shift (0..7)
+ * as used in training. */
+int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint32_t shift, float* out,
+                hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S5_LEARNED_H */

@@ -10,7 +10,9 @@ quantiles; classification stays the exact key comparison of Section 3.1, so the
 sort's output never depends on the model.
 
 Model (fixed by the build, see the design notes): 8 input features, the key's
-bytes divided by 255 (most significant byte first); two hidden layers of 32
+bytes divided by 255 (most significant byte first) after dropping the bytes
+that every key of the sample shares (the shift: common leading bytes of the
+smallest and largest sampled key, at most 7); two hidden layers of 32
 ReLU units; one sigmoid output, the estimated CDF.  1377 parameters in this
 order: W1 (32x8, row major), b1 (32), W2 (32x32), b2 (32), w3 (32), b3 (1).
 
@@ -69,9 +71,18 @@ def unpack(p: np.ndarray):
     return {k: p[o:o + int(np.prod(s))].reshape(s) for k, (o, s) in SLICES.items()}
 
 
-def features(keys: np.ndarray) -> np.ndarray:
-    """(n, 8) features: bytes of the big-endian 64-bit keys / 255."""
+def prefix_shift(sorted_keys: np.ndarray) -> int:
+    """Leading bytes shared by every key of a sorted sample (at most 7)."""
+    x = int(sorted_keys[0]) ^ int(sorted_keys[-1])
+    return min(7, (64 - x.bit_length()) // 8)
+
+
+def features(keys: np.ndarray, shift: int = 0) -> np.ndarray:
+    """(n, 8) features: bytes of the big-endian 64-bit keys, the first `shift`
+    bytes dropped (zeros shifted in), / 255."""
     keys = np.asarray(keys, dtype=np.uint64)
+    if shift:
+        keys = keys << np.uint64(8 * shift)
     shifts = np.arange(56, -8, -8, dtype=np.uint64)
     return ((keys[:, None] >> shifts[None, :]) & np.uint64(0xFF)).astype(np.float64) / 255.0
 
@@ -127,7 +138,7 @@ def cdf_targets(m: int) -> np.ndarray:
 def train(sorted_keys: np.ndarray, steps: int, lr: float, seed: int):
     """Full-batch Adam on the empirical CDF of a sorted sample; returns
     (params, losses) with losses[s] the loss before step s+1 and a final one."""
-    x = features(sorted_keys)
+    x = features(sorted_keys, prefix_shift(sorted_keys))
     t = cdf_targets(len(sorted_keys))
     p = init_params(seed)
     m1 = np.zeros_like(p)
@@ -153,7 +164,7 @@ def quantile_splitters(cdf: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.n
 def propose(p: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
     """v splitters (sorted, may repeat) at the quantiles j/(v+1) of the model's
     monotone CDF over the sorted sample."""
-    y, _ = forward(p, features(sorted_keys))
+    y, _ = forward(p, features(sorted_keys, prefix_shift(sorted_keys)))
     return quantile_splitters(y, sorted_keys, v)
 
 

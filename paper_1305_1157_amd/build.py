@@ -30,7 +30,7 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     objs = []
-    for src, lang in (("s5_kernels.hip", "hip"), ("s5_host.cpp", "hip")):
+    for src, lang in (("s5_kernels.hip", "hip"), ("s5_learn.hip", "hip"), ("s5_host.cpp", "hip")):
         obj = os.path.join(BUILD_DIR, src + ".o")
         out = _run([HIPCC, "-x", lang, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
         if verbose and out.strip():

@@ -19,6 +19,7 @@
 
 #include "../../include/s5.h"
 #include "../../include/s5_profile.h"
+#include "../../include/s5_learned.h"
 #include "s5_internal.h"
 
 namespace s5 {
@@ -48,11 +49,36 @@ void launch_lcp_fix(const uint8_t*, const uint64_t*, const uint64_t*, uint32_t, 
                     const uint32_t*, uint32_t*, hipStream_t);
 void launch_classify_plain(const uint64_t*, uint32_t, const uint64_t*, uint32_t, uint32_t,
                            uint64_t*, uint64_t*, uint16_t*, hipStream_t);
+struct LearnCtx {
+    uint64_t* samples;
+    float* W;
+    float* M1;
+    float* M2;
+    float* part;
+    uint32_t* shift;
+    uint32_t m, groups;
+};
+size_t learn_bytes(uint32_t slots, uint32_t groups);
+LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m);
+void launch_learn_sort_trees(const LearnCtx&, uint32_t, const LSeg*, const uint32_t*,
+                             const uint64_t*, uint64_t, uint32_t, float, uint64_t*, uint64_t*,
+                             uint8_t*, hipStream_t);
+void launch_learn_check(uint32_t, LSeg*, const uint32_t*, const uint32_t*, float, Globals*,
+                        hipStream_t);
+void launch_mlp_train(const LearnCtx&, const uint64_t*, uint32_t, uint32_t, float, uint64_t,
+                      float*, hipStream_t);
+void launch_mlp_grad(const LearnCtx&, const float*, const uint64_t*, uint32_t, float*,
+                     hipStream_t);
+void launch_mlp_eval(const float*, const uint64_t*, uint32_t, uint32_t, float*, hipStream_t);
 }  // namespace s5
 
 using namespace s5;
 
 namespace {
+
+// learned splitters: samples per segment, Adam steps and learning rate
+constexpr uint32_t kLearnSamples = 4096, kLearnSteps = 64;
+constexpr float kLearnRate = 0.01f;
 
 struct Cfg {
     uint32_t dmax, alpha, unroll, tile_min, T, mode;
@@ -89,7 +115,8 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
     size_t key[2], idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
-        bstart, base_list, counters[2], glob, total;
+        bstart, base_list, learn, learn_seg, counters[2], glob, total;
+    uint32_t learn_cap;
     Caps caps;
 };
 
@@ -136,6 +163,10 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     L.cs = take((size_t)cp.cs * 4);
     L.bstart = take((size_t)cp.bstart * 4);
     L.base_list = take((size_t)(cp.base[0] + cp.base[1] + cp.base[2]) * sizeof(Seg));
+    // learned splitters: one slot per segment of >= kLearnMin strings in a pass
+    L.learn_cap = c.mode == S5_SPLIT_LEARNED ? (uint32_t)std::min<uint64_t>(large, n / kLearnMin + 1) : 0u;
+    L.learn = take(learn_bytes(L.learn_cap, kLearnSamples / 64));
+    L.learn_seg = take((size_t)L.learn_cap * 4);
     // [counters 0 | globals | counters 1] back to back: one copy reads a pass's
     // counters together with the globals
     L.counters[0] = take(sizeof(Counters) + sizeof(Globals) + sizeof(Counters));
@@ -192,15 +223,15 @@ int pool_get(size_t bytes, DevPool** out) {
 
 // ---- per-kernel event timing (s5_profile.h) --------------------------------
 enum KId { K_INIT, K_ROOTS, K_SAMPLE, K_CLASSIFY, K_COLSCAN, K_PLAN, K_SCATTER, K_BASE, K_LCPFIX,
-           K_COUNT };
+           K_LEARN, K_COUNT };
 const char* const kKName[K_COUNT] = {"init_keys", "plan_roots", "sample_tree", "classify",
                                      "colscan",   "bucket_plan", "scatter",    "base_sort",
-                                     "lcp_fix"};
+                                     "lcp_fix",   "learn_splitters"};
 // algorithmic bytes per string processed: init reads an offset and 8 key bytes
 // and writes key + index; classify reads a key and writes a bucket id; a
 // redistribution pass reads and writes (key, index); the base case reads
 // (key, index) and writes perm + lcp; the LCP completion reads one lcp word
-const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4};
+const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4, 0};
 struct ProfAcc {
     uint64_t launches = 0, items = 0;
     double ms = 0, bytes = 0;
@@ -286,6 +317,8 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
     uint32_t* cm = (uint32_t*)(W + L.cm);
     uint32_t* cs = (uint32_t*)(W + L.cs);
     uint32_t* bstart = (uint32_t*)(W + L.bstart);
+    uint32_t* learn_seg = (uint32_t*)(W + L.learn_seg);
+    const LearnCtx lctx = learn_ctx(W + L.learn, L.learn_cap, kLearnSamples);
     Seg* base_list[kBaseClasses];
     base_list[0] = (Seg*)(W + L.base_list);
     base_list[1] = base_list[0] + L.caps.base[0];
@@ -305,6 +338,9 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         x.T = c.T;
         x.d_max = c.dmax;
         x.tile_min = c.tile_min;
+        x.learn = c.mode == S5_SPLIT_LEARNED ? 1u : 0u;
+        x.learn_cap = L.learn_cap;
+        x.learn_seg = learn_seg;
         return x;
     };
     auto readback = [&](int which) -> int {
@@ -341,12 +377,42 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
             launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
                                tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
         });
+        const uint32_t n_learn = std::min(now.pad0, L.learn_cap);
+        if (n_learn) {
+            timed(K_LEARN, n_learn, st, [&] {
+                launch_learn_sort_trees(lctx, n_learn, lseg[cur], learn_seg, key[buf], c.seed,
+                                        kLearnSteps, kLearnRate, tree_lo, tree_in, tree_lcp, st);
+            });
+        }
         timed(K_CLASSIFY, now.moved, st, [&] {
             launch_classify(now.tiles, c.unroll, lseg[cur], tile_tab, key[buf], tree_lo, tree_in,
                             bid, cm, vmax, kmax, st);
         });
         timed(K_COLSCAN, now.moved, st,
               [&] { launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st); });
+        if (n_learn) {
+            // learned splitters that leave a range bucket too large are redone sampled
+            const uint32_t before = hg->fallbacks;
+            launch_learn_check(n_learn, lseg[cur], learn_seg, cs, c.beta, glob, st);
+            rc = readback(cur);
+            if (rc) {
+                prof_collect();
+                return rc;
+            }
+            if (hg->fallbacks != before) {
+                timed(K_SAMPLE, now.n_large, st, [&] {
+                    launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed,
+                                       tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
+                });
+                timed(K_CLASSIFY, now.moved, st, [&] {
+                    launch_classify(now.tiles, c.unroll, lseg[cur], tile_tab, key[buf], tree_lo,
+                                    tree_in, bid, cm, vmax, kmax, st);
+                });
+                timed(K_COLSCAN, now.moved, st, [&] {
+                    launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st);
+                });
+            }
+        }
         timed(K_PLAN, now.moved, st, [&] {
             launch_bucket_plan(now.n_large, lseg[cur], cs, bstart, tree_in, tree_lcp, ctx_for(nxt),
                                (uint32_t)(buf ^ 1), st);
@@ -373,6 +439,7 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         buf ^= 1;
     }
     stats->passes = level;
+    stats->fallbacks = hg->fallbacks;
     uint32_t n_base[kBaseClasses];
     for (int q = 0; q < kBaseClasses; ++q) n_base[q] = hg->n_base[q];
     stats->base_items = (uint64_t)n_base[0] + n_base[1] + n_base[2];
@@ -560,6 +627,41 @@ int s5_profile_read(s5_kernel_profile* out, uint32_t max, uint32_t* count) {
     }
     *count = c;
     return S5_OK;
+}
+
+
+static int mlp_check_m(uint32_t m) { return (m >= 64 && m <= 4096 && m % 64 == 0) ? S5_OK : S5_ERR_INVALID; }
+
+int s5_mlp_train(const uint64_t* sorted_keys, uint32_t m, uint32_t steps, float lr, uint64_t seed,
+                 float* out_params, hipStream_t stream) {
+    if (!sorted_keys || !out_params || mlp_check_m(m) || steps > 100000) return S5_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    DevPool* P = nullptr;
+    int rc = pool_get(learn_bytes(1, m / 64), &P);
+    if (rc) return rc;
+    launch_mlp_train(learn_ctx(P->ptr, 1, m), sorted_keys, m, steps, lr, seed, out_params, stream);
+    if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
+    return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;
+}
+
+int s5_mlp_grad(const float* params, const uint64_t* sorted_keys, uint32_t m, float* out_grad,
+                hipStream_t stream) {
+    if (!params || !sorted_keys || !out_grad || mlp_check_m(m)) return S5_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    DevPool* P = nullptr;
+    int rc = pool_get(learn_bytes(1, m / 64), &P);
+    if (rc) return rc;
+    launch_mlp_grad(learn_ctx(P->ptr, 1, m), params, sorted_keys, m, out_grad, stream);
+    if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
+    return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;
+}
+
+int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint32_t shift, float* out,
+                hipStream_t stream) {
+    if (n > 0 && (!params || !keys || !out)) return S5_ERR_INVALID;
+    if (shift > 7) return S5_ERR_INVALID;
+    launch_mlp_eval(params, keys, n, shift, out, stream);
+    return hipGetLastError() == hipSuccess ? S5_OK : S5_ERR_HIP;
 }
 
 }  // extern "C"

@@ -39,7 +39,8 @@ struct LSeg {
     uint32_t tiles, tile_base;      // tiles and first tile id
     uint32_t chunks, chunk_base;    // column-scan chunks and first chunk id
     uint32_t tree_base, bstart_base;
-    uint32_t pad0, pad1;
+    uint32_t pad0;                  // learned-splitter slot, or 0xFFFFFFFF for sampled splitters
+    uint32_t pad1;
     unsigned long long cm_base;     // tiles x k count matrix (row-major)
     unsigned long long cs_base;     // chunks x k chunk sums / prefixes
 };
@@ -47,7 +48,7 @@ struct LSeg {
 // Counters written by one planning step and read back by the host.
 struct Counters {
     uint32_t n_large, tiles, chunks, tree;
-    uint32_t bstart, kmax, pad0, pad1;
+    uint32_t bstart, kmax, pad0, pad1;   // pad0: learned segments planned
     unsigned long long cm, cs;
     unsigned long long moved;       // strings in the planned large segments
     unsigned long long max_bucket;  // largest bucket seen by the planning step
@@ -68,7 +69,12 @@ struct Globals {
     uint32_t n_base[kBaseClasses];  // base-case items appended so far, per class
     uint32_t status;                // error bits
     unsigned long long base_elems;  // strings in those items
+    uint32_t fallbacks;             // learned segments redone with sampled splitters
+    uint32_t pad;
 };
+
+// Learned splitters apply to segments of at least this many strings.
+constexpr uint32_t kLearnMin = 65536;
 
 // Capacities of the per-pass storage.
 struct Caps {
@@ -83,6 +89,9 @@ struct PlanCtx {
     Seg* base_list[kBaseClasses];  // base-case items (all passes), per size class
     Globals* glob;
     Caps caps;
+    uint32_t* learn_seg;  // learned slot -> next pass's segment index
+    uint32_t learn;       // 1: learned splitters for segments >= kLearnMin
+    uint32_t learn_cap;   // learned slots available
     uint32_t T;           // base threshold
     uint32_t d_max;       // tree depth limit for this sort
     uint32_t tile_min;    // minimum strings per tile

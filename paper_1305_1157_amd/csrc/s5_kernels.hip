@@ -84,7 +84,7 @@ __device__ uint32_t block_exclusive_scan(const uint32_t* cnt, uint32_t* out, uin
 // global counters beyond one atomic per counter and block).
 
 struct PlanTally {
-    uint32_t n_base[kBaseClasses], n_large, tiles, chunks, tree, bstart, kmax, err;
+    uint32_t n_base[kBaseClasses], n_large, tiles, chunks, tree, bstart, kmax, err, n_learn;
     unsigned long long cm, cs, moved, base_elems;
 };
 
@@ -119,6 +119,7 @@ __device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, Plan
     atomicAdd(&T->cs, (unsigned long long)chunks * k);
     atomicAdd(&T->moved, (unsigned long long)size);
     atomicMax(&T->kmax, k);
+    if (c.learn && size >= kLearnMin) atomicAdd(&T->n_learn, 1u);
 }
 
 // Phase 2, one thread: turn block totals into global bases (stored back into T).
@@ -138,12 +139,14 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
         uint32_t t0 = atomicAdd(&c.cnt->tree, T->tree);
         uint32_t s0 = atomicAdd(&c.cnt->bstart, T->bstart);
         unsigned long long m0 = atomicAdd(&c.cnt->cm, T->cm);
-        unsigned long long q0 = atomicAdd(&c.cnt->cs, T->cs);
+        unsigned long long q0s = atomicAdd(&c.cnt->cs, T->cs);
         atomicAdd(&c.cnt->moved, T->moved);
         atomicMax(&c.cnt->kmax, T->kmax);
+        uint32_t q0 = 0;
+        if (T->n_learn) q0 = atomicAdd(&c.cnt->pad0, T->n_learn);
         if (l0 + T->n_large > c.caps.large) err |= kErrLargeCap;
         if (u0 + T->tiles > c.caps.tiles || h0 + T->chunks > c.caps.chunks) err |= kErrTileCap;
-        if (m0 + T->cm > c.caps.cm || q0 + T->cs > c.caps.cs) err |= kErrCmCap;
+        if (m0 + T->cm > c.caps.cm || q0s + T->cs > c.caps.cs) err |= kErrCmCap;
         if (t0 + T->tree > c.caps.tree || s0 + T->bstart > c.caps.bstart) err |= kErrTreeCap;
         T->n_large = l0;
         T->tiles = u0;
@@ -151,7 +154,8 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
         T->tree = t0;
         T->bstart = s0;
         T->cm = m0;
-        T->cs = q0;
+        T->cs = q0s;
+        T->n_learn = q0;
     }
     if (err) atomicOr(&c.glob->status, err);
     T->err = err;
@@ -189,16 +193,26 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
     g.chunk_base = atomicAdd(&T->chunks, chunks);
     g.tree_base = atomicAdd(&T->tree, v + 1);
     g.bstart_base = atomicAdd(&T->bstart, k + 1);
-    g.pad0 = g.pad1 = 0;
+    g.pad0 = 0xFFFFFFFFu;
+    g.pad1 = 0;
     g.cm_base = atomicAdd(&T->cm, (unsigned long long)tiles * k);
     g.cs_base = atomicAdd(&T->cs, (unsigned long long)chunks * k);
-    c.lseg[atomicAdd(&T->n_large, 1u)] = g;
+    const uint32_t slot = atomicAdd(&T->n_large, 1u);
+    if (c.learn && size >= kLearnMin) {
+        const uint32_t ls = atomicAdd(&T->n_learn, 1u);
+        if (ls < c.learn_cap) {  // beyond the cap the segment keeps sampled splitters
+            g.pad0 = ls;
+            c.learn_seg[ls] = slot;
+        }
+    }
+    c.lseg[slot] = g;
 }
 
 __device__ __forceinline__ void tally_clear(PlanTally* T) {
     if (threadIdx.x == 0) {
         T->n_base[0] = T->n_base[1] = T->n_base[2] = 0;
         T->n_large = T->tiles = T->chunks = T->tree = T->bstart = T->kmax = T->err = 0;
+        T->n_learn = 0;
         T->cm = T->cs = T->moved = T->base_elems = 0;
     }
 }
@@ -263,6 +277,9 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
     const uint32_t slot = blockIdx.x;
     const LSeg g = lseg[slot];
     const uint32_t tid = threadIdx.x;
+    for (uint32_t u = tid; u < g.tiles; u += kWG) tile_tab[g.tile_base + u] = slot;
+    for (uint32_t c = tid; c < g.chunks; c += kWG) chunk_tab[g.chunk_base + c] = slot;
+    if (g.pad0 != 0xFFFFFFFFu) return;  // learned splitters: the tree comes from the model
     const uint32_t m = alpha * (g.v + 1) - 1;
     uint32_t P = 1;
     while (P < m) P <<= 1;
@@ -340,8 +357,6 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
             lcp_out[i] = 0;
         }
     }
-    for (uint32_t u = tid; u < g.tiles; u += kWG) tile_tab[g.tile_base + u] = slot;
-    for (uint32_t c = tid; c < g.chunks; c += kWG) chunk_tab[g.chunk_base + c] = slot;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,452 @@
+// Learned splitter proposal for S^5 (gfx950, FP32, no MFMA).
+//
+// The paper proposes adapting the algorithm to the input by inspecting the
+// sample and measures what a set of splitters gains by the entropy of the
+// bucket sizes (appendix A, "Adaptivity").  Here a small network models the
+// distribution function of a segment's 8-byte keys and its quantiles become
+// the splitters.  Classification is still the exact key comparison of
+// Section 3.1, so the sort's output never depends on the model; a segment
+// whose learned splitters leave a range bucket too large is redone with
+// sampled splitters.
+//
+// Model: features = the key's 8 bytes / 255 (most significant first); two
+// hidden layers of 32 ReLU units; sigmoid output.  1377 parameters:
+// W1 (32x8), b1, W2 (32x32), b2, w3 (32), b3.  Weights start from splitmix64
+// used as a counter-based generator; training is full-batch mean squared
+// error against the sample's empirical CDF, optimised with Adam.  One step is
+// one launch: 64-sample groups compute partial gradients in parallel; every
+// group of the next step sums the previous partials in the same fixed order
+// and applies the identical Adam update, so the result is deterministic.
+#include "s5_internal.h"
+#include "s5_word.h"
+
+namespace s5 {
+
+constexpr uint32_t kLearnM = 4096;    // sampled keys per learned segment
+constexpr uint32_t kGrp = 64;         // samples per training workgroup (one per lane)
+constexpr int kH = 32;                // hidden units per layer
+constexpr uint32_t kNP = 1377;        // parameters
+constexpr uint32_t kNPS = 1408;       // stride of one parameter vector
+constexpr uint32_t oW1 = 0, oB1 = 256, oW2 = 288, oB2 = 1312, oW3 = 1344, oB3 = 1376;
+constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
+
+// Learned-splitter state of all learned segments of one pass.
+struct LearnCtx {
+    uint64_t* samples;  // [slot][kLearnM] sorted sampled keys
+    float* W;           // [slot][2][kNPS] weights, double-buffered by step parity
+    float* M1;          // [slot][2][kNPS] Adam first moments
+    float* M2;          // [slot][2][kNPS] Adam second moments
+    float* part;        // [slot][2][groups][kNPS] partial gradients
+    uint32_t* shift;    // [slot] leading bytes shared by the whole sample (dropped from features)
+    uint32_t m;         // samples per slot (multiple of kGrp, <= kLearnM)
+    uint32_t groups;    // m / kGrp
+};
+
+__device__ __forceinline__ float* wbuf(const LearnCtx& c, uint32_t slot, uint32_t b) {
+    return c.W + ((size_t)slot * 2 + b) * kNPS;
+}
+__device__ __forceinline__ float* m1buf(const LearnCtx& c, uint32_t slot, uint32_t b) {
+    return c.M1 + ((size_t)slot * 2 + b) * kNPS;
+}
+__device__ __forceinline__ float* m2buf(const LearnCtx& c, uint32_t slot, uint32_t b) {
+    return c.M2 + ((size_t)slot * 2 + b) * kNPS;
+}
+__device__ __forceinline__ float* pbuf(const LearnCtx& c, uint32_t slot, uint32_t b,
+                                       uint32_t grp) {
+    return c.part + (((size_t)slot * 2 + b) * c.groups + grp) * kNPS;
+}
+
+__device__ __forceinline__ float init_weight(uint64_t seed, uint32_t i) {
+    float a;
+    if (i < oB1) a = 0.8660254037844386f;             // sqrt(6 / 8)
+    else if (i >= oW2 && i < oB2) a = 0.4330127018922193f;  // sqrt(6 / 32)
+    else if (i >= oW3 && i < oB3) a = 0.04330127018922193f; // 0.1 * sqrt(6 / 32)
+    else return 0.0f;
+    const uint64_t r = mix64(seed + i + 1 + 0x9E3779B97F4A7C15ull);  // splitmix64(seed + i + 1)
+    const float u = (float)(uint32_t)(r >> 40) * (1.0f / 16777216.0f);
+    return (2.0f * u - 1.0f) * a;
+}
+
+__device__ __forceinline__ void key_features(uint64_t k, uint32_t shift, float (&x)[8]) {
+    k = shift ? k << (8 * shift) : k;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) x[b] = (float)((k >> (56 - 8 * b)) & 0xFFull) * (1.0f / 255.0f);
+}
+
+// forward pass for one key with weights w (LDS or global); optional activations
+__device__ __forceinline__ float mlp_forward(const float* w, const float (&x)[8], float* h1o,
+                                             float* h2o) {
+    float h1[kH];
+#pragma unroll
+    for (int i = 0; i < kH; ++i) {
+        float z = w[oB1 + i];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) z = fmaf(w[oW1 + i * 8 + j], x[j], z);
+        h1[i] = z > 0.0f ? z : 0.0f;
+    }
+    float z3 = w[oB3];
+#pragma unroll 4
+    for (int i = 0; i < kH; ++i) {
+        float z = w[oB2 + i];
+#pragma unroll
+        for (int j = 0; j < kH; ++j) z = fmaf(w[oW2 + i * kH + j], h1[j], z);
+        const float h = z > 0.0f ? z : 0.0f;
+        if (h2o) h2o[i] = h;
+        z3 = fmaf(w[oW3 + i], h, z3);
+    }
+    if (h1o) {
+#pragma unroll
+        for (int i = 0; i < kH; ++i) h1o[i] = h1[i];
+    }
+    return 1.0f / (1.0f + __expf(-z3));
+}
+
+// Adam update of parameter p from the summed gradient g (step t >= 1).
+__device__ __forceinline__ float adam(float w, float g, float& m1, float& m2, uint32_t t,
+                                      float lr) {
+    m1 = kB1 * m1 + (1.0f - kB1) * g;
+    m2 = kB2 * m2 + (1.0f - kB2) * g * g;
+    const float mh = m1 / (1.0f - __powf(kB1, (float)t));
+    const float vh = m2 / (1.0f - __powf(kB2, (float)t));
+    return w - lr * mh / (sqrtf(vh) + kEps);
+}
+
+// ---------------------------------------------------------------------------
+// one training step: update from the previous partial gradients, then the
+// partial gradients of this step's weights over this group's 64 samples.
+
+__global__ __launch_bounds__(64) void k_learn_step(LearnCtx c, uint32_t step, float lr) {
+    __shared__ float w[kNPS];
+    __shared__ float sx[kGrp][8];
+    __shared__ float sh1[kGrp][kH + 1];
+    __shared__ float sh2[kGrp][kH + 1];
+    __shared__ float sd1[kGrp][kH + 1];
+    __shared__ float sd2[kGrp][kH + 1];
+    __shared__ float sd3[kGrp];
+    const uint32_t slot = blockIdx.y, grp = blockIdx.x, lane = threadIdx.x;
+    const uint32_t prev = (step + 1) & 1u, cur = step & 1u;
+    const float* wp = wbuf(c, slot, prev);
+    for (uint32_t p = lane; p < kNP; p += kGrp) {
+        float wv = wp[p];
+        float m1 = 0.0f, m2 = 0.0f;
+        if (step > 0) {
+            float g = 0.0f;
+            for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, slot, prev, q)[p];
+            m1 = m1buf(c, slot, prev)[p];
+            m2 = m2buf(c, slot, prev)[p];
+            wv = adam(wv, g, m1, m2, step, lr);
+        }
+        w[p] = wv;
+        if (grp == 0) {
+            wbuf(c, slot, cur)[p] = wv;
+            m1buf(c, slot, cur)[p] = m1;
+            m2buf(c, slot, cur)[p] = m2;
+        }
+    }
+    __syncthreads();
+    // forward and backward for this lane's sample
+    const uint32_t i = grp * kGrp + lane;
+    float x[8];
+    key_features(c.samples[(size_t)slot * kLearnM + i], c.shift[slot], x);
+    float h1[kH], h2[kH];
+    const float y = mlp_forward(w, x, h1, h2);
+    const float t = ((float)i + 0.5f) / (float)c.m;
+    const float d3 = (2.0f / (float)c.m) * (y - t) * y * (1.0f - y);
+    float d1[kH];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) d1[j] = 0.0f;
+#pragma unroll 4
+    for (int r = 0; r < kH; ++r) {
+        const float d2 = h2[r] > 0.0f ? d3 * w[oW3 + r] : 0.0f;
+        sd2[lane][r] = d2;
+#pragma unroll
+        for (int j = 0; j < kH; ++j) d1[j] = fmaf(d2, w[oW2 + r * kH + j], d1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sx[lane][j] = x[j];
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        sh1[lane][j] = h1[j];
+        sh2[lane][j] = h2[j];
+        sd1[lane][j] = h1[j] > 0.0f ? d1[j] : 0.0f;
+    }
+    sd3[lane] = d3;
+    __syncthreads();
+    // partial gradients: every lane owns parameters lane, lane + 64, ...
+    float* out = pbuf(c, slot, cur, grp);
+    for (uint32_t p = lane; p < kNP; p += kGrp) {
+        float g = 0.0f;
+        if (p < oB1) {
+            const uint32_t r = p / 8, j = p % 8;
+            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd1[b][r], sx[b][j], g);
+        } else if (p < oW2) {
+            const uint32_t r = p - oB1;
+            for (uint32_t b = 0; b < kGrp; ++b) g += sd1[b][r];
+        } else if (p < oB2) {
+            const uint32_t r = (p - oW2) / kH, j = (p - oW2) % kH;
+            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd2[b][r], sh1[b][j], g);
+        } else if (p < oW3) {
+            const uint32_t r = p - oB2;
+            for (uint32_t b = 0; b < kGrp; ++b) g += sd2[b][r];
+        } else if (p < oB3) {
+            const uint32_t r = p - oW3;
+            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd3[b], sh2[b][r], g);
+        } else {
+            for (uint32_t b = 0; b < kGrp; ++b) g += sd3[b];
+        }
+        out[p] = g;
+    }
+}
+
+// Final Adam update after `steps` steps: weights land in buffer (steps & 1).
+__device__ void learn_final_update(const LearnCtx& c, uint32_t slot, uint32_t steps, float lr,
+                                   float* w_lds) {
+    const uint32_t prev = (steps + 1) & 1u, cur = steps & 1u;
+    for (uint32_t p = threadIdx.x; p < kNP; p += blockDim.x) {
+        float g = 0.0f;
+        for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, slot, prev, q)[p];
+        float m1 = m1buf(c, slot, prev)[p], m2 = m2buf(c, slot, prev)[p];
+        const float wv = adam(wbuf(c, slot, prev)[p], g, m1, m2, steps, lr);
+        if (w_lds) w_lds[p] = wv;
+        wbuf(c, slot, cur)[p] = wv;
+    }
+}
+
+// leading bytes shared by a sorted sample of m keys (at most 7)
+__device__ __forceinline__ uint32_t sample_shift(const uint64_t* smp, uint32_t m) {
+    const uint64_t x = smp[0] ^ smp[m - 1];
+    const uint32_t c = x ? (uint32_t)__builtin_clzll((unsigned long long)x) >> 3 : 8u;
+    return c < 7 ? c : 7u;
+}
+
+// initial weights into buffer 1 (read by step 0 as "previous") and the feature shift
+__global__ __launch_bounds__(256) void k_learn_init(LearnCtx c, uint64_t seed) {
+    const uint32_t slot = blockIdx.x;
+    for (uint32_t p = threadIdx.x; p < kNP; p += blockDim.x) wbuf(c, slot, 1)[p] = init_weight(seed, p);
+    if (threadIdx.x == 0) c.shift[slot] = sample_shift(c.samples + (size_t)slot * kLearnM, c.m);
+}
+
+__global__ __launch_bounds__(256) void k_learn_final(LearnCtx c, uint32_t steps, float lr) {
+    learn_final_update(c, blockIdx.x, steps, lr, nullptr);
+}
+
+// ---------------------------------------------------------------------------
+// in-sort path: sample + sort, then propose splitters and build the tree
+
+__global__ __launch_bounds__(256) void k_learn_prep(LearnCtx c, const LSeg* lseg,
+                                                    const uint32_t* learn_seg,
+                                                    const uint64_t* key_in, uint64_t seed) {
+    __shared__ uint64_t smp[kLearnM];
+    const uint32_t slot = blockIdx.x;
+    const LSeg g = lseg[learn_seg[slot]];
+    const uint64_t sseed = mix64(seed ^ 0x5A5A5A5A5A5A5A5Aull ^ mix64(((uint64_t)g.begin << 32) | g.depth));
+    for (uint32_t r = threadIdx.x; r < kLearnM; r += blockDim.x) {
+        const uint64_t h = mix64(sseed + 0x9E3779B97F4A7C15ull * (r + 1));
+        smp[r] = key_in[g.begin + (uint32_t)(((h >> 32) * (uint64_t)g.size) >> 32)];
+    }
+    __syncthreads();
+    for (uint32_t kk = 2; kk <= kLearnM; kk <<= 1) {
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = threadIdx.x; i < kLearnM / 2; i += blockDim.x) {
+                const uint32_t lo = 2 * i - (i & (j - 1)), hi = lo + j;
+                const bool up = (lo & kk) == 0;
+                const uint64_t a = smp[lo], b = smp[hi];
+                if ((a > b) == up) {
+                    smp[lo] = b;
+                    smp[hi] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (uint32_t r = threadIdx.x; r < kLearnM; r += blockDim.x) c.samples[(size_t)slot * kLearnM + r] = smp[r];
+    for (uint32_t p = threadIdx.x; p < kNP; p += blockDim.x) wbuf(c, slot, 1)[p] = init_weight(seed, p);
+    if (threadIdx.x == 0) c.shift[slot] = sample_shift(smp, kLearnM);
+}
+
+// running maximum of F over kLearnM values by 256 threads (16 consecutive each)
+__global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, const LSeg* lseg,
+                                                      const uint32_t* learn_seg, uint32_t steps,
+                                                      float lr, uint64_t* tree_lo,
+                                                      uint64_t* tree_in, uint8_t* tree_lcp) {
+    __shared__ float w[kNPS];
+    __shared__ float F[kLearnM];
+    __shared__ uint64_t spl[1u << kDMax];
+    __shared__ float tmx[256];
+    const uint32_t slot = blockIdx.x, tid = threadIdx.x;
+    const LSeg g = lseg[learn_seg[slot]];
+    learn_final_update(c, slot, steps, lr, w);
+    __syncthreads();
+    const uint64_t* smp = c.samples + (size_t)slot * kLearnM;
+    constexpr uint32_t per = kLearnM / 256;
+    float run = 0.0f;
+    for (uint32_t e = 0; e < per; ++e) {
+        float x[8];
+        key_features(smp[tid * per + e], c.shift[slot], x);
+        const float y = mlp_forward(w, x, nullptr, nullptr);
+        run = y > run ? y : run;
+        F[tid * per + e] = run;
+    }
+    tmx[tid] = run;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        const float o = tid >= off ? tmx[tid - off] : 0.0f;
+        __syncthreads();
+        if (o > tmx[tid]) tmx[tid] = o;
+        __syncthreads();
+    }
+    const float before = tid ? tmx[tid - 1] : 0.0f;
+    for (uint32_t e = 0; e < per; ++e)
+        if (F[tid * per + e] < before) F[tid * per + e] = before;
+    __syncthreads();
+    // splitter j-1 at the first sample whose monotone CDF reaches j / (v + 1)
+    for (uint32_t j = tid + 1; j <= g.v; j += 256) {
+        const float q = (float)j / (float)(g.v + 1);
+        uint32_t lo = 0, hi = kLearnM;
+        while (lo < hi) {
+            const uint32_t md = (lo + hi) >> 1;
+            if (F[md] < q) lo = md + 1; else hi = md;
+        }
+        spl[j - 1] = smp[lo < kLearnM ? lo : kLearnM - 1];
+    }
+    __syncthreads();
+    uint64_t* lo_out = tree_lo + g.tree_base;
+    uint64_t* in_out = tree_in + g.tree_base;
+    uint8_t* lcp_out = tree_lcp + g.tree_base;
+    for (uint32_t j = tid; j <= g.v; j += 256) {
+        if (j < g.v) {
+            const uint64_t x = spl[j];
+            lo_out[inorder_node(j, g.d)] = x;
+            in_out[j] = x;
+            uint8_t l = 0;
+            if (j > 0 && spl[j - 1] != x)
+                l = (uint8_t)(__builtin_clzll((unsigned long long)(spl[j - 1] ^ x)) >> 3);
+            lcp_out[j] = l;
+        } else {
+            lo_out[0] = 0;
+            in_out[j] = 0;
+            lcp_out[j] = 0;
+        }
+    }
+}
+
+// Largest range bucket of every learned segment against beta * |S| / (v + 1);
+// an imbalanced segment is switched back to sampled splitters.
+__global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t* learn_seg,
+                                                     const uint32_t* cs, float beta,
+                                                     Globals* glob) {
+    __shared__ uint32_t smax;
+    const uint32_t si = learn_seg[blockIdx.x];
+    const LSeg g = lseg[si];
+    if (threadIdx.x == 0) smax = 0;
+    __syncthreads();
+    uint32_t mx = 0;
+    for (uint32_t b = threadIdx.x * 2; b < g.k; b += 2 * 256) {
+        uint32_t t = 0;
+        for (uint32_t q = 0; q < g.chunks; ++q) t += cs[g.cs_base + (uint64_t)q * g.k + b];
+        mx = t > mx ? t : mx;
+    }
+    atomicMax(&smax, mx);
+    __syncthreads();
+    if (threadIdx.x == 0 && (double)smax > (double)beta * g.size / (g.v + 1)) {
+        lseg[si].pad0 = 0xFFFFFFFFu;
+        atomicAdd(&glob->fallbacks, 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// building blocks for callers and step-level checks
+
+__global__ __launch_bounds__(256) void k_mlp_eval(const float* w, const uint64_t* keys, uint32_t n,
+                                                  uint32_t shift, float* out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float x[8];
+    key_features(keys[i], shift, x);
+    out[i] = mlp_forward(w, x, nullptr, nullptr);
+}
+
+__global__ __launch_bounds__(256) void k_learn_sum(LearnCtx c, uint32_t b, float* out) {
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < kNP; p += gridDim.x * blockDim.x) {
+        float g = 0.0f;
+        for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, 0, b, q)[p];
+        out[p] = g;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side launchers
+
+size_t learn_bytes(uint32_t slots, uint32_t groups) {
+    return (size_t)slots * kLearnM * 8 + (size_t)slots * 2 * kNPS * 4 * 3 +
+           (size_t)slots * 2 * groups * kNPS * 4 + (size_t)slots * 4;
+}
+
+LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m) {
+    LearnCtx c;
+    char* p = (char*)mem;
+    c.samples = (uint64_t*)p;
+    p += (size_t)slots * kLearnM * 8;
+    c.W = (float*)p;
+    p += (size_t)slots * 2 * kNPS * 4;
+    c.M1 = (float*)p;
+    p += (size_t)slots * 2 * kNPS * 4;
+    c.M2 = (float*)p;
+    p += (size_t)slots * 2 * kNPS * 4;
+    c.part = (float*)p;
+    p += (size_t)slots * 2 * (m / kGrp) * kNPS * 4;
+    c.shift = (uint32_t*)p;
+    c.m = m;
+    c.groups = m / kGrp;
+    return c;
+}
+
+void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, const LSeg* lseg,
+                             const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
+                             uint32_t steps, float lr, uint64_t* tree_lo, uint64_t* tree_in,
+                             uint8_t* tree_lcp, hipStream_t st) {
+    hipLaunchKernelGGL(k_learn_prep, dim3(slots), dim3(256), 0, st, c, lseg, learn_seg, key_in, seed);
+    for (uint32_t s = 0; s < steps; ++s)
+        hipLaunchKernelGGL(k_learn_step, dim3(c.groups, slots), dim3(kGrp), 0, st, c, s, lr);
+    hipLaunchKernelGGL(k_learn_finish, dim3(slots), dim3(256), 0, st, c, lseg, learn_seg, steps, lr,
+                       tree_lo, tree_in, tree_lcp);
+}
+
+void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,
+                        float beta, Globals* glob, hipStream_t st) {
+    hipLaunchKernelGGL(k_learn_check, dim3(slots), dim3(256), 0, st, lseg, learn_seg, cs, beta, glob);
+}
+
+// train on caller-sorted keys (slot 0); final weights copied to out
+void launch_mlp_train(const LearnCtx& c, const uint64_t* sorted_keys, uint32_t m, uint32_t steps,
+                      float lr, uint64_t seed, float* out, hipStream_t st) {
+    (void)hipMemcpyAsync(c.samples, sorted_keys, (size_t)m * 8, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_learn_init, dim3(1), dim3(256), 0, st, c, seed);
+    for (uint32_t s = 0; s < steps; ++s)
+        hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, s, lr);
+    if (steps) {
+        hipLaunchKernelGGL(k_learn_final, dim3(1), dim3(256), 0, st, c, steps, lr);
+        (void)hipMemcpyAsync(out, c.W + (size_t)(steps & 1u) * kNPS, kNP * 4, hipMemcpyDeviceToDevice, st);
+    } else {
+        (void)hipMemcpyAsync(out, c.W + kNPS, kNP * 4, hipMemcpyDeviceToDevice, st);
+    }
+}
+
+// gradient at `params` over caller-sorted keys (slot 0)
+void launch_mlp_grad(const LearnCtx& c, const float* params, const uint64_t* sorted_keys,
+                     uint32_t m, float* out, hipStream_t st) {
+    (void)hipMemcpyAsync(c.samples, sorted_keys, (size_t)m * 8, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_learn_init, dim3(1), dim3(256), 0, st, c, 0ull);
+    (void)hipMemcpyAsync(c.W + kNPS, params, kNP * 4, hipMemcpyDeviceToDevice, st);
+    hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, 0u, 0.0f);
+    hipLaunchKernelGGL(k_learn_sum, dim3(8), dim3(256), 0, st, c, 0u, out);
+}
+
+void launch_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint32_t shift,
+                     float* out, hipStream_t st) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_mlp_eval, dim3((n + 255) / 256), dim3(256), 0, st, params, keys, n, shift,
+                       out);
+}
+
+}  // namespace s5

@@ -19,7 +19,7 @@ SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched", "s5_stats_get",
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
-           "s5_profile_read")
+           "s5_profile_read", "s5_mlp_train", "s5_mlp_grad", "s5_mlp_eval")
 
 
 class Config(ctypes.Structure):
@@ -74,10 +74,14 @@ def load(path: str = LIB_PATH):
     lib.s5_release.restype = None
     lib.s5_prefix_keys.argtypes = [P, P, U32, U32, P, P]
     lib.s5_classify.argtypes = [P, U32, P, U32, P, P]
+    lib.s5_mlp_train.argtypes = [P, U32, U32, ctypes.c_float, U64, P, P]
+    lib.s5_mlp_grad.argtypes = [P, P, U32, P, P]
+    lib.s5_mlp_eval.argtypes = [P, P, U32, U32, P, P]
     lib.s5_profile_enable.argtypes = [ctypes.c_int]
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
     for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_stats_get", "s5_prefix_keys",
-              "s5_classify", "s5_profile_enable", "s5_profile_read"):
+              "s5_classify", "s5_profile_enable", "s5_profile_read", "s5_mlp_train", "s5_mlp_grad",
+              "s5_mlp_eval"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -211,4 +215,30 @@ def profile_read() -> dict:
         e = arr[i]
         out[e.name.decode()] = {"launches": e.launches, "total_ms": e.total_ms,
                                 "items": e.items, "alg_bytes": e.alg_bytes}
+    return out
+
+
+N_MLP_PARAMS = 1377
+
+
+def mlp_train(sorted_keys: torch.Tensor, steps: int, lr: float, seed: int, stream=None):
+    """Train the learned-splitter model on sorted uint64 keys; returns 1377 float32 params."""
+    out = torch.empty(N_MLP_PARAMS, dtype=torch.float32, device=sorted_keys.device)
+    _check(load().s5_mlp_train(_dev(sorted_keys, torch.uint64, "sorted_keys"), sorted_keys.numel(),
+                               steps, lr, seed, _dev(out, torch.float32, "out"), _stream(stream)))
+    return out
+
+
+def mlp_grad(params: torch.Tensor, sorted_keys: torch.Tensor, stream=None):
+    out = torch.empty(N_MLP_PARAMS, dtype=torch.float32, device=sorted_keys.device)
+    _check(load().s5_mlp_grad(_dev(params, torch.float32, "params"),
+                              _dev(sorted_keys, torch.uint64, "sorted_keys"), sorted_keys.numel(),
+                              _dev(out, torch.float32, "out"), _stream(stream)))
+    return out
+
+
+def mlp_eval(params: torch.Tensor, keys: torch.Tensor, shift: int = 0, stream=None):
+    out = torch.empty(keys.numel(), dtype=torch.float32, device=keys.device)
+    _check(load().s5_mlp_eval(_dev(params, torch.float32, "params"), _dev(keys, torch.uint64, "keys"),
+                              keys.numel(), shift, _dev(out, torch.float32, "out"), _stream(stream)))
     return out

@@ -98,3 +98,11 @@ def test_entropy_and_imbalance():
     sizes = np.array([10, 0, 10, 0, 100])
     assert mlp_ref.imbalanced(sizes, v=2, size=120, beta=2.0)
     assert not mlp_ref.imbalanced(sizes, v=2, size=120, beta=3.0)
+
+
+def test_prefix_shift_and_features():
+    k = np.array([0x6161610000000000, 0x6161620000000000], dtype=np.uint64)
+    assert mlp_ref.prefix_shift(k) == 2
+    assert mlp_ref.prefix_shift(np.array([5, 5], dtype=np.uint64)) == 7
+    f = mlp_ref.features(k, 2)
+    assert np.allclose(f[:, 0] * 255, [0x61, 0x62]) and np.allclose(f[:, 1:], 0)
