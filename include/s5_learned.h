@@ -8,12 +8,17 @@
  * segment of >= 65536 strings with a small network trained on 4096 sampled
  * keys and places the splitters at its quantiles; classification remains the
  * exact comparison of Section 3.1, so the output never depends on the model.
- * The calls below expose the same model, training and evaluation code.
+ * A proposal is replaced by sampled splitters if a range bucket holds more
+ * than imbalance_bound times its ideal share |S|/(v+1), counted first on the
+ * training sample and then on the exact bucket histogram (s5_stats.fallbacks
+ * counts both).  The calls below expose the same model, training and
+ * evaluation code.
  *
- * Model: features = the key's 8 bytes / 255 (most significant first) after
- * dropping the `shift` leading bytes that the whole training sample shares
- * (shift = common leading bytes of its smallest and largest key, at most 7);
- * two hidden layers of 32 ReLU units; sigmoid output.  Parameters (1377 floats):
+ * Model: one feature per key byte b (most significant first),
+ * (c_b - lo_b) / max(hi_b - lo_b, 1), where lo and hi hold the byte-wise
+ * minimum and maximum over the training keys (packed like the keys; lo = 0,
+ * hi = ~0 gives plain c_b / 255); two hidden layers of 32 ReLU units; sigmoid
+ * output.  Parameters (1377 floats):
  * W1 (32x8, row major), b1 (32), W2 (32x32), b2 (32), w3 (32), b3 (1).
  * Initial weights: splitmix64 as a counter-based generator, parameter i gets
  * (2u - 1) * a with u = top 24 bits of splitmix64(seed + i + 1) / 2^24 and
@@ -33,22 +38,25 @@
 extern "C" {
 #endif
 
-/* Train from the initial weights of `seed` on m sorted keys (64 <= m <= 4096,
- * m a multiple of 64) for `steps` Adam steps of learning rate lr; the 1377
- * final parameters go to out_params.  Returns S5_OK or S5_ERR_INVALID. */
+/* Train from the initial weights of `seed` on m sorted keys (256 <= m <= 4096,
+ * m a multiple of 256; features scaled by the keys' own byte-wise range) for
+ * `steps` Adam steps of learning rate lr; the 1377 final parameters go to
+ * out_params.  Synchronizes the stream.  Returns S5_OK, S5_ERR_INVALID (bad m,
+ * NULL pointer, steps > 100000), S5_ERR_NOMEM or S5_ERR_HIP. */
 int s5_mlp_train(const uint64_t* sorted_keys, uint32_t m, uint32_t steps, float lr,
                  uint64_t seed, float* out_params, hipStream_t stream);
 
 /* Gradient of the mean squared error at `params` over m sorted keys (same
- * constraints on m, features shifted as in training) into out_grad (1377
- * floats). */
+ * constraints on m, features scaled as in training) into out_grad (1377
+ * floats).  Synchronizes the stream; same return codes. */
 int s5_mlp_grad(const float* params, const uint64_t* sorted_keys, uint32_t m, float* out_grad,
                 hipStream_t stream);
 
-/* Model output (estimated CDF) for n keys into out (n floats); shift (0..7)
- * as used in training. */
-int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint32_t shift, float* out,
-                hipStream_t stream);
+/* Model output (estimated CDF) for n keys into out (n floats), features
+ * scaled by the byte-wise range (lo, hi).  Asynchronous; returns S5_OK,
+ * S5_ERR_INVALID (NULL pointer with n > 0) or S5_ERR_HIP. */
+int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo, uint64_t hi,
+                float* out, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -9,12 +9,14 @@ distribution function with a small network and places splitters at its
 quantiles; classification stays the exact key comparison of Section 3.1, so the
 sort's output never depends on the model.
 
-Model (fixed by the build, see the design notes): 8 input features, the key's
-bytes divided by 255 (most significant byte first) after dropping the bytes
-that every key of the sample shares (the shift: common leading bytes of the
-smallest and largest sampled key, at most 7); two hidden layers of 32
-ReLU units; one sigmoid output, the estimated CDF.  1377 parameters in this
-order: W1 (32x8, row major), b1 (32), W2 (32x32), b2 (32), w3 (32), b3 (1).
+Model (fixed by the build, see the design notes): 8 input features, one per
+key byte (most significant first), each scaled by the range that byte takes
+over the training sample: x_b = (c_b - lo_b) / max(hi_b - lo_b, 1) with lo_b
+and hi_b the smallest and largest value of byte b among the sampled keys (so a
+byte every sampled key shares is a constant 0, and lo = 0, hi = 255 gives the
+plain c_b / 255); two hidden layers of 32 ReLU units; one sigmoid output, the
+estimated CDF.  1377 parameters in this order: W1 (32x8, row major), b1 (32),
+W2 (32x32), b2 (32), w3 (32), b3 (1).
 
 Initialisation draws uniform numbers from splitmix64 (Steele, Lea and Flood,
 2014) used as a counter-based generator: u_i = top 24 bits of
@@ -71,20 +73,31 @@ def unpack(p: np.ndarray):
     return {k: p[o:o + int(np.prod(s))].reshape(s) for k, (o, s) in SLICES.items()}
 
 
-def prefix_shift(sorted_keys: np.ndarray) -> int:
-    """Leading bytes shared by every key of a sorted sample (at most 7)."""
-    x = int(sorted_keys[0]) ^ int(sorted_keys[-1])
-    return min(7, (64 - x.bit_length()) // 8)
-
-
-def features(keys: np.ndarray, shift: int = 0) -> np.ndarray:
-    """(n, 8) features: bytes of the big-endian 64-bit keys, the first `shift`
-    bytes dropped (zeros shifted in), / 255."""
+def key_bytes(keys: np.ndarray) -> np.ndarray:
+    """(n, 8) bytes of big-endian 64-bit keys, most significant first."""
     keys = np.asarray(keys, dtype=np.uint64)
-    if shift:
-        keys = keys << np.uint64(8 * shift)
     shifts = np.arange(56, -8, -8, dtype=np.uint64)
-    return ((keys[:, None] >> shifts[None, :]) & np.uint64(0xFF)).astype(np.float64) / 255.0
+    return ((keys[:, None] >> shifts[None, :]) & np.uint64(0xFF)).astype(np.int64)
+
+
+def pack_bytes(b) -> int:
+    return int(sum(int(v) << (56 - 8 * i) for i, v in enumerate(b)))
+
+
+def feature_range(sample_keys: np.ndarray):
+    """(lo, hi): byte-wise minimum and maximum over the sample, each packed
+    into a 64-bit word like the keys."""
+    b = key_bytes(sample_keys)
+    return pack_bytes(b.min(axis=0)), pack_bytes(b.max(axis=0))
+
+
+def features(keys: np.ndarray, lo: int = 0, hi: int = MASK64) -> np.ndarray:
+    """(n, 8) features: byte b of every key minus byte b of lo, divided by
+    max(byte b of hi - byte b of lo, 1)."""
+    c = key_bytes(keys).astype(np.float64)
+    lb = key_bytes(np.array([lo], dtype=np.uint64))[0].astype(np.float64)
+    hb = key_bytes(np.array([hi], dtype=np.uint64))[0].astype(np.float64)
+    return (c - lb) / np.maximum(hb - lb, 1.0)
 
 
 def forward(p: np.ndarray, x: np.ndarray):
@@ -138,7 +151,7 @@ def cdf_targets(m: int) -> np.ndarray:
 def train(sorted_keys: np.ndarray, steps: int, lr: float, seed: int):
     """Full-batch Adam on the empirical CDF of a sorted sample; returns
     (params, losses) with losses[s] the loss before step s+1 and a final one."""
-    x = features(sorted_keys, prefix_shift(sorted_keys))
+    x = features(sorted_keys, *feature_range(sorted_keys))
     t = cdf_targets(len(sorted_keys))
     p = init_params(seed)
     m1 = np.zeros_like(p)
@@ -164,8 +177,26 @@ def quantile_splitters(cdf: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.n
 def propose(p: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
     """v splitters (sorted, may repeat) at the quantiles j/(v+1) of the model's
     monotone CDF over the sorted sample."""
-    y, _ = forward(p, features(sorted_keys, prefix_shift(sorted_keys)))
+    y, _ = forward(p, features(sorted_keys, *feature_range(sorted_keys)))
     return quantile_splitters(y, sorted_keys, v)
+
+
+def sample_imbalance(splitters: np.ndarray, sorted_keys: np.ndarray) -> int:
+    """Largest number of sample keys strictly between two consecutive splitters
+    (or below the first, or above the last): the range buckets the proposal
+    would make, counted on the sample itself."""
+    s = np.asarray(splitters, dtype=np.uint64)
+    k = np.asarray(sorted_keys, dtype=np.uint64)
+    lower = np.searchsorted(k, s, side="left")   # keys < s_j
+    upper = np.searchsorted(k, s, side="right")  # keys <= s_j
+    gaps = np.concatenate([[lower[0]], lower[1:] - upper[:-1], [len(k) - upper[-1]]])
+    return int(np.max(np.maximum(gaps, 0)))
+
+
+def sample_imbalanced(splitters: np.ndarray, sorted_keys: np.ndarray, v: int, beta: float) -> bool:
+    """The proposal is rejected before classification if a range bucket of the
+    sample alone holds more than beta times the ideal share m / (v + 1)."""
+    return sample_imbalance(splitters, sorted_keys) > beta * len(sorted_keys) / (v + 1)
 
 
 def imbalanced(bucket_sizes: np.ndarray, v: int, size: int, beta: float) -> bool:

@@ -49,19 +49,10 @@ void launch_lcp_fix(const uint8_t*, const uint64_t*, const uint64_t*, uint32_t, 
                     const uint32_t*, uint32_t*, hipStream_t);
 void launch_classify_plain(const uint64_t*, uint32_t, const uint64_t*, uint32_t, uint32_t,
                            uint64_t*, uint64_t*, uint16_t*, hipStream_t);
-struct LearnCtx {
-    uint64_t* samples;
-    float* W;
-    float* M1;
-    float* M2;
-    float* part;
-    uint32_t* shift;
-    uint32_t m, groups;
-};
-size_t learn_bytes(uint32_t slots, uint32_t groups);
+size_t learn_bytes(uint32_t slots, uint32_t m);
 LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m);
-void launch_learn_sort_trees(const LearnCtx&, uint32_t, const LSeg*, const uint32_t*,
-                             const uint64_t*, uint64_t, uint32_t, float, uint64_t*, uint64_t*,
+void launch_learn_sort_trees(const LearnCtx&, uint32_t, LSeg*, const uint32_t*, const uint64_t*,
+                             uint64_t, uint32_t, float, float, Globals*, uint64_t*, uint64_t*,
                              uint8_t*, hipStream_t);
 void launch_learn_check(uint32_t, LSeg*, const uint32_t*, const uint32_t*, float, Globals*,
                         hipStream_t);
@@ -69,7 +60,8 @@ void launch_mlp_train(const LearnCtx&, const uint64_t*, uint32_t, uint32_t, floa
                       float*, hipStream_t);
 void launch_mlp_grad(const LearnCtx&, const float*, const uint64_t*, uint32_t, float*,
                      hipStream_t);
-void launch_mlp_eval(const float*, const uint64_t*, uint32_t, uint32_t, float*, hipStream_t);
+void launch_mlp_eval(const float*, const uint64_t*, uint32_t, uint64_t, uint64_t, float*,
+                     hipStream_t);
 }  // namespace s5
 
 using namespace s5;
@@ -77,8 +69,8 @@ using namespace s5;
 namespace {
 
 // learned splitters: samples per segment, Adam steps and learning rate
-constexpr uint32_t kLearnSamples = 4096, kLearnSteps = 64;
-constexpr float kLearnRate = 0.01f;
+constexpr uint32_t kLearnSamples = kLearnM, kLearnSteps = 64;
+constexpr float kLearnRate = 0.03f;
 
 struct Cfg {
     uint32_t dmax, alpha, unroll, tile_min, T, mode;
@@ -165,7 +157,7 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     L.base_list = take((size_t)(cp.base[0] + cp.base[1] + cp.base[2]) * sizeof(Seg));
     // learned splitters: one slot per segment of >= kLearnMin strings in a pass
     L.learn_cap = c.mode == S5_SPLIT_LEARNED ? (uint32_t)std::min<uint64_t>(large, n / kLearnMin + 1) : 0u;
-    L.learn = take(learn_bytes(L.learn_cap, kLearnSamples / 64));
+    L.learn = take(learn_bytes(L.learn_cap, kLearnSamples));
     L.learn_seg = take((size_t)L.learn_cap * 4);
     // [counters 0 | globals | counters 1] back to back: one copy reads a pass's
     // counters together with the globals
@@ -373,17 +365,20 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         const Counters now = *hc;
         const uint32_t kmax = now.kmax, vmax = (kmax - 1) / 2;
         const int nxt = cur ^ 1;
-        timed(K_SAMPLE, now.n_large, st, [&] {
-            launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
-                               tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
-        });
+        // learned proposals first: a proposal that fails on its own sample is
+        // switched back to sampled splitters before the sampled trees are built
         const uint32_t n_learn = std::min(now.pad0, L.learn_cap);
         if (n_learn) {
             timed(K_LEARN, n_learn, st, [&] {
                 launch_learn_sort_trees(lctx, n_learn, lseg[cur], learn_seg, key[buf], c.seed,
-                                        kLearnSteps, kLearnRate, tree_lo, tree_in, tree_lcp, st);
+                                        kLearnSteps, kLearnRate, c.beta, glob, tree_lo, tree_in,
+                                        tree_lcp, st);
             });
         }
+        timed(K_SAMPLE, now.n_large, st, [&] {
+            launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
+                               tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
+        });
         timed(K_CLASSIFY, now.moved, st, [&] {
             launch_classify(now.tiles, c.unroll, lseg[cur], tile_tab, key[buf], tree_lo, tree_in,
                             bid, cm, vmax, kmax, st);
@@ -392,14 +387,14 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
               [&] { launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st); });
         if (n_learn) {
             // learned splitters that leave a range bucket too large are redone sampled
-            const uint32_t before = hg->fallbacks;
+            const uint32_t before = hg->late_fallbacks;
             launch_learn_check(n_learn, lseg[cur], learn_seg, cs, c.beta, glob, st);
             rc = readback(cur);
             if (rc) {
                 prof_collect();
                 return rc;
             }
-            if (hg->fallbacks != before) {
+            if (hg->late_fallbacks != before) {
                 timed(K_SAMPLE, now.n_large, st, [&] {
                     launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed,
                                        tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
@@ -630,14 +625,16 @@ int s5_profile_read(s5_kernel_profile* out, uint32_t max, uint32_t* count) {
 }
 
 
-static int mlp_check_m(uint32_t m) { return (m >= 64 && m <= 4096 && m % 64 == 0) ? S5_OK : S5_ERR_INVALID; }
+static int mlp_check_m(uint32_t m) {
+    return (m >= kLearnGrp && m <= kLearnM && m % kLearnGrp == 0) ? S5_OK : S5_ERR_INVALID;
+}
 
 int s5_mlp_train(const uint64_t* sorted_keys, uint32_t m, uint32_t steps, float lr, uint64_t seed,
                  float* out_params, hipStream_t stream) {
     if (!sorted_keys || !out_params || mlp_check_m(m) || steps > 100000) return S5_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_mu);
     DevPool* P = nullptr;
-    int rc = pool_get(learn_bytes(1, m / 64), &P);
+    int rc = pool_get(learn_bytes(1, m), &P);
     if (rc) return rc;
     launch_mlp_train(learn_ctx(P->ptr, 1, m), sorted_keys, m, steps, lr, seed, out_params, stream);
     if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
@@ -649,18 +646,17 @@ int s5_mlp_grad(const float* params, const uint64_t* sorted_keys, uint32_t m, fl
     if (!params || !sorted_keys || !out_grad || mlp_check_m(m)) return S5_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_mu);
     DevPool* P = nullptr;
-    int rc = pool_get(learn_bytes(1, m / 64), &P);
+    int rc = pool_get(learn_bytes(1, m), &P);
     if (rc) return rc;
     launch_mlp_grad(learn_ctx(P->ptr, 1, m), params, sorted_keys, m, out_grad, stream);
     if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
     return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;
 }
 
-int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint32_t shift, float* out,
-                hipStream_t stream) {
+int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo, uint64_t hi,
+                float* out, hipStream_t stream) {
     if (n > 0 && (!params || !keys || !out)) return S5_ERR_INVALID;
-    if (shift > 7) return S5_ERR_INVALID;
-    launch_mlp_eval(params, keys, n, shift, out, stream);
+    launch_mlp_eval(params, keys, n, lo, hi, out, stream);
     return hipGetLastError() == hipSuccess ? S5_OK : S5_ERR_HIP;
 }
 

@@ -70,11 +70,25 @@ struct Globals {
     uint32_t status;                // error bits
     unsigned long long base_elems;  // strings in those items
     uint32_t fallbacks;             // learned segments redone with sampled splitters
-    uint32_t pad;
+    uint32_t late_fallbacks;        // those of them rejected only on the exact histogram
 };
 
 // Learned splitters apply to segments of at least this many strings.
 constexpr uint32_t kLearnMin = 65536;
+constexpr uint32_t kLearnM = 4096;    // sampled keys per learned segment, at most
+constexpr uint32_t kLearnGrp = 256;   // samples per training workgroup (one per thread)
+
+// Learned-splitter state of all learned segments of one pass (one slot each).
+struct LearnCtx {
+    uint64_t* samples;  // [slot][kLearnM] sorted sampled keys
+    float* W;           // [slot][2][stride] weights, double-buffered by step parity
+    float* M1;          // [slot][2][stride] Adam first moments
+    float* M2;          // [slot][2][stride] Adam second moments
+    float* part;        // [slot][2][groups][stride] partial gradients of the workgroups
+    uint64_t* range;    // [slot][2] byte-wise minimum and maximum of the sample
+    uint32_t m;         // samples per slot (multiple of kLearnGrp, <= kLearnM)
+    uint32_t groups;    // m / kLearnGrp
+};
 
 // Capacities of the per-pass storage.
 struct Caps {

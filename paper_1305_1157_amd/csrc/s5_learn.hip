@@ -5,42 +5,34 @@
 // bucket sizes (appendix A, "Adaptivity").  Here a small network models the
 // distribution function of a segment's 8-byte keys and its quantiles become
 // the splitters.  Classification is still the exact key comparison of
-// Section 3.1, so the sort's output never depends on the model; a segment
-// whose learned splitters leave a range bucket too large is redone with
-// sampled splitters.
+// Section 3.1, so the sort's output never depends on the model.  A proposal
+// is rejected, and the segment gets sampled splitters, if a range bucket holds
+// more than beta times its ideal share: first counted on the training sample
+// itself (before any classification), then on the exact bucket histogram.
 //
-// Model: features = the key's 8 bytes / 255 (most significant first); two
+// Model: one feature per key byte (most significant first), scaled by the
+// range that byte takes over the sample, (c - lo) / max(hi - lo, 1); two
 // hidden layers of 32 ReLU units; sigmoid output.  1377 parameters:
 // W1 (32x8), b1, W2 (32x32), b2, w3 (32), b3.  Weights start from splitmix64
 // used as a counter-based generator; training is full-batch mean squared
 // error against the sample's empirical CDF, optimised with Adam.  One step is
-// one launch: 64-sample groups compute partial gradients in parallel; every
-// group of the next step sums the previous partials in the same fixed order
-// and applies the identical Adam update, so the result is deterministic.
+// one launch: 256-sample workgroups compute partial gradients in parallel;
+// every workgroup of the next step sums the previous partials in the same
+// fixed order and applies the identical Adam update, so the result is
+// deterministic.
 #include "s5_internal.h"
 #include "s5_word.h"
 
 namespace s5 {
 
-constexpr uint32_t kLearnM = 4096;    // sampled keys per learned segment
-constexpr uint32_t kGrp = 64;         // samples per training workgroup (one per lane)
+constexpr uint32_t kGrp = kLearnGrp;  // samples per training workgroup (one per thread)
 constexpr int kH = 32;                // hidden units per layer
 constexpr uint32_t kNP = 1377;        // parameters
 constexpr uint32_t kNPS = 1408;       // stride of one parameter vector
 constexpr uint32_t oW1 = 0, oB1 = 256, oW2 = 288, oB2 = 1312, oW3 = 1344, oB3 = 1376;
 constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
-
-// Learned-splitter state of all learned segments of one pass.
-struct LearnCtx {
-    uint64_t* samples;  // [slot][kLearnM] sorted sampled keys
-    float* W;           // [slot][2][kNPS] weights, double-buffered by step parity
-    float* M1;          // [slot][2][kNPS] Adam first moments
-    float* M2;          // [slot][2][kNPS] Adam second moments
-    float* part;        // [slot][2][groups][kNPS] partial gradients
-    uint32_t* shift;    // [slot] leading bytes shared by the whole sample (dropped from features)
-    uint32_t m;         // samples per slot (multiple of kGrp, <= kLearnM)
-    uint32_t groups;    // m / kGrp
-};
+constexpr uint32_t kS = kH + 1;       // LDS row stride of per-sample vectors
+constexpr uint32_t kS4 = kH + 4;      // same, 16-byte aligned rows (read four at a time)
 
 __device__ __forceinline__ float* wbuf(const LearnCtx& c, uint32_t slot, uint32_t b) {
     return c.W + ((size_t)slot * 2 + b) * kNPS;
@@ -67,10 +59,52 @@ __device__ __forceinline__ float init_weight(uint64_t seed, uint32_t i) {
     return (2.0f * u - 1.0f) * a;
 }
 
-__device__ __forceinline__ void key_features(uint64_t k, uint32_t shift, float (&x)[8]) {
-    k = shift ? k << (8 * shift) : k;
+__device__ __forceinline__ uint32_t byte_at(uint64_t k, int b) {
+    return (uint32_t)(k >> (56 - 8 * b)) & 0xFFu;
+}
+
+// byte b of k minus byte b of lo, over max(byte b of hi - byte b of lo, 1)
+__device__ __forceinline__ void key_features(uint64_t k, uint64_t lo, uint64_t hi, float (&x)[8]) {
 #pragma unroll
-    for (int b = 0; b < 8; ++b) x[b] = (float)((k >> (56 - 8 * b)) & 0xFFull) * (1.0f / 255.0f);
+    for (int b = 0; b < 8; ++b) {
+        const int l = (int)byte_at(lo, b), w = (int)byte_at(hi, b) - l;
+        x[b] = (float)((int)byte_at(k, b) - l) / (float)(w > 1 ? w : 1);
+    }
+}
+
+__device__ __forceinline__ uint64_t bytes_minmax(uint64_t a, uint64_t b, bool take_max) {
+    uint64_t r = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const uint32_t x = byte_at(a, i), y = byte_at(b, i);
+        r |= (uint64_t)(take_max ? (x > y ? x : y) : (x < y ? x : y)) << (56 - 8 * i);
+    }
+    return r;
+}
+
+// byte-wise minimum and maximum of m keys into out[0], out[1] (256 threads)
+__device__ void sample_range(const uint64_t* smp, uint32_t m, uint64_t* out) {
+    __shared__ uint64_t rlo[256], rhi[256];
+    const uint32_t tid = threadIdx.x;
+    uint64_t lo = ~0ull, hi = 0;
+    for (uint32_t i = tid; i < m; i += 256) {
+        lo = bytes_minmax(lo, smp[i], false);
+        hi = bytes_minmax(hi, smp[i], true);
+    }
+    rlo[tid] = lo;
+    rhi[tid] = hi;
+    __syncthreads();
+    for (uint32_t off = 128; off > 0; off >>= 1) {
+        if (tid < off) {
+            rlo[tid] = bytes_minmax(rlo[tid], rlo[tid + off], false);
+            rhi[tid] = bytes_minmax(rhi[tid], rhi[tid + off], true);
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        out[0] = rlo[0];
+        out[1] = rhi[0];
+    }
 }
 
 // forward pass for one key with weights w (LDS or global); optional activations
@@ -111,27 +145,34 @@ __device__ __forceinline__ float adam(float w, float g, float& m1, float& m2, ui
     return w - lr * mh / (sqrtf(vh) + kEps);
 }
 
+// sum of the previous step's partial gradients for parameter p, fixed order
+__device__ __forceinline__ float summed_grad(const LearnCtx& c, uint32_t slot, uint32_t b,
+                                             uint32_t p) {
+    float g = 0.0f;
+#pragma unroll 8
+    for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, slot, b, q)[p];
+    return g;
+}
+
 // ---------------------------------------------------------------------------
 // one training step: update from the previous partial gradients, then the
-// partial gradients of this step's weights over this group's 64 samples.
+// partial gradients of this step's weights over this group's 256 samples.
 
-__global__ __launch_bounds__(64) void k_learn_step(LearnCtx c, uint32_t step, float lr) {
+__global__ __launch_bounds__(256) void k_learn_step(LearnCtx c, uint32_t step, float lr) {
     __shared__ float w[kNPS];
-    __shared__ float sx[kGrp][8];
-    __shared__ float sh1[kGrp][kH + 1];
-    __shared__ float sh2[kGrp][kH + 1];
-    __shared__ float sd1[kGrp][kH + 1];
-    __shared__ float sd2[kGrp][kH + 1];
+    __shared__ float sx[kGrp * 8];
+    __shared__ __align__(16) float sh1[kGrp * kS4];
+    __shared__ float sh2[kGrp * kS];  // later reused for the first layer's deltas
+    __shared__ float sd2[kGrp * kS];
     __shared__ float sd3[kGrp];
-    const uint32_t slot = blockIdx.y, grp = blockIdx.x, lane = threadIdx.x;
+    const uint32_t slot = blockIdx.y, grp = blockIdx.x, tid = threadIdx.x;
     const uint32_t prev = (step + 1) & 1u, cur = step & 1u;
     const float* wp = wbuf(c, slot, prev);
-    for (uint32_t p = lane; p < kNP; p += kGrp) {
+    for (uint32_t p = tid; p < kNP; p += kGrp) {
         float wv = wp[p];
         float m1 = 0.0f, m2 = 0.0f;
         if (step > 0) {
-            float g = 0.0f;
-            for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, slot, prev, q)[p];
+            const float g = summed_grad(c, slot, prev, p);
             m1 = m1buf(c, slot, prev)[p];
             m2 = m2buf(c, slot, prev)[p];
             wv = adam(wv, g, m1, m2, step, lr);
@@ -144,10 +185,11 @@ __global__ __launch_bounds__(64) void k_learn_step(LearnCtx c, uint32_t step, fl
         }
     }
     __syncthreads();
-    // forward and backward for this lane's sample
-    const uint32_t i = grp * kGrp + lane;
+    // forward and backward for this thread's sample
+    const uint32_t i = grp * kGrp + tid;
+    const uint64_t lo = c.range[2 * slot], hi = c.range[2 * slot + 1];
     float x[8];
-    key_features(c.samples[(size_t)slot * kLearnM + i], c.shift[slot], x);
+    key_features(c.samples[(size_t)slot * kLearnM + i], lo, hi, x);
     float h1[kH], h2[kH];
     const float y = mlp_forward(w, x, h1, h2);
     const float t = ((float)i + 0.5f) / (float)c.m;
@@ -158,43 +200,69 @@ __global__ __launch_bounds__(64) void k_learn_step(LearnCtx c, uint32_t step, fl
 #pragma unroll 4
     for (int r = 0; r < kH; ++r) {
         const float d2 = h2[r] > 0.0f ? d3 * w[oW3 + r] : 0.0f;
-        sd2[lane][r] = d2;
+        sd2[tid * kS + r] = d2;
 #pragma unroll
         for (int j = 0; j < kH; ++j) d1[j] = fmaf(d2, w[oW2 + r * kH + j], d1[j]);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) sx[lane][j] = x[j];
+    for (int j = 0; j < 8; ++j) sx[tid * 8 + j] = x[j];
 #pragma unroll
     for (int j = 0; j < kH; ++j) {
-        sh1[lane][j] = h1[j];
-        sh2[lane][j] = h2[j];
-        sd1[lane][j] = h1[j] > 0.0f ? d1[j] : 0.0f;
+        sh1[tid * kS4 + j] = h1[j];
+        sh2[tid * kS + j] = h2[j];
+        d1[j] = h1[j] > 0.0f ? d1[j] : 0.0f;
     }
-    sd3[lane] = d3;
+    sd3[tid] = d3;
     __syncthreads();
-    // partial gradients: every lane owns parameters lane, lane + 64, ...
     float* out = pbuf(c, slot, cur, grp);
-    for (uint32_t p = lane; p < kNP; p += kGrp) {
-        float g = 0.0f;
-        if (p < oB1) {
-            const uint32_t r = p / 8, j = p % 8;
-            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd1[b][r], sx[b][j], g);
-        } else if (p < oW2) {
-            const uint32_t r = p - oB1;
-            for (uint32_t b = 0; b < kGrp; ++b) g += sd1[b][r];
-        } else if (p < oB2) {
-            const uint32_t r = (p - oW2) / kH, j = (p - oW2) % kH;
-            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd2[b][r], sh1[b][j], g);
-        } else if (p < oW3) {
-            const uint32_t r = p - oB2;
-            for (uint32_t b = 0; b < kGrp; ++b) g += sd2[b][r];
-        } else if (p < oB3) {
-            const uint32_t r = p - oW3;
-            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd3[b], sh2[b][r], g);
-        } else {
-            for (uint32_t b = 0; b < kGrp; ++b) g += sd3[b];
+    // second and third layer: thread t owns W2[t / 8][4 (t % 8) .. +3] and one
+    // of b2, w3, b3 (t < 65)
+    {
+        const uint32_t r = tid >> 3, jq = (tid & 7u) << 2;
+        float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, g3 = 0.0f;
+        for (uint32_t b = 0; b < kGrp; ++b) {
+            const float d = sd2[b * kS + r];
+            const float4 h = *reinterpret_cast<const float4*>(&sh1[b * kS4 + jq]);
+            g0 = fmaf(d, h.x, g0);
+            g1 = fmaf(d, h.y, g1);
+            g2 = fmaf(d, h.z, g2);
+            g3 = fmaf(d, h.w, g3);
         }
-        out[p] = g;
+        float* o = out + oW2 + r * kH + jq;
+        o[0] = g0;
+        o[1] = g1;
+        o[2] = g2;
+        o[3] = g3;
+        if (tid < 32) {
+            float g = 0.0f;
+            for (uint32_t b = 0; b < kGrp; ++b) g += sd2[b * kS + tid];
+            out[oB2 + tid] = g;
+        } else if (tid < 64) {
+            float g = 0.0f;
+            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd3[b], sh2[b * kS + tid - 32], g);
+            out[oW3 + tid - 32] = g;
+        } else if (tid == 64) {
+            float g = 0.0f;
+            for (uint32_t b = 0; b < kGrp; ++b) g += sd3[b];
+            out[oB3] = g;
+        }
+    }
+    __syncthreads();
+    float* sd1 = sh2;
+#pragma unroll
+    for (int j = 0; j < kH; ++j) sd1[tid * kS + j] = d1[j];
+    __syncthreads();
+    // first layer: thread t owns W1[t / 8][t % 8], and b1[t] for t < 32
+    {
+        const uint32_t r = tid >> 3, j = tid & 7u;
+        float g = 0.0f;
+        for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd1[b * kS + r], sx[b * 8 + j], g);
+        out[oW1 + tid] = g;
+        if (tid < 32) {
+            float gb = 0.0f;
+            for (uint32_t b = 0; b < kGrp; ++b) gb += sd1[b * kS + tid];
+            out[oB1 + tid] = gb;
+        }
     }
 }
 
@@ -203,8 +271,7 @@ __device__ void learn_final_update(const LearnCtx& c, uint32_t slot, uint32_t st
                                    float* w_lds) {
     const uint32_t prev = (steps + 1) & 1u, cur = steps & 1u;
     for (uint32_t p = threadIdx.x; p < kNP; p += blockDim.x) {
-        float g = 0.0f;
-        for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, slot, prev, q)[p];
+        const float g = summed_grad(c, slot, prev, p);
         float m1 = m1buf(c, slot, prev)[p], m2 = m2buf(c, slot, prev)[p];
         const float wv = adam(wbuf(c, slot, prev)[p], g, m1, m2, steps, lr);
         if (w_lds) w_lds[p] = wv;
@@ -212,18 +279,12 @@ __device__ void learn_final_update(const LearnCtx& c, uint32_t slot, uint32_t st
     }
 }
 
-// leading bytes shared by a sorted sample of m keys (at most 7)
-__device__ __forceinline__ uint32_t sample_shift(const uint64_t* smp, uint32_t m) {
-    const uint64_t x = smp[0] ^ smp[m - 1];
-    const uint32_t c = x ? (uint32_t)__builtin_clzll((unsigned long long)x) >> 3 : 8u;
-    return c < 7 ? c : 7u;
-}
-
-// initial weights into buffer 1 (read by step 0 as "previous") and the feature shift
+// initial weights into buffer 1 (read by step 0 as "previous") and the
+// feature range of the caller's sample
 __global__ __launch_bounds__(256) void k_learn_init(LearnCtx c, uint64_t seed) {
     const uint32_t slot = blockIdx.x;
     for (uint32_t p = threadIdx.x; p < kNP; p += blockDim.x) wbuf(c, slot, 1)[p] = init_weight(seed, p);
-    if (threadIdx.x == 0) c.shift[slot] = sample_shift(c.samples + (size_t)slot * kLearnM, c.m);
+    sample_range(c.samples + (size_t)slot * kLearnM, c.m, c.range + 2 * slot);
 }
 
 __global__ __launch_bounds__(256) void k_learn_final(LearnCtx c, uint32_t steps, float lr) {
@@ -261,28 +322,45 @@ __global__ __launch_bounds__(256) void k_learn_prep(LearnCtx c, const LSeg* lseg
     }
     for (uint32_t r = threadIdx.x; r < kLearnM; r += blockDim.x) c.samples[(size_t)slot * kLearnM + r] = smp[r];
     for (uint32_t p = threadIdx.x; p < kNP; p += blockDim.x) wbuf(c, slot, 1)[p] = init_weight(seed, p);
-    if (threadIdx.x == 0) c.shift[slot] = sample_shift(smp, kLearnM);
+    sample_range(smp, kLearnM, c.range + 2 * slot);
 }
 
-// running maximum of F over kLearnM values by 256 threads (16 consecutive each)
-__global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, const LSeg* lseg,
+// first index of sorted a[0..m) holding a value >= x (strict: > x)
+__device__ __forceinline__ uint32_t bound(const uint64_t* a, uint32_t m, uint64_t x, bool strict) {
+    uint32_t lo = 0, hi = m;
+    while (lo < hi) {
+        const uint32_t md = (lo + hi) >> 1;
+        if (strict ? a[md] <= x : a[md] < x) lo = md + 1; else hi = md;
+    }
+    return lo;
+}
+
+// Final update, model CDF over the sorted sample made monotone by a running
+// maximum (256 threads, 16 consecutive values each), splitters at its
+// quantiles, the check on the sample, and the splitter tree.
+__global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, LSeg* lseg,
                                                       const uint32_t* learn_seg, uint32_t steps,
-                                                      float lr, uint64_t* tree_lo,
-                                                      uint64_t* tree_in, uint8_t* tree_lcp) {
+                                                      float lr, float beta, Globals* glob,
+                                                      uint64_t* tree_lo, uint64_t* tree_in,
+                                                      uint8_t* tree_lcp) {
     __shared__ float w[kNPS];
     __shared__ float F[kLearnM];
     __shared__ uint64_t spl[1u << kDMax];
     __shared__ float tmx[256];
+    __shared__ uint32_t gmax;
     const uint32_t slot = blockIdx.x, tid = threadIdx.x;
-    const LSeg g = lseg[learn_seg[slot]];
+    const uint32_t si = learn_seg[slot];
+    const LSeg g = lseg[si];
     learn_final_update(c, slot, steps, lr, w);
+    if (tid == 0) gmax = 0;
     __syncthreads();
     const uint64_t* smp = c.samples + (size_t)slot * kLearnM;
+    const uint64_t flo = c.range[2 * slot], fhi = c.range[2 * slot + 1];
     constexpr uint32_t per = kLearnM / 256;
     float run = 0.0f;
     for (uint32_t e = 0; e < per; ++e) {
         float x[8];
-        key_features(smp[tid * per + e], c.shift[slot], x);
+        key_features(smp[tid * per + e], flo, fhi, x);
         const float y = mlp_forward(w, x, nullptr, nullptr);
         run = y > run ? y : run;
         F[tid * per + e] = run;
@@ -310,6 +388,23 @@ __global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, const LSeg* ls
         spl[j - 1] = smp[lo < kLearnM ? lo : kLearnM - 1];
     }
     __syncthreads();
+    // range bucket j (between splitters j-1 and j) counted on the sample
+    uint32_t mx = 0;
+    for (uint32_t j = tid; j <= g.v; j += 256) {
+        const uint32_t a = j ? bound(smp, kLearnM, spl[j - 1], true) : 0u;
+        const uint32_t b = j < g.v ? bound(smp, kLearnM, spl[j], false) : kLearnM;
+        const uint32_t n = b > a ? b - a : 0u;
+        mx = n > mx ? n : mx;
+    }
+    atomicMax(&gmax, mx);
+    __syncthreads();
+    if ((double)gmax > (double)beta * (double)kLearnM / (double)(g.v + 1)) {
+        if (tid == 0) {
+            lseg[si].pad0 = 0xFFFFFFFFu;  // the sampled tree is built instead
+            atomicAdd(&glob->fallbacks, 1u);
+        }
+        return;
+    }
     uint64_t* lo_out = tree_lo + g.tree_base;
     uint64_t* in_out = tree_in + g.tree_base;
     uint8_t* lcp_out = tree_lcp + g.tree_base;
@@ -330,14 +425,16 @@ __global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, const LSeg* ls
     }
 }
 
-// Largest range bucket of every learned segment against beta * |S| / (v + 1);
-// an imbalanced segment is switched back to sampled splitters.
+// Largest range bucket of every segment still on learned splitters against
+// beta * |S| / (v + 1); an imbalanced segment is switched back to sampled
+// splitters.
 __global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t* learn_seg,
                                                      const uint32_t* cs, float beta,
                                                      Globals* glob) {
     __shared__ uint32_t smax;
     const uint32_t si = learn_seg[blockIdx.x];
     const LSeg g = lseg[si];
+    if (g.pad0 == 0xFFFFFFFFu) return;  // rejected on its sample already
     if (threadIdx.x == 0) smax = 0;
     __syncthreads();
     uint32_t mx = 0;
@@ -351,6 +448,7 @@ __global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t*
     if (threadIdx.x == 0 && (double)smax > (double)beta * g.size / (g.v + 1)) {
         lseg[si].pad0 = 0xFFFFFFFFu;
         atomicAdd(&glob->fallbacks, 1u);
+        atomicAdd(&glob->late_fallbacks, 1u);
     }
 }
 
@@ -358,28 +456,26 @@ __global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t*
 // building blocks for callers and step-level checks
 
 __global__ __launch_bounds__(256) void k_mlp_eval(const float* w, const uint64_t* keys, uint32_t n,
-                                                  uint32_t shift, float* out) {
+                                                  uint64_t lo, uint64_t hi, float* out) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float x[8];
-    key_features(keys[i], shift, x);
+    key_features(keys[i], lo, hi, x);
     out[i] = mlp_forward(w, x, nullptr, nullptr);
 }
 
 __global__ __launch_bounds__(256) void k_learn_sum(LearnCtx c, uint32_t b, float* out) {
-    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < kNP; p += gridDim.x * blockDim.x) {
-        float g = 0.0f;
-        for (uint32_t q = 0; q < c.groups; ++q) g += pbuf(c, 0, b, q)[p];
-        out[p] = g;
-    }
+    for (uint32_t p = blockIdx.x * blockDim.x + threadIdx.x; p < kNP; p += gridDim.x * blockDim.x)
+        out[p] = summed_grad(c, 0, b, p);
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers
 
-size_t learn_bytes(uint32_t slots, uint32_t groups) {
+size_t learn_bytes(uint32_t slots, uint32_t m) {
+    const size_t groups = m / kGrp;
     return (size_t)slots * kLearnM * 8 + (size_t)slots * 2 * kNPS * 4 * 3 +
-           (size_t)slots * 2 * groups * kNPS * 4 + (size_t)slots * 4;
+           (size_t)slots * 2 * groups * kNPS * 4 + (size_t)slots * 16;
 }
 
 LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m) {
@@ -387,6 +483,8 @@ LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m) {
     char* p = (char*)mem;
     c.samples = (uint64_t*)p;
     p += (size_t)slots * kLearnM * 8;
+    c.range = (uint64_t*)p;
+    p += (size_t)slots * 16;
     c.W = (float*)p;
     p += (size_t)slots * 2 * kNPS * 4;
     c.M1 = (float*)p;
@@ -394,22 +492,21 @@ LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m) {
     c.M2 = (float*)p;
     p += (size_t)slots * 2 * kNPS * 4;
     c.part = (float*)p;
-    p += (size_t)slots * 2 * (m / kGrp) * kNPS * 4;
-    c.shift = (uint32_t*)p;
     c.m = m;
     c.groups = m / kGrp;
     return c;
 }
 
-void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, const LSeg* lseg,
+void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
                              const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
-                             uint32_t steps, float lr, uint64_t* tree_lo, uint64_t* tree_in,
-                             uint8_t* tree_lcp, hipStream_t st) {
+                             uint32_t steps, float lr, float beta, Globals* glob,
+                             uint64_t* tree_lo, uint64_t* tree_in, uint8_t* tree_lcp,
+                             hipStream_t st) {
     hipLaunchKernelGGL(k_learn_prep, dim3(slots), dim3(256), 0, st, c, lseg, learn_seg, key_in, seed);
     for (uint32_t s = 0; s < steps; ++s)
         hipLaunchKernelGGL(k_learn_step, dim3(c.groups, slots), dim3(kGrp), 0, st, c, s, lr);
     hipLaunchKernelGGL(k_learn_finish, dim3(slots), dim3(256), 0, st, c, lseg, learn_seg, steps, lr,
-                       tree_lo, tree_in, tree_lcp);
+                       beta, glob, tree_lo, tree_in, tree_lcp);
 }
 
 void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,
@@ -442,10 +539,10 @@ void launch_mlp_grad(const LearnCtx& c, const float* params, const uint64_t* sor
     hipLaunchKernelGGL(k_learn_sum, dim3(8), dim3(256), 0, st, c, 0u, out);
 }
 
-void launch_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint32_t shift,
-                     float* out, hipStream_t st) {
+void launch_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo,
+                     uint64_t hi, float* out, hipStream_t st) {
     if (!n) return;
-    hipLaunchKernelGGL(k_mlp_eval, dim3((n + 255) / 256), dim3(256), 0, st, params, keys, n, shift,
+    hipLaunchKernelGGL(k_mlp_eval, dim3((n + 255) / 256), dim3(256), 0, st, params, keys, n, lo, hi,
                        out);
 }
 

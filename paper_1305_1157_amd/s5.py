@@ -76,7 +76,7 @@ def load(path: str = LIB_PATH):
     lib.s5_classify.argtypes = [P, U32, P, U32, P, P]
     lib.s5_mlp_train.argtypes = [P, U32, U32, ctypes.c_float, U64, P, P]
     lib.s5_mlp_grad.argtypes = [P, P, U32, P, P]
-    lib.s5_mlp_eval.argtypes = [P, P, U32, U32, P, P]
+    lib.s5_mlp_eval.argtypes = [P, P, U32, U64, U64, P, P]
     lib.s5_profile_enable.argtypes = [ctypes.c_int]
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
     for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_stats_get", "s5_prefix_keys",
@@ -237,8 +237,11 @@ def mlp_grad(params: torch.Tensor, sorted_keys: torch.Tensor, stream=None):
     return out
 
 
-def mlp_eval(params: torch.Tensor, keys: torch.Tensor, shift: int = 0, stream=None):
+def mlp_eval(params: torch.Tensor, keys: torch.Tensor, lo: int = 0, hi: int = 2**64 - 1,
+             stream=None):
+    """Model output for every key, features scaled by the byte-wise range (lo, hi)."""
     out = torch.empty(keys.numel(), dtype=torch.float32, device=keys.device)
     _check(load().s5_mlp_eval(_dev(params, torch.float32, "params"), _dev(keys, torch.uint64, "keys"),
-                              keys.numel(), shift, _dev(out, torch.float32, "out"), _stream(stream)))
+                              keys.numel(), lo, hi, _dev(out, torch.float32, "out"),
+                              _stream(stream)))
     return out

@@ -100,9 +100,35 @@ def test_entropy_and_imbalance():
     assert not mlp_ref.imbalanced(sizes, v=2, size=120, beta=3.0)
 
 
-def test_prefix_shift_and_features():
-    k = np.array([0x6161610000000000, 0x6161620000000000], dtype=np.uint64)
-    assert mlp_ref.prefix_shift(k) == 2
-    assert mlp_ref.prefix_shift(np.array([5, 5], dtype=np.uint64)) == 7
-    f = mlp_ref.features(k, 2)
-    assert np.allclose(f[:, 0] * 255, [0x61, 0x62]) and np.allclose(f[:, 1:], 0)
+def test_feature_range_and_features():
+    # byte-wise range written out per byte, against hand-computed values
+    k = np.array([0x6161610000000000, 0x6162790000000000, 0x6163620000000000], dtype=np.uint64)
+    lo, hi = mlp_ref.feature_range(k)
+    assert lo == 0x6161610000000000 and hi == 0x6163790000000000
+    f = mlp_ref.features(k, lo, hi)
+    assert np.allclose(f[:, 0], 0) and np.allclose(f[:, 3:], 0)  # shared bytes -> 0
+    assert np.allclose(f[:, 1], [0, 0.5, 1.0])                    # 0x61, 0x62, 0x63 over [0x61, 0x63]
+    assert np.allclose(f[:, 2], [0, (0x79 - 0x61) / 0x18, (0x62 - 0x61) / 0x18])
+    # default range is the plain byte / 255 encoding
+    g = mlp_ref.features(np.array([0x00FF7F0102030405], dtype=np.uint64))
+    assert np.allclose(g[0] * 255, [0x00, 0xFF, 0x7F, 1, 2, 3, 4, 5])
+    # each feature of the sample lies in [0, 1] and reaches both ends where bytes vary
+    rng = np.random.default_rng(3)
+    s = rng.integers(0, 2**64 - 1, size=500, dtype=np.uint64, endpoint=True)
+    fs = mlp_ref.features(s, *mlp_ref.feature_range(s))
+    assert fs.min() == 0.0 and fs.max() == 1.0
+    assert np.all(fs.min(axis=0) == 0) and np.all(fs.max(axis=0) == 1)
+
+
+def test_sample_imbalance_brute_force():
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        k = np.sort(rng.integers(0, 50, size=200).astype(np.uint64))
+        s = np.sort(rng.choice(k, size=7))
+        brute = []
+        edges = [None] + list(s) + [None]
+        for a, b in zip(edges[:-1], edges[1:]):
+            brute.append(sum(1 for x in k if (a is None or x > a) and (b is None or x < b)))
+        assert mlp_ref.sample_imbalance(s, k) == max(brute)
+
+
