@@ -76,6 +76,10 @@ typedef struct s5_config {
                                 range bucket exceeds this many times the ideal
                                 size (default 4) */
     uint64_t seed;           /* sampling / training seed; the output never depends on it */
+    uint32_t graph_levels;   /* batched sorts: distribution levels captured in the
+                                sort's hipGraph (0 = 12, at most 64); deeper inputs
+                                finish with host-driven passes after the graph */
+    uint32_t reserved;       /* must be 0 */
 } s5_config;
 
 /* Counters of the last completed sort on a stream. */
@@ -111,10 +115,37 @@ size_t s5_workspace_bytes(uint32_t n, const s5_config* cfg);
  * offsets[set_begin[s] .. set_begin[s+1]); set_begin (num_sets+1 entries,
  * DEVICE memory, non-decreasing, set_begin[0] = 0) fixes where each set's
  * results go: out_perm holds set-local indices and out_lcp is 0 at every
- * set's first slot.  n = set_begin[num_sets] < 2^32. */
+ * set's first slot.  n = set_begin[num_sets] < 2^32.
+ *
+ * All sets are sorted together: every distribution pass covers the segments
+ * of every set (the segmented form of the level-by-level recursion of
+ * Section 3.1), and the first cfg->graph_levels passes, the base case and the
+ * boundary LCPs are one hipGraph, captured on the first call and replayed by
+ * later calls with the same pointers, sizes and cfg (kernels only; work
+ * counts are read on the device).  Reads set_begin[0] and set_begin[num_sets]
+ * back (synchronizes the stream) and synchronizes again at the end. */
 int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
                     const uint64_t* set_begin, uint32_t num_sets, uint32_t* out_perm,
                     uint32_t* out_lcp, const s5_config* cfg, hipStream_t stream);
+
+/* Per-set parameters of s5_sort_batched_tuned (the entries of an autotuned
+ * table; 0 = the value from cfg).  The paper tunes such thresholds by hand
+ * (Section 3.1 "Implementation Details"). */
+typedef struct s5_set_tuning {
+    uint16_t splitters;       /* most splitters per pass in this set, 2^d - 1, 7..1023 */
+    uint16_t base_threshold;  /* base-case threshold T of this set, 64..2048 */
+    uint32_t tile;            /* minimum strings per tile, multiple of 64, <= 2^20 */
+} s5_set_tuning;
+
+/* s5_sort_batched with per-set parameters: set_tuning is a HOST array of
+ * num_sets entries (NULL = cfg for every set), validated and copied before
+ * the call returns.  The launch-wide limits (largest T and tree depth) are
+ * the maxima over the sets and cfg; cfg->unroll applies to every set.
+ * Returns S5_ERR_INVALID for an entry out of range. */
+int s5_sort_batched_tuned(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                          const uint64_t* set_begin, uint32_t num_sets,
+                          const s5_set_tuning* set_tuning, uint32_t* out_perm, uint32_t* out_lcp,
+                          const s5_config* cfg, hipStream_t stream);
 
 /* Copy the counters of the last sort finished on `stream` to host_out.
  * Synchronizes `stream`; returns S5_ERR_DEVICE if that sort's device status

@@ -22,47 +22,7 @@
 #include "../../include/s5_learned.h"
 #include "s5_internal.h"
 
-namespace s5 {
-void launch_init_keys(const uint8_t*, const uint64_t*, uint32_t, uint64_t*, uint32_t*, hipStream_t);
-void launch_prefix_keys(const uint8_t*, const uint64_t*, uint32_t, uint32_t, uint64_t*, hipStream_t);
-void launch_plan_roots(const uint64_t*, uint32_t, uint32_t, uint32_t*, uint32_t*, const PlanCtx&,
-                       hipStream_t);
-void launch_sample_tree(uint32_t, const LSeg*, const uint64_t*, uint32_t, uint32_t, uint64_t,
-                        uint64_t*, uint64_t*, uint8_t*, uint32_t*, uint32_t*, Counters*,
-                        hipStream_t);
-void launch_classify(uint32_t, uint32_t, const LSeg*, const uint32_t*, const uint64_t*,
-                     const uint64_t*, const uint64_t*, uint16_t*, uint32_t*, uint32_t, uint32_t,
-                     hipStream_t);
-void launch_colscan(uint32_t, uint32_t, const LSeg*, const uint32_t*, uint32_t*, uint32_t*,
-                    hipStream_t);
-void launch_bucket_plan(uint32_t, const LSeg*, uint32_t*, uint32_t*, const uint64_t*,
-                        const uint8_t*, const PlanCtx&, uint32_t, hipStream_t);
-void launch_scatter(uint32_t, uint32_t, const LSeg*, const uint32_t*, const uint16_t*,
-                    const uint64_t*, const uint32_t*, uint64_t*, uint32_t*, const uint32_t*,
-                    const uint32_t*, const uint32_t*, const uint64_t*, const uint8_t*,
-                    const uint8_t*, const uint64_t*, uint32_t*, uint32_t*, uint32_t, uint32_t,
-                    hipStream_t);
-void launch_base_sort(const uint32_t*, Seg* const*, const uint64_t*, const uint64_t*,
-                      const uint32_t*, const uint32_t*, const uint8_t*, const uint64_t*, uint32_t*,
-                      uint32_t*, uint32_t, hipStream_t);
-void launch_lcp_fix(const uint8_t*, const uint64_t*, const uint64_t*, uint32_t, uint32_t,
-                    const uint32_t*, uint32_t*, hipStream_t);
-void launch_classify_plain(const uint64_t*, uint32_t, const uint64_t*, uint32_t, uint32_t,
-                           uint64_t*, uint64_t*, uint16_t*, hipStream_t);
-size_t learn_bytes(uint32_t slots, uint32_t m);
-LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m);
-void launch_learn_sort_trees(const LearnCtx&, uint32_t, LSeg*, const uint32_t*, const uint64_t*,
-                             uint64_t, uint32_t, float, float, Globals*, uint64_t*, uint64_t*,
-                             uint8_t*, hipStream_t);
-void launch_learn_check(uint32_t, LSeg*, const uint32_t*, const uint32_t*, float, Globals*,
-                        hipStream_t);
-void launch_mlp_train(const LearnCtx&, const uint64_t*, uint32_t, uint32_t, float, uint64_t,
-                      float*, hipStream_t);
-void launch_mlp_grad(const LearnCtx&, const float*, const uint64_t*, uint32_t, float*,
-                     hipStream_t);
-void launch_mlp_eval(const float*, const uint64_t*, uint32_t, uint64_t, uint64_t, float*,
-                     hipStream_t);
-}  // namespace s5
+#include "s5_launch.h"
 
 using namespace s5;
 
@@ -74,11 +34,17 @@ constexpr float kLearnRate = 0.03f;
 
 struct Cfg {
     uint32_t dmax, alpha, unroll, tile_min, T, mode;
+    uint32_t T_caps, tile_caps;  // smallest T and tile of any set: storage capacities
     float beta;
+    uint32_t graph_levels;
     uint64_t seed;
 };
 
+// distribution levels a batched sort captures in its graph by default
+constexpr uint32_t kGraphLevels = 12, kGraphLevelsMax = 64;
+
 int resolve_cfg(const s5_config* c, Cfg* o) {
+    memset(o, 0, sizeof *o);  // Cfg is compared byte-wise as part of graph keys
     s5_config z;
     memset(&z, 0, sizeof z);
     if (!c) c = &z;
@@ -95,9 +61,13 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     if (o->tile_min % 64 || o->tile_min > (1u << 20)) return S5_ERR_INVALID;
     o->T = c->base_threshold ? c->base_threshold : 1024u;
     if (o->T < 64 || o->T > 2048) return S5_ERR_INVALID;
+    o->T_caps = o->T;
+    o->tile_caps = o->tile_min;
     o->mode = c->splitter_mode;
     if (o->mode != S5_SPLIT_SAMPLED && o->mode != S5_SPLIT_LEARNED) return S5_ERR_INVALID;
     o->beta = c->imbalance_bound > 0 ? c->imbalance_bound : 4.0f;
+    o->graph_levels = c->graph_levels ? c->graph_levels : kGraphLevels;
+    if (o->graph_levels > kGraphLevelsMax) return S5_ERR_INVALID;
     o->seed = c->seed;
     return S5_OK;
 }
@@ -107,21 +77,21 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
     size_t key[2], idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
-        bstart, base_list, learn, learn_seg, counters[2], glob, total;
-    uint32_t learn_cap;
+        bstart, base_list, learn, learn_seg, set_tune, counters[2], glob, total;
+    uint32_t learn_cap, tune_sets;
     Caps caps;
 };
 
-Layout make_layout(uint64_t n, const Cfg& c) {
+Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     Layout L;
     const uint64_t kmax = (2ull << c.dmax) - 1;
     Caps cp;
-    uint64_t large = n / (c.T + 1) + 2;
+    uint64_t large = n / (c.T_caps + 1) + 2;
     // tiles of a segment: ceil(|S| / tile_len) with tile_len >= tile_min
-    uint64_t tiles = n / c.tile_min + large + 1;
+    uint64_t tiles = n / c.tile_caps + large + 1;
     uint64_t chunks = tiles / kChunkRows + large + 1;
     // sum over segments of 2^d < 4 |S| / T (plus the d >= 1 floor)
-    uint64_t tree = 4 * n / c.T + 2 * large + 2;
+    uint64_t tree = 4 * n / c.T_caps + 2 * large + 2;
     cp.large = (uint32_t)large;
     cp.tiles = (uint32_t)std::min<uint64_t>(tiles, 0xFFFFFFFFull);
     cp.chunks = (uint32_t)chunks;
@@ -133,8 +103,8 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     cp.base[2] = (uint32_t)(n / (kBaseMid + 1) + 2);
     // sum over segments of tiles x k: tiles_s <= |S|/tile_min + 1 and
     // k_s <= max(3, min(kmax, 8 |S| / T))
-    const uint64_t ksum = 3 * large + 8 * n / c.T + kmax;
-    cp.cm = (unsigned long long)(kmax * (n / c.tile_min + 1) + 4 * ksum);
+    const uint64_t ksum = 3 * large + 8 * n / c.T_caps + kmax;
+    cp.cm = (unsigned long long)(kmax * (n / c.tile_caps + 1) + 4 * ksum);
     cp.cs = (unsigned long long)(cp.cm / kChunkRows + ksum);
     size_t p = 0;
     auto take = [&](size_t bytes) {
@@ -159,6 +129,9 @@ Layout make_layout(uint64_t n, const Cfg& c) {
     L.learn_cap = c.mode == S5_SPLIT_LEARNED ? (uint32_t)std::min<uint64_t>(large, n / kLearnMin + 1) : 0u;
     L.learn = take(learn_bytes(L.learn_cap, kLearnSamples));
     L.learn_seg = take((size_t)L.learn_cap * 4);
+    // packed per-set parameters of a tuned batched sort
+    L.tune_sets = tune_sets;
+    L.set_tune = take((size_t)tune_sets * 4);
     // [counters 0 | globals | counters 1] back to back: one copy reads a pass's
     // counters together with the globals
     L.counters[0] = take(sizeof(Counters) + sizeof(Globals) + sizeof(Counters));
@@ -189,6 +162,8 @@ std::unordered_map<hipStream_t, StreamRecord> g_last;
         if (e_ != hipSuccess) return S5_ERR_HIP;       \
     } while (0)
 
+void graphs_release();
+
 // Get the pool of the current device with at least `bytes`.
 int pool_get(size_t bytes, DevPool** out) {
     int dev = 0;
@@ -198,6 +173,7 @@ int pool_get(size_t bytes, DevPool** out) {
     if (P.bytes < bytes) {
         if (P.ptr) {
             S5_HIP(hipDeviceSynchronize());
+            graphs_release();  // captured graphs point into the old pool
             S5_HIP(hipFree(P.ptr));
             P.ptr = nullptr;
             P.bytes = 0;
@@ -215,15 +191,15 @@ int pool_get(size_t bytes, DevPool** out) {
 
 // ---- per-kernel event timing (s5_profile.h) --------------------------------
 enum KId { K_INIT, K_ROOTS, K_SAMPLE, K_CLASSIFY, K_COLSCAN, K_PLAN, K_SCATTER, K_BASE, K_LCPFIX,
-           K_LEARN, K_COUNT };
-const char* const kKName[K_COUNT] = {"init_keys", "plan_roots", "sample_tree", "classify",
-                                     "colscan",   "bucket_plan", "scatter",    "base_sort",
-                                     "lcp_fix",   "learn_splitters"};
+           K_LEARN, K_GRAPH, K_COUNT };
+const char* const kKName[K_COUNT] = {"init_keys", "plan_roots",      "sample_tree", "classify",
+                                     "colscan",   "bucket_plan",     "scatter",     "base_sort",
+                                     "lcp_fix",   "learn_splitters", "sort_graph"};
 // algorithmic bytes per string processed: init reads an offset and 8 key bytes
 // and writes key + index; classify reads a key and writes a bucket id; a
 // redistribution pass reads and writes (key, index); the base case reads
 // (key, index) and writes perm + lcp; the LCP completion reads one lcp word
-const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4, 0};
+const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4, 0, 0};
 struct ProfAcc {
     uint64_t launches = 0, items = 0;
     double ms = 0, bytes = 0;
@@ -287,173 +263,427 @@ struct SortArgs {
     uint32_t num_sets, n;
     uint32_t* perm;
     uint32_t* lcp;
+    const uint32_t* tune_host;  // packed per-set parameters (host), or null
 };
 
-// The whole sort on one workspace.  `host` is a pinned block of >= 4 KiB.
-int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* host,
-             hipStream_t st, s5_stats* stats) {
-    memset(stats, 0, sizeof *stats);
-    const Layout L = make_layout(a.n, c);
-    if (ws_bytes < L.total) return S5_ERR_NOMEM;
-    stats->workspace_bytes = L.total;
-    char* W = (char*)ws;
-    uint64_t* key[2] = {(uint64_t*)(W + L.key[0]), (uint64_t*)(W + L.key[1])};
-    uint32_t* idx[2] = {(uint32_t*)(W + L.idx[0]), (uint32_t*)(W + L.idx[1])};
-    uint16_t* bid = (uint16_t*)(W + L.bid);
-    LSeg* lseg[2] = {(LSeg*)(W + L.lseg[0]), (LSeg*)(W + L.lseg[1])};
-    uint32_t* tile_tab = (uint32_t*)(W + L.tile_tab);
-    uint32_t* chunk_tab = (uint32_t*)(W + L.chunk_tab);
-    uint64_t* tree_lo = (uint64_t*)(W + L.tree_lo);
-    uint64_t* tree_in = (uint64_t*)(W + L.tree_in);
-    uint8_t* tree_lcp = (uint8_t*)(W + L.tree_lcp);
-    uint32_t* cm = (uint32_t*)(W + L.cm);
-    uint32_t* cs = (uint32_t*)(W + L.cs);
-    uint32_t* bstart = (uint32_t*)(W + L.bstart);
-    uint32_t* learn_seg = (uint32_t*)(W + L.learn_seg);
-    const LearnCtx lctx = learn_ctx(W + L.learn, L.learn_cap, kLearnSamples);
+// Device views of one workspace.
+struct Ptrs {
+    uint64_t* key[2];
+    uint32_t* idx[2];
+    uint16_t* bid;
+    LSeg* lseg[2];
+    uint32_t *tile_tab, *chunk_tab;
+    uint64_t *tree_lo, *tree_in;
+    uint8_t* tree_lcp;
+    uint32_t *cm, *cs, *bstart, *learn_seg, *set_tune;
+    LearnCtx lctx;
     Seg* base_list[kBaseClasses];
-    base_list[0] = (Seg*)(W + L.base_list);
-    base_list[1] = base_list[0] + L.caps.base[0];
-    base_list[2] = base_list[1] + L.caps.base[1];
-    Counters* cnt[2] = {(Counters*)(W + L.counters[0]), (Counters*)(W + L.counters[1])};
-    Globals* glob = (Globals*)(W + L.glob);
-    Counters* hc = (Counters*)((char*)host + 1024);
-    Globals* hg = (Globals*)((char*)host + 2048);
+    Counters* cnt[2];
+    Globals* glob;
+};
 
-    auto ctx_for = [&](int next) {
-        PlanCtx x;
-        x.lseg = lseg[next];
-        x.cnt = cnt[next];
-        for (int q = 0; q < kBaseClasses; ++q) x.base_list[q] = base_list[q];
-        x.glob = glob;
-        x.caps = L.caps;
-        x.T = c.T;
-        x.d_max = c.dmax;
-        x.tile_min = c.tile_min;
-        x.learn = c.mode == S5_SPLIT_LEARNED ? 1u : 0u;
-        x.learn_cap = L.learn_cap;
-        x.learn_seg = learn_seg;
-        return x;
-    };
-    auto readback = [&](int which) -> int {
-        char* src = which == 0 ? (char*)cnt[0] : (char*)glob;
-        S5_HIP(hipMemcpyAsync(host, src, sizeof(Counters) + sizeof(Globals), hipMemcpyDeviceToHost,
-                              st));
-        S5_HIP(hipStreamSynchronize(st));
-        const char* hb = (const char*)host;
-        memcpy(hc, which == 0 ? hb : hb + sizeof(Globals), sizeof(Counters));
-        memcpy(hg, which == 0 ? hb + sizeof(Counters) : hb, sizeof(Globals));
-        return hg->status ? S5_ERR_DEVICE : S5_OK;
-    };
-
-    S5_HIP(hipMemsetAsync(cnt[0], 0, 2 * sizeof(Counters) + sizeof(Globals), st));
-    timed(K_INIT, a.n, st, [&] { launch_init_keys(a.chars, a.offsets, a.n, key[0], idx[0], st); });
-    timed(K_ROOTS, a.num_sets, st, [&] {
-        launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, ctx_for(0), st);
-    });
-    S5_HIP(hipGetLastError());
-    int rc = readback(0);
-    if (rc) {
-        prof_collect();
-        return rc;
+Ptrs make_ptrs(const Layout& L, char* W) {
+    Ptrs P;
+    for (int b = 0; b < 2; ++b) {
+        P.key[b] = (uint64_t*)(W + L.key[b]);
+        P.idx[b] = (uint32_t*)(W + L.idx[b]);
+        P.lseg[b] = (LSeg*)(W + L.lseg[b]);
+        P.cnt[b] = (Counters*)(W + L.counters[b]);
     }
+    P.bid = (uint16_t*)(W + L.bid);
+    P.tile_tab = (uint32_t*)(W + L.tile_tab);
+    P.chunk_tab = (uint32_t*)(W + L.chunk_tab);
+    P.tree_lo = (uint64_t*)(W + L.tree_lo);
+    P.tree_in = (uint64_t*)(W + L.tree_in);
+    P.tree_lcp = (uint8_t*)(W + L.tree_lcp);
+    P.cm = (uint32_t*)(W + L.cm);
+    P.cs = (uint32_t*)(W + L.cs);
+    P.bstart = (uint32_t*)(W + L.bstart);
+    P.learn_seg = (uint32_t*)(W + L.learn_seg);
+    P.set_tune = L.tune_sets ? (uint32_t*)(W + L.set_tune) : nullptr;
+    P.lctx = learn_ctx(W + L.learn, L.learn_cap, kLearnSamples);
+    P.base_list[0] = (Seg*)(W + L.base_list);
+    P.base_list[1] = P.base_list[0] + L.caps.base[0];
+    P.base_list[2] = P.base_list[1] + L.caps.base[1];
+    P.glob = (Globals*)(W + L.glob);
+    return P;
+}
 
-    int cur = 0;  // lseg / counters index of the pass about to run
-    int buf = 0;  // work buffer holding the pass's input
-    uint32_t level = 0;
-    while (hc->n_large > 0) {
-        const Counters now = *hc;
-        const uint32_t kmax = now.kmax, vmax = (kmax - 1) / 2;
+PlanCtx plan_ctx(const Ptrs& P, const Layout& L, const Cfg& c, const SortArgs& a, int next) {
+    PlanCtx x;
+    x.set_begin = a.set_begin;
+    x.set_tune = P.set_tune;
+    x.num_sets = a.num_sets;
+    x.lseg = P.lseg[next];
+    x.cnt = P.cnt[next];
+    for (int q = 0; q < kBaseClasses; ++q) x.base_list[q] = P.base_list[q];
+    x.glob = P.glob;
+    x.caps = L.caps;
+    x.T = c.T;
+    x.d_max = c.dmax;
+    x.tile_min = c.tile_min;
+    x.learn = c.mode == S5_SPLIT_LEARNED ? 1u : 0u;
+    x.learn_cap = L.learn_cap;
+    x.learn_seg = P.learn_seg;
+    return x;
+}
+
+// Launch shapes of one pass: the host-read counters (host-driven) or the
+// capacities and fixed grids (graph mode).
+struct PassShape {
+    Counters now;                // host-driven: this pass's counters
+    uint32_t vmax, kmax;
+    Dyn seg, tile, chunk, learn;  // graph mode: device counts
+    uint32_t n_learn;            // host-driven: learned segments
+};
+
+Dyn dyn_of(const uint32_t* cnt, uint32_t cap, uint32_t gmax) {
+    Dyn d;
+    d.cnt = cnt;
+    d.cap = cap;
+    d.grid = std::max<uint32_t>(1u, std::min(cap, gmax));
+    return d;
+}
+
+// Fixed grids of graph-mode launches (grid-stride over the device counts).
+constexpr uint32_t kGraphSegGrid = 4096, kGraphTileGrid = 4096, kGraphLearnGrid = 512,
+                   kGraphBaseGrid = 8192;
+
+PassShape graph_shape(const Ptrs& P, const Layout& L, const Cfg& c, int cur) {
+    PassShape S;
+    memset(&S.now, 0, sizeof S.now);
+    S.vmax = (1u << c.dmax) - 1;
+    S.kmax = 2 * S.vmax + 1;
+    S.seg = dyn_of(&P.cnt[cur]->n_large, L.caps.large, kGraphSegGrid);
+    S.tile = dyn_of(&P.cnt[cur]->tiles, L.caps.tiles, kGraphTileGrid);
+    S.chunk = dyn_of(&P.cnt[cur]->chunks, L.caps.chunks, kGraphTileGrid);
+    S.learn = dyn_of(&P.cnt[cur]->pad0, L.learn_cap, kGraphLearnGrid);
+    S.n_learn = 0;
+    return S;
+}
+
+PassShape host_shape(const Counters& now, const Layout& L) {
+    PassShape S;
+    S.now = now;
+    S.kmax = now.kmax;
+    S.vmax = (now.kmax - 1) / 2;
+    S.n_learn = std::min(now.pad0, L.learn_cap);
+    return S;
+}
+
+// Learned proposals (a proposal that fails on its own sample is switched back
+// to sampled splitters), sampled trees, classification and column scans.
+// redo = 1: the same for the segments the exact learned check rejected.
+void pass_front(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
+                const PassShape& S, int cur, int buf, uint32_t redo, hipStream_t st) {
+    const bool graph = S.seg.cnt != nullptr;
+    const int nxt = cur ^ 1;
+    if (!redo && c.mode == S5_SPLIT_LEARNED && (graph || S.n_learn)) {
+        timed(K_LEARN, S.n_learn, st, [&] {
+            launch_learn_sort_trees(P.lctx, S.n_learn, P.lseg[cur], P.learn_seg, P.key[buf],
+                                    c.seed, kLearnSteps, kLearnRate, c.beta, P.glob, P.tree_lo,
+                                    P.tree_in, P.tree_lcp, S.learn, st);
+        });
+    }
+    timed(K_SAMPLE, S.now.n_large, st, [&] {
+        launch_sample_tree(S.now.n_large, P.lseg[cur], P.key[buf], c.alpha, S.vmax, c.seed,
+                           P.tree_lo, P.tree_in, P.tree_lcp, P.tile_tab, P.chunk_tab, P.cnt[nxt],
+                           P.glob, S.seg, redo, st);
+    });
+    timed(K_CLASSIFY, S.now.moved, st, [&] {
+        launch_classify(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.key[buf], P.tree_lo,
+                        P.tree_in, P.bid, P.cm, S.vmax, S.kmax, P.glob, S.tile, redo, st);
+    });
+    timed(K_COLSCAN, S.now.moved, st, [&] {
+        launch_colscan(S.now.chunks, S.kmax, P.lseg[cur], P.chunk_tab, P.cm, P.cs, P.glob,
+                       S.chunk, redo, st);
+    });
+    (void)a;
+    (void)L;
+}
+
+// Bucket plan of the next pass, then the redistribution.
+void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
+               const PassShape& S, int cur, int buf, hipStream_t st) {
+    const int nxt = cur ^ 1;
+    timed(K_PLAN, S.now.moved, st, [&] {
+        launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp,
+                           plan_ctx(P, L, c, a, nxt), (uint32_t)(buf ^ 1), S.seg, st);
+    });
+    timed(K_SCATTER, S.now.moved, st, [&] {
+        launch_scatter(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.bid, P.key[buf],
+                       P.idx[buf], P.key[buf ^ 1], P.idx[buf ^ 1], P.cm, P.cs, P.bstart,
+                       P.tree_in, P.tree_lcp, a.chars, a.offsets, a.perm, a.lcp, S.vmax, S.kmax,
+                       P.glob, S.tile, st);
+    });
+}
+
+void clear_counters(const Ptrs& P, hipStream_t st) {
+    launch_zero_words(P.cnt[0], 2 * sizeof(Counters) + sizeof(Globals), st);
+}
+
+void start_sort(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P, hipStream_t st) {
+    clear_counters(P, st);
+    timed(K_INIT, a.n, st, [&] { launch_init_keys(a.chars, a.offsets, a.n, P.key[0], P.idx[0], st); });
+    timed(K_ROOTS, a.num_sets, st, [&] {
+        launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, plan_ctx(P, L, c, a, 0), st);
+    });
+}
+
+// Host-side state of a sort in progress (pinned readback block).
+struct HostView {
+    void* host;
+    Counters* hc;
+    Globals* hg;
+};
+
+HostView host_view(void* host) {
+    return HostView{host, (Counters*)((char*)host + 1024), (Globals*)((char*)host + 2048)};
+}
+
+// Copy a pass's counters together with the globals and wait for them.
+int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
+    char* src = which == 0 ? (char*)P.cnt[0] : (char*)P.glob;
+    S5_HIP(hipMemcpyAsync(H.host, src, sizeof(Counters) + sizeof(Globals), hipMemcpyDeviceToHost, st));
+    S5_HIP(hipStreamSynchronize(st));
+    const char* hb = (const char*)H.host;
+    memcpy(H.hc, which == 0 ? hb : hb + sizeof(Globals), sizeof(Counters));
+    memcpy(H.hg, which == 0 ? hb + sizeof(Counters) : hb, sizeof(Globals));
+    return H.hg->status ? S5_ERR_DEVICE : S5_OK;
+}
+
+// Host-driven passes from `level` on (counters of the pass about to run in
+// H.hc), then the base case and the boundary LCPs.
+int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
+                const HostView& H, uint32_t level, hipStream_t st, s5_stats* stats) {
+    int cur = (int)(level & 1u), buf = (int)(level & 1u);
+    int rc = S5_OK;
+    while (H.hc->n_large > 0) {
+        const PassShape S = host_shape(*H.hc, L);
         const int nxt = cur ^ 1;
-        // learned proposals first: a proposal that fails on its own sample is
-        // switched back to sampled splitters before the sampled trees are built
-        const uint32_t n_learn = std::min(now.pad0, L.learn_cap);
-        if (n_learn) {
-            timed(K_LEARN, n_learn, st, [&] {
-                launch_learn_sort_trees(lctx, n_learn, lseg[cur], learn_seg, key[buf], c.seed,
-                                        kLearnSteps, kLearnRate, c.beta, glob, tree_lo, tree_in,
-                                        tree_lcp, st);
-            });
-        }
-        timed(K_SAMPLE, now.n_large, st, [&] {
-            launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed, tree_lo,
-                               tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
-        });
-        timed(K_CLASSIFY, now.moved, st, [&] {
-            launch_classify(now.tiles, c.unroll, lseg[cur], tile_tab, key[buf], tree_lo, tree_in,
-                            bid, cm, vmax, kmax, st);
-        });
-        timed(K_COLSCAN, now.moved, st,
-              [&] { launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st); });
-        if (n_learn) {
+        pass_front(a, c, L, P, S, cur, buf, 0u, st);
+        if (S.n_learn) {
             // learned splitters that leave a range bucket too large are redone sampled
-            const uint32_t before = hg->late_fallbacks;
-            launch_learn_check(n_learn, lseg[cur], learn_seg, cs, c.beta, glob, st);
-            rc = readback(cur);
-            if (rc) {
-                prof_collect();
-                return rc;
-            }
-            if (hg->late_fallbacks != before) {
-                timed(K_SAMPLE, now.n_large, st, [&] {
-                    launch_sample_tree(now.n_large, lseg[cur], key[buf], c.alpha, vmax, c.seed,
-                                       tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, cnt[nxt], st);
-                });
-                timed(K_CLASSIFY, now.moved, st, [&] {
-                    launch_classify(now.tiles, c.unroll, lseg[cur], tile_tab, key[buf], tree_lo,
-                                    tree_in, bid, cm, vmax, kmax, st);
-                });
-                timed(K_COLSCAN, now.moved, st, [&] {
-                    launch_colscan(now.chunks, kmax, lseg[cur], chunk_tab, cm, cs, st);
-                });
-            }
+            const uint32_t before = H.hg->late_fallbacks;
+            launch_learn_check(S.n_learn, P.lseg[cur], P.learn_seg, P.cs, c.beta, P.glob, Dyn{}, st);
+            rc = readback(P, H, cur, st);
+            if (rc) return rc;
+            if (H.hg->late_fallbacks != before) pass_front(a, c, L, P, S, cur, buf, 1u, st);
         }
-        timed(K_PLAN, now.moved, st, [&] {
-            launch_bucket_plan(now.n_large, lseg[cur], cs, bstart, tree_in, tree_lcp, ctx_for(nxt),
-                               (uint32_t)(buf ^ 1), st);
-        });
-        timed(K_SCATTER, now.moved, st, [&] {
-            launch_scatter(now.tiles, c.unroll, lseg[cur], tile_tab, bid, key[buf], idx[buf],
-                           key[buf ^ 1], idx[buf ^ 1], cm, cs, bstart, tree_in, tree_lcp, a.chars,
-                           a.offsets, a.perm, a.lcp, vmax, kmax, st);
-        });
+        pass_back(a, c, L, P, S, cur, buf, st);
         S5_HIP(hipGetLastError());
-        rc = readback(nxt);
-        if (rc) {
-            prof_collect();
-            return rc;
-        }
-        stats->moved_M += now.moved;
-        stats->segments += now.n_large;
+        rc = readback(P, H, nxt, st);
+        if (rc) return rc;
+        stats->moved_M += S.now.moved;
+        stats->segments += S.now.n_large;
         if (level == 0) {
-            stats->max_bucket = hc->max_bucket;
-            stats->entropy_bits = now.moved ? hc->entropy_sum / (double)now.moved : 0.0;
+            stats->max_bucket = H.hc->max_bucket;
+            stats->entropy_bits = S.now.moved ? H.hc->entropy_sum / (double)S.now.moved : 0.0;
         }
         ++level;
         cur = nxt;
         buf ^= 1;
     }
     stats->passes = level;
-    stats->fallbacks = hg->fallbacks;
     uint32_t n_base[kBaseClasses];
-    for (int q = 0; q < kBaseClasses; ++q) n_base[q] = hg->n_base[q];
-    stats->base_items = (uint64_t)n_base[0] + n_base[1] + n_base[2];
-    timed(K_BASE, hg->base_elems, st, [&] {
-        launch_base_sort(n_base, base_list, key[0], key[1], idx[0], idx[1], a.chars, a.offsets,
-                         a.perm, a.lcp, c.T, st);
+    for (int q = 0; q < kBaseClasses; ++q) n_base[q] = H.hg->n_base[q];
+    const Dyn none[kBaseClasses];
+    timed(K_BASE, H.hg->base_elems, st, [&] {
+        launch_base_sort(n_base, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
+                         a.offsets, a.perm, a.lcp, c.T, P.glob, none, nullptr, st);
     });
     timed(K_LCPFIX, a.n, st, [&] {
-        launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, st);
+        launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, nullptr,
+                       st);
     });
     S5_HIP(hipGetLastError());
-    S5_HIP(hipMemcpyAsync(hg, glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
-    S5_HIP(hipStreamSynchronize(st));
+    return S5_OK;
+}
+
+void final_stats(const HostView& H, s5_stats* stats) {
+    stats->fallbacks = H.hg->fallbacks;
+    stats->base_items = (uint64_t)H.hg->n_base[0] + H.hg->n_base[1] + H.hg->n_base[2];
+}
+
+// The whole sort on one workspace, host-driven.  `host` is a pinned block of
+// >= 4 KiB.
+int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* host,
+             hipStream_t st, s5_stats* stats) {
+    memset(stats, 0, sizeof *stats);
+    const Layout L = make_layout(a.n, c, 0);
+    if (ws_bytes < L.total) return S5_ERR_NOMEM;
+    stats->workspace_bytes = L.total;
+    const Ptrs P = make_ptrs(L, (char*)ws);
+    const HostView H = host_view(host);
+    start_sort(a, c, L, P, st);
+    S5_HIP(hipGetLastError());
+    int rc = readback(P, H, 0, st);
+    if (!rc) rc = host_passes(a, c, L, P, H, 0, st, stats);
+    if (!rc) {
+        S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+        S5_HIP(hipStreamSynchronize(st));
+        final_stats(H, stats);
+        rc = H.hg->status ? S5_ERR_DEVICE : S5_OK;
+    }
     prof_collect();
-    return hg->status ? S5_ERR_DEVICE : S5_OK;
+    return rc;
+}
+
+// ---- graph-captured sorts --------------------------------------------------
+// The first `levels` passes, the base case and the boundary LCPs are captured
+// once into a hipGraph (kernels only: counters are cleared by a kernel) and
+// replayed by one launch.  Every pass kernel reads its work count on the
+// device; the base case and the LCP completion run only if no segment is left
+// for a further pass, otherwise the host finishes the remaining passes.
+
+struct GraphKey {
+    const void *chars, *offsets, *set_begin, *perm, *lcp, *ws;
+    size_t ws_bytes;
+    uint32_t num_sets, n, levels, tuned;
+    Cfg c;
+    int dev;
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec;
+};
+
+std::vector<GraphEntry> g_graphs;  // most recent last
+std::unordered_map<int, hipStream_t> g_capture_streams;
+constexpr size_t kGraphCache = 8;
+
+bool same_key(const GraphKey& x, const GraphKey& y) { return memcmp(&x, &y, sizeof x) == 0; }
+
+void graphs_release() {
+    for (auto& e : g_graphs) (void)hipGraphExecDestroy(e.exec);
+    g_graphs.clear();
+}
+
+void enqueue_graph_body(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
+                        uint32_t levels, hipStream_t st) {
+    start_sort(a, c, L, P, st);
+    for (uint32_t level = 0; level < levels; ++level) {
+        const int cur = (int)(level & 1u), buf = cur;
+        const PassShape S = graph_shape(P, L, c, cur);
+        pass_front(a, c, L, P, S, cur, buf, 0u, st);
+        if (c.mode == S5_SPLIT_LEARNED) {
+            launch_learn_check(0, P.lseg[cur], P.learn_seg, P.cs, c.beta, P.glob, S.learn, st);
+            pass_front(a, c, L, P, S, cur, buf, 1u, st);
+        }
+        pass_back(a, c, L, P, S, cur, buf, st);
+        launch_pass_stats(P.cnt[cur], P.cnt[cur ^ 1], P.glob, level, st);
+    }
+    const uint32_t* guard = &P.cnt[levels & 1u]->n_large;
+    Dyn bd[kBaseClasses];
+    for (int q = 0; q < kBaseClasses; ++q) {
+        const uint32_t units = q == 0 ? (L.caps.base[0] + kWaves - 1) / kWaves : L.caps.base[q];
+        bd[q] = dyn_of(&P.glob->n_base[q], L.caps.base[q], std::min(units, kGraphBaseGrid));
+    }
+    const uint32_t zero[kBaseClasses] = {0, 0, 0};
+    launch_base_sort(zero, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
+                     a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard, st);
+    launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, guard, st);
+}
+
+int get_graph(const GraphKey& key, const SortArgs& a, const Cfg& c, const Layout& L,
+              const Ptrs& P, hipGraphExec_t* out) {
+    for (size_t i = 0; i < g_graphs.size(); ++i)
+        if (same_key(g_graphs[i].key, key)) {
+            GraphEntry e = g_graphs[i];
+            g_graphs.erase(g_graphs.begin() + i);
+            g_graphs.push_back(e);
+            *out = e.exec;
+            return S5_OK;
+        }
+    hipStream_t& cs = g_capture_streams[key.dev];
+    if (!cs) S5_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    S5_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const bool prof = g_prof_on;
+    g_prof_on = false;  // no event records inside the capture
+    enqueue_graph_body(a, c, L, P, key.levels, cs);
+    g_prof_on = prof;
+    hipGraph_t graph = nullptr;
+    const hipError_t le = hipGetLastError();
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (le != hipSuccess || ee != hipSuccess || !graph) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return S5_ERR_HIP;
+    }
+    hipGraphExec_t exec = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) return S5_ERR_HIP;
+    if (g_graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(g_graphs.front().exec);
+        g_graphs.erase(g_graphs.begin());
+    }
+    g_graphs.push_back(GraphEntry{key, exec});
+    *out = exec;
+    return S5_OK;
+}
+
+int run_graph(const SortArgs& a, const Cfg& c, uint32_t levels, void* ws, size_t ws_bytes,
+              void* host, hipStream_t st, s5_stats* stats) {
+    memset(stats, 0, sizeof *stats);
+    const uint32_t tune_sets = a.tune_host ? a.num_sets : 0u;
+    const Layout L = make_layout(a.n, c, tune_sets);
+    if (ws_bytes < L.total) return S5_ERR_NOMEM;
+    stats->workspace_bytes = L.total;
+    const Ptrs P = make_ptrs(L, (char*)ws);
+    const HostView H = host_view(host);
+    GraphKey key;
+    memset(&key, 0, sizeof key);
+    key.chars = a.chars;
+    key.offsets = a.offsets;
+    key.set_begin = a.set_begin;
+    key.perm = a.perm;
+    key.lcp = a.lcp;
+    key.ws = ws;
+    key.ws_bytes = ws_bytes;
+    key.num_sets = a.num_sets;
+    key.n = a.n;
+    key.levels = levels;
+    key.tuned = tune_sets ? 1u : 0u;
+    key.c = c;
+    S5_HIP(hipGetDevice(&key.dev));
+    if (tune_sets)
+        S5_HIP(hipMemcpyAsync(P.set_tune, a.tune_host, (size_t)tune_sets * 4,
+                              hipMemcpyHostToDevice, st));
+    hipGraphExec_t exec = nullptr;
+    int rc = get_graph(key, a, c, L, P, &exec);
+    if (rc) return rc;
+    timed(K_GRAPH, a.n, st, [&] { (void)hipGraphLaunch(exec, st); });
+    S5_HIP(hipGetLastError());
+    rc = readback(P, H, (int)(levels & 1u), st);
+    if (!rc) {
+        stats->passes = H.hg->passes;
+        stats->moved_M = H.hg->moved;
+        stats->segments = H.hg->segments;
+        stats->max_bucket = H.hg->max_bucket0;
+        stats->entropy_bits = H.hg->moved0 ? H.hg->entropy_sum0 / (double)H.hg->moved0 : 0.0;
+        if (H.hc->n_large > 0) {
+            // deeper than the captured levels: the host finishes the sort
+            s5_stats tail;
+            memset(&tail, 0, sizeof tail);
+            rc = host_passes(a, c, L, P, H, levels, st, &tail);
+            stats->passes = tail.passes;
+            stats->moved_M += tail.moved_M;
+            stats->segments += tail.segments;
+        }
+    }
+    if (!rc) {
+        S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+        S5_HIP(hipStreamSynchronize(st));
+        final_stats(H, stats);
+        rc = H.hg->status ? S5_ERR_DEVICE : S5_OK;
+    }
+    prof_collect();
+    return rc;
 }
 
 int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_bytes,
-                hipStream_t st) {
+                hipStream_t st, bool graph) {
     Cfg c;
     int rc = resolve_cfg(cfg, &c);
     if (rc) return rc;
@@ -464,8 +694,18 @@ int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_byt
         r.status = S5_OK;
         return S5_OK;
     }
+    // per-set parameters raise the launch-wide limits they must fit in
+    if (a.tune_host) {
+        for (uint32_t s = 0; s < a.num_sets; ++s) {
+            const SetP t = unpack_set_tune(a.tune_host[s]);
+            c.T = std::max(c.T, t.T);
+            c.dmax = std::max(c.dmax, t.d_max);
+            c.T_caps = std::min(c.T_caps, t.T);
+            c.tile_caps = std::min(c.tile_caps, t.tile_min);
+        }
+    }
     std::lock_guard<std::mutex> g(g_mu);
-    const size_t need = make_layout(a.n, c).total;
+    const size_t need = make_layout(a.n, c, a.tune_host ? a.num_sets : 0u).total;
     void* host = nullptr;
     if (!ws) {
         DevPool* P = nullptr;
@@ -481,7 +721,8 @@ int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_byt
         host = P->host;
     }
     s5_stats stats;
-    rc = run_sort(a, c, ws, ws_bytes, host, st, &stats);
+    rc = graph ? run_graph(a, c, c.graph_levels, ws, ws_bytes, host, st, &stats)
+               : run_sort(a, c, ws, ws_bytes, host, st, &stats);
     StreamRecord& r = g_last[st];
     r.stats = stats;
     r.status = rc;
@@ -498,8 +739,8 @@ int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets
     (void)chars_len;
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
     if (n == 0xFFFFFFFFu) return S5_ERR_INVALID;
-    SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp};
-    return sort_common(a, cfg, workspace, workspace_bytes, stream);
+    SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
+    return sort_common(a, cfg, workspace, workspace_bytes, stream, false);
 }
 
 int s5_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* out_perm,
@@ -510,15 +751,35 @@ int s5_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t*
 size_t s5_workspace_bytes(uint32_t n, const s5_config* cfg) {
     Cfg c;
     if (resolve_cfg(cfg, &c)) return 0;
-    return make_layout(n, c).total;
+    return make_layout(n, c, 0).total;
 }
 
-int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
-                    const uint64_t* set_begin, uint32_t num_sets, uint32_t* out_perm,
-                    uint32_t* out_lcp, const s5_config* cfg, hipStream_t stream) {
+int s5_sort_batched_tuned(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                          const uint64_t* set_begin, uint32_t num_sets,
+                          const s5_set_tuning* set_tuning, uint32_t* out_perm, uint32_t* out_lcp,
+                          const s5_config* cfg, hipStream_t stream) {
     (void)chars_len;
     if (num_sets == 0) return S5_OK;
-    if (!set_begin) return S5_ERR_INVALID;
+    if (!set_begin || num_sets == 0xFFFFFFFFu) return S5_ERR_INVALID;
+    Cfg base;
+    if (resolve_cfg(cfg, &base)) return S5_ERR_INVALID;
+    // per-set parameters: validated and packed on the host
+    std::vector<uint32_t> packed;
+    if (set_tuning) {
+        packed.resize(num_sets);
+        for (uint32_t s = 0; s < num_sets; ++s) {
+            const s5_set_tuning& t = set_tuning[s];
+            const uint32_t v = t.splitters ? t.splitters : (1u << base.dmax) - 1;
+            uint32_t d = 0;
+            while (((1u << (d + 1)) - 1) <= v && d < 31) ++d;
+            if (v < 7 || v > 1023 || ((1u << d) - 1) != v) return S5_ERR_INVALID;
+            const uint32_t T = t.base_threshold ? t.base_threshold : base.T;
+            if (T < 64 || T > 2048) return S5_ERR_INVALID;
+            const uint32_t tile = t.tile ? t.tile : base.tile_min;
+            if (tile % 64 || tile > (1u << 20)) return S5_ERR_INVALID;
+            packed[s] = pack_set_tune(T, d, tile);
+        }
+    }
     uint64_t ends[2];
     if (hipMemcpyAsync(ends, set_begin, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         hipMemcpyAsync(ends + 1, set_begin + num_sets, 8, hipMemcpyDeviceToHost, stream) !=
@@ -528,8 +789,16 @@ int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* of
     if (ends[0] != 0 || ends[1] >= 0xFFFFFFFFull) return S5_ERR_INVALID;
     const uint32_t n = (uint32_t)ends[1];
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
-    SortArgs a{chars, offsets, set_begin, num_sets, n, out_perm, out_lcp};
-    return sort_common(a, cfg, nullptr, 0, stream);
+    SortArgs a{chars, offsets, set_begin, num_sets, n, out_perm, out_lcp,
+               set_tuning ? packed.data() : nullptr};
+    return sort_common(a, cfg, nullptr, 0, stream, true);
+}
+
+int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                    const uint64_t* set_begin, uint32_t num_sets, uint32_t* out_perm,
+                    uint32_t* out_lcp, const s5_config* cfg, hipStream_t stream) {
+    return s5_sort_batched_tuned(chars, chars_len, offsets, set_begin, num_sets, nullptr, out_perm,
+                                 out_lcp, cfg, stream);
 }
 
 int s5_stats_get(hipStream_t stream, s5_stats* host_out) {
@@ -560,6 +829,16 @@ void s5_release(void) {
     std::lock_guard<std::mutex> g(g_mu);
     int cur = 0;
     (void)hipGetDevice(&cur);
+    for (auto& kv : g_pools) {
+        (void)hipSetDevice(kv.first);
+        (void)hipDeviceSynchronize();
+    }
+    graphs_release();
+    for (auto& kv : g_capture_streams) {
+        (void)hipSetDevice(kv.first);
+        if (kv.second) (void)hipStreamDestroy(kv.second);
+    }
+    g_capture_streams.clear();
     for (auto& kv : g_pools) {
         (void)hipSetDevice(kv.first);
         (void)hipDeviceSynchronize();

@@ -71,6 +71,11 @@ struct Globals {
     unsigned long long base_elems;  // strings in those items
     uint32_t fallbacks;             // learned segments redone with sampled splitters
     uint32_t late_fallbacks;        // those of them rejected only on the exact histogram
+    // statistics kept on the device by graph-captured sorts (no per-pass readback)
+    uint32_t passes, pad;
+    unsigned long long moved, segments;        // sums over the passes
+    unsigned long long moved0, max_bucket0;    // first pass
+    double entropy_sum0;
 };
 
 // Learned splitters apply to segments of at least this many strings.
@@ -96,8 +101,20 @@ struct Caps {
     unsigned long long cm, cs;
 };
 
+// Launch mode of one pass kernel: host-driven (cnt == nullptr, the grid is
+// the work read back by the host) or graph mode (a fixed grid striding over
+// the device count at cnt, clamped to cap).
+struct Dyn {
+    const uint32_t* cnt = nullptr;
+    uint32_t cap = 0;
+    uint32_t grid = 0;
+};
+
 // Everything a planning step needs to append work.
 struct PlanCtx {
+    const uint64_t* set_begin;  // first string of every set (with per-set tuning)
+    const uint32_t* set_tune;   // packed per-set parameters, or nullptr
+    uint32_t num_sets;
     LSeg* lseg;           // next pass's segment list
     Counters* cnt;        // next pass's counters
     Seg* base_list[kBaseClasses];  // base-case items (all passes), per size class
@@ -110,5 +127,59 @@ struct PlanCtx {
     uint32_t d_max;       // tree depth limit for this sort
     uint32_t tile_min;    // minimum strings per tile
 };
+
+// Per-set parameters of a batched sort, packed in one word: base threshold T
+// (bits 0..11), tree depth limit (bits 12..15), minimum tile / 64 (bits 16..31).
+__host__ __device__ inline uint32_t pack_set_tune(uint32_t T, uint32_t d_max, uint32_t tile_min) {
+    return (T & 0xFFFu) | ((d_max & 0xFu) << 12) | ((tile_min / 64u) << 16);
+}
+
+// Planning parameters of one set: base threshold, tree depth limit, minimum tile.
+struct SetP {
+    uint32_t T, d_max, tile_min;
+};
+
+__host__ __device__ inline SetP unpack_set_tune(uint32_t w) {
+    return SetP{w & 0xFFFu, (w >> 12) & 0xFu, (w >> 16) * 64u};
+}
+
+__host__ __device__ inline SetP default_set_params(const PlanCtx& c) {
+    return SetP{c.T, c.d_max, c.tile_min};
+}
+
+// Parameters of the set whose first string is `base` (the last set that
+// starts at or before it: sets starting at the same place before it are empty).
+__device__ inline SetP set_params(const PlanCtx& c, uint32_t base) {
+    if (!c.set_tune) return default_set_params(c);
+    uint32_t lo = 0, hi = c.num_sets - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (c.set_begin[mid] <= base) lo = mid; else hi = mid - 1;
+    }
+    return unpack_set_tune(c.set_tune[lo]);
+}
+
+// Work units of one launch.  A host-driven launch sizes its grid to the work
+// (wcnt == nullptr: the grid is the count).  A graph-captured launch reads the
+// count from a counter written by an earlier kernel, clamps it to the storage
+// capacity, and does nothing once the status word holds an error or while
+// *guard is non-zero.  One thread reads and broadcasts it, so every wavefront
+// of the block runs the same number of iterations.
+__device__ inline uint32_t block_work_count(const uint32_t* wcnt, uint32_t cap,
+                                            const Globals* glob, uint32_t grid_units,
+                                            const uint32_t* guard = nullptr) {
+    if (!wcnt) return grid_units;
+    __shared__ uint32_t s_units;
+    if (threadIdx.x == 0) {
+        uint32_t u = 0;
+        if (!glob->status && !(guard && *guard)) {
+            u = *wcnt;
+            if (u > cap) u = cap;
+        }
+        s_units = u;
+    }
+    __syncthreads();
+    return s_units;
+}
 
 }  // namespace s5

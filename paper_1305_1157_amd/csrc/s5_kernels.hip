@@ -30,6 +30,7 @@
 // followed, once every bucket is small, by k_base_sort (LDS sorter that emits
 // LCPs) and k_lcp_fix (LCPs at bucket boundaries).
 #include "s5_internal.h"
+#include "s5_launch.h"
 #include "s5_word.h"
 
 namespace s5 {
@@ -89,7 +90,7 @@ struct PlanTally {
 };
 
 // tree depth and tiles of a large segment of `size` strings
-__device__ __forceinline__ void seg_shape(uint32_t size, const PlanCtx& c, uint32_t& d,
+__device__ __forceinline__ void seg_shape(uint32_t size, const SetP& c, uint32_t& d,
                                           uint32_t& ulen, uint32_t& tiles, uint32_t& chunks) {
     d = 1;
     while (d < c.d_max && ((uint64_t)c.T << d) < 2ull * size) ++d;  // 2^d * T/2 >= size
@@ -101,14 +102,15 @@ __device__ __forceinline__ void seg_shape(uint32_t size, const PlanCtx& c, uint3
 }
 
 // Phase 1 for one request (begin, size >= 2, depth).
-__device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, PlanTally* T) {
-    if (size <= c.T) {
+__device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, const SetP& sp,
+                                           PlanTally* T) {
+    if (size <= sp.T) {
         atomicAdd(&T->n_base[base_class(size)], 1u);
         atomicAdd(&T->base_elems, (unsigned long long)size);
         return;
     }
     uint32_t d, ulen, tiles, chunks;
-    seg_shape(size, c, d, ulen, tiles, chunks);
+    seg_shape(size, sp, d, ulen, tiles, chunks);
     const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
     atomicAdd(&T->n_large, 1u);
     atomicAdd(&T->tiles, tiles);
@@ -163,8 +165,8 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
 
 // Phase 3 for one request: take slots from the LDS counters and write the record.
 __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_t base,
-                          uint32_t buf, const PlanCtx& c, PlanTally* T) {
-    if (size <= c.T) {
+                          uint32_t buf, const PlanCtx& c, const SetP& sp, PlanTally* T) {
+    if (size <= sp.T) {
         const int q = base_class(size);
         uint32_t slot = atomicAdd(&T->n_base[q], 1u);
         Seg s;
@@ -176,7 +178,7 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
         return;
     }
     uint32_t d, ulen, tiles, chunks;
-    seg_shape(size, c, d, ulen, tiles, chunks);
+    seg_shape(size, sp, d, ulen, tiles, chunks);
     const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
     LSeg g;
     g.begin = begin;
@@ -253,32 +255,56 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
         }
     }
     const bool req = e > b + 1;
-    if (req) plan_tally(e - b, ctx, &T);
+    const SetP sp = (ctx.set_tune && s < num_sets) ? unpack_set_tune(ctx.set_tune[s])
+                                                   : default_set_params(ctx);
+    if (req) plan_tally(e - b, ctx, sp, &T);
     __syncthreads();
     if (threadIdx.x == 0) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
-    if (req) plan_emit(b, e - b, 0, b, 0, ctx, &T);
+    if (req) plan_emit(b, e - b, 0, b, 0, ctx, sp, &T);
+}
+
+// Graph-captured sorts keep their statistics on the device: after each pass,
+// add the pass's totals (and the first pass's bucket statistics).
+__global__ void k_pass_stats(const Counters* cur, const Counters* next, Globals* glob,
+                             uint32_t level) {
+    if (threadIdx.x != 0 || glob->status || !cur->n_large) return;
+    glob->passes += 1;
+    glob->moved += cur->moved;
+    glob->segments += cur->n_large;
+    if (level == 0) {
+        glob->moved0 = cur->moved;
+        glob->max_bucket0 = next->max_bucket;
+        glob->entropy_sum0 = next->entropy_sum;
+    }
+}
+
+// zero n words (a kernel, so that graph captures hold no memset nodes)
+__global__ void k_zero_words(uint32_t* p, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
 }
 
 // ---------------------------------------------------------------------------
 // K2: sample, sort the sample, select splitters recursively, build the tree
 
-__global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uint64_t* key_in,
-                                                     uint32_t alpha, uint64_t seed,
-                                                     uint64_t* tree_lo, uint64_t* tree_in,
-                                                     uint8_t* tree_lcp, uint32_t* tile_tab,
-                                                     uint32_t* chunk_tab, Counters* next_cnt) {
+__device__ __forceinline__ void sample_tree_body(uint32_t slot, uint32_t redo, const LSeg* lseg,
+                                                 const uint64_t* key_in, uint32_t alpha,
+                                                 uint64_t seed, uint64_t* tree_lo,
+                                                 uint64_t* tree_in, uint8_t* tree_lcp,
+                                                 uint32_t* tile_tab, uint32_t* chunk_tab) {
     extern __shared__ uint64_t smp[];  // sample, padded to a power of two
-    // the next pass's counters are planned later in this pass: clear them here
-    if (blockIdx.x == 0 && threadIdx.x < sizeof(Counters) / 4) ((uint32_t*)next_cnt)[threadIdx.x] = 0;
     __shared__ uint32_t ra[1u << kDMax], rb[1u << kDMax];
     __shared__ uint64_t t[1u << kDMax];
-    const uint32_t slot = blockIdx.x;
     const LSeg g = lseg[slot];
     const uint32_t tid = threadIdx.x;
-    for (uint32_t u = tid; u < g.tiles; u += kWG) tile_tab[g.tile_base + u] = slot;
-    for (uint32_t c = tid; c < g.chunks; c += kWG) chunk_tab[g.chunk_base + c] = slot;
+    if (!redo) {
+        for (uint32_t u = tid; u < g.tiles; u += kWG) tile_tab[g.tile_base + u] = slot;
+        for (uint32_t c = tid; c < g.chunks; c += kWG) chunk_tab[g.chunk_base + c] = slot;
+    } else if (g.pad1 != 1u) {
+        return;  // only segments whose learned splitters failed are redone
+    }
     if (g.pad0 != 0xFFFFFFFFu) return;  // learned splitters: the tree comes from the model
     const uint32_t m = alpha * (g.v + 1) - 1;
     uint32_t P = 1;
@@ -359,6 +385,32 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
     }
 }
 
+// One workgroup per segment (G: grid-stride over a device count, graph mode).
+// redo = 1: only segments flagged by the exact learned-splitter check.
+template <bool G>
+__global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uint64_t* key_in,
+                                                     uint32_t alpha, uint64_t seed,
+                                                     uint64_t* tree_lo, uint64_t* tree_in,
+                                                     uint8_t* tree_lcp, uint32_t* tile_tab,
+                                                     uint32_t* chunk_tab, Counters* next_cnt,
+                                                     const uint32_t* wcnt, uint32_t cap,
+                                                     const Globals* glob, uint32_t redo) {
+    // the next pass's counters are planned later in this pass: clear them here
+    if (!redo && blockIdx.x == 0 && threadIdx.x < sizeof(Counters) / 4)
+        ((uint32_t*)next_cnt)[threadIdx.x] = 0;
+    if (!G) {
+        sample_tree_body(blockIdx.x, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp,
+                         tile_tab, chunk_tab);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        sample_tree_body(u, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp, tile_tab,
+                         chunk_tab);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K3: classification + per-tile histogram.  The workgroup walks its tile in
 // steps of kWG * U strings; every wavefront classifies U chunks of 64 coalesced
@@ -367,16 +419,17 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
 // into the tile's row of the count matrix.
 
 template <int U>
-__global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32_t* tile_tab,
-                                                  const uint64_t* key_in, const uint64_t* tree_lo,
-                                                  const uint64_t* tree_in, uint16_t* bid,
-                                                  uint32_t* cm, uint32_t vmax, uint32_t kmax) {
+__device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, const LSeg* lseg,
+                                              const uint32_t* tile_tab, const uint64_t* key_in,
+                                              const uint64_t* tree_lo, const uint64_t* tree_in,
+                                              uint16_t* bid, uint32_t* cm, uint32_t vmax,
+                                              uint32_t kmax) {
     extern __shared__ uint64_t dyn[];
     uint64_t* t = dyn;
     uint64_t* tin = t + (vmax + 1);
     uint32_t* hist = (uint32_t*)(tin + (vmax + 1));  // kWaves * kmax
-    const uint32_t tile = blockIdx.x;
     const LSeg g = lseg[tile_tab[tile]];
+    if (redo && g.pad1 != 1u) return;
     for (uint32_t i = threadIdx.x; i <= g.v; i += kWG) {
         t[i] = tree_lo[g.tree_base + i];
         tin[i] = tree_in[g.tree_base + i];
@@ -426,13 +479,33 @@ __global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32
     }
 }
 
+template <int U, bool G>
+__global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32_t* tile_tab,
+                                                  const uint64_t* key_in, const uint64_t* tree_lo,
+                                                  const uint64_t* tree_in, uint16_t* bid,
+                                                  uint32_t* cm, uint32_t vmax, uint32_t kmax,
+                                                  const uint32_t* wcnt, uint32_t cap,
+                                                  const Globals* glob, uint32_t redo) {
+    if (!G) {
+        classify_body<U>(blockIdx.x, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax,
+                         kmax);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        classify_body<U>(u, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K4a: exclusive scan down every bucket column within a chunk of unit rows
 
-__global__ __launch_bounds__(256) void k_colscan(const LSeg* lseg, const uint32_t* chunk_tab,
-                                                 uint32_t* cm, uint32_t* cs) {
-    const uint32_t cg = blockIdx.x;
+__device__ __forceinline__ void colscan_body(uint32_t cg, uint32_t redo, const LSeg* lseg,
+                                             const uint32_t* chunk_tab, uint32_t* cm,
+                                             uint32_t* cs) {
     const LSeg g = lseg[chunk_tab[cg]];
+    if (redo && g.pad1 != 1u) return;
     const uint32_t b = blockIdx.y * kWG + threadIdx.x;
     if (b >= g.k) return;
     const uint32_t c = cg - g.chunk_base;
@@ -448,17 +521,30 @@ __global__ __launch_bounds__(256) void k_colscan(const LSeg* lseg, const uint32_
     cs[g.cs_base + (uint64_t)c * g.k + b] = run;
 }
 
+template <bool G>
+__global__ __launch_bounds__(256) void k_colscan(const LSeg* lseg, const uint32_t* chunk_tab,
+                                                 uint32_t* cm, uint32_t* cs, const uint32_t* wcnt,
+                                                 uint32_t cap, const Globals* glob, uint32_t redo) {
+    if (!G) {
+        colscan_body(blockIdx.x, redo, lseg, chunk_tab, cm, cs);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) colscan_body(u, redo, lseg, chunk_tab, cm, cs);
+}
+
 // ---------------------------------------------------------------------------
 // K4b: chunk prefixes, bucket starts, and the plan of every bucket
 
-__global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t* cs,
-                                                     uint32_t* bstart, const uint64_t* tree_in,
-                                                     const uint8_t* tree_lcp, PlanCtx ctx,
-                                                     uint32_t next_buf) {
+__device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg, uint32_t* cs,
+                                                 uint32_t* bstart, const uint64_t* tree_in,
+                                                 const uint8_t* tree_lcp, const PlanCtx& ctx,
+                                                 uint32_t next_buf) {
     __shared__ uint32_t tot[1u << (kDMax + 1)];
     __shared__ uint32_t st[1u << (kDMax + 1)];
     __shared__ uint32_t tmp[kWG + 1];
-    const LSeg g = lseg[blockIdx.x];
+    const LSeg g = lseg[seg];
+    const SetP sp = set_params(ctx, g.base);
     const uint32_t k = g.k;
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
         uint32_t run = 0;
@@ -523,14 +609,32 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
         return g.depth + ((j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j]);
     };
     for (uint32_t b = threadIdx.x; b < k; b += kWG)
-        if (next_depth(b) != 0xFFFFFFFFu) plan_tally(tot[b], ctx, &T);
+        if (next_depth(b) != 0xFFFFFFFFu) plan_tally(tot[b], ctx, sp, &T);
     __syncthreads();
     if (threadIdx.x == 0) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
         const uint32_t nd = next_depth(b);
-        if (nd != 0xFFFFFFFFu) plan_emit(g.begin + st[b], tot[b], nd, g.base, next_buf, ctx, &T);
+        if (nd != 0xFFFFFFFFu)
+            plan_emit(g.begin + st[b], tot[b], nd, g.base, next_buf, ctx, sp, &T);
+    }
+}
+
+template <bool G>
+__global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t* cs,
+                                                     uint32_t* bstart, const uint64_t* tree_in,
+                                                     const uint8_t* tree_lcp, PlanCtx ctx,
+                                                     uint32_t next_buf, const uint32_t* wcnt,
+                                                     uint32_t cap) {
+    if (!G) {
+        bucket_plan_body(blockIdx.x, lseg, cs, bstart, tree_in, tree_lcp, ctx, next_buf);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, ctx.glob, gridDim.x);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        bucket_plan_body(u, lseg, cs, bstart, tree_in, tree_lcp, ctx, next_buf);
+        __syncthreads();
     }
 }
 
@@ -576,12 +680,12 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
     return pre + inc - v;
 }
 
-__global__ __launch_bounds__(256) void k_scatter(
-    const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
-    const uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm,
-    const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
-    const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp,
-    uint32_t vmax, uint32_t kmax) {
+__device__ __forceinline__ void scatter_body(
+    uint32_t tile, const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid,
+    const uint64_t* key_in, const uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out,
+    const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in,
+    const uint8_t* tree_lcp, const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
+    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax) {
     extern __shared__ uint64_t dyn[];
     uint64_t* SK = dyn;                                   // kSubTile staged keys
     uint32_t* SI = (uint32_t*)(SK + kSubTile);            // kSubTile staged indices
@@ -595,7 +699,6 @@ __global__ __launch_bounds__(256) void k_scatter(
     __shared__ uint32_t wl[kWaves];
     (void)vmax;
 
-    const uint32_t tile = blockIdx.x;
     const LSeg g = lseg[tile_tab[tile]];
     const uint32_t k = g.k, tid = threadIdx.x;
     const uint32_t row = tile - g.tile_base, chunk = row / kChunkRows;
@@ -741,6 +844,26 @@ __global__ __launch_bounds__(256) void k_scatter(
     }
 }
 
+template <bool G>
+__global__ __launch_bounds__(256) void k_scatter(
+    const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
+    const uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm,
+    const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
+    const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp,
+    uint32_t vmax, uint32_t kmax, const uint32_t* wcnt, uint32_t cap, const Globals* glob) {
+    if (!G) {
+        scatter_body(blockIdx.x, lseg, tile_tab, bid, key_in, idx_in, key_out, idx_out, cm, cs,
+                     bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        scatter_body(u, lseg, tile_tab, bid, key_in, idx_in, key_out, idx_out, cm, cs, bstart,
+                     tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K8: base case.  A bucket of n <= T strings that share `depth` leading
 // bytes is finished on chip:
@@ -825,14 +948,12 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
     return a;
 }
 
-__global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_items,
-                                                   const uint64_t* key0, const uint64_t* key1,
-                                                   const uint32_t* idx0, const uint32_t* idx1,
-                                                   const uint8_t* chars, const uint64_t* offsets,
-                                                   uint32_t* out_perm, uint32_t* out_lcp) {
+__device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
+                                               const uint64_t* key0, const uint64_t* key1,
+                                               const uint32_t* idx0, const uint32_t* idx1,
+                                               const uint8_t* chars, const uint64_t* offsets,
+                                               uint32_t* out_perm, uint32_t* out_lcp) {
     const uint32_t lane = lane_id();
-    const uint32_t item = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (item >= n_items) return;  // uniform per wavefront
     const Seg it = items[item];
     const uint32_t buf = it.depth >> 31;
     const uint32_t h = it.depth & ~kBufBit;
@@ -845,6 +966,27 @@ __global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_
     wave_sort(k, a);
     const uint32_t fa = wave_rounds(k, a, valid, h, lane, iin, chars, offsets, out_lcp + it.begin);
     if (valid) out_perm[it.begin + lane] = iin[fa & 0xFFFFu] - it.base;
+}
+
+// One wavefront per item (items are wavefront-uniform; no workgroup barriers).
+template <bool G>
+__global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_items,
+                                                   const uint64_t* key0, const uint64_t* key1,
+                                                   const uint32_t* idx0, const uint32_t* idx1,
+                                                   const uint8_t* chars, const uint64_t* offsets,
+                                                   uint32_t* out_perm, uint32_t* out_lcp,
+                                                   const uint32_t* wcnt, uint32_t cap,
+                                                   const Globals* glob, const uint32_t* guard) {
+    if (!G) {
+        const uint32_t it = blockIdx.x * kWaves + (threadIdx.x >> 6);
+        if (it < n_items)  // uniform per wavefront
+            base_wave_body(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, glob, n_items, guard);
+    for (uint32_t it = blockIdx.x * kWaves + (threadIdx.x >> 6); it < units;
+         it += gridDim.x * kWaves)
+        base_wave_body(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp);
 }
 
 template <int E, int J>
@@ -974,11 +1116,12 @@ __device__ uint32_t block_scan_max_add(uint32_t& mx, uint32_t& ad, uint32_t* wl)
 }
 
 template <int EMAX>
-__global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint64_t* key0,
-                                                    const uint64_t* key1, const uint32_t* idx0,
-                                                    const uint32_t* idx1, const uint8_t* chars,
-                                                    const uint64_t* offsets, uint32_t* out_perm,
-                                                    uint32_t* out_lcp, uint32_t pmax) {
+__device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
+                                                const uint64_t* key0, const uint64_t* key1,
+                                                const uint32_t* idx0, const uint32_t* idx1,
+                                                const uint8_t* chars, const uint64_t* offsets,
+                                                uint32_t* out_perm, uint32_t* out_lcp,
+                                                uint32_t pmax) {
     extern __shared__ uint64_t dyn[];
     uint64_t* K = dyn;                          // pmax keys, by position
     uint64_t* SK = K + pmax;                    // pmax keys, compacted members
@@ -988,7 +1131,7 @@ __global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint
     uint16_t* POS = ST + pmax;                  // pmax position of each compacted member
     uint8_t* F = (uint8_t*)(POS + pmax);        // pmax: pair (i-1, i) undecided
     __shared__ uint32_t wl[2 * kWaves];
-    const Seg it = items[blockIdx.x];
+    const Seg it = items[item];
     const uint32_t buf = it.depth >> 31;
     uint32_t h = it.depth & ~kBufBit;
     const uint32_t n = it.size;
@@ -1109,6 +1252,27 @@ __global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint
     for (uint32_t i = tid; i < n; i += kWG) out_perm[it.begin + i] = iin[A[i] & 0xFFFFu] - it.base;
 }
 
+template <int EMAX, bool G>
+__global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint64_t* key0,
+                                                    const uint64_t* key1, const uint32_t* idx0,
+                                                    const uint32_t* idx1, const uint8_t* chars,
+                                                    const uint64_t* offsets, uint32_t* out_perm,
+                                                    uint32_t* out_lcp, uint32_t pmax,
+                                                    const uint32_t* wcnt, uint32_t cap,
+                                                    const Globals* glob, const uint32_t* guard) {
+    if (!G) {
+        base_block_body<EMAX>(blockIdx.x, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+                              out_lcp, pmax);
+        return;
+    }
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x, guard);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+        base_block_body<EMAX>(u, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                              pmax);
+        __syncthreads();
+    }
+}
+
 // ---------------------------------------------------------------------------
 // K9: LCPs at bucket boundaries.  A boundary between two buckets of a pass at
 // depth h holds kLcpFlag | h; both strings share h bytes (the bucket
@@ -1117,7 +1281,8 @@ __global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint
 __global__ __launch_bounds__(256) void k_lcp_fix(const uint8_t* chars, const uint64_t* offsets,
                                                  const uint64_t* set_begin, uint32_t num_sets,
                                                  uint32_t n, const uint32_t* out_perm,
-                                                 uint32_t* out_lcp) {
+                                                 uint32_t* out_lcp, const uint32_t* guard) {
+    if (guard && *guard) return;  // large segments remain: the host finishes them first
     uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0 || p >= n) return;
     uint32_t l = out_lcp[p];
@@ -1197,10 +1362,16 @@ __global__ __launch_bounds__(256) void k_classify_plain(const uint64_t* keys, ui
 }
 
 // ---------------------------------------------------------------------------
-// host-side launchers
+// host-side launchers.  Dyn selects the launch mode: host-driven (cnt ==
+// nullptr; the grid is the work the host read back) or graph mode (a fixed
+// grid that strides over the count at cnt, clamped to cap).
 
 #define S5_LAUNCH(kern, grid, block, lds, stream, ...)                                  \
     hipLaunchKernelGGL(kern, grid, block, lds, stream, __VA_ARGS__)
+
+static inline uint32_t dyn_grid(const Dyn& dy, uint32_t host_units) {
+    return dy.cnt ? dy.grid : host_units;
+}
 
 void launch_init_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint64_t* key,
                       uint32_t* idx, hipStream_t st) {
@@ -1223,40 +1394,78 @@ void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
               n, out_perm, out_lcp, ctx);
 }
 
+void launch_pass_stats(const Counters* cur, const Counters* next, Globals* glob, uint32_t level,
+                       hipStream_t st) {
+    S5_LAUNCH(k_pass_stats, dim3(1), dim3(64), 0, st, cur, next, glob, level);
+}
+
+void launch_zero_words(void* p, size_t bytes, hipStream_t st) {
+    const uint32_t n = (uint32_t)(bytes / 4);
+    if (n) S5_LAUNCH(k_zero_words, dim3((n + 255) / 256), dim3(256), 0, st, (uint32_t*)p, n);
+}
+
 void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_in,
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
                         uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* tile_tab,
-                        uint32_t* chunk_tab, Counters* next_cnt, hipStream_t st) {
+                        uint32_t* chunk_tab, Counters* next_cnt, const Globals* glob,
+                        const Dyn& dy, uint32_t redo, hipStream_t st) {
     uint32_t m = alpha * (vmax + 1) - 1, P = 1;
     while (P < m) P <<= 1;
-    S5_LAUNCH(k_sample_tree, dim3(n_large), dim3(kWG), (size_t)P * 8, st, lseg, key_in, alpha,
-              seed, tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, next_cnt);
+    if (dy.cnt)
+        S5_LAUNCH(k_sample_tree<true>, dim3(dy.grid), dim3(kWG), (size_t)P * 8, st, lseg, key_in,
+                  alpha, seed, tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, next_cnt, dy.cnt,
+                  dy.cap, glob, redo);
+    else
+        S5_LAUNCH(k_sample_tree<false>, dim3(n_large), dim3(kWG), (size_t)P * 8, st, lseg, key_in,
+                  alpha, seed, tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, next_cnt, dy.cnt,
+                  dy.cap, glob, redo);
 }
 
 void launch_classify(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
                      const uint64_t* key_in, const uint64_t* tree_lo, const uint64_t* tree_in,
-                     uint16_t* bid, uint32_t* cm, uint32_t vmax, uint32_t kmax, hipStream_t st) {
+                     uint16_t* bid, uint32_t* cm, uint32_t vmax, uint32_t kmax,
+                     const Globals* glob, const Dyn& dy, uint32_t redo, hipStream_t st) {
     size_t lds = (size_t)(vmax + 1) * 16 + (size_t)kWaves * kmax * 4;
-    dim3 grid(tiles);
+    dim3 grid(dyn_grid(dy, tiles));
+#define S5_CLASSIFY(U)                                                                       \
+    do {                                                                                     \
+        if (dy.cnt)                                                                          \
+            S5_LAUNCH((k_classify<U, true>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in,  \
+                      tree_lo, tree_in, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo);     \
+        else                                                                                 \
+            S5_LAUNCH((k_classify<U, false>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, \
+                      tree_lo, tree_in, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo);     \
+    } while (0)
     switch (unroll) {
-        case 1: S5_LAUNCH(k_classify<1>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
-        case 2: S5_LAUNCH(k_classify<2>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
-        case 8: S5_LAUNCH(k_classify<8>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
-        default: S5_LAUNCH(k_classify<4>, grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax); break;
+        case 1: S5_CLASSIFY(1); break;
+        case 2: S5_CLASSIFY(2); break;
+        case 8: S5_CLASSIFY(8); break;
+        default: S5_CLASSIFY(4); break;
     }
+#undef S5_CLASSIFY
 }
 
 void launch_colscan(uint32_t chunks, uint32_t kmax, const LSeg* lseg, const uint32_t* chunk_tab,
-                    uint32_t* cm, uint32_t* cs, hipStream_t st) {
-    S5_LAUNCH(k_colscan, dim3(chunks, (kmax + kWG - 1) / kWG), dim3(kWG), 0, st, lseg, chunk_tab,
-              cm, cs);
+                    uint32_t* cm, uint32_t* cs, const Globals* glob, const Dyn& dy, uint32_t redo,
+                    hipStream_t st) {
+    const dim3 grid(dyn_grid(dy, chunks), (kmax + kWG - 1) / kWG);
+    if (dy.cnt)
+        S5_LAUNCH(k_colscan<true>, grid, dim3(kWG), 0, st, lseg, chunk_tab, cm, cs, dy.cnt, dy.cap,
+                  glob, redo);
+    else
+        S5_LAUNCH(k_colscan<false>, grid, dim3(kWG), 0, st, lseg, chunk_tab, cm, cs, dy.cnt, dy.cap,
+                  glob, redo);
 }
 
 void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t* bstart,
                         const uint64_t* tree_in, const uint8_t* tree_lcp, const PlanCtx& ctx,
-                        uint32_t next_buf, hipStream_t st) {
-    S5_LAUNCH(k_bucket_plan, dim3(n_large), dim3(kWG), 0, st, lseg, cs, bstart, tree_in, tree_lcp,
-              ctx, next_buf);
+                        uint32_t next_buf, const Dyn& dy, hipStream_t st) {
+    if (dy.cnt)
+        S5_LAUNCH(k_bucket_plan<true>, dim3(dy.grid), dim3(kWG), 0, st, lseg, cs, bstart, tree_in,
+                  tree_lcp, ctx, next_buf, dy.cnt, dy.cap);
+    else
+        S5_LAUNCH(k_bucket_plan<false>, dim3(n_large), dim3(kWG), 0, st, lseg, cs, bstart, tree_in,
+                  tree_lcp, ctx, next_buf, dy.cnt, dy.cap);
 }
 
 void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
@@ -1264,46 +1473,78 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs,
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
-                    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, hipStream_t st) {
+                    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
+                    const Dyn& dy, hipStream_t st) {
     (void)unroll;
     const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
                        (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
-    S5_LAUNCH(k_scatter, dim3(tiles), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in, idx_in,
-              key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,
-              out_lcp, vmax, kmax);
+    if (dy.cnt)
+        S5_LAUNCH(k_scatter<true>, dim3(dy.grid), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,
+                  idx_in, key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
+                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob);
+    else
+        S5_LAUNCH(k_scatter<false>, dim3(tiles), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,
+                  idx_in, key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
+                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob);
 }
 
-void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
-                      const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
-                      const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
-                      uint32_t* out_lcp, uint32_t T, hipStream_t st) {
-    if (n_items[0])
-        S5_LAUNCH(k_base_wave, dim3((n_items[0] + kWaves - 1) / kWaves), dim3(kWG), 0, st,
-                  items[0], n_items[0], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp);
+// Host-driven: n_items[q] items of class q.  Graph mode (dy[q].cnt set): the
+// counts are read on the device, and nothing runs while *guard != 0.
+template <bool G>
+static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
+                             const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
+                             const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
+                             uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
+                             const uint32_t* guard, hipStream_t st) {
+    if (G || n_items[0]) {
+        const uint32_t g = G ? dy[0].grid : (n_items[0] + kWaves - 1) / kWaves;
+        S5_LAUNCH(k_base_wave<G>, dim3(g), dim3(kWG), 0, st, items[0], n_items[0], key0, key1,
+                  idx0, idx1, chars, offsets, out_perm, out_lcp, dy[0].cnt, dy[0].cap, glob,
+                  guard);
+    }
     uint32_t PT = 1;
     while (PT < T) PT <<= 1;
     const size_t per = 8 + 8 + 4 + 4 + 2 + 2 + 1;
-    if (n_items[1]) {
+    if (G || n_items[1]) {
         const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
-        S5_LAUNCH(k_base_block<kBaseMid / kWG>, dim3(n_items[1]), dim3(kWG), per * P, st, items[1],
-                  key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P);
+        S5_LAUNCH((k_base_block<kBaseMid / kWG, G>), dim3(G ? dy[1].grid : n_items[1]), dim3(kWG),
+                  per * P, st, items[1], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                  P, dy[1].cnt, dy[1].cap, glob, guard);
     }
-    if (n_items[2]) {
+    if ((G || n_items[2]) && PT > kBaseMid) {
+        const dim3 g(G ? dy[2].grid : n_items[2]);
         if (PT <= 4u * kWG)
-            S5_LAUNCH(k_base_block<4>, dim3(n_items[2]), dim3(kWG), per * PT, st, items[2], key0,
-                      key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT);
+            S5_LAUNCH((k_base_block<4, G>), g, dim3(kWG), per * PT, st, items[2], key0, key1, idx0,
+                      idx1, chars, offsets, out_perm, out_lcp, PT, dy[2].cnt, dy[2].cap, glob,
+                      guard);
         else
-            S5_LAUNCH(k_base_block<8>, dim3(n_items[2]), dim3(kWG), per * PT, st, items[2], key0,
-                      key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT);
+            S5_LAUNCH((k_base_block<8, G>), g, dim3(kWG), per * PT, st, items[2], key0, key1, idx0,
+                      idx1, chars, offsets, out_perm, out_lcp, PT, dy[2].cnt, dy[2].cap, glob,
+                      guard);
     }
+}
+
+// Host-driven: n_items[q] items of class q.  Graph mode (dy[0].cnt set): the
+// counts are read on the device, and nothing runs while *guard != 0.
+void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
+                      const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
+                      const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
+                      uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
+                      const uint32_t* guard, hipStream_t st) {
+    if (dy[0].cnt)
+        base_sort_launch<true>(n_items, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+                               out_lcp, T, glob, dy, guard, st);
+    else
+        base_sort_launch<false>(n_items, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+                                out_lcp, T, glob, dy, guard, st);
 }
 
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,
                     uint32_t num_sets, uint32_t n, const uint32_t* out_perm, uint32_t* out_lcp,
-                    hipStream_t st) {
+                    const uint32_t* guard, hipStream_t st) {
     if (n < 2) return;
     S5_LAUNCH(k_lcp_fix, dim3((n + 255) / 256), dim3(256), 0, st, chars, offsets, set_begin,
-              num_sets, n, out_perm, out_lcp);
+              num_sets, n, out_perm, out_lcp, guard);
 }
 
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,

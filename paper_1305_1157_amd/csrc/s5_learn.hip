@@ -21,6 +21,7 @@
 // fixed order and applies the identical Adam update, so the result is
 // deterministic.
 #include "s5_internal.h"
+#include "s5_launch.h"
 #include "s5_word.h"
 
 namespace s5 {
@@ -158,14 +159,15 @@ __device__ __forceinline__ float summed_grad(const LearnCtx& c, uint32_t slot, u
 // one training step: update from the previous partial gradients, then the
 // partial gradients of this step's weights over this group's 256 samples.
 
-__global__ __launch_bounds__(256) void k_learn_step(LearnCtx c, uint32_t step, float lr) {
+__device__ __forceinline__ void learn_step_body(const LearnCtx& c, uint32_t slot, uint32_t step,
+                                                float lr) {
     __shared__ float w[kNPS];
     __shared__ float sx[kGrp * 8];
     __shared__ __align__(16) float sh1[kGrp * kS4];
     __shared__ float sh2[kGrp * kS];  // later reused for the first layer's deltas
     __shared__ float sd2[kGrp * kS];
     __shared__ float sd3[kGrp];
-    const uint32_t slot = blockIdx.y, grp = blockIdx.x, tid = threadIdx.x;
+    const uint32_t grp = blockIdx.x, tid = threadIdx.x;
     const uint32_t prev = (step + 1) & 1u, cur = step & 1u;
     const float* wp = wbuf(c, slot, prev);
     for (uint32_t p = tid; p < kNP; p += kGrp) {
@@ -220,6 +222,7 @@ __global__ __launch_bounds__(256) void k_learn_step(LearnCtx c, uint32_t step, f
     {
         const uint32_t r = tid >> 3, jq = (tid & 7u) << 2;
         float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, g3 = 0.0f;
+#pragma unroll 8
         for (uint32_t b = 0; b < kGrp; ++b) {
             const float d = sd2[b * kS + r];
             const float4 h = *reinterpret_cast<const float4*>(&sh1[b * kS4 + jq]);
@@ -235,14 +238,17 @@ __global__ __launch_bounds__(256) void k_learn_step(LearnCtx c, uint32_t step, f
         o[3] = g3;
         if (tid < 32) {
             float g = 0.0f;
+#pragma unroll 8
             for (uint32_t b = 0; b < kGrp; ++b) g += sd2[b * kS + tid];
             out[oB2 + tid] = g;
         } else if (tid < 64) {
             float g = 0.0f;
+#pragma unroll 8
             for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd3[b], sh2[b * kS + tid - 32], g);
             out[oW3 + tid - 32] = g;
         } else if (tid == 64) {
             float g = 0.0f;
+#pragma unroll 8
             for (uint32_t b = 0; b < kGrp; ++b) g += sd3[b];
             out[oB3] = g;
         }
@@ -256,13 +262,26 @@ __global__ __launch_bounds__(256) void k_learn_step(LearnCtx c, uint32_t step, f
     {
         const uint32_t r = tid >> 3, j = tid & 7u;
         float g = 0.0f;
+#pragma unroll 8
         for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd1[b * kS + r], sx[b * 8 + j], g);
         out[oW1 + tid] = g;
         if (tid < 32) {
             float gb = 0.0f;
+#pragma unroll 8
             for (uint32_t b = 0; b < kGrp; ++b) gb += sd1[b * kS + tid];
             out[oB1 + tid] = gb;
         }
+    }
+}
+
+// grid (groups, slots); graph mode strides over the learned segments of the pass
+__global__ __launch_bounds__(256) void k_learn_step(LearnCtx c, uint32_t step, float lr,
+                                                    const uint32_t* wcnt, uint32_t cap,
+                                                    const Globals* glob) {
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.y);
+    for (uint32_t slot = blockIdx.y; slot < units; slot += gridDim.y) {
+        learn_step_body(c, slot, step, lr);
+        __syncthreads();
     }
 }
 
@@ -294,11 +313,10 @@ __global__ __launch_bounds__(256) void k_learn_final(LearnCtx c, uint32_t steps,
 // ---------------------------------------------------------------------------
 // in-sort path: sample + sort, then propose splitters and build the tree
 
-__global__ __launch_bounds__(256) void k_learn_prep(LearnCtx c, const LSeg* lseg,
-                                                    const uint32_t* learn_seg,
-                                                    const uint64_t* key_in, uint64_t seed) {
+__device__ __forceinline__ void learn_prep_body(const LearnCtx& c, uint32_t slot,
+                                                const LSeg* lseg, const uint32_t* learn_seg,
+                                                const uint64_t* key_in, uint64_t seed) {
     __shared__ uint64_t smp[kLearnM];
-    const uint32_t slot = blockIdx.x;
     const LSeg g = lseg[learn_seg[slot]];
     const uint64_t sseed = mix64(seed ^ 0x5A5A5A5A5A5A5A5Aull ^ mix64(((uint64_t)g.begin << 32) | g.depth));
     for (uint32_t r = threadIdx.x; r < kLearnM; r += blockDim.x) {
@@ -325,6 +343,18 @@ __global__ __launch_bounds__(256) void k_learn_prep(LearnCtx c, const LSeg* lseg
     sample_range(smp, kLearnM, c.range + 2 * slot);
 }
 
+__global__ __launch_bounds__(256) void k_learn_prep(LearnCtx c, const LSeg* lseg,
+                                                    const uint32_t* learn_seg,
+                                                    const uint64_t* key_in, uint64_t seed,
+                                                    const uint32_t* wcnt, uint32_t cap,
+                                                    const Globals* glob) {
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t slot = blockIdx.x; slot < units; slot += gridDim.x) {
+        learn_prep_body(c, slot, lseg, learn_seg, key_in, seed);
+        __syncthreads();
+    }
+}
+
 // first index of sorted a[0..m) holding a value >= x (strict: > x)
 __device__ __forceinline__ uint32_t bound(const uint64_t* a, uint32_t m, uint64_t x, bool strict) {
     uint32_t lo = 0, hi = m;
@@ -338,17 +368,17 @@ __device__ __forceinline__ uint32_t bound(const uint64_t* a, uint32_t m, uint64_
 // Final update, model CDF over the sorted sample made monotone by a running
 // maximum (256 threads, 16 consecutive values each), splitters at its
 // quantiles, the check on the sample, and the splitter tree.
-__global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, LSeg* lseg,
-                                                      const uint32_t* learn_seg, uint32_t steps,
-                                                      float lr, float beta, Globals* glob,
-                                                      uint64_t* tree_lo, uint64_t* tree_in,
-                                                      uint8_t* tree_lcp) {
+__device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t slot, LSeg* lseg,
+                                                  const uint32_t* learn_seg, uint32_t steps,
+                                                  float lr, float beta, Globals* glob,
+                                                  uint64_t* tree_lo, uint64_t* tree_in,
+                                                  uint8_t* tree_lcp) {
     __shared__ float w[kNPS];
     __shared__ float F[kLearnM];
     __shared__ uint64_t spl[1u << kDMax];
     __shared__ float tmx[256];
     __shared__ uint32_t gmax;
-    const uint32_t slot = blockIdx.x, tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x;
     const uint32_t si = learn_seg[slot];
     const LSeg g = lseg[si];
     learn_final_update(c, slot, steps, lr, w);
@@ -425,14 +455,28 @@ __global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, LSeg* lseg,
     }
 }
 
+__global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, LSeg* lseg,
+                                                      const uint32_t* learn_seg, uint32_t steps,
+                                                      float lr, float beta, Globals* glob,
+                                                      uint64_t* tree_lo, uint64_t* tree_in,
+                                                      uint8_t* tree_lcp, const uint32_t* wcnt,
+                                                      uint32_t cap) {
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t slot = blockIdx.x; slot < units; slot += gridDim.x) {
+        learn_finish_body(c, slot, lseg, learn_seg, steps, lr, beta, glob, tree_lo, tree_in,
+                          tree_lcp);
+        __syncthreads();
+    }
+}
+
 // Largest range bucket of every segment still on learned splitters against
 // beta * |S| / (v + 1); an imbalanced segment is switched back to sampled
 // splitters.
-__global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t* learn_seg,
-                                                     const uint32_t* cs, float beta,
-                                                     Globals* glob) {
+__device__ __forceinline__ void learn_check_body(uint32_t slot, LSeg* lseg,
+                                                 const uint32_t* learn_seg, const uint32_t* cs,
+                                                 float beta, Globals* glob) {
     __shared__ uint32_t smax;
-    const uint32_t si = learn_seg[blockIdx.x];
+    const uint32_t si = learn_seg[slot];
     const LSeg g = lseg[si];
     if (g.pad0 == 0xFFFFFFFFu) return;  // rejected on its sample already
     if (threadIdx.x == 0) smax = 0;
@@ -447,8 +491,20 @@ __global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t*
     __syncthreads();
     if (threadIdx.x == 0 && (double)smax > (double)beta * g.size / (g.v + 1)) {
         lseg[si].pad0 = 0xFFFFFFFFu;
+        lseg[si].pad1 = 1u;  // redo: sampled tree, classification and column scan again
         atomicAdd(&glob->fallbacks, 1u);
         atomicAdd(&glob->late_fallbacks, 1u);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_learn_check(LSeg* lseg, const uint32_t* learn_seg,
+                                                     const uint32_t* cs, float beta,
+                                                     Globals* glob, const uint32_t* wcnt,
+                                                     uint32_t cap) {
+    const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
+    for (uint32_t slot = blockIdx.x; slot < units; slot += gridDim.x) {
+        learn_check_body(slot, lseg, learn_seg, cs, beta, glob);
+        __syncthreads();
     }
 }
 
@@ -501,17 +557,21 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
                              const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
                              uint32_t steps, float lr, float beta, Globals* glob,
                              uint64_t* tree_lo, uint64_t* tree_in, uint8_t* tree_lcp,
-                             hipStream_t st) {
-    hipLaunchKernelGGL(k_learn_prep, dim3(slots), dim3(256), 0, st, c, lseg, learn_seg, key_in, seed);
+                             const Dyn& dy, hipStream_t st) {
+    const uint32_t g = dy.cnt ? dy.grid : slots;
+    hipLaunchKernelGGL(k_learn_prep, dim3(g), dim3(256), 0, st, c, lseg, learn_seg, key_in, seed,
+                       dy.cnt, dy.cap, glob);
     for (uint32_t s = 0; s < steps; ++s)
-        hipLaunchKernelGGL(k_learn_step, dim3(c.groups, slots), dim3(kGrp), 0, st, c, s, lr);
-    hipLaunchKernelGGL(k_learn_finish, dim3(slots), dim3(256), 0, st, c, lseg, learn_seg, steps, lr,
-                       beta, glob, tree_lo, tree_in, tree_lcp);
+        hipLaunchKernelGGL(k_learn_step, dim3(c.groups, g), dim3(kGrp), 0, st, c, s, lr, dy.cnt,
+                           dy.cap, glob);
+    hipLaunchKernelGGL(k_learn_finish, dim3(g), dim3(256), 0, st, c, lseg, learn_seg, steps, lr,
+                       beta, glob, tree_lo, tree_in, tree_lcp, dy.cnt, dy.cap);
 }
 
 void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,
-                        float beta, Globals* glob, hipStream_t st) {
-    hipLaunchKernelGGL(k_learn_check, dim3(slots), dim3(256), 0, st, lseg, learn_seg, cs, beta, glob);
+                        float beta, Globals* glob, const Dyn& dy, hipStream_t st) {
+    hipLaunchKernelGGL(k_learn_check, dim3(dy.cnt ? dy.grid : slots), dim3(256), 0, st, lseg,
+                       learn_seg, cs, beta, glob, dy.cnt, dy.cap);
 }
 
 // train on caller-sorted keys (slot 0); final weights copied to out
@@ -520,7 +580,8 @@ void launch_mlp_train(const LearnCtx& c, const uint64_t* sorted_keys, uint32_t m
     (void)hipMemcpyAsync(c.samples, sorted_keys, (size_t)m * 8, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(k_learn_init, dim3(1), dim3(256), 0, st, c, seed);
     for (uint32_t s = 0; s < steps; ++s)
-        hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, s, lr);
+        hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, s, lr,
+                           (const uint32_t*)nullptr, 0u, (const Globals*)nullptr);
     if (steps) {
         hipLaunchKernelGGL(k_learn_final, dim3(1), dim3(256), 0, st, c, steps, lr);
         (void)hipMemcpyAsync(out, c.W + (size_t)(steps & 1u) * kNPS, kNP * 4, hipMemcpyDeviceToDevice, st);
@@ -535,7 +596,8 @@ void launch_mlp_grad(const LearnCtx& c, const float* params, const uint64_t* sor
     (void)hipMemcpyAsync(c.samples, sorted_keys, (size_t)m * 8, hipMemcpyDeviceToDevice, st);
     hipLaunchKernelGGL(k_learn_init, dim3(1), dim3(256), 0, st, c, 0ull);
     (void)hipMemcpyAsync(c.W + kNPS, params, kNP * 4, hipMemcpyDeviceToDevice, st);
-    hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, 0u, 0.0f);
+    hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, 0u, 0.0f,
+                       (const uint32_t*)nullptr, 0u, (const Globals*)nullptr);
     hipLaunchKernelGGL(k_learn_sum, dim3(8), dim3(256), 0, st, c, 0u, out);
 }
 

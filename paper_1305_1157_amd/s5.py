@@ -17,7 +17,8 @@ LIB_PATH = os.path.join(_PKG, "libs5.so")
 S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP, S5_ERR_DEVICE = 0, -1, -2, -3, -4
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 
-EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched", "s5_stats_get",
+EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched",
+           "s5_sort_batched_tuned", "s5_stats_get",
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
            "s5_profile_read", "s5_mlp_train", "s5_mlp_grad", "s5_mlp_eval")
 
@@ -26,7 +27,14 @@ class Config(ctypes.Structure):
     _fields_ = [("splitters", ctypes.c_uint32), ("oversample", ctypes.c_uint32),
                 ("unroll", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("base_threshold", ctypes.c_uint32), ("splitter_mode", ctypes.c_uint32),
-                ("imbalance_bound", ctypes.c_float), ("seed", ctypes.c_uint64)]
+                ("imbalance_bound", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("graph_levels", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class SetTuning(ctypes.Structure):
+    """Per-set parameters of ``sort_batched(..., tuning=...)`` (0 = the config's value)."""
+    _fields_ = [("splitters", ctypes.c_uint16), ("base_threshold", ctypes.c_uint16),
+                ("tile", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -67,6 +75,8 @@ def load(path: str = LIB_PATH):
     lib.s5_workspace_bytes.argtypes = [U32, ctypes.POINTER(Config)]
     lib.s5_workspace_bytes.restype = ctypes.c_size_t
     lib.s5_sort_batched.argtypes = [P, U64, P, P, U32, P, P, ctypes.POINTER(Config), P]
+    lib.s5_sort_batched_tuned.argtypes = [P, U64, P, P, U32, ctypes.POINTER(SetTuning), P, P,
+                                          ctypes.POINTER(Config), P]
     lib.s5_stats_get.argtypes = [P, ctypes.POINTER(Stats)]
     lib.s5_strerror.argtypes = [ctypes.c_int]
     lib.s5_strerror.restype = ctypes.c_char_p
@@ -79,7 +89,8 @@ def load(path: str = LIB_PATH):
     lib.s5_mlp_eval.argtypes = [P, P, U32, U64, U64, P, P]
     lib.s5_profile_enable.argtypes = [ctypes.c_int]
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
-    for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_stats_get", "s5_prefix_keys",
+    for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
+              "s5_prefix_keys",
               "s5_classify", "s5_profile_enable", "s5_profile_read", "s5_mlp_train", "s5_mlp_grad",
               "s5_mlp_eval"):
         getattr(lib, f).restype = ctypes.c_int
@@ -106,9 +117,10 @@ def _dev(t: torch.Tensor, dtype, name: str):
 
 
 def make_config(splitters=0, oversample=0, unroll=0, tile=0, base_threshold=0,
-                splitter_mode=SPLIT_SAMPLED, imbalance_bound=0.0, seed=0) -> Config:
+                splitter_mode=SPLIT_SAMPLED, imbalance_bound=0.0, seed=0,
+                graph_levels=0) -> Config:
     return Config(splitters, oversample, unroll, tile, base_threshold, splitter_mode,
-                  imbalance_bound, seed)
+                  imbalance_bound, seed, graph_levels, 0)
 
 
 def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,
@@ -147,22 +159,39 @@ def sort_plain(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tenso
     return out_perm, out_lcp
 
 
+def make_tuning(rows) -> ctypes.Array:
+    """Host array of SetTuning from (splitters, base_threshold, tile) rows."""
+    arr = (SetTuning * len(rows))()
+    for i, (v, t, tile) in enumerate(rows):
+        arr[i] = SetTuning(v, t, tile)
+    return arr
+
+
 def sort_batched(chars: torch.Tensor, offsets: torch.Tensor, set_begin: torch.Tensor,
-                 cfg: Config | None = None, stream=None):
-    """Sort every set ``offsets[set_begin[s]:set_begin[s+1]]`` on its own.
+                 cfg: Config | None = None, tuning=None, out_perm: torch.Tensor | None = None,
+                 out_lcp: torch.Tensor | None = None, stream=None):
+    """Sort every set ``offsets[set_begin[s]:set_begin[s+1]]`` on its own (one
+    graph launch for all sets; ``tuning``: per-set parameters from
+    ``make_tuning``).
 
     Returns set-local ``perm`` and ``lcp`` (0 at each set's first slot)."""
     lib = load()
     n = offsets.numel()
-    perm = torch.empty(n, dtype=torch.uint32, device=offsets.device)
-    lcp = torch.empty(n, dtype=torch.uint32, device=offsets.device)
-    rc = lib.s5_sort_batched(_dev(chars, torch.uint8, "chars"), chars.numel(),
-                             _dev(offsets, torch.uint64, "offsets"),
-                             _dev(set_begin, torch.uint64, "set_begin"), set_begin.numel() - 1,
-                             _dev(perm, torch.uint32, "out_perm"), _dev(lcp, torch.uint32, "out_lcp"),
-                             ctypes.byref(cfg) if cfg is not None else None, _stream(stream))
+    if out_perm is None:
+        out_perm = torch.empty(n, dtype=torch.uint32, device=offsets.device)
+    if out_lcp is None:
+        out_lcp = torch.empty(n, dtype=torch.uint32, device=offsets.device)
+    num_sets = set_begin.numel() - 1
+    if tuning is not None and len(tuning) != num_sets:
+        raise ValueError("tuning needs one entry per set")
+    rc = lib.s5_sort_batched_tuned(_dev(chars, torch.uint8, "chars"), chars.numel(),
+                                   _dev(offsets, torch.uint64, "offsets"),
+                                   _dev(set_begin, torch.uint64, "set_begin"), num_sets, tuning,
+                                   _dev(out_perm, torch.uint32, "out_perm"),
+                                   _dev(out_lcp, torch.uint32, "out_lcp"),
+                                   ctypes.byref(cfg) if cfg is not None else None, _stream(stream))
     _check(rc)
-    return perm, lcp
+    return out_perm, out_lcp
 
 
 def workspace_bytes(n: int, cfg: Config | None = None) -> int:
