@@ -1,5 +1,5 @@
 #!/usr/bin/env python3
-"""Benchmark of plain S^5 on one MI355X: strings/s and HBM GB/s.
+"""Benchmark of S^5 on one MI355X: strings/s and HBM GB/s.
 
 One step = one complete sort (every distribution pass, the base case and the
 LCP completion) of the URL-like workload: 10,000,000 synthetic strings
@@ -8,6 +8,11 @@ LCP completion) of the URL-like workload: 10,000,000 synthetic strings
 JSON line carries the roofline of the dominant kernel (the redistribution
 pass, timed with HIP events inside the library on its launch stream) and the
 CPU oracle timed on a bounded sample of the same workload.
+
+Beside it (skip with --no-extras): the learned splitter proposal against
+sampled splitters on the DNA and word workloads, and the batched form (4,096
+sets in one graph launch, autotuned per-set parameters), each with its own
+strings/s and a full-size correctness check.
 """
 import argparse
 import json
@@ -63,6 +68,118 @@ def cpu_baseline(name, n_sample, min_seconds=10.0):
                       f"{total:.1f} s total on 1 host core"}
 
 
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _timed_sorts(fn, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def learned_extra(name, steps=3):
+    """Learned vs sampled splitters on one workload (same output, checked)."""
+    import torch
+    from paper_1305_1157_amd import gen, s5
+    chars, offs = gen.workload(name)
+    n = int(offs.size)
+    dc, do = torch.from_numpy(chars).cuda(), torch.from_numpy(offs).cuda()
+    perm = torch.empty(n, dtype=torch.uint32, device="cuda")
+    lcp = torch.empty_like(perm)
+    res, ref = {"workload": WORKLOAD_TEXT[name], "name": name, "n": n}, None
+    variants = [("sampled", s5.make_config()),
+                ("learned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED)),
+                ("learned_no_fallback", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
+                                                       imbalance_bound=1e9))]
+    for label, cfg in variants:
+        log(f"{name}: {label}")
+        ws = torch.empty(s5.workspace_bytes(n, cfg), dtype=torch.uint8, device="cuda")
+        run = lambda: s5.sort(dc, do, cfg=cfg, out_perm=perm, out_lcp=lcp, workspace=ws)  # noqa
+        run()
+        sec = _timed_sorts(run, steps)
+        st = s5.stats()
+        s5.profile_enable(True)
+        run()
+        torch.cuda.synchronize()
+        prof = s5.profile_read()
+        s5.profile_enable(False)
+        if ref is None:
+            ref = (perm.clone(), lcp.clone())
+        same = bool(torch.equal(ref[0], perm) and torch.equal(ref[1], lcp))
+        res[label] = {"value": n / sec, "ms": sec * 1e3, "passes": st["passes"],
+                      "moved_M": st["moved_M"], "fallbacks": st["fallbacks"],
+                      "entropy_bits_first_pass": st["entropy_bits"],
+                      "max_bucket_first_pass": st["max_bucket"],
+                      "learn_ms": prof.get("learn_splitters", {}).get("total_ms", 0.0),
+                      "output_identical_to_sampled": same}
+        del ws
+    return res
+
+
+def batched_extra(steps=3, check_positions=1_000_000, oracle_sets=8):
+    """The batched form on 4,096 sets in one graph launch, with a full-size check."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_1305_1157_amd import autotune, gen, s5
+    spec = gen.BATCHED["sets_4096"]
+    t0 = time.perf_counter()
+    chars, offs, sb = gen.batched(**spec)
+    gen_s = time.perf_counter() - t0
+    n, sizes = int(offs.size), np.diff(sb).astype(np.int64)
+    log(f"batched: generated {n:,} strings in {len(sizes)} sets ({gen_s:.1f} s)")
+    dc, do, ds = (torch.from_numpy(chars).cuda(), torch.from_numpy(offs).cuda(),
+                  torch.from_numpy(sb).cuda())
+    perm = torch.empty(n, dtype=torch.uint32, device="cuda")
+    lcp = torch.empty_like(perm)
+    table = autotune.load_table()
+    tuned = s5.make_tuning(autotune.tuning_for(sizes, table))
+    res = {"workload": f"{spec['num_sets']:,} independent sets, sizes log-uniform in "
+                       f"[{spec['min_size']:,}, {spec['max_size']:,}], each from one of the "
+                       f"{'/'.join(spec['kinds'])} generators", "n": n, "sets": len(sizes),
+           "arena_bytes": int(chars.size), "generate_s": gen_s, "tuning": table.get("source"),
+           "unroll": table["unroll"], "launches": "one hipGraph per sort (host reads back "
+           "set_begin ends and the final counters)"}
+    variants = [("learned_tuned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
+                                                  unroll=table["unroll"]), tuned),
+                ("sampled_tuned", s5.make_config(unroll=table["unroll"]), tuned),
+                ("sampled_defaults", s5.make_config(), None)]
+    for label, cfg, tun in variants:
+        log(f"batched: {label}")
+        run = lambda: s5.sort_batched(dc, do, ds, cfg=cfg, tuning=tun, out_perm=perm,  # noqa
+                                      out_lcp=lcp)
+        run()  # capture
+        sec = _timed_sorts(run, steps)
+        st = s5.stats()
+        res[label] = {"value": n / sec, "ms": sec * 1e3, "passes": st["passes"],
+                      "moved_M": st["moved_M"], "fallbacks": st["fallbacks"],
+                      "segments": st["segments"], "base_items": st["base_items"]}
+    # full-size check of the last result: permutation per set, sampled neighbour
+    # pairs (order and LCP), and whole small sets against the oracle
+    log("batched: full-size check")
+    hp, hl = perm.cpu().numpy(), lcp.cpu().numpy()
+    rng = np.random.default_rng(11)
+    pos = rng.integers(0, n, size=check_positions).astype(np.uint64)
+    ok_perm = oracle.check_perm(hp, sb)
+    bad_pairs = oracle.check_pairs(chars, offs, hp, hl, pos, sb)
+    small = np.flatnonzero((sizes > 1) & (sizes <= 200_000))
+    pick = rng.choice(small, size=min(oracle_sets, small.size), replace=False)
+    sets_ok = 0
+    for s_ in pick:
+        b, e = int(sb[s_]), int(sb[s_ + 1])
+        rp, rl = oracle.sort(chars, offs[b:e])
+        sets_ok += int(np.array_equal(hp[b:e], rp) and np.array_equal(hl[b:e], rl))
+    res["check"] = {"perm_is_permutation_per_set": ok_perm, "pairs_checked": check_positions,
+                    "pairs_bad": bad_pairs, "whole_sets_vs_oracle": f"{sets_ok}/{len(pick)}"}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +190,8 @@ def main():
                     help="strings in the oracle's timed sample (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (PMC calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the learned-splitter and batched measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -158,8 +277,25 @@ def main():
         "kernels": kernels,
         "stats": st,
     }
+    log(f"{args.workload}: {value / 1e9:.3f} G strings/s, {ms_per_step:.3f} ms per sort")
     if args.cpu_sample:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, min(args.cpu_sample, n))
+    if not args.no_extras:
+        del d_chars, d_offs, perm, lcp, ws
+        torch.cuda.empty_cache()
+        extras = {}
+        for name in ("dna_16M", "words_50M"):
+            try:
+                extras[name] = learned_extra(name)
+            except Exception as e:  # reported, never hides the main line
+                extras[name] = {"error": repr(e)}
+            torch.cuda.empty_cache()
+        out["learned"] = extras
+        try:
+            out["batched"] = batched_extra()
+        except Exception as e:
+            out["batched"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)
 
 

@@ -49,6 +49,11 @@ def _load():
         lib.oracle_dist_prefix.restype = ctypes.c_uint64
         lib.oracle_lcp.argtypes = [P, P, P, ctypes.c_uint64, P]
         lib.oracle_lcp.restype = None
+        lib.oracle_check_perm.argtypes = [P, P, ctypes.c_uint32, ctypes.c_uint64]
+        lib.oracle_check_perm.restype = ctypes.c_int
+        lib.oracle_check_pairs.argtypes = [P, P, P, ctypes.c_uint32, ctypes.c_uint64, P, P, P,
+                                           ctypes.c_uint64]
+        lib.oracle_check_pairs.restype = ctypes.c_uint64
         _lib = lib
     return _lib
 
@@ -113,3 +118,31 @@ def dist_prefix(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray,
         return 0
     return int(_load().oracle_dist_prefix(_ptr(chars), _ptr(offsets), _ptr(perm),
                                           _ptr(lcp), perm.size))
+
+
+def check_perm(perm: np.ndarray, set_begin: np.ndarray | None = None) -> bool:
+    """True if ``perm`` restricted to every set is a permutation of the set's
+    local indices (whole-array check, any size)."""
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    sb = None if set_begin is None else np.ascontiguousarray(set_begin, dtype=np.uint64)
+    ns = 1 if sb is None else sb.size - 1
+    r = _load().oracle_check_perm(_ptr(perm), None if sb is None else _ptr(sb), ns, perm.size)
+    if r < 0:
+        raise MemoryError("oracle_check_perm ran out of memory")
+    return bool(r)
+
+
+def check_pairs(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray, lcp: np.ndarray,
+                positions: np.ndarray, set_begin: np.ndarray | None = None) -> int:
+    """Number of the given positions p whose neighbours (perm[p-1], perm[p]) are
+    out of order (bytes, then index) or whose lcp[p] is wrong; lcp must be 0 at
+    a set's first slot.  Checks a result one pair at a time, at any size."""
+    chars, offsets = _check(chars, offsets)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    lcp = np.ascontiguousarray(lcp, dtype=np.uint32)
+    pos = np.ascontiguousarray(positions, dtype=np.uint64)
+    sb = None if set_begin is None else np.ascontiguousarray(set_begin, dtype=np.uint64)
+    ns = 1 if sb is None else sb.size - 1
+    return int(_load().oracle_check_pairs(_ptr(chars), _ptr(offsets),
+                                          None if sb is None else _ptr(sb), ns, perm.size,
+                                          _ptr(perm), _ptr(lcp), _ptr(pos), pos.size))

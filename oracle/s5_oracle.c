@@ -188,3 +188,74 @@ uint64_t oracle_dist_prefix(const uint8_t* chars, const uint64_t* offsets,
     }
     return d;
 }
+
+/* ---- checks of results too large to recompute -------------------------------
+ * Both follow the definition of the output (Section 2): perm lists every
+ * input index of a set exactly once, neighbours are in non-descending string
+ * order (equal strings by ascending index), and lcp[i] is the LCP of the
+ * neighbours, 0 at a set's first slot. */
+
+/* 1 if perm restricted to every set is a permutation of 0..|set|-1, else 0
+ * (set_begin NULL: one set of n). */
+int oracle_check_perm(const uint32_t* perm, const uint64_t* set_begin, uint32_t num_sets,
+                      uint64_t n) {
+    uint8_t* seen = (uint8_t*)calloc(n ? n : 1, 1);
+    if (!seen) return -1;
+    int ok = 1;
+    uint32_t ns = set_begin ? num_sets : 1;
+    for (uint32_t s = 0; s < ns && ok; ++s) {
+        uint64_t b = set_begin ? set_begin[s] : 0, e = set_begin ? set_begin[s + 1] : n;
+        for (uint64_t i = b; i < e; ++i) {
+            uint64_t g = b + perm[i];
+            if (perm[i] >= e - b || seen[g]) {
+                ok = 0;
+                break;
+            }
+            seen[g] = 1;
+        }
+    }
+    free(seen);
+    return ok;
+}
+
+/* Number of the given positions whose pair (perm[p-1], perm[p]) is out of
+ * order or whose lcp[p] is wrong (lcp must be 0 at a set's first slot). */
+uint64_t oracle_check_pairs(const uint8_t* chars, const uint64_t* offsets,
+                            const uint64_t* set_begin, uint32_t num_sets, uint64_t n,
+                            const uint32_t* perm, const uint32_t* lcp,
+                            const uint64_t* positions, uint64_t count) {
+    uint64_t bad = 0;
+    for (uint64_t q = 0; q < count; ++q) {
+        uint64_t p = positions[q];
+        if (p >= n) {
+            ++bad;
+            continue;
+        }
+        uint64_t b = 0, e = n;
+        if (set_begin) { /* last set starting at or before p */
+            uint32_t lo = 0, hi = num_sets - 1;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi + 1) / 2;
+                if (set_begin[mid] <= p) lo = mid; else hi = mid - 1;
+            }
+            b = set_begin[lo];
+            e = set_begin[lo + 1];
+        }
+        if (perm[p] >= e - b) {
+            ++bad;
+            continue;
+        }
+        if (p == b) {
+            if (lcp[p] != 0) ++bad;
+            continue;
+        }
+        if (perm[p - 1] >= e - b) {
+            ++bad;
+            continue;
+        }
+        uint32_t x = (uint32_t)(b + perm[p - 1]), y = (uint32_t)(b + perm[p]);
+        if (!str_less(chars, offsets, x, y, 0)) ++bad;
+        else if (lcp2(chars + offsets[x], chars + offsets[y]) != lcp[p]) ++bad;
+    }
+    return bad;
+}

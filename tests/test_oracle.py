@@ -179,3 +179,65 @@ def test_batched_equals_per_set():
         ref = lib_sorted_perm(strings)
         assert perm[b:e].tolist() == ref
         assert lcp[b:e].tolist() == lib_lcp(strings, ref)
+
+
+# ---- checkers for results too large to recompute --------------------------
+
+def _batched_case():
+    from paper_1305_1157_amd import gen
+    chars, offs, sb = gen.batched(12, 1, 3000, kinds=("random", "url", "dna", "words"), seed=77)
+    perm, lcp = oracle.sort_batched(chars, offs, sb)
+    return chars, offs, sb, perm, lcp
+
+
+def test_checkers_accept_correct_results():
+    chars, offs, sb, perm, lcp = _batched_case()
+    assert oracle.check_perm(perm, sb)
+    allpos = np.arange(perm.size, dtype=np.uint64)
+    assert oracle.check_pairs(chars, offs, perm, lcp, allpos, sb) == 0
+    # single set
+    p1, l1 = oracle.sort(chars, offs)
+    assert oracle.check_perm(p1)
+    assert oracle.check_pairs(chars, offs, p1, l1, np.arange(p1.size, dtype=np.uint64)) == 0
+
+
+def test_checkers_catch_planted_mistakes():
+    chars, offs, sb, perm, lcp = _batched_case()
+    allpos = np.arange(perm.size, dtype=np.uint64)
+    s0 = int(sb[2])  # a position inside a set with >= 3 strings
+    while int(sb[np.searchsorted(sb, s0, side="right")]) - s0 < 3:
+        s0 += 1
+    # a duplicated index is no permutation
+    bad = perm.copy()
+    bad[s0 + 1] = bad[s0]
+    assert not oracle.check_perm(bad, sb)
+    # an index beyond its set
+    bad = perm.copy()
+    bad[s0] = 10**6
+    assert not oracle.check_perm(bad, sb)
+    # two distinct neighbours swapped: order broken at p or p+1
+    bad = perm.copy()
+    for p in range(s0 + 1, perm.size):
+        a, b = int(offs[s0 + perm[p - 1]]), int(offs[s0 + perm[p]])
+        if lcp[p] < 1000 and chars[a + lcp[p]] != chars[b + lcp[p]]:
+            break
+    bad[p - 1], bad[p] = bad[p], bad[p - 1]
+    assert oracle.check_pairs(chars, offs, bad, lcp, allpos, sb) > 0
+    # one wrong LCP value
+    badl = lcp.copy()
+    badl[s0 + 1] += 1
+    assert oracle.check_pairs(chars, offs, perm, badl, allpos, sb) == 1
+    # non-zero LCP at a set's first slot
+    badl = lcp.copy()
+    badl[int(sb[3])] = 1
+    assert oracle.check_pairs(chars, offs, perm, badl, allpos, sb) >= 1
+
+
+def test_check_pairs_tie_break_by_index():
+    # equal strings must appear in ascending input order
+    chars, offs = gen.from_strings([b"same", b"same", b"other", b"same"])
+    perm, lcp = oracle.sort(chars, offs)
+    assert list(perm) == [2, 0, 1, 3]
+    bad = perm.copy()
+    bad[1], bad[2] = bad[2], bad[1]  # same strings, indices descending
+    assert oracle.check_pairs(chars, offs, bad, lcp, np.arange(4, dtype=np.uint64)) == 1
