@@ -917,11 +917,17 @@ __device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& a) {
 // Rounds of decide / re-key / sort inside one wavefront.  Lane r owns output
 // position pos; lanes are sorted by (group, key, local index) and padding
 // lanes (valid == false) are last.  Returns the final packed element of the lane.
+// Refinement rounds of one wavefront (<= 64 elements, sorted by (group, key,
+// local index)).  offl[local] holds the string start of element `local` (LDS);
+// with fill_n > 0 it is filled by lanes < fill_n on the first round that needs
+// it.  A round re-keys the undecided members 8 bytes deeper; it re-sorts only
+// if some group's keys now differ (equal keys keep their local-index order).
 __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, uint32_t pos,
-                                const uint32_t* iin, const uint8_t* chars,
-                                const uint64_t* offsets, uint32_t* olcp) {
+                                uint64_t* offl, uint32_t fill_n, const uint32_t* iin,
+                                const uint8_t* chars, const uint64_t* offsets, uint32_t* olcp) {
     const uint32_t lane = lane_id();
     const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
+    bool filled = fill_n == 0;
     for (;;) {
         const uint64_t kp = shfl_up64(k, 1);
         const uint32_t ap = __shfl_up(a, 1);
@@ -934,16 +940,26 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
         }
         const uint64_t U = __ballot(und);
         if (!U) break;
+        if (!filled) {
+            if (lane < fill_n) offl[lane] = offsets[iin[lane]];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            filled = true;
+        }
         const bool member = ((U >> lane) & 1ull) || (lane < 63 && ((U >> (lane + 1)) & 1ull));
         const uint32_t st = 63u - (uint32_t)__builtin_clzll((unsigned long long)(~U & upto));
         h += 8;
         if (member) {
-            k = load_key(chars, offsets[iin[a & 0xFFFFu]] + h);
+            k = load_key(chars, offl[a & 0xFFFFu] + h);
             a = (st << 16) | (a & 0xFFFFu);
         } else if (valid) {
             a = (lane << 16) | (a & 0xFFFFu);
         }
-        wave_sort(k, a);
+        const uint64_t kq = shfl_up64(k, 1);
+        const uint32_t aq = __shfl_up(a, 1);
+        const bool split = member && lane > 0 && (aq >> 16) == (a >> 16) && kq != k;
+        if (__ballot(split)) wave_sort(k, a);
     }
     return a;
 }
@@ -953,6 +969,7 @@ __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
                                                const uint32_t* idx0, const uint32_t* idx1,
                                                const uint8_t* chars, const uint64_t* offsets,
                                                uint32_t* out_perm, uint32_t* out_lcp) {
+    __shared__ uint64_t offl[kWaves][64];  // string starts, by local index
     const uint32_t lane = lane_id();
     const Seg it = items[item];
     const uint32_t buf = it.depth >> 31;
@@ -964,7 +981,8 @@ __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
     uint64_t k = valid ? kin[lane] : ~0ull;
     uint32_t a = valid ? lane : 0xFFFFFFFFu;
     wave_sort(k, a);
-    const uint32_t fa = wave_rounds(k, a, valid, h, lane, iin, chars, offsets, out_lcp + it.begin);
+    const uint32_t fa = wave_rounds(k, a, valid, h, lane, offl[threadIdx.x >> 6], n, iin, chars,
+                                    offsets, out_lcp + it.begin);
     if (valid) out_perm[it.begin + lane] = iin[fa & 0xFFFFu] - it.base;
 }
 
@@ -1125,10 +1143,10 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     extern __shared__ uint64_t dyn[];
     uint64_t* K = dyn;                          // pmax keys, by position
     uint64_t* SK = K + pmax;                    // pmax keys, compacted members
-    uint32_t* A = (uint32_t*)(SK + pmax);       // pmax packed group | local, by position
+    uint64_t* OFFL = SK + pmax;                 // pmax string starts, by local index
+    uint32_t* A = (uint32_t*)(OFFL + pmax);     // pmax packed group | local, by position
     uint32_t* SA = A + pmax;                    // pmax compacted members
-    uint16_t* ST = (uint16_t*)(SA + pmax);      // pmax group start of each position
-    uint16_t* POS = ST + pmax;                  // pmax position of each compacted member
+    uint16_t* POS = (uint16_t*)(SA + pmax);     // pmax position of each compacted member
     uint8_t* F = (uint8_t*)(POS + pmax);        // pmax: pair (i-1, i) undecided
     __shared__ uint32_t wl[2 * kWaves];
     const Seg it = items[item];
@@ -1165,6 +1183,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         any |= un;
     }
     any = __syncthreads_or(any);
+    bool first = true;
     while (any) {
         // group start of every position (running max of decided positions) and
         // the rank of every group member among all members
@@ -1185,13 +1204,22 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             }
         }
         __syncthreads();
+        if (first) {  // string starts of the undecided strings (later members are among them)
+            for (uint32_t q = tid; q < m; q += kWG) {
+                const uint32_t l = SA[q] & 0xFFFFu;
+                OFFL[l] = offsets[iin[l]];
+            }
+            first = false;
+            __syncthreads();
+        }
         if (m <= 64) {
             // few undecided strings left: wavefront 0 finishes them in registers
             if (tid < 64) {
                 const bool valid = tid < m;
                 const uint32_t pos = valid ? POS[tid] : 0u;
                 const uint32_t fa = wave_rounds(valid ? SK[tid] : ~0ull, valid ? SA[tid] : 0xFFFFFFFFu,
-                                                valid, h, pos, iin, chars, offsets, olcp);
+                                                valid, h, pos, OFFL, 0u, iin, chars, offsets,
+                                                olcp);
                 if (valid) A[pos] = fa;
             }
             __syncthreads();
@@ -1205,35 +1233,41 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             // up to pmax / kWG members per thread: all their gathers in flight at once
             constexpr int G = EMAX;
             uint64_t pos[G], nkey[G];
-            uint32_t gi[G];
             bool need[G];
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const uint32_t q = tid + e * kWG;
                 need[e] = q < m;
-                gi[e] = iin[need[e] ? (SA[q] & 0xFFFFu) : 0u];
+                pos[e] = need[e] ? OFFL[SA[q] & 0xFFFFu] + h : 0ull;
             }
-#pragma unroll
-            for (int e = 0; e < G; ++e) pos[e] = offsets[gi[e]];
-#pragma unroll
-            for (int e = 0; e < G; ++e) pos[e] += h;
             load_keys<G>(chars, pos, need, nkey);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const uint32_t q = tid + e * kWG;
                 if (q < m) SK[q] = nkey[e];
             }
+        }
+        __syncthreads();
+        // re-sort only if some group's keys now differ (equal keys keep their
+        // local-index order)
+        int split = 0;
+        for (uint32_t q = tid + 1; q < m; q += kWG)
+            split |= ((SA[q] >> 16) == (SA[q - 1] >> 16) && SK[q] != SK[q - 1]) ? 1 : 0;
+        split = __syncthreads_or(split);
+        if (split) {
             for (uint32_t q = m + tid; q < Pm; q += kWG) {
                 SK[q] = ~0ull;
                 SA[q] = 0xFFFFFFFFu;
             }
-        }
-        __syncthreads();
-        sort_pow2<EMAX>(SK, SA, Pm);
-        for (uint32_t q = tid; q < m; q += kWG) {
-            const uint32_t i = POS[q];
-            K[i] = SK[q];
-            A[i] = SA[q];
+            __syncthreads();
+            sort_pow2<EMAX>(SK, SA, Pm);
+            for (uint32_t q = tid; q < m; q += kWG) {
+                const uint32_t i = POS[q];
+                K[i] = SK[q];
+                A[i] = SA[q];
+            }
+        } else {
+            for (uint32_t q = tid; q < m; q += kWG) K[POS[q]] = SK[q];
         }
         __syncthreads();
         any = 0;
@@ -1504,7 +1538,7 @@ static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const u
     }
     uint32_t PT = 1;
     while (PT < T) PT <<= 1;
-    const size_t per = 8 + 8 + 4 + 4 + 2 + 2 + 1;
+    const size_t per = 8 + 8 + 8 + 4 + 4 + 2 + 1;  // K, SK, OFFL, A, SA, POS, F
     if (G || n_items[1]) {
         const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
         S5_LAUNCH((k_base_block<kBaseMid / kWG, G>), dim3(G ? dy[1].grid : n_items[1]), dim3(kWG),
