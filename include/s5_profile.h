@@ -32,6 +32,12 @@ typedef struct s5_kernel_profile {
  * cleared.  Returns S5_OK. */
 int s5_profile_enable(int on);
 
+/* Restrict the event timing to the launches of one kernel (a name as
+ * reported by s5_profile_read, e.g. "scatter"), so that the events themselves
+ * add little to a timed sort; NULL or "" times every kernel again.  Returns
+ * S5_OK, or S5_ERR_INVALID for an unknown name. */
+int s5_profile_only(const char* kernel);
+
 /* Copy up to `max` kernel entries to `out` (host memory); *count receives the
  * number of kernels with at least one launch.  Returns S5_OK or
  * S5_ERR_INVALID for a NULL pointer. */

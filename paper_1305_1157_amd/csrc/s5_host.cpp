@@ -210,6 +210,7 @@ struct Pending {
     uint64_t items;
 };
 bool g_prof_on = false;
+int g_prof_only = -1;  // time only this kernel (-1: all)
 ProfAcc g_prof[K_COUNT];
 std::vector<hipEvent_t> g_event_pool;
 std::vector<Pending> g_pending;
@@ -228,7 +229,7 @@ hipEvent_t prof_event() {
 // Launch `fn` on `st`, bracketed by events when profiling is on.
 template <class F>
 void timed(int k, uint64_t items, hipStream_t st, F&& fn) {
-    if (!g_prof_on) {
+    if (!g_prof_on || (g_prof_only >= 0 && k != g_prof_only)) {
         fn();
         return;
     }
@@ -880,6 +881,20 @@ int s5_profile_enable(int on) {
     g_prof_on = on != 0;
     for (auto& A : g_prof) A = ProfAcc();
     return S5_OK;
+}
+
+int s5_profile_only(const char* kernel) {
+    std::lock_guard<std::mutex> g(g_mu);
+    if (!kernel || !kernel[0]) {
+        g_prof_only = -1;
+        return S5_OK;
+    }
+    for (int k = 0; k < K_COUNT; ++k)
+        if (strcmp(kernel, kKName[k]) == 0) {
+            g_prof_only = k;
+            return S5_OK;
+        }
+    return S5_ERR_INVALID;
 }
 
 int s5_profile_read(s5_kernel_profile* out, uint32_t max, uint32_t* count) {

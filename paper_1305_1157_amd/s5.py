@@ -20,6 +20,7 @@ SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched",
            "s5_sort_batched_tuned", "s5_stats_get",
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
+           "s5_profile_only",
            "s5_profile_read", "s5_mlp_train", "s5_mlp_grad", "s5_mlp_eval")
 
 
@@ -88,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.s5_mlp_grad.argtypes = [P, P, U32, P, P]
     lib.s5_mlp_eval.argtypes = [P, P, U32, U64, U64, P, P]
     lib.s5_profile_enable.argtypes = [ctypes.c_int]
+    lib.s5_profile_only.argtypes = [ctypes.c_char_p]
+    lib.s5_profile_only.restype = ctypes.c_int
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
     for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
               "s5_prefix_keys",
@@ -232,6 +235,11 @@ def release():
 def profile_enable(on: bool = True):
     """Turn per-kernel HIP-event timing on or off (clears the accumulators)."""
     _check(load().s5_profile_enable(1 if on else 0))
+
+
+def profile_only(kernel: str | None = None):
+    """Time only the launches of ``kernel`` (None: every kernel)."""
+    _check(load().s5_profile_only(kernel.encode() if kernel else None))
 
 
 def profile_read() -> dict:
