@@ -124,43 +124,73 @@ __device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, cons
     if (c.learn && size >= kLearnMin) atomicAdd(&T->n_learn, 1u);
 }
 
-// Phase 2, one thread: turn block totals into global bases (stored back into T).
+// Phase 2, by the 64 lanes of wavefront 0: turn block totals into global
+// bases (stored back into T).  Each lane owns one global counter, so the
+// block's atomics are independent and in flight together.
 __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
+    const uint32_t l = threadIdx.x;
+    const uint32_t nl = T->n_large;
     uint32_t err = 0;
-    if (T->base_elems) atomicAdd(&c.glob->base_elems, T->base_elems);
-    for (int q = 0; q < kBaseClasses; ++q) {
-        if (!T->n_base[q]) continue;
-        uint32_t b0 = atomicAdd(&c.glob->n_base[q], T->n_base[q]);
-        if (b0 + T->n_base[q] > c.caps.base[q]) err |= kErrBaseCap;
-        T->n_base[q] = b0;
+    if (l == 0) {
+        if (T->base_elems) atomicAdd(&c.glob->base_elems, T->base_elems);
+    } else if (l <= (uint32_t)kBaseClasses) {
+        const int q = (int)l - 1;
+        const uint32_t nb = T->n_base[q];
+        if (nb) {
+            const uint32_t b0 = atomicAdd(&c.glob->n_base[q], nb);
+            if (b0 + nb > c.caps.base[q]) err = kErrBaseCap;
+            T->n_base[q] = b0;
+        }
+    } else if (nl) {
+        switch (l) {
+            case 4: {
+                const uint32_t x = atomicAdd(&c.cnt->n_large, nl);
+                if (x + nl > c.caps.large) err = kErrLargeCap;
+                T->n_large = x;
+            } break;
+            case 5: {
+                const uint32_t v = T->tiles, x = atomicAdd(&c.cnt->tiles, v);
+                if (x + v > c.caps.tiles) err = kErrTileCap;
+                T->tiles = x;
+            } break;
+            case 6: {
+                const uint32_t v = T->chunks, x = atomicAdd(&c.cnt->chunks, v);
+                if (x + v > c.caps.chunks) err = kErrTileCap;
+                T->chunks = x;
+            } break;
+            case 7: {
+                const uint32_t v = T->tree, x = atomicAdd(&c.cnt->tree, v);
+                if (x + v > c.caps.tree) err = kErrTreeCap;
+                T->tree = x;
+            } break;
+            case 8: {
+                const uint32_t v = T->bstart, x = atomicAdd(&c.cnt->bstart, v);
+                if (x + v > c.caps.bstart) err = kErrTreeCap;
+                T->bstart = x;
+            } break;
+            case 9: {
+                const unsigned long long v = T->cm, x = atomicAdd(&c.cnt->cm, v);
+                if (x + v > c.caps.cm) err = kErrCmCap;
+                T->cm = x;
+            } break;
+            case 10: {
+                const unsigned long long v = T->cs, x = atomicAdd(&c.cnt->cs, v);
+                if (x + v > c.caps.cs) err = kErrCmCap;
+                T->cs = x;
+            } break;
+            case 11: atomicAdd(&c.cnt->moved, T->moved); break;
+            case 12: atomicMax(&c.cnt->kmax, T->kmax); break;
+            case 13: {
+                const uint32_t v = T->n_learn;
+                T->n_learn = v ? atomicAdd(&c.cnt->pad0, v) : 0u;
+            } break;
+            default: break;
+        }
     }
-    if (T->n_large) {
-        uint32_t l0 = atomicAdd(&c.cnt->n_large, T->n_large);
-        uint32_t u0 = atomicAdd(&c.cnt->tiles, T->tiles);
-        uint32_t h0 = atomicAdd(&c.cnt->chunks, T->chunks);
-        uint32_t t0 = atomicAdd(&c.cnt->tree, T->tree);
-        uint32_t s0 = atomicAdd(&c.cnt->bstart, T->bstart);
-        unsigned long long m0 = atomicAdd(&c.cnt->cm, T->cm);
-        unsigned long long q0s = atomicAdd(&c.cnt->cs, T->cs);
-        atomicAdd(&c.cnt->moved, T->moved);
-        atomicMax(&c.cnt->kmax, T->kmax);
-        uint32_t q0 = 0;
-        if (T->n_learn) q0 = atomicAdd(&c.cnt->pad0, T->n_learn);
-        if (l0 + T->n_large > c.caps.large) err |= kErrLargeCap;
-        if (u0 + T->tiles > c.caps.tiles || h0 + T->chunks > c.caps.chunks) err |= kErrTileCap;
-        if (m0 + T->cm > c.caps.cm || q0s + T->cs > c.caps.cs) err |= kErrCmCap;
-        if (t0 + T->tree > c.caps.tree || s0 + T->bstart > c.caps.bstart) err |= kErrTreeCap;
-        T->n_large = l0;
-        T->tiles = u0;
-        T->chunks = h0;
-        T->tree = t0;
-        T->bstart = s0;
-        T->cm = m0;
-        T->cs = q0s;
-        T->n_learn = q0;
+    if (err) {
+        atomicOr(&T->err, err);
+        atomicOr(&c.glob->status, err);
     }
-    if (err) atomicOr(&c.glob->status, err);
-    T->err = err;
 }
 
 // Phase 3 for one request: take slots from the LDS counters and write the record.
@@ -259,7 +289,7 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
                                                    : default_set_params(ctx);
     if (req) plan_tally(e - b, ctx, sp, &T);
     __syncthreads();
-    if (threadIdx.x == 0) plan_allocate(ctx, &T);
+    if (threadIdx.x < 64) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
     if (req) plan_emit(b, e - b, 0, b, 0, ctx, sp, &T);
@@ -513,10 +543,18 @@ __device__ __forceinline__ void colscan_body(uint32_t cg, uint32_t redo, const L
     const uint32_t r1 = r0 + kChunkRows < g.tiles ? r0 + kChunkRows : g.tiles;
     uint32_t run = 0;
     uint32_t* col = cm + g.cm_base + b;
-    for (uint32_t r = r0; r < r1; ++r) {
-        uint32_t x = col[(uint64_t)r * g.k];
-        col[(uint64_t)r * g.k] = run;
-        run += x;
+    // 16 rows at a time: their loads are in flight together
+    for (uint32_t r = r0; r < r1; r += 16) {
+        const uint32_t m = r1 - r < 16 ? r1 - r : 16u;
+        uint32_t x[16];
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(r + i) * g.k] : 0u;
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i)
+            if (i < m) {
+                col[(uint64_t)(r + i) * g.k] = run;
+                run += x[i];
+            }
     }
     cs[g.cs_base + (uint64_t)c * g.k + b] = run;
 }
@@ -611,7 +649,7 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     for (uint32_t b = threadIdx.x; b < k; b += kWG)
         if (next_depth(b) != 0xFFFFFFFFu) plan_tally(tot[b], ctx, sp, &T);
     __syncthreads();
-    if (threadIdx.x == 0) plan_allocate(ctx, &T);
+    if (threadIdx.x < 64) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
