@@ -144,8 +144,9 @@ def learned_extra(name, steps=3):
     return res
 
 
-def batched_extra(steps=3, check_positions=1_000_000, oracle_sets=8):
-    """The batched form on 4,096 sets in one graph launch, with a full-size check."""
+def batched_extra(steps=3, check_positions=1_000_000, oracle_sets=8, learned=None):
+    """The batched form on 4,096 sets in one graph launch, with a full-size check
+    (learned: only that variant, else all three)."""
     import numpy as np
     import torch
     import oracle
@@ -172,6 +173,8 @@ def batched_extra(steps=3, check_positions=1_000_000, oracle_sets=8):
                                                   unroll=table["unroll"]), tuned),
                 ("sampled_tuned", s5.make_config(unroll=table["unroll"]), tuned),
                 ("sampled_defaults", s5.make_config(), None)]
+    if learned is not None:
+        variants = [v for v in variants if v[0] == ("learned_tuned" if learned else "sampled_tuned")]
     for label, cfg, tun in variants:
         log(f"batched: {label}")
         run = lambda: s5.sort_batched(dc, do, ds, cfg=cfg, tuning=tun, out_perm=perm,  # noqa
@@ -202,12 +205,39 @@ def batched_extra(steps=3, check_positions=1_000_000, oracle_sets=8):
     return res
 
 
+def batched_main(args):
+    """The batched workload as the main line: whole-job strings/s of one graph
+    launch per sort (autotuned per-set parameters), checked at full size."""
+    res = batched_extra(steps=args.steps, learned=args.learned)
+    label = "learned_tuned" if args.learned else "sampled_tuned"
+    r = res[label]
+    out = {
+        "metric": "strings/s and HBM GB/s (% peak), plain vs learned-splitter vs batched S^5",
+        "value": r["value"], "unit": "strings/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": r["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": res["workload"], "name": "sets_4096", "n": res["n"],
+                   "sets": res["sets"], "arena_bytes": res["arena_bytes"],
+                   "variant": "batched S^5 in one hipGraph, " +
+                   ("learned splitters per set with sampled fallback" if args.learned
+                    else "sampled splitters") + ", autotuned per-set parameters"},
+        "roofline": None,
+        "roofline_note": "kernels inside one graph launch are not bracketed by events; "
+                         "per-kernel durations come from rocprofv3 (profiles/)",
+        "batched": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="url_10M", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--workload", default="url_10M", choices=sorted(WORKLOAD_TEXT) + ["sets_4096"],
+                    help="sets_4096: the batched form (one graph launch per sort) as the main line")
+    ap.add_argument("--learned", action="store_true",
+                    help="learned splitter proposal (with its sampled fallback) for the main line")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000,
                     help="strings in the oracle's timed sample (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -228,13 +258,17 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.workload == "sets_4096":
+        batched_main(args)
+        return
+    cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED if args.learned else s5.SPLIT_SAMPLED)
     chars, offs = gen.workload(args.workload)
     n = int(offs.size)
     d_chars = torch.from_numpy(chars).to(dev)
     d_offs = torch.from_numpy(offs).to(dev)
     perm = torch.empty(n, dtype=torch.uint32, device=dev)
     lcp = torch.empty(n, dtype=torch.uint32, device=dev)
-    ws = torch.empty(s5.workspace_bytes(n), dtype=torch.uint8, device=dev)
+    ws = torch.empty(s5.workspace_bytes(n, cfg), dtype=torch.uint8, device=dev)
     if args.copy_probe_mib:
         a = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -243,7 +277,7 @@ def main():
         del a, b
 
     for _ in range(args.warmup):
-        s5.sort(d_chars, d_offs, out_perm=perm, out_lcp=lcp, workspace=ws)
+        s5.sort(d_chars, d_offs, cfg=cfg, out_perm=perm, out_lcp=lcp, workspace=ws)
     torch.cuda.synchronize()
     # timed region: HIP events bracket only the dominant kernel's launches
     s5.profile_enable(True)
@@ -251,7 +285,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        s5.sort(d_chars, d_offs, out_perm=perm, out_lcp=lcp, workspace=ws)
+        s5.sort(d_chars, d_offs, cfg=cfg, out_perm=perm, out_lcp=lcp, workspace=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     prof_dom = s5.profile_read()[DOMINANT]
@@ -260,7 +294,7 @@ def main():
     s5.profile_only(None)
     s5.profile_enable(True)
     for _ in range(3):
-        s5.sort(d_chars, d_offs, out_perm=perm, out_lcp=lcp, workspace=ws)
+        s5.sort(d_chars, d_offs, cfg=cfg, out_perm=perm, out_lcp=lcp, workspace=ws)
     torch.cuda.synchronize()
     prof = s5.profile_read()
     s5.profile_enable(False)
@@ -296,7 +330,9 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "n": n,
-                   "arena_bytes": int(chars.size), "D": D, "variant": "plain S^5, sampled splitters",
+                   "arena_bytes": int(chars.size), "D": D,
+                   "variant": "S^5, learned splitter proposal with sampled fallback" if args.learned
+                   else "plain S^5, sampled splitters",
                    "splitters_max": 255, "base_threshold": 1024},
         "hbm": {"B_min_bytes": b_min, "B_alg_bytes": b_alg, "moved_M": st["moved_M"],
                 "passes": st["passes"], "B_min_GBps": b_min / sec / 1e9,
