@@ -1062,8 +1062,9 @@ __device__ __forceinline__ void cex_local(uint64_t (&k)[E], uint32_t (&a)[E], ui
 }
 
 // Sort SK/SA[0..P) ascending, P a power of two, P / E <= kWG.  All threads call.
-// Each thread holds E consecutive elements in registers; only stages whose
-// partner lives in another thread exchange through LDS.
+// Each thread holds E consecutive elements in registers.  A stage whose
+// partner is another thread of the same wavefront exchanges by cross-lane
+// shuffles; only partners in other wavefronts go through LDS (with barriers).
 template <int E>
 __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     const uint32_t t = threadIdx.x;
@@ -1077,7 +1078,23 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     }
     for (uint32_t kk = 2; kk <= P; kk <<= 1) {
         for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            if (j >= (uint32_t)E) {
+            if (j >= (uint32_t)E && j / E < 64u) {
+                // partner thread t ^ (j / E) is in this wavefront (every lane
+                // takes part in the shuffles; inactive lanes hold padding)
+                const uint32_t m = j / E;
+#pragma unroll
+                for (int s = 0; s < E; ++s) {
+                    const uint64_t pk = shfl_xor64(k[s], (int)m);
+                    const uint32_t pa = __shfl_xor(a[s], (int)m);
+                    const uint32_t e = t * E + s;
+                    const bool keep_min = ((e & j) == 0) == ((e & kk) == 0);
+                    const bool pl = elem_less(pk, pa, k[s], a[s]);
+                    if (act && (keep_min ? pl : !pl)) {
+                        k[s] = pk;
+                        a[s] = pa;
+                    }
+                }
+            } else if (j >= (uint32_t)E) {
                 // exchange through LDS; slot s of thread t lives at t*E + ((s + t) mod E)
                 // so that the lanes of one access hit distinct banks
                 __syncthreads();
