@@ -326,6 +326,7 @@ PlanCtx plan_ctx(const Ptrs& P, const Layout& L, const Cfg& c, const SortArgs& a
     x.learn = c.mode == S5_SPLIT_LEARNED ? 1u : 0u;
     x.learn_cap = L.learn_cap;
     x.learn_seg = P.learn_seg;
+    x.stats = 0;
     return x;
 }
 
@@ -405,11 +406,13 @@ void pass_front(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
 
 // Bucket plan of the next pass, then the redistribution.
 void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
-               const PassShape& S, int cur, int buf, hipStream_t st) {
+               const PassShape& S, int cur, int buf, uint32_t level, hipStream_t st) {
     const int nxt = cur ^ 1;
+    PlanCtx x = plan_ctx(P, L, c, a, nxt);
+    x.stats = level == 0 ? 1u : 0u;  // the statistics report the first pass only
     timed(K_PLAN, S.now.moved, st, [&] {
-        launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp,
-                           plan_ctx(P, L, c, a, nxt), (uint32_t)(buf ^ 1), S.seg, st);
+        launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp, x,
+                           (uint32_t)(buf ^ 1), S.seg, st);
     });
     timed(K_SCATTER, S.now.moved, st, [&] {
         launch_scatter(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.bid, P.key[buf],
@@ -471,7 +474,7 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
             if (rc) return rc;
             if (H.hg->late_fallbacks != before) pass_front(a, c, L, P, S, cur, buf, 1u, st);
         }
-        pass_back(a, c, L, P, S, cur, buf, st);
+        pass_back(a, c, L, P, S, cur, buf, level, st);
         S5_HIP(hipGetLastError());
         rc = readback(P, H, nxt, st);
         if (rc) return rc;
@@ -572,7 +575,7 @@ void enqueue_graph_body(const SortArgs& a, const Cfg& c, const Layout& L, const 
             launch_learn_check(0, P.lseg[cur], P.learn_seg, P.cs, c.beta, P.glob, S.learn, st);
             pass_front(a, c, L, P, S, cur, buf, 1u, st);
         }
-        pass_back(a, c, L, P, S, cur, buf, st);
+        pass_back(a, c, L, P, S, cur, buf, level, st);
         launch_pass_stats(P.cnt[cur], P.cnt[cur ^ 1], P.glob, level, st);
     }
     const uint32_t* guard = &P.cnt[levels & 1u]->n_large;

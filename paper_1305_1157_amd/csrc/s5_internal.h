@@ -126,6 +126,7 @@ struct PlanCtx {
     uint32_t T;           // base threshold
     uint32_t d_max;       // tree depth limit for this sort
     uint32_t tile_min;    // minimum strings per tile
+    uint32_t stats;       // 1: accumulate bucket entropy and max bucket (first pass only)
 };
 
 // Per-set parameters of a batched sort, packed in one word: base threshold T

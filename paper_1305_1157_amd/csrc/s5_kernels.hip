@@ -585,12 +585,20 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     const SetP sp = set_params(ctx, g.base);
     const uint32_t k = g.k;
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
+        // exclusive prefix over the chunk sums, 16 chunks' loads in flight at once
         uint32_t run = 0;
-        for (uint32_t c = 0; c < g.chunks; ++c) {
-            uint32_t* p = cs + g.cs_base + (uint64_t)c * k + b;
-            uint32_t x = *p;
-            *p = run;
-            run += x;
+        uint32_t* col = cs + g.cs_base + b;
+        for (uint32_t c = 0; c < g.chunks; c += 16) {
+            const uint32_t m = g.chunks - c < 16 ? g.chunks - c : 16u;
+            uint32_t x[16];
+#pragma unroll
+            for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(c + i) * k] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < 16; ++i)
+                if (i < m) {
+                    col[(uint64_t)(c + i) * k] = run;
+                    run += x[i];
+                }
         }
         tot[b] = run;
     }
@@ -604,34 +612,46 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
         const uint32_t s0 = st[b];
         bs[b] = s0;
-        for (uint32_t c = 0; c < g.chunks; ++c) cs[g.cs_base + (uint64_t)c * k + b] += s0;
+        uint32_t* col = cs + g.cs_base + b;
+        for (uint32_t c = 0; c < g.chunks; c += 16) {
+            const uint32_t m = g.chunks - c < 16 ? g.chunks - c : 16u;
+            uint32_t x[16];
+#pragma unroll
+            for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(c + i) * k] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < 16; ++i)
+                if (i < m) col[(uint64_t)(c + i) * k] = x[i] + s0;
+        }
         const uint32_t sz = tot[b];
-        if (sz == 0) continue;
+        if (sz == 0 || !ctx.stats) continue;
         ent += (double)sz * log2((double)g.size / (double)sz);
         if (sz > mx) mx = sz;
     }
     if (threadIdx.x == 0) bs[k] = g.size;
-    // block-reduce the statistics, then one atomic each per block
-    __shared__ double s_ent;
-    __shared__ unsigned long long s_mx;
-    if (threadIdx.x == 0) {
-        s_ent = 0.0;
-        s_mx = 0;
-    }
     __syncthreads();
-    for (uint32_t o = 32; o > 0; o >>= 1) {
-        ent += __shfl_xor(ent, (int)o);
-        const unsigned long long om = __shfl_xor(mx, (int)o);
-        mx = om > mx ? om : mx;
-    }
-    if (lane_id() == 0) {
-        atomicAdd(&s_ent, ent);
-        atomicMax(&s_mx, mx);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (s_mx) atomicMax(&ctx.cnt->max_bucket, s_mx);
-        if (s_ent != 0.0) atomicAdd(&ctx.cnt->entropy_sum, s_ent);
+    if (ctx.stats) {
+        // block-reduce the statistics, then one atomic each per block
+        __shared__ double s_ent;
+        __shared__ unsigned long long s_mx;
+        if (threadIdx.x == 0) {
+            s_ent = 0.0;
+            s_mx = 0;
+        }
+        __syncthreads();
+        for (uint32_t o = 32; o > 0; o >>= 1) {
+            ent += __shfl_xor(ent, (int)o);
+            const unsigned long long om = __shfl_xor(mx, (int)o);
+            mx = om > mx ? om : mx;
+        }
+        if (lane_id() == 0) {
+            atomicAdd(&s_ent, ent);
+            atomicMax(&s_mx, mx);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (s_mx) atomicMax(&ctx.cnt->max_bucket, s_mx);
+            if (s_ent != 0.0) atomicAdd(&ctx.cnt->entropy_sum, s_ent);
+        }
     }
     // new depth of bucket b, or 0xFFFFFFFF if it needs no further sorting
     // (empty, a single string, or an equality bucket whose splitter ends the
