@@ -1221,7 +1221,8 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     uint64_t* OFFL = SK + pmax;                 // pmax string starts, by local index
     uint32_t* A = (uint32_t*)(OFFL + pmax);     // pmax packed group | local, by position
     uint32_t* SA = A + pmax;                    // pmax compacted members
-    uint16_t* POS = (uint16_t*)(SA + pmax);     // pmax position of each compacted member
+    uint32_t* IDX = SA + pmax;                  // pmax input index of every local index
+    uint16_t* POS = (uint16_t*)(IDX + pmax);    // pmax position of each compacted member
     uint8_t* F = (uint8_t*)(POS + pmax);        // pmax: pair (i-1, i) undecided
     __shared__ uint32_t wl[2 * kWaves];
     const Seg it = items[item];
@@ -1237,6 +1238,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     for (uint32_t i = tid; i < P; i += kWG) {
         K[i] = i < n ? kin[i] : ~0ull;
         A[i] = i < n ? i : 0xFFFFFFFFu;
+        if (i < n) IDX[i] = iin[i];
     }
     __syncthreads();
     sort_pow2<EMAX>(K, A, P);
@@ -1282,7 +1284,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         if (first) {  // string starts of the undecided strings (later members are among them)
             for (uint32_t q = tid; q < m; q += kWG) {
                 const uint32_t l = SA[q] & 0xFFFFu;
-                OFFL[l] = offsets[iin[l]];
+                OFFL[l] = offsets[IDX[l]];
             }
             first = false;
             __syncthreads();
@@ -1358,7 +1360,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         }
         any = __syncthreads_or(any);
     }
-    for (uint32_t i = tid; i < n; i += kWG) out_perm[it.begin + i] = iin[A[i] & 0xFFFFu] - it.base;
+    for (uint32_t i = tid; i < n; i += kWG) out_perm[it.begin + i] = IDX[A[i] & 0xFFFFu] - it.base;
 }
 
 template <int EMAX, bool G>
@@ -1613,7 +1615,7 @@ static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const u
     }
     uint32_t PT = 1;
     while (PT < T) PT <<= 1;
-    const size_t per = 8 + 8 + 8 + 4 + 4 + 2 + 1;  // K, SK, OFFL, A, SA, POS, F
+    const size_t per = 8 + 8 + 8 + 4 + 4 + 4 + 2 + 1;  // K, SK, OFFL, A, SA, IDX, POS, F
     if (G || n_items[1]) {
         const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
         S5_LAUNCH((k_base_block<kBaseMid / kWG, G>), dim3(G ? dy[1].grid : n_items[1]), dim3(kWG),
