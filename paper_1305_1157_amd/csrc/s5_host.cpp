@@ -100,7 +100,8 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     // every base item holds >= 2 strings, and > 64 / > 512 in the larger classes
     cp.base[0] = (uint32_t)(n / 2 + 2);
     cp.base[1] = (uint32_t)(n / (kBaseWave + 1) + 2);
-    cp.base[2] = (uint32_t)(n / (kBaseMid + 1) + 2);
+    cp.base[2] = (uint32_t)(n / (kBaseSmall + 1) + 2);
+    cp.base[3] = (uint32_t)(n / (kBaseMid + 1) + 2);
     // sum over segments of tiles x k: tiles_s <= |S|/tile_min + 1 and
     // k_s <= max(3, min(kmax, 8 |S| / T))
     const uint64_t ksum = 3 * large + 8 * n / c.T_caps + kmax;
@@ -124,7 +125,9 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     L.cm = take((size_t)cp.cm * 4);
     L.cs = take((size_t)cp.cs * 4);
     L.bstart = take((size_t)cp.bstart * 4);
-    L.base_list = take((size_t)(cp.base[0] + cp.base[1] + cp.base[2]) * sizeof(Seg));
+    size_t base_items = 0;
+    for (int q = 0; q < kBaseClasses; ++q) base_items += cp.base[q];
+    L.base_list = take(base_items * sizeof(Seg));
     // learned splitters: one slot per segment of >= kLearnMin strings in a pass
     L.learn_cap = c.mode == S5_SPLIT_LEARNED ? (uint32_t)std::min<uint64_t>(large, n / kLearnMin + 1) : 0u;
     L.learn = take(learn_bytes(L.learn_cap, kLearnSamples));
@@ -304,8 +307,7 @@ Ptrs make_ptrs(const Layout& L, char* W) {
     P.set_tune = L.tune_sets ? (uint32_t*)(W + L.set_tune) : nullptr;
     P.lctx = learn_ctx(W + L.learn, L.learn_cap, kLearnSamples);
     P.base_list[0] = (Seg*)(W + L.base_list);
-    P.base_list[1] = P.base_list[0] + L.caps.base[0];
-    P.base_list[2] = P.base_list[1] + L.caps.base[1];
+    for (int q = 1; q < kBaseClasses; ++q) P.base_list[q] = P.base_list[q - 1] + L.caps.base[q - 1];
     P.glob = (Globals*)(W + L.glob);
     return P;
 }
@@ -506,7 +508,8 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
 
 void final_stats(const HostView& H, s5_stats* stats) {
     stats->fallbacks = H.hg->fallbacks;
-    stats->base_items = (uint64_t)H.hg->n_base[0] + H.hg->n_base[1] + H.hg->n_base[2];
+    stats->base_items = 0;
+    for (int q = 0; q < kBaseClasses; ++q) stats->base_items += H.hg->n_base[q];
 }
 
 // The whole sort on one workspace, host-driven.  `host` is a pinned block of
@@ -584,7 +587,7 @@ void enqueue_graph_body(const SortArgs& a, const Cfg& c, const Layout& L, const 
         const uint32_t units = q == 0 ? (L.caps.base[0] + kWaves - 1) / kWaves : L.caps.base[q];
         bd[q] = dyn_of(&P.glob->n_base[q], L.caps.base[q], std::min(units, kGraphBaseGrid));
     }
-    const uint32_t zero[kBaseClasses] = {0, 0, 0};
+    const uint32_t zero[kBaseClasses] = {};
     launch_base_sort(zero, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
                      a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard, st);
     launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, guard, st);

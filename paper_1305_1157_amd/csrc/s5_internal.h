@@ -57,12 +57,14 @@ struct Counters {
 };
 
 // Device-global state that survives the whole sort.
-// Base-case items go to one of three lists by size: <= 64 strings (one
-// wavefront each), <= 512, and <= T (one workgroup each).
-constexpr int kBaseClasses = 3;
-constexpr uint32_t kBaseWave = 64, kBaseMid = 512;
+// Base-case items go to one of four lists by size: <= 64 strings (one
+// wavefront each, in registers), <= 256 (a one-wavefront workgroup), <= 512
+// (two wavefronts) and <= T (four wavefronts), so that small items hold little
+// LDS and many of them are in flight on a compute unit.
+constexpr int kBaseClasses = 4;
+constexpr uint32_t kBaseWave = 64, kBaseSmall = 256, kBaseMid = 512;
 __host__ __device__ inline int base_class(uint32_t size) {
-    return size <= kBaseWave ? 0 : (size <= kBaseMid ? 1 : 2);
+    return size <= kBaseWave ? 0 : (size <= kBaseSmall ? 1 : (size <= kBaseMid ? 2 : 3));
 }
 
 struct Globals {

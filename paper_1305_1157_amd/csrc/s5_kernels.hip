@@ -128,12 +128,13 @@ __device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, cons
 // bases (stored back into T).  Each lane owns one global counter, so the
 // block's atomics are independent and in flight together.
 __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
+    constexpr uint32_t kLane = 8;  // first lane of the next pass's counters
     const uint32_t l = threadIdx.x;
     const uint32_t nl = T->n_large;
     uint32_t err = 0;
     if (l == 0) {
         if (T->base_elems) atomicAdd(&c.glob->base_elems, T->base_elems);
-    } else if (l <= (uint32_t)kBaseClasses) {
+    } else if (l <= (uint32_t)kBaseClasses) {  // lanes 1..kBaseClasses: base lists
         const int q = (int)l - 1;
         const uint32_t nb = T->n_base[q];
         if (nb) {
@@ -143,44 +144,44 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
         }
     } else if (nl) {
         switch (l) {
-            case 4: {
+            case kLane + 0: {
                 const uint32_t x = atomicAdd(&c.cnt->n_large, nl);
                 if (x + nl > c.caps.large) err = kErrLargeCap;
                 T->n_large = x;
             } break;
-            case 5: {
+            case kLane + 1: {
                 const uint32_t v = T->tiles, x = atomicAdd(&c.cnt->tiles, v);
                 if (x + v > c.caps.tiles) err = kErrTileCap;
                 T->tiles = x;
             } break;
-            case 6: {
+            case kLane + 2: {
                 const uint32_t v = T->chunks, x = atomicAdd(&c.cnt->chunks, v);
                 if (x + v > c.caps.chunks) err = kErrTileCap;
                 T->chunks = x;
             } break;
-            case 7: {
+            case kLane + 3: {
                 const uint32_t v = T->tree, x = atomicAdd(&c.cnt->tree, v);
                 if (x + v > c.caps.tree) err = kErrTreeCap;
                 T->tree = x;
             } break;
-            case 8: {
+            case kLane + 4: {
                 const uint32_t v = T->bstart, x = atomicAdd(&c.cnt->bstart, v);
                 if (x + v > c.caps.bstart) err = kErrTreeCap;
                 T->bstart = x;
             } break;
-            case 9: {
+            case kLane + 5: {
                 const unsigned long long v = T->cm, x = atomicAdd(&c.cnt->cm, v);
                 if (x + v > c.caps.cm) err = kErrCmCap;
                 T->cm = x;
             } break;
-            case 10: {
+            case kLane + 6: {
                 const unsigned long long v = T->cs, x = atomicAdd(&c.cnt->cs, v);
                 if (x + v > c.caps.cs) err = kErrCmCap;
                 T->cs = x;
             } break;
-            case 11: atomicAdd(&c.cnt->moved, T->moved); break;
-            case 12: atomicMax(&c.cnt->kmax, T->kmax); break;
-            case 13: {
+            case kLane + 7: atomicAdd(&c.cnt->moved, T->moved); break;
+            case kLane + 8: atomicMax(&c.cnt->kmax, T->kmax); break;
+            case kLane + 9: {
                 const uint32_t v = T->n_learn;
                 T->n_learn = v ? atomicAdd(&c.cnt->pad0, v) : 0u;
             } break;
@@ -242,7 +243,7 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
 
 __device__ __forceinline__ void tally_clear(PlanTally* T) {
     if (threadIdx.x == 0) {
-        T->n_base[0] = T->n_base[1] = T->n_base[2] = 0;
+        for (int q = 0; q < kBaseClasses; ++q) T->n_base[q] = 0;
         T->n_large = T->tiles = T->chunks = T->tree = T->bstart = T->kmax = T->err = 0;
         T->n_learn = 0;
         T->cm = T->cs = T->moved = T->base_elems = 0;
@@ -1081,11 +1082,11 @@ __device__ __forceinline__ void cex_local(uint64_t (&k)[E], uint32_t (&a)[E], ui
     }
 }
 
-// Sort SK/SA[0..P) ascending, P a power of two, P / E <= kWG.  All threads call.
+// Sort SK/SA[0..P) ascending, P a power of two, P / E <= NT.  All NT threads call.
 // Each thread holds E consecutive elements in registers.  A stage whose
 // partner is another thread of the same wavefront exchanges by cross-lane
 // shuffles; only partners in other wavefronts go through LDS (with barriers).
-template <int E>
+template <int E, int NT>
 __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
@@ -1160,24 +1161,26 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     __syncthreads();
 }
 
-// P <= EMAX * kWG; only the instantiations up to EMAX are compiled into a kernel,
+// P <= EMAX * NT; only the instantiations up to EMAX are compiled into a kernel,
 // so small-bucket kernels keep a small register footprint.
-template <int EMAX>
+template <int EMAX, int NT>
 __device__ void sort_pow2(uint64_t* SK, uint32_t* SA, uint32_t P) {
-    if (P <= (uint32_t)kWG) block_bitonic<1>(SK, SA, P);
+    if (P <= (uint32_t)NT) block_bitonic<1, NT>(SK, SA, P);
     else if constexpr (EMAX >= 2) {
-        if (P <= 2u * kWG) block_bitonic<2>(SK, SA, P);
+        if (P <= 2u * NT) block_bitonic<2, NT>(SK, SA, P);
         else if constexpr (EMAX >= 4) {
-            if (P <= 4u * kWG) block_bitonic<4>(SK, SA, P);
-            else if constexpr (EMAX >= 8) block_bitonic<8>(SK, SA, P);
+            if (P <= 4u * NT) block_bitonic<4, NT>(SK, SA, P);
+            else if constexpr (EMAX >= 8) block_bitonic<8, NT>(SK, SA, P);
         }
     }
 }
 
 // Exclusive block scans of two per-thread values at once: running maximum of
-// `mx` and running sum of `ad` (in thread order).  `wl` holds 2 * kWaves
+// `mx` and running sum of `ad` (in thread order).  `wl` holds 2 * NT / 64
 // words.  Returns the block-wide sum of `ad`.
+template <int NT>
 __device__ uint32_t block_scan_max_add(uint32_t& mx, uint32_t& ad, uint32_t* wl) {
+    constexpr uint32_t kW = NT / 64;
     const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
     uint32_t im = mx, ia = ad;
     for (uint32_t o = 1; o < 64; o <<= 1) {
@@ -1189,16 +1192,16 @@ __device__ uint32_t block_scan_max_add(uint32_t& mx, uint32_t& ad, uint32_t* wl)
     }
     if (lane == 63) {
         wl[w] = im;
-        wl[kWaves + w] = ia;
+        wl[kW + w] = ia;
     }
     __syncthreads();
     uint32_t pm = 0, pa = 0, total = 0;
-    for (uint32_t q = 0; q < (uint32_t)kWaves; ++q) {
+    for (uint32_t q = 0; q < kW; ++q) {
         if (q < w) {
             pm = wl[q] > pm ? wl[q] : pm;
-            pa += wl[kWaves + q];
+            pa += wl[kW + q];
         }
-        total += wl[kWaves + q];
+        total += wl[kW + q];
     }
     uint32_t em = __shfl_up(im, 1), ea = __shfl_up(ia, 1);
     if (lane == 0) em = ea = 0;
@@ -1208,7 +1211,7 @@ __device__ uint32_t block_scan_max_add(uint32_t& mx, uint32_t& ad, uint32_t* wl)
     return total;
 }
 
-template <int EMAX>
+template <int EMAX, int NT>
 __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
                                                 const uint64_t* key0, const uint64_t* key1,
                                                 const uint32_t* idx0, const uint32_t* idx1,
@@ -1224,7 +1227,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     uint32_t* IDX = SA + pmax;                  // pmax input index of every local index
     uint16_t* POS = (uint16_t*)(IDX + pmax);    // pmax position of each compacted member
     uint8_t* F = (uint8_t*)(POS + pmax);        // pmax: pair (i-1, i) undecided
-    __shared__ uint32_t wl[2 * kWaves];
+    __shared__ uint32_t wl[2 * (NT / 64)];
     const Seg it = items[item];
     const uint32_t buf = it.depth >> 31;
     uint32_t h = it.depth & ~kBufBit;
@@ -1235,15 +1238,15 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     const uint32_t* iin = (buf ? idx1 : idx0) + it.begin;
     uint32_t* olcp = out_lcp + it.begin;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < P; i += kWG) {
+    for (uint32_t i = tid; i < P; i += NT) {
         K[i] = i < n ? kin[i] : ~0ull;
         A[i] = i < n ? i : 0xFFFFFFFFu;
         if (i < n) IDX[i] = iin[i];
     }
     __syncthreads();
-    sort_pow2<EMAX>(K, A, P);
+    sort_pow2<EMAX, NT>(K, A, P);
     // each thread owns positions [c0, c1)
-    const uint32_t per = (n + kWG - 1) / kWG;
+    const uint32_t per = (n + NT - 1) / NT;
     const uint32_t c0 = tid * per < n ? tid * per : n;
     const uint32_t c1 = c0 + per < n ? c0 + per : n;
     int any = 0;
@@ -1269,7 +1272,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             if (!F[i]) mx = i;
             cnt += (F[i] || (i + 1 < n && F[i + 1])) ? 1u : 0u;
         }
-        const uint32_t m = block_scan_max_add(mx, cnt, wl);
+        const uint32_t m = block_scan_max_add<NT>(mx, cnt, wl);
         uint32_t run = mx, r = cnt;
         for (uint32_t i = c0; i < c1; ++i) {
             if (!F[i]) run = i;
@@ -1282,7 +1285,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         }
         __syncthreads();
         if (first) {  // string starts of the undecided strings (later members are among them)
-            for (uint32_t q = tid; q < m; q += kWG) {
+            for (uint32_t q = tid; q < m; q += NT) {
                 const uint32_t l = SA[q] & 0xFFFFu;
                 OFFL[l] = offsets[IDX[l]];
             }
@@ -1307,20 +1310,20 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         uint32_t Pm = 1;
         while (Pm < m) Pm <<= 1;
         {
-            // up to pmax / kWG members per thread: all their gathers in flight at once
+            // up to pmax / NT members per thread: all their gathers in flight at once
             constexpr int G = EMAX;
             uint64_t pos[G], nkey[G];
             bool need[G];
 #pragma unroll
             for (int e = 0; e < G; ++e) {
-                const uint32_t q = tid + e * kWG;
+                const uint32_t q = tid + e * NT;
                 need[e] = q < m;
                 pos[e] = need[e] ? OFFL[SA[q] & 0xFFFFu] + h : 0ull;
             }
             load_keys<G>(chars, pos, need, nkey);
 #pragma unroll
             for (int e = 0; e < G; ++e) {
-                const uint32_t q = tid + e * kWG;
+                const uint32_t q = tid + e * NT;
                 if (q < m) SK[q] = nkey[e];
             }
         }
@@ -1328,23 +1331,23 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         // re-sort only if some group's keys now differ (equal keys keep their
         // local-index order)
         int split = 0;
-        for (uint32_t q = tid + 1; q < m; q += kWG)
+        for (uint32_t q = tid + 1; q < m; q += NT)
             split |= ((SA[q] >> 16) == (SA[q - 1] >> 16) && SK[q] != SK[q - 1]) ? 1 : 0;
         split = __syncthreads_or(split);
         if (split) {
-            for (uint32_t q = m + tid; q < Pm; q += kWG) {
+            for (uint32_t q = m + tid; q < Pm; q += NT) {
                 SK[q] = ~0ull;
                 SA[q] = 0xFFFFFFFFu;
             }
             __syncthreads();
-            sort_pow2<EMAX>(SK, SA, Pm);
-            for (uint32_t q = tid; q < m; q += kWG) {
+            sort_pow2<EMAX, NT>(SK, SA, Pm);
+            for (uint32_t q = tid; q < m; q += NT) {
                 const uint32_t i = POS[q];
                 K[i] = SK[q];
                 A[i] = SA[q];
             }
         } else {
-            for (uint32_t q = tid; q < m; q += kWG) K[POS[q]] = SK[q];
+            for (uint32_t q = tid; q < m; q += NT) K[POS[q]] = SK[q];
         }
         __syncthreads();
         any = 0;
@@ -1360,11 +1363,11 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         }
         any = __syncthreads_or(any);
     }
-    for (uint32_t i = tid; i < n; i += kWG) out_perm[it.begin + i] = IDX[A[i] & 0xFFFFu] - it.base;
+    for (uint32_t i = tid; i < n; i += NT) out_perm[it.begin + i] = IDX[A[i] & 0xFFFFu] - it.base;
 }
 
-template <int EMAX, bool G>
-__global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint64_t* key0,
+template <int EMAX, bool G, int NT>
+__global__ __launch_bounds__(NT) void k_base_block(const Seg* items, const uint64_t* key0,
                                                     const uint64_t* key1, const uint32_t* idx0,
                                                     const uint32_t* idx1, const uint8_t* chars,
                                                     const uint64_t* offsets, uint32_t* out_perm,
@@ -1372,13 +1375,13 @@ __global__ __launch_bounds__(256) void k_base_block(const Seg* items, const uint
                                                     const uint32_t* wcnt, uint32_t cap,
                                                     const Globals* glob, const uint32_t* guard) {
     if (!G) {
-        base_block_body<EMAX>(blockIdx.x, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+        base_block_body<EMAX, NT>(blockIdx.x, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
                               out_lcp, pmax);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x, guard);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        base_block_body<EMAX>(u, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+        base_block_body<EMAX, NT>(u, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
                               pmax);
         __syncthreads();
     }
@@ -1616,22 +1619,28 @@ static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const u
     uint32_t PT = 1;
     while (PT < T) PT <<= 1;
     const size_t per = 8 + 8 + 8 + 4 + 4 + 4 + 2 + 1;  // K, SK, OFFL, A, SA, IDX, POS, F
-    if (G || n_items[1]) {
-        const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
-        S5_LAUNCH((k_base_block<kBaseMid / kWG, G>), dim3(G ? dy[1].grid : n_items[1]), dim3(kWG),
-                  per * P, st, items[1], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
-                  P, dy[1].cnt, dy[1].cap, glob, guard);
+    if ((G || n_items[1]) && PT > kBaseWave) {  // <= 256 strings: one wavefront
+        const uint32_t P = PT < kBaseSmall ? PT : kBaseSmall;
+        S5_LAUNCH((k_base_block<4, G, 64>), dim3(G ? dy[1].grid : n_items[1]), dim3(64), per * P,
+                  st, items[1], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P,
+                  dy[1].cnt, dy[1].cap, glob, guard);
     }
-    if ((G || n_items[2]) && PT > kBaseMid) {
-        const dim3 g(G ? dy[2].grid : n_items[2]);
+    if ((G || n_items[2]) && PT > kBaseSmall) {  // <= 512 strings: two wavefronts
+        const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
+        S5_LAUNCH((k_base_block<4, G, 128>), dim3(G ? dy[2].grid : n_items[2]), dim3(128), per * P,
+                  st, items[2], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P,
+                  dy[2].cnt, dy[2].cap, glob, guard);
+    }
+    if ((G || n_items[3]) && PT > kBaseMid) {  // <= T strings: four wavefronts
+        const dim3 g(G ? dy[3].grid : n_items[3]);
         if (PT <= 4u * kWG)
-            S5_LAUNCH((k_base_block<4, G>), g, dim3(kWG), per * PT, st, items[2], key0, key1, idx0,
-                      idx1, chars, offsets, out_perm, out_lcp, PT, dy[2].cnt, dy[2].cap, glob,
-                      guard);
+            S5_LAUNCH((k_base_block<4, G, kWG>), g, dim3(kWG), per * PT, st, items[3], key0, key1,
+                      idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt, dy[3].cap,
+                      glob, guard);
         else
-            S5_LAUNCH((k_base_block<8, G>), g, dim3(kWG), per * PT, st, items[2], key0, key1, idx0,
-                      idx1, chars, offsets, out_perm, out_lcp, PT, dy[2].cnt, dy[2].cap, glob,
-                      guard);
+            S5_LAUNCH((k_base_block<8, G, kWG>), g, dim3(kWG), per * PT, st, items[3], key0, key1,
+                      idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt, dy[3].cap,
+                      glob, guard);
     }
 }
 
