@@ -17,8 +17,9 @@
  *   - chars: the arena.  Each string runs from chars[offsets[i]] to its first
  *     0 byte.  Strings may overlap (e.g. all suffixes of one text) and offsets
  *     need not be increasing.  The library only reads aligned 8-byte words that
- *     contain at least one byte of some string, so it never touches memory
- *     outside the arena's pages.  No string may be 2^31 bytes or longer.
+ *     lie in a 4 KiB page holding at least one byte of some string, so it
+ *     never touches memory outside the arena's pages.  No string may be 2^31
+ *     bytes or longer.
  *   - out_perm[i]: input index of the i-th smallest string; equal strings are
  *     listed by ascending input index, which makes the output unique.
  *   - out_lcp[0] = 0; out_lcp[i] = number of equal leading bytes of strings

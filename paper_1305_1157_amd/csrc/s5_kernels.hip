@@ -254,11 +254,15 @@ __device__ __forceinline__ void tally_clear(PlanTally* T) {
 // K1: prefix cache at depth 0 (and the building-block entry point)
 
 __global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, const uint64_t* offsets,
-                                                   uint32_t n, uint64_t* key, uint32_t* idx) {
+                                                   uint32_t n, uint64_t* key, uint64_t* key2,
+                                                   uint32_t* idx) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     idx[i] = i;
-    key[i] = load_key(chars, offsets[i]);
+    uint64_t k0, k1;
+    load_key16(chars, offsets[i], &k0, &k1);
+    key[i] = k0;
+    key2[i] = k1;
 }
 
 __global__ __launch_bounds__(256) void k_prefix_keys(const uint8_t* chars, const uint64_t* offsets,
@@ -715,6 +719,9 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
 constexpr uint32_t kPerWave = kSubTile / kWaves;  // strings per wavefront per sub-tile
 constexpr int kChunks = (int)(kPerWave / 64);     // chunks of 64 per wavefront
 
+// bucket / rank word of a lane that holds no string (never a (bucket << 16 | rank))
+constexpr uint32_t kNoString = 0xFFFFFFFFu;
+
 // per-bucket byte: mode in bits 4..5, depth increase (0..8) in bits 0..3
 constexpr uint32_t kModeLive = 0, kModeSingle = 1, kModeIdentical = 2;
 
@@ -741,10 +748,10 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
 
 __device__ __forceinline__ void scatter_body(
     uint32_t tile, const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid,
-    const uint64_t* key_in, const uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out,
-    const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in,
+    const uint64_t* key_in, const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out,
+    uint64_t* key2_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in,
     const uint8_t* tree_lcp, const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
-    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax) {
+    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, bool fresh) {
     extern __shared__ uint64_t dyn[];
     uint64_t* SK = dyn;                                   // kSubTile staged keys
     uint32_t* SI = (uint32_t*)(SK + kSubTile);            // kSubTile staged indices
@@ -800,30 +807,32 @@ __device__ __forceinline__ void scatter_body(
         const uint32_t se = sub + kSubTile < end ? sub + kSubTile : end;
         const uint32_t pw = sub + w * kPerWave + lane;
         // A: load, refresh, rank inside the wavefront
-        uint64_t nk[kChunks];
+        uint64_t nk[kChunks], n2[kChunks];
         uint32_t id[kChunks], bb[kChunks];
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             const uint32_t p = pw + c * 64;
             const bool valid = p < se;
-            bb[c] = valid ? bid[p] : 0xFFFFu;
+            bb[c] = valid ? bid[p] : kNoString;
             nk[c] = valid ? key_in[p] : 0ull;
+            n2[c] = valid ? key2_in[p] : 0ull;
             id[c] = valid ? idx_in[p] : 0u;
         }
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            if (bb[c] == 0xFFFFu) continue;
+            if (bb[c] == kNoString) continue;
             const uint32_t info = binfo[bb[c]];
             const uint32_t delta = info & 15u;
             if ((info >> 4) != kModeLive || delta == 0) continue;
-            if (delta < 8 && has_zero(nk[c]))
-                nk[c] <<= 8 * delta;
-            else
-                nk[c] = load_key(chars, offsets[id[c]] + g.depth + delta);
+            // the first pass reads strings in input order, where a gather is
+            // cheap: it gathers whenever the second word would become unknown
+            if (!advance_key16(&nk[c], &n2[c], delta) || (fresh && n2[c] == kKeyUnknown))
+                load_key16(chars, offsets[id[c]] + g.depth + delta, &nk[c], &n2[c]);
         }
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            const bool valid = bb[c] != 0xFFFFu;
+            // a chunk past the sub-tile's end leaves every later chunk kNoString too
+            const bool valid = bb[c] != kNoString;
             const uint64_t act = __ballot(valid);
             if (!act) break;
             const uint32_t b = valid ? bb[c] : 0u;
@@ -831,7 +840,7 @@ __device__ __forceinline__ void scatter_body(
             const uint32_t old = valid ? wh[b] : 0u;
             if (valid && lane == (uint32_t)(__ffsll((long long)m) - 1))
                 wh[b] = (uint16_t)(old + (uint32_t)__popcll(m));
-            bb[c] = valid ? ((b << 16) | (old + (uint32_t)__popcll(m & ltmask))) : 0xFFFFFFFFu;
+            bb[c] = valid ? ((b << 16) | (old + (uint32_t)__popcll(m & ltmask))) : kNoString;
         }
         __syncthreads();
         // B: prefix over wavefronts per bucket, then bucket starts inside the sub-tile
@@ -868,12 +877,15 @@ __device__ __forceinline__ void scatter_body(
         // C: stage in bucket order
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            if (bb[c] == 0xFFFFFFFFu) continue;
+            if (bb[c] == kNoString) continue;
             const uint32_t b = bb[c] >> 16;
             const uint32_t s = (uint32_t)tstart[b] + whist[w * kmax + b] + (bb[c] & 0xFFFFu);
             SK[s] = nk[c];
             SI[s] = id[c];
             SB[s] = (uint16_t)b;
+            // the second key word goes straight to its place (runs of a bucket
+            // are consecutive within a chunk)
+            if ((binfo[b] >> 4) == kModeLive) key2_out[g.begin + base[b] + s - tstart[b]] = n2[c];
         }
         __syncthreads();
         // D: write contiguous runs
@@ -906,19 +918,22 @@ __device__ __forceinline__ void scatter_body(
 template <bool G>
 __global__ __launch_bounds__(256) void k_scatter(
     const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
-    const uint32_t* idx_in, uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm,
-    const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
-    const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp,
-    uint32_t vmax, uint32_t kmax, const uint32_t* wcnt, uint32_t cap, const Globals* glob) {
+    const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out, uint64_t* key2_out,
+    uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart,
+    const uint64_t* tree_in, const uint8_t* tree_lcp, const uint8_t* chars,
+    const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp, uint32_t vmax, uint32_t kmax,
+    const uint32_t* wcnt, uint32_t cap, const Globals* glob, uint32_t fresh) {
     if (!G) {
-        scatter_body(blockIdx.x, lseg, tile_tab, bid, key_in, idx_in, key_out, idx_out, cm, cs,
-                     bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax);
+        scatter_body(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out,
+                     idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp,
+                     vmax, kmax, fresh != 0);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        scatter_body(u, lseg, tile_tab, bid, key_in, idx_in, key_out, idx_out, cm, cs, bstart,
-                     tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax);
+        scatter_body(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out,
+                     cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax,
+                     kmax, fresh != 0);
         __syncthreads();
     }
 }
@@ -1488,9 +1503,10 @@ static inline uint32_t dyn_grid(const Dyn& dy, uint32_t host_units) {
 }
 
 void launch_init_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint64_t* key,
-                      uint32_t* idx, hipStream_t st) {
+                      uint64_t* key2, uint32_t* idx, hipStream_t st) {
     if (!n) return;
-    S5_LAUNCH(k_init_keys, dim3((n + 255) / 256), dim3(256), 0, st, chars, offsets, n, key, idx);
+    S5_LAUNCH(k_init_keys, dim3((n + 255) / 256), dim3(256), 0, st, chars, offsets, n, key, key2,
+              idx);
 }
 
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
@@ -1583,23 +1599,24 @@ void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32
 }
 
 void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
-                    const uint16_t* bid, const uint64_t* key_in, const uint32_t* idx_in,
-                    uint64_t* key_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs,
+                    const uint16_t* bid, const uint64_t* key_in, const uint64_t* key2_in,
+                    const uint32_t* idx_in, uint64_t* key_out, uint64_t* key2_out,
+                    uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs,
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, hipStream_t st) {
+                    const Dyn& dy, uint32_t fresh, hipStream_t st) {
     (void)unroll;
     const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
                        (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
     if (dy.cnt)
         S5_LAUNCH(k_scatter<true>, dim3(dy.grid), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,
-                  idx_in, key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
-                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob);
+                  key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
+                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob, fresh);
     else
         S5_LAUNCH(k_scatter<false>, dim3(tiles), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,
-                  idx_in, key_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
-                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob);
+                  key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
+                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob, fresh);
 }
 
 // Host-driven: n_items[q] items of class q.  Graph mode (dy[q].cnt set): the

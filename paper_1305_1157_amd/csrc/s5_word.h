@@ -52,6 +52,65 @@ S5_HD uint64_t load_key(const uint8_t* chars, uint64_t pos) {
     return clip_at_zero(k);
 }
 
+// Second key word of a string whose next 8 bytes after the first key are not
+// known (a word of 8 bytes 0xFF, which a string may also hold, only costs a
+// gather).
+constexpr uint64_t kKeyUnknown = ~0ull;
+
+// The 16 bytes at chars[pos..pos+16) as two keys: *k0 = bytes pos..pos+8,
+// *k1 = bytes pos+8..pos+16, both big-endian and zero from the first 0 byte
+// on.  The (up to three) aligned words holding those bytes are read at once
+// when they lie in the 4 KiB page of chars[pos]; otherwise in order, stopping
+// after the first word that holds the terminator.  Either way every word read
+// lies in a page that holds a byte of the string.
+S5_HD void load_key16(const uint8_t* chars, uint64_t pos, uint64_t* k0, uint64_t* k1) {
+    uintptr_t a = (uintptr_t)(chars + pos);
+    const uint64_t* w = (const uint64_t*)(a & ~(uintptr_t)7);
+    uint32_t sh = (uint32_t)(a & 7) * 8;
+    uint64_t x, y, z = 0;
+    if ((a & 4095) < 4080) {
+        // all three words lie in the 4 KiB page of the first byte: read them at once
+        x = __builtin_bswap64(w[0]) << sh;
+        y = __builtin_bswap64(w[1]);
+        z = __builtin_bswap64(w[2]);
+        if (zero_byte_mask(x) & (~0ull << sh)) {
+            *k0 = clip_at_zero(x);
+            *k1 = 0;
+            return;
+        }
+    } else {
+        x = __builtin_bswap64(w[0]) << sh;
+        if (zero_byte_mask(x) & (~0ull << sh)) {  // ends inside the first word
+            *k0 = clip_at_zero(x);
+            *k1 = 0;
+            return;
+        }
+        y = __builtin_bswap64(w[1]);
+        if (sh && !has_zero(y)) z = __builtin_bswap64(w[2]);
+    }
+    const uint64_t hi = sh ? x | (y >> (64 - sh)) : x;
+    const uint64_t lo = sh ? (y << sh) | (z >> (64 - sh)) : y;
+    *k0 = clip_at_zero(hi);
+    *k1 = has_zero(*k0) ? 0ull : clip_at_zero(lo);
+}
+
+// Both key words of a string advanced by `delta` bytes (1..8), from what is
+// known: the first word k0 is exact, the second k1 exact or kKeyUnknown.
+// Returns false when the bytes are not all known (then a gather is needed).
+S5_HD bool advance_key16(uint64_t* k0, uint64_t* k1, uint32_t delta) {
+    const uint64_t x = *k0, y = *k1;
+    if (has_zero(x)) {  // the string ends inside k0: everything after is zero
+        *k0 = delta < 8 ? x << (8 * delta) : 0ull;
+        *k1 = 0;
+        return true;
+    }
+    if (y == kKeyUnknown) return false;
+    const bool ends = has_zero(y);
+    *k0 = delta < 8 ? (x << (8 * delta)) | (y >> (64 - 8 * delta)) : y;
+    *k1 = ends ? (delta < 8 ? y << (8 * delta) : 0ull) : kKeyUnknown;
+    return true;
+}
+
 S5_HD uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

@@ -70,9 +70,53 @@ static void test_load_key_guarded(std::mt19937_64& rng) {
             load_keys<4>(mem, pos, need, out);
             CHECK(out[0] == ref_key(tmp) && out[2] == ref_key(tmp) && out[1] == 2 && out[3] == 4,
                   "load_keys len %d depth %d", len, dep);
+            // two words at once: the second is the key 8 bytes deeper
+            uint64_t k0 = 0, k1 = 0;
+            load_key16(mem, (uint64_t)(s - mem) + dep, &k0, &k1);
+            uint8_t tmp2[8];
+            for (int i = 0; i < 8; ++i) tmp2[i] = dep + 8 + i <= len ? s[dep + 8 + i] : 0;
+            CHECK(k0 == ref_key(tmp) && k1 == ref_key(tmp2), "load_key16 len %d depth %d", len,
+                  dep);
         }
     }
     munmap(mem, 2 * pg);
+}
+
+// Walk strings deeper by random steps of 1..8 bytes keeping (k0, k1) as the
+// redistribution does: advance from what is known, gather when it is not;
+// both words must always equal the keys at the current depth (k1 may also be
+// unknown).  Strings of 0xFF bytes check that a real all-0xFF word is harmless.
+static void test_advance_key16(std::mt19937_64& rng) {
+    std::vector<uint8_t> s(80);
+    int gathers = 0, steps = 0;
+    for (int t = 0; t < 4000; ++t) {
+        const int len = (int)(rng() % 70);
+        const bool ff = t % 7 == 0;
+        for (int i = 0; i < len; ++i) s[i] = ff ? 0xFF : (uint8_t)(1 + rng() % 255);
+        for (int i = len; i < 80; ++i) s[i] = 0;
+        int dep = 0;
+        uint64_t k0, k1;
+        load_key16(s.data(), 0, &k0, &k1);
+        while (dep < len) {
+            const uint32_t delta = 1 + (uint32_t)(rng() % 8);
+            if (dep + (int)delta > len) break;
+            dep += (int)delta;
+            ++steps;
+            if (!advance_key16(&k0, &k1, delta)) {
+                load_key16(s.data(), (uint64_t)dep, &k0, &k1);
+                ++gathers;
+            }
+            CHECK(k0 == ref_key(&s[dep]), "advance k0 len %d depth %d", len, dep);
+            CHECK(k1 == kKeyUnknown || k1 == ref_key(&s[dep + 8]), "advance k1 len %d depth %d",
+                  len, dep);
+        }
+        // past the terminator everything is known to be zero
+        if (len < 8) {
+            uint64_t a = ref_key(&s[0]), b = ref_key(&s[8]);
+            CHECK(advance_key16(&a, &b, 3) && a == ref_key(&s[3]) && b == 0, "ended len %d", len);
+        }
+    }
+    CHECK(gathers < steps, "some steps need no gather (%d of %d)", gathers, steps);
 }
 
 static void test_load_key_random(std::mt19937_64& rng) {
@@ -234,6 +278,7 @@ int main(int argc, char** argv) {
     std::mt19937_64 rng(12345);
     test_load_key_guarded(rng);
     test_load_key_random(rng);
+    test_advance_key16(rng);
     test_inorder_map();
     test_tree_and_classify(rng);
     if (argc > 1) test_fig1(argv[1]);

@@ -172,6 +172,30 @@ def test_user_workspace():
         s5.sort(to_dev(chars), to_dev(offs), cfg=cfg, workspace=small)
 
 
+@pytest.mark.parametrize("name,n,cfg", [("url_10M", 70_001, "default"),
+                                        ("dna_16M", 50_003, "tiny_T_v7"),
+                                        ("words_50M", 40_009, "v1023_u8")])
+def test_no_writes_outside_outputs_and_workspace(name, n, cfg):
+    """Guard bytes around the outputs and after a caller workspace stay as
+    they were (ragged sizes: the last sub-tile of a tile is partly empty)."""
+    chars, offs = gen.workload(name, n)
+    c = CFGS[cfg]
+    pad, fill = 1 << 16, 0x5A5A5A5A
+    wsb = s5.workspace_bytes(n, c)
+    ws = torch.full((wsb + 4 * pad,), 0xA5, dtype=torch.uint8, device="cuda")
+    big_p = torch.full((n + 2 * pad,), fill, dtype=torch.int64, device="cuda").to(torch.uint32)
+    big_l = big_p.clone()
+    perm, lcp = big_p[pad:pad + n], big_l[pad:pad + n]
+    s5.sort(to_dev(chars), to_dev(offs), cfg=c, out_perm=perm, out_lcp=lcp, workspace=ws[:wsb])
+    torch.cuda.synchronize()
+    rp, rl = oracle.sort(chars, offs)
+    assert np.array_equal(perm.cpu().numpy(), rp) and np.array_equal(lcp.cpu().numpy(), rl)
+    assert bool((ws[wsb:] == 0xA5).all())
+    for big in (big_p, big_l):
+        h = big.cpu().numpy()
+        assert (h[:pad] == fill).all() and (h[pad + n:] == fill).all()
+
+
 @pytest.mark.parametrize("cfg", ["default", "tiny_T_v7"])
 def test_batched_small(cfg):
     chars, offs, sb = gen.batched(60, 1, 5000, kinds=("random", "url", "dna", "words"), seed=7)
