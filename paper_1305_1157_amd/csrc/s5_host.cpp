@@ -168,12 +168,16 @@ std::unordered_map<hipStream_t, StreamRecord> g_last;
 
 void graphs_release();
 
+// Pinned readback block of a device: [raw copy | counters | globals], one slot each.
+constexpr size_t kHostSlot = 4096;
+static_assert(2 * sizeof(Counters) + sizeof(Globals) <= kHostSlot, "readback slot too small");
+
 // Get the pool of the current device with at least `bytes`.
 int pool_get(size_t bytes, DevPool** out) {
     int dev = 0;
     S5_HIP(hipGetDevice(&dev));
     DevPool& P = g_pools[dev];
-    if (!P.host) S5_HIP(hipHostMalloc(&P.host, 4096, hipHostMallocDefault));
+    if (!P.host) S5_HIP(hipHostMalloc(&P.host, 3 * kHostSlot, hipHostMallocDefault));
     if (P.bytes < bytes) {
         if (P.ptr) {
             S5_HIP(hipDeviceSynchronize());
@@ -450,7 +454,8 @@ struct HostView {
 };
 
 HostView host_view(void* host) {
-    return HostView{host, (Counters*)((char*)host + 1024), (Globals*)((char*)host + 2048)};
+    return HostView{host, (Counters*)((char*)host + kHostSlot),
+                    (Globals*)((char*)host + 2 * kHostSlot)};
 }
 
 // Copy a pass's counters together with the globals and wait for them.

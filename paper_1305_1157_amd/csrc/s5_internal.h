@@ -46,14 +46,25 @@ struct LSeg {
 };
 
 // Counters written by one planning step and read back by the host.
+// Every workgroup of the planning step adds to these counters with one atomic
+// each.  Device-scope atomics on one 128-byte line are serialized (≈12 ns
+// each, measured); on different lines they proceed in parallel, so each
+// counter that many workgroups update has a line of its own.
+#define S5_LINE alignas(128)
 struct Counters {
-    uint32_t n_large, tiles, chunks, tree;
-    uint32_t bstart, kmax, pad0, pad1;   // pad0: learned segments planned
-    unsigned long long cm, cs;
-    unsigned long long moved;       // strings in the planned large segments
-    unsigned long long max_bucket;  // largest bucket seen by the planning step
-    double entropy_sum;             // sum over buckets of |b| log2(|S|/|b|)
-    unsigned long long planned;     // strings in buckets of size >= 2 planned
+    S5_LINE uint32_t n_large;
+    S5_LINE uint32_t tiles;
+    S5_LINE uint32_t chunks;
+    S5_LINE uint32_t tree;
+    S5_LINE uint32_t bstart;
+    S5_LINE uint32_t kmax;
+    S5_LINE uint32_t pad0;  // learned segments planned
+    uint32_t pad1;
+    S5_LINE unsigned long long cm;
+    S5_LINE unsigned long long cs;
+    S5_LINE unsigned long long moved;       // strings in the planned large segments
+    S5_LINE unsigned long long max_bucket;  // largest bucket seen by the planning step
+    S5_LINE double entropy_sum;             // sum over buckets of |b| log2(|S|/|b|)
 };
 
 // Device-global state that survives the whole sort.
@@ -68,10 +79,10 @@ __host__ __device__ inline int base_class(uint32_t size) {
 }
 
 struct Globals {
-    uint32_t n_base[kBaseClasses];  // base-case items appended so far, per class
-    uint32_t status;                // error bits
-    unsigned long long base_elems;  // strings in those items
-    uint32_t fallbacks;             // learned segments redone with sampled splitters
+    S5_LINE uint32_t n_base[kBaseClasses];  // base-case items appended so far, per class
+    uint32_t status;                        // error bits
+    S5_LINE unsigned long long base_elems;  // strings in those items
+    S5_LINE uint32_t fallbacks;             // learned segments redone with sampled splitters
     uint32_t late_fallbacks;        // those of them rejected only on the exact histogram
     // statistics kept on the device by graph-captured sorts (no per-pass readback)
     uint32_t passes, pad;

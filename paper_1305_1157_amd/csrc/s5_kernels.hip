@@ -431,8 +431,9 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
                                                      const uint32_t* wcnt, uint32_t cap,
                                                      const Globals* glob, uint32_t redo) {
     // the next pass's counters are planned later in this pass: clear them here
-    if (!redo && blockIdx.x == 0 && threadIdx.x < sizeof(Counters) / 4)
-        ((uint32_t*)next_cnt)[threadIdx.x] = 0;
+    if (!redo && blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += blockDim.x)
+            ((uint32_t*)next_cnt)[i] = 0;
     if (!G) {
         sample_tree_body(blockIdx.x, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp,
                          tile_tab, chunk_tab);
