@@ -79,15 +79,44 @@ __device__ uint32_t block_exclusive_scan(const uint32_t* cnt, uint32_t* out, uin
 }
 
 // ---------------------------------------------------------------------------
-// planning: decide what happens to every bucket of >= 2 strings.  A block
-// first tallies its requests in LDS, then takes one global allocation per
-// counter, then hands out the slots from LDS counters (no contention on the
-// global counters beyond one atomic per counter and block).
+// planning: decide what happens to every bucket of >= 2 strings.  Every thread
+// adds up the requests of its buckets in registers (PlanAcc); a block-wide
+// exclusive scan turns them into each thread's offsets and the block's totals;
+// one global allocation per counter and block turns the totals into bases; the
+// threads then hand out slots from base + offset.  (Contended LDS atomics on a
+// few counters cost tens of microseconds per workgroup; the scan costs about
+// one.)
 
-struct PlanTally {
-    uint32_t n_base[kBaseClasses], n_large, tiles, chunks, tree, bstart, kmax, err, n_learn;
-    unsigned long long cm, cs, moved, base_elems;
+// 32-bit counters of a plan, by index; 64-bit ones below
+constexpr int kPU_Base = 0;                   // kBaseClasses counters: base items per class
+constexpr int kPU_Large = kBaseClasses;       // large segments
+constexpr int kPU_Tiles = kBaseClasses + 1;
+constexpr int kPU_Chunks = kBaseClasses + 2;
+constexpr int kPU_Tree = kBaseClasses + 3;    // tree slots (v + 1 per segment)
+constexpr int kPU_Bstart = kBaseClasses + 4;  // bucket-start slots (k + 1 per segment)
+constexpr int kPU_Learn = kBaseClasses + 5;   // learned-splitter slots
+constexpr int kPU = kBaseClasses + 6;
+constexpr int kPQ_Cm = 0, kPQ_Cs = 1, kPQ_Moved = 2, kPQ_BaseElems = 3, kPQ = 4;
+
+struct PlanAcc {
+    uint32_t u[kPU];
+    unsigned long long q[kPQ];
+    uint32_t kmax;
 };
+
+// block totals, then (after plan_allocate) global bases
+struct PlanTally {
+    PlanAcc a;
+    uint32_t err;
+};
+
+__device__ __forceinline__ void acc_clear(PlanAcc& a) {
+#pragma unroll
+    for (int i = 0; i < kPU; ++i) a.u[i] = 0;
+#pragma unroll
+    for (int i = 0; i < kPQ; ++i) a.q[i] = 0;
+    a.kmax = 0;
+}
 
 // tree depth and tiles of a large segment of `size` strings
 __device__ __forceinline__ void seg_shape(uint32_t size, const SetP& c, uint32_t& d,
@@ -101,89 +130,153 @@ __device__ __forceinline__ void seg_shape(uint32_t size, const SetP& c, uint32_t
     chunks = (tiles + kChunkRows - 1) / kChunkRows;
 }
 
-// Phase 1 for one request (begin, size >= 2, depth).
-__device__ __forceinline__ void plan_tally(uint32_t size, const PlanCtx& c, const SetP& sp,
-                                           PlanTally* T) {
+// Count one request (a bucket of size >= 2 that needs sorting).
+__device__ __forceinline__ void plan_count(uint32_t size, const PlanCtx& c, const SetP& sp,
+                                           PlanAcc& a) {
     if (size <= sp.T) {
-        atomicAdd(&T->n_base[base_class(size)], 1u);
-        atomicAdd(&T->base_elems, (unsigned long long)size);
+        const int cls = base_class(size);
+#pragma unroll
+        for (int i = 0; i < kBaseClasses; ++i) a.u[kPU_Base + i] += cls == i ? 1u : 0u;
+        a.q[kPQ_BaseElems] += size;
         return;
     }
     uint32_t d, ulen, tiles, chunks;
     seg_shape(size, sp, d, ulen, tiles, chunks);
     const uint32_t v = (1u << d) - 1, k = 2 * v + 1;
-    atomicAdd(&T->n_large, 1u);
-    atomicAdd(&T->tiles, tiles);
-    atomicAdd(&T->chunks, chunks);
-    atomicAdd(&T->tree, v + 1);
-    atomicAdd(&T->bstart, k + 1);
-    atomicAdd(&T->cm, (unsigned long long)tiles * k);
-    atomicAdd(&T->cs, (unsigned long long)chunks * k);
-    atomicAdd(&T->moved, (unsigned long long)size);
-    atomicMax(&T->kmax, k);
-    if (c.learn && size >= kLearnMin) atomicAdd(&T->n_learn, 1u);
+    a.u[kPU_Large] += 1;
+    a.u[kPU_Tiles] += tiles;
+    a.u[kPU_Chunks] += chunks;
+    a.u[kPU_Tree] += v + 1;
+    a.u[kPU_Bstart] += k + 1;
+    a.q[kPQ_Cm] += (unsigned long long)tiles * k;
+    a.q[kPQ_Cs] += (unsigned long long)chunks * k;
+    a.q[kPQ_Moved] += size;
+    a.kmax = k > a.kmax ? k : a.kmax;
+    if (c.learn && size >= kLearnMin) a.u[kPU_Learn] += 1;
 }
 
-// Phase 2, by the 64 lanes of wavefront 0: turn block totals into global
+__device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, uint32_t d) {
+    const uint32_t lo = __shfl_up((uint32_t)v, d), hi = __shfl_up((uint32_t)(v >> 32), d);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Block-wide: a (this thread's counts) becomes its exclusive prefix over the
+// threads before it; T->a receives the block totals and T->err is cleared.
+// All threads of the block call.
+__device__ void plan_scan(PlanAcc& a, PlanTally* T) {
+    __shared__ PlanAcc ws[kWaves];
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    PlanAcc inc = a;
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int i = 0; i < kPU; ++i) {
+            const uint32_t x = __shfl_up(inc.u[i], o);
+            if (lane >= o) inc.u[i] += x;
+        }
+#pragma unroll
+        for (int i = 0; i < kPQ; ++i) {
+            const unsigned long long x = shfl_up_u64(inc.q[i], o);
+            if (lane >= o) inc.q[i] += x;
+        }
+        const uint32_t x = __shfl_up(inc.kmax, o);
+        if (lane >= o && x > inc.kmax) inc.kmax = x;
+    }
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    // field by field: offsets of the waves before this one, and block totals
+#pragma unroll
+    for (int i = 0; i < kPU; ++i) {
+        uint32_t pre = 0, tot = 0;
+        for (uint32_t qw = 0; qw < nw; ++qw) {
+            const uint32_t x = ws[qw].u[i];
+            pre += qw < w ? x : 0u;
+            tot += x;
+        }
+        a.u[i] = pre + inc.u[i] - a.u[i];
+        if (threadIdx.x == 0) T->a.u[i] = tot;
+    }
+#pragma unroll
+    for (int i = 0; i < kPQ; ++i) {
+        unsigned long long pre = 0, tot = 0;
+        for (uint32_t qw = 0; qw < nw; ++qw) {
+            const unsigned long long x = ws[qw].q[i];
+            pre += qw < w ? x : 0ull;
+            tot += x;
+        }
+        a.q[i] = pre + inc.q[i] - a.q[i];
+        if (threadIdx.x == 0) T->a.q[i] = tot;
+    }
+    if (threadIdx.x == 0) {
+        uint32_t mx = 0;
+        for (uint32_t qw = 0; qw < nw; ++qw) mx = ws[qw].kmax > mx ? ws[qw].kmax : mx;
+        T->a.kmax = mx;
+        T->err = 0;
+    }
+    __syncthreads();
+}
+
+// By the 64 lanes of wavefront 0: turn the block totals in T into global
 // bases (stored back into T).  Each lane owns one global counter, so the
-// block's atomics are independent and in flight together.
+// block's atomics are independent and in flight together; every counter that
+// many workgroups update sits on a cache line of its own.
 __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
     constexpr uint32_t kLane = 8;  // first lane of the next pass's counters
     const uint32_t l = threadIdx.x;
-    const uint32_t nl = T->n_large;
+    PlanAcc& a = T->a;
+    const uint32_t nl = a.u[kPU_Large];
     uint32_t err = 0;
     if (l == 0) {
-        if (T->base_elems) atomicAdd(&c.glob->base_elems, T->base_elems);
+        if (a.q[kPQ_BaseElems]) atomicAdd(&c.glob->base_elems, a.q[kPQ_BaseElems]);
     } else if (l <= (uint32_t)kBaseClasses) {  // lanes 1..kBaseClasses: base lists
         const int q = (int)l - 1;
-        const uint32_t nb = T->n_base[q];
+        const uint32_t nb = a.u[kPU_Base + q];
         if (nb) {
             const uint32_t b0 = atomicAdd(&c.glob->n_base[q], nb);
             if (b0 + nb > c.caps.base[q]) err = kErrBaseCap;
-            T->n_base[q] = b0;
+            a.u[kPU_Base + q] = b0;
         }
     } else if (nl) {
         switch (l) {
             case kLane + 0: {
                 const uint32_t x = atomicAdd(&c.cnt->n_large, nl);
                 if (x + nl > c.caps.large) err = kErrLargeCap;
-                T->n_large = x;
+                a.u[kPU_Large] = x;
             } break;
             case kLane + 1: {
-                const uint32_t v = T->tiles, x = atomicAdd(&c.cnt->tiles, v);
+                const uint32_t v = a.u[kPU_Tiles], x = atomicAdd(&c.cnt->tiles, v);
                 if (x + v > c.caps.tiles) err = kErrTileCap;
-                T->tiles = x;
+                a.u[kPU_Tiles] = x;
             } break;
             case kLane + 2: {
-                const uint32_t v = T->chunks, x = atomicAdd(&c.cnt->chunks, v);
+                const uint32_t v = a.u[kPU_Chunks], x = atomicAdd(&c.cnt->chunks, v);
                 if (x + v > c.caps.chunks) err = kErrTileCap;
-                T->chunks = x;
+                a.u[kPU_Chunks] = x;
             } break;
             case kLane + 3: {
-                const uint32_t v = T->tree, x = atomicAdd(&c.cnt->tree, v);
+                const uint32_t v = a.u[kPU_Tree], x = atomicAdd(&c.cnt->tree, v);
                 if (x + v > c.caps.tree) err = kErrTreeCap;
-                T->tree = x;
+                a.u[kPU_Tree] = x;
             } break;
             case kLane + 4: {
-                const uint32_t v = T->bstart, x = atomicAdd(&c.cnt->bstart, v);
+                const uint32_t v = a.u[kPU_Bstart], x = atomicAdd(&c.cnt->bstart, v);
                 if (x + v > c.caps.bstart) err = kErrTreeCap;
-                T->bstart = x;
+                a.u[kPU_Bstart] = x;
             } break;
             case kLane + 5: {
-                const unsigned long long v = T->cm, x = atomicAdd(&c.cnt->cm, v);
+                const unsigned long long v = a.q[kPQ_Cm], x = atomicAdd(&c.cnt->cm, v);
                 if (x + v > c.caps.cm) err = kErrCmCap;
-                T->cm = x;
+                a.q[kPQ_Cm] = x;
             } break;
             case kLane + 6: {
-                const unsigned long long v = T->cs, x = atomicAdd(&c.cnt->cs, v);
+                const unsigned long long v = a.q[kPQ_Cs], x = atomicAdd(&c.cnt->cs, v);
                 if (x + v > c.caps.cs) err = kErrCmCap;
-                T->cs = x;
+                a.q[kPQ_Cs] = x;
             } break;
-            case kLane + 7: atomicAdd(&c.cnt->moved, T->moved); break;
-            case kLane + 8: atomicMax(&c.cnt->kmax, T->kmax); break;
+            case kLane + 7: atomicAdd(&c.cnt->moved, a.q[kPQ_Moved]); break;
+            case kLane + 8: atomicMax(&c.cnt->kmax, a.kmax); break;
             case kLane + 9: {
-                const uint32_t v = T->n_learn;
-                T->n_learn = v ? atomicAdd(&c.cnt->pad0, v) : 0u;
+                const uint32_t v = a.u[kPU_Learn];
+                a.u[kPU_Learn] = v ? atomicAdd(&c.cnt->pad0, v) : 0u;
             } break;
             default: break;
         }
@@ -194,12 +287,19 @@ __device__ void plan_allocate(const PlanCtx& c, PlanTally* T) {
     }
 }
 
-// Phase 3 for one request: take slots from the LDS counters and write the record.
+// Write the record of one request; slots come from the global bases in T plus
+// this thread's running offsets `off` (its exclusive prefix, advanced here).
 __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_t base,
-                          uint32_t buf, const PlanCtx& c, const SetP& sp, PlanTally* T) {
+                          uint32_t buf, const PlanCtx& c, const SetP& sp, const PlanTally* T,
+                          PlanAcc& off) {
+    const PlanAcc& g0 = T->a;
     if (size <= sp.T) {
         const int q = base_class(size);
-        uint32_t slot = atomicAdd(&T->n_base[q], 1u);
+        uint32_t o = 0;  // this thread's next offset in class q (unrolled: no indexed registers)
+#pragma unroll
+        for (int i = 0; i < kBaseClasses; ++i)
+            if (q == i) o = off.u[kPU_Base + i]++;
+        const uint32_t slot = g0.u[kPU_Base + q] + o;
         Seg s;
         s.begin = begin;
         s.size = size;
@@ -221,33 +321,30 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
     g.k = k;
     g.tile_len = ulen;
     g.tiles = tiles;
-    g.tile_base = atomicAdd(&T->tiles, tiles);
+    g.tile_base = g0.u[kPU_Tiles] + off.u[kPU_Tiles];
+    off.u[kPU_Tiles] += tiles;
     g.chunks = chunks;
-    g.chunk_base = atomicAdd(&T->chunks, chunks);
-    g.tree_base = atomicAdd(&T->tree, v + 1);
-    g.bstart_base = atomicAdd(&T->bstart, k + 1);
+    g.chunk_base = g0.u[kPU_Chunks] + off.u[kPU_Chunks];
+    off.u[kPU_Chunks] += chunks;
+    g.tree_base = g0.u[kPU_Tree] + off.u[kPU_Tree];
+    off.u[kPU_Tree] += v + 1;
+    g.bstart_base = g0.u[kPU_Bstart] + off.u[kPU_Bstart];
+    off.u[kPU_Bstart] += k + 1;
     g.pad0 = 0xFFFFFFFFu;
     g.pad1 = 0;
-    g.cm_base = atomicAdd(&T->cm, (unsigned long long)tiles * k);
-    g.cs_base = atomicAdd(&T->cs, (unsigned long long)chunks * k);
-    const uint32_t slot = atomicAdd(&T->n_large, 1u);
+    g.cm_base = g0.q[kPQ_Cm] + off.q[kPQ_Cm];
+    off.q[kPQ_Cm] += (unsigned long long)tiles * k;
+    g.cs_base = g0.q[kPQ_Cs] + off.q[kPQ_Cs];
+    off.q[kPQ_Cs] += (unsigned long long)chunks * k;
+    const uint32_t slot = g0.u[kPU_Large] + off.u[kPU_Large]++;
     if (c.learn && size >= kLearnMin) {
-        const uint32_t ls = atomicAdd(&T->n_learn, 1u);
+        const uint32_t ls = g0.u[kPU_Learn] + off.u[kPU_Learn]++;
         if (ls < c.learn_cap) {  // beyond the cap the segment keeps sampled splitters
             g.pad0 = ls;
             c.learn_seg[ls] = slot;
         }
     }
     c.lseg[slot] = g;
-}
-
-__device__ __forceinline__ void tally_clear(PlanTally* T) {
-    if (threadIdx.x == 0) {
-        for (int q = 0; q < kBaseClasses; ++q) T->n_base[q] = 0;
-        T->n_large = T->tiles = T->chunks = T->tree = T->bstart = T->kmax = T->err = 0;
-        T->n_learn = 0;
-        T->cm = T->cs = T->moved = T->base_elems = 0;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -277,8 +374,6 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
                                                     uint32_t n, uint32_t* out_perm,
                                                     uint32_t* out_lcp, PlanCtx ctx) {
     __shared__ PlanTally T;
-    tally_clear(&T);
-    __syncthreads();
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t b = 0, e = 0;
     if (s < num_sets) {
@@ -292,12 +387,14 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
     const bool req = e > b + 1;
     const SetP sp = (ctx.set_tune && s < num_sets) ? unpack_set_tune(ctx.set_tune[s])
                                                    : default_set_params(ctx);
-    if (req) plan_tally(e - b, ctx, sp, &T);
-    __syncthreads();
+    PlanAcc acc;
+    acc_clear(acc);
+    if (req) plan_count(e - b, ctx, sp, acc);
+    plan_scan(acc, &T);
     if (threadIdx.x < 64) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
-    if (req) plan_emit(b, e - b, 0, b, 0, ctx, sp, &T);
+    if (req) plan_emit(b, e - b, 0, b, 0, ctx, sp, &T, acc);
 }
 
 // Graph-captured sorts keep their statistics on the device: after each pass,
@@ -614,7 +711,6 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     double ent = 0.0;
     unsigned long long mx = 0;
     __shared__ PlanTally T;
-    tally_clear(&T);
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
         const uint32_t s0 = st[b];
         bs[b] = s0;
@@ -672,16 +768,27 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
         }
         return g.depth + ((j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j]);
     };
-    for (uint32_t b = threadIdx.x; b < k; b += kWG)
-        if (next_depth(b) != 0xFFFFFFFFu) plan_tally(tot[b], ctx, sp, &T);
-    __syncthreads();
+    // the buckets of this thread are b = tid + e * kWG, e < kPlanPer
+    constexpr int kPlanPer = (int)((2u << kDMax) / kWG);
+    static_assert(kPlanPer * kWG >= (int)(2u << kDMax) - 1, "buckets per thread");
+    uint32_t nd[kPlanPer];
+    PlanAcc acc;
+    acc_clear(acc);
+#pragma unroll
+    for (int e = 0; e < kPlanPer; ++e) {
+        const uint32_t b = threadIdx.x + e * kWG;
+        nd[e] = b < k ? next_depth(b) : 0xFFFFFFFFu;
+        if (nd[e] != 0xFFFFFFFFu) plan_count(tot[b], ctx, sp, acc);
+    }
+    plan_scan(acc, &T);
     if (threadIdx.x < 64) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
-    for (uint32_t b = threadIdx.x; b < k; b += kWG) {
-        const uint32_t nd = next_depth(b);
-        if (nd != 0xFFFFFFFFu)
-            plan_emit(g.begin + st[b], tot[b], nd, g.base, next_buf, ctx, sp, &T);
+#pragma unroll
+    for (int e = 0; e < kPlanPer; ++e) {
+        const uint32_t b = threadIdx.x + e * kWG;
+        if (nd[e] != 0xFFFFFFFFu)
+            plan_emit(g.begin + st[b], tot[b], nd[e], g.base, next_buf, ctx, sp, &T, acc);
     }
 }
 
