@@ -1432,30 +1432,48 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         h += 8;
         uint32_t Pm = 1;
         while (Pm < m) Pm <<= 1;
-        {
-            // up to pmax / NT members per thread: all their gathers in flight at once
-            constexpr int G = EMAX;
-            uint64_t pos[G], nkey[G];
-            bool need[G];
+        // up to pmax / NT members per thread: all their gathers in flight at once
+        constexpr int G = EMAX;
+        uint64_t pos[G], nkey[G];
+        bool need[G];
 #pragma unroll
-            for (int e = 0; e < G; ++e) {
-                const uint32_t q = tid + e * NT;
-                need[e] = q < m;
-                pos[e] = need[e] ? OFFL[SA[q] & 0xFFFFu] + h : 0ull;
-            }
-            load_keys<G>(chars, pos, need, nkey);
-#pragma unroll
-            for (int e = 0; e < G; ++e) {
-                const uint32_t q = tid + e * NT;
-                if (q < m) SK[q] = nkey[e];
-            }
+        for (int e = 0; e < G; ++e) {
+            const uint32_t q = tid + e * NT;
+            need[e] = q < m;
+            pos[e] = need[e] ? OFFL[SA[q] & 0xFFFFu] : 0ull;
         }
-        __syncthreads();
+        // does member q's key differ from its group predecessor's?
+        auto differs = [&](uint32_t q) {
+            return q > 0 && (SA[q] >> 16) == (SA[q - 1] >> 16) && SK[q] != SK[q - 1];
+        };
+        // Re-key 8 bytes deeper.  A depth at which no group's keys differ and
+        // no key ends the strings decides nothing, so the groups stay as they
+        // are and only the depth moves on (long equal runs such as duplicate
+        // strings cost a gather per 8 bytes, not a whole round).
+        for (;;) {
+            uint64_t at[G];
+#pragma unroll
+            for (int e = 0; e < G; ++e) at[e] = pos[e] + h;
+            load_keys<G>(chars, at, need, nkey);
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                if (need[e]) SK[tid + e * NT] = nkey[e];
+            __syncthreads();
+            int prog = 0;
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                const uint32_t q = tid + e * NT;
+                if (need[e] && (differs(q) || has_zero(SK[q]))) prog = 1;
+            }
+            if (__syncthreads_or(prog)) break;
+            h += 8;
+        }
         // re-sort only if some group's keys now differ (equal keys keep their
         // local-index order)
         int split = 0;
-        for (uint32_t q = tid + 1; q < m; q += NT)
-            split |= ((SA[q] >> 16) == (SA[q - 1] >> 16) && SK[q] != SK[q - 1]) ? 1 : 0;
+#pragma unroll
+        for (int e = 0; e < G; ++e)
+            if (need[e] && differs(tid + e * NT)) split = 1;
         split = __syncthreads_or(split);
         if (split) {
             for (uint32_t q = m + tid; q < Pm; q += NT) {

@@ -94,6 +94,38 @@ S5_HD void load_key16(const uint8_t* chars, uint64_t pos, uint64_t* k0, uint64_t
     *k1 = has_zero(*k0) ? 0ull : clip_at_zero(lo);
 }
 
+// The keys at chars[pos], chars[pos + 8], ..., chars[pos + 8 (N - 1)] (each as
+// load_key gives it; all zero past the terminator).  The N + 1 aligned words
+// holding those bytes are read at once when they lie in the 4 KiB page of
+// chars[pos]; otherwise in order, stopping after the word that holds the
+// terminator.  Every word read lies in a page that holds a byte of the string.
+template <int N>
+S5_HD void load_key_run(const uint8_t* chars, uint64_t pos, uint64_t (&out)[N]) {
+    const uintptr_t a = (uintptr_t)(chars + pos);
+    const uint64_t* w = (const uint64_t*)(a & ~(uintptr_t)7);
+    const uint32_t sh = (uint32_t)(a & 7) * 8;
+    uint64_t x[N + 1];
+    if ((a & 4088) + 8 * (N + 1) <= 4096) {
+#pragma unroll
+        for (int i = 0; i <= N; ++i) x[i] = __builtin_bswap64(w[i]);
+    } else {
+        bool end = false;
+#pragma unroll
+        for (int i = 0; i <= N; ++i) {
+            x[i] = end ? 0ull : __builtin_bswap64(w[i]);
+            end = end || (i == 0 ? (zero_byte_mask(x[0] << sh) & (~0ull << sh)) != 0
+                                 : has_zero(x[i]));
+        }
+    }
+    bool dead = false;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const uint64_t k = sh ? (x[i] << sh) | (x[i + 1] >> (64 - sh)) : x[i];
+        out[i] = dead ? 0ull : clip_at_zero(k);
+        dead = dead || has_zero(k);
+    }
+}
+
 // Both key words of a string advanced by `delta` bytes (1..8), from what is
 // known: the first word k0 is exact, the second k1 exact or kKeyUnknown.
 // Returns false when the bytes are not all known (then a gather is needed).

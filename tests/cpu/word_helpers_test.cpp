@@ -77,6 +77,14 @@ static void test_load_key_guarded(std::mt19937_64& rng) {
             for (int i = 0; i < 8; ++i) tmp2[i] = dep + 8 + i <= len ? s[dep + 8 + i] : 0;
             CHECK(k0 == ref_key(tmp) && k1 == ref_key(tmp2), "load_key16 len %d depth %d", len,
                   dep);
+            // four keys in a run
+            uint64_t run[4];
+            load_key_run<4>(mem, (uint64_t)(s - mem) + dep, run);
+            for (int j = 0; j < 4; ++j) {
+                uint8_t t[8];
+                for (int i = 0; i < 8; ++i) t[i] = dep + 8 * j + i <= len ? s[dep + 8 * j + i] : 0;
+                CHECK(run[j] == ref_key(t), "load_key_run len %d depth %d word %d", len, dep, j);
+            }
         }
     }
     munmap(mem, 2 * pg);
@@ -138,6 +146,12 @@ static void test_load_key_random(std::mt19937_64& rng) {
             const uint8_t* s = arena.data() + sl.first + dep;
             uint64_t got = load_key(arena.data(), sl.first + dep);
             CHECK(got == ref_key(s), "random key at %zu depth %d", sl.first, dep);
+            uint64_t run[4];
+            load_key_run<4>(arena.data(), sl.first + dep, run);
+            for (int j = 0; j < 4; ++j) {
+                const uint64_t want = dep + 8 * j <= sl.second ? ref_key(s + 8 * j) : 0ull;
+                CHECK(run[j] == want, "random run at %zu depth %d word %d", sl.first, dep, j);
+            }
         }
     // lcp8 and nz_bytes against byte loops
     for (size_t t = 1; t < strs.size(); ++t) {
