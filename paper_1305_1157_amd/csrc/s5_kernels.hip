@@ -1450,23 +1450,44 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         // no key ends the strings decides nothing, so the groups stay as they
         // are and only the depth moves on (long equal runs such as duplicate
         // strings cost a gather per 8 bytes, not a whole round).
-        for (;;) {
-            uint64_t at[G];
-#pragma unroll
-            for (int e = 0; e < G; ++e) at[e] = pos[e] + h;
-            load_keys<G>(chars, at, need, nkey);
-#pragma unroll
-            for (int e = 0; e < G; ++e)
-                if (need[e]) SK[tid + e * NT] = nkey[e];
-            __syncthreads();
+        // can some pair be decided at the current depth (a group's keys differ,
+        // or a key ends the strings)?  Block-wide; all threads call.
+        auto progress = [&]() {
             int prog = 0;
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const uint32_t q = tid + e * NT;
                 if (need[e] && (differs(q) || has_zero(SK[q]))) prog = 1;
             }
-            if (__syncthreads_or(prog)) break;
+            return __syncthreads_or(prog);
+        };
+        {
+            uint64_t at[G];
+#pragma unroll
+            for (int e = 0; e < G; ++e) at[e] = pos[e] + h;
+            load_keys<G>(chars, at, need, nkey);
+        }
+#pragma unroll
+        for (int e = 0; e < G; ++e)
+            if (need[e]) SK[tid + e * NT] = nkey[e];
+        __syncthreads();
+        while (!progress()) {
+            // a run of equal bytes: from here on 16 bytes per gather
             h += 8;
+            uint64_t k2[G];
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                if (need[e]) load_key16(chars, pos[e] + h, &nkey[e], &k2[e]);
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                if (need[e]) SK[tid + e * NT] = nkey[e];
+            __syncthreads();
+            if (progress()) break;
+            h += 8;
+#pragma unroll
+            for (int e = 0; e < G; ++e)
+                if (need[e]) SK[tid + e * NT] = k2[e];
+            __syncthreads();
         }
         // re-sort only if some group's keys now differ (equal keys keep their
         // local-index order)
