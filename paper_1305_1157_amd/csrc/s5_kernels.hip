@@ -1062,12 +1062,72 @@ __global__ __launch_bounds__(256) void k_scatter(
 // use a workgroup and LDS; once <= 64 strings remain undecided, wavefront 0
 // finishes them the same way without further workgroup barriers.
 
-// (group, key, local index) order of two packed elements; a = group << 16 | local
-__device__ __forceinline__ bool elem_less(uint64_t k1, uint32_t a1, uint64_t k2, uint32_t a2) {
-    uint32_t g1 = a1 >> 16, g2 = a2 >> 16;
-    if (g1 != g2) return g1 < g2;
-    if (k1 != k2) return k1 < k2;
-    return (a1 & 0xFFFFu) < (a2 & 0xFFFFu);
+// The sorting networks order elements (key, a = group << 16 | local index) by
+// (group, key, local index).  Inside a network an element is the 96-bit number
+// group:16 | key:64 | local:16, held as hi = group << 48 | key >> 16 and
+// lo = (key & 0xFFFF) << 16 | local, so that one three-word subtraction
+// compares two elements (no branches; the compiler turns the three-way
+// comparison into divergent control flow with scalar mask logic otherwise).
+__device__ __forceinline__ void pack96(uint64_t k, uint32_t a, uint64_t& h, uint32_t& l) {
+    h = ((uint64_t)(a >> 16) << 48) | (k >> 16);
+    l = ((uint32_t)k << 16) | (a & 0xFFFFu);
+}
+__device__ __forceinline__ void unpack96(uint64_t h, uint32_t l, uint64_t& k, uint32_t& a) {
+    k = (h << 16) | (l >> 16);
+    a = ((uint32_t)(h >> 48) << 16) | (l & 0xFFFFu);
+}
+
+// (h, l) := (ph, pl) iff ((ph, pl) < (h, l)) != flip  (flip is 0 or 1).
+// Vector instructions only: the borrow of (ph, pl) - (h, l) is the comparison.
+__device__ __forceinline__ void take96(uint64_t& h, uint32_t& l, uint64_t ph, uint32_t pl,
+                                       uint32_t flip) {
+    uint32_t h0 = (uint32_t)h, h1 = (uint32_t)(h >> 32), t;
+    asm("v_sub_co_u32 %[t], vcc, %[pl], %[l]\n\t"
+        "v_subb_co_u32 %[t], vcc, %[ph0], %[h0], vcc\n\t"
+        "v_subb_co_u32 %[t], vcc, %[ph1], %[h1], vcc\n\t"
+        "v_cndmask_b32_e64 %[t], 0, 1, vcc\n\t"
+        "v_cmp_ne_u32 vcc, %[t], %[flip]\n\t"
+        "v_cndmask_b32 %[l], %[l], %[pl], vcc\n\t"
+        "v_cndmask_b32 %[h0], %[h0], %[ph0], vcc\n\t"
+        "v_cndmask_b32 %[h1], %[h1], %[ph1], vcc"
+        : [t] "=&v"(t), [l] "+v"(l), [h0] "+v"(h0), [h1] "+v"(h1)
+        : [pl] "v"(pl), [ph0] "v"((uint32_t)ph), [ph1] "v"((uint32_t)(ph >> 32)), [flip] "v"(flip)
+        : "vcc");
+    h = ((uint64_t)h1 << 32) | h0;
+}
+
+// (x, y) := (y, x) iff (y < x) != flip: ascending pair for flip 0, descending for 1.
+__device__ __forceinline__ void cex96(uint64_t& xh, uint32_t& xl, uint64_t& yh, uint32_t& yl,
+                                      uint32_t flip) {
+    const uint32_t x0 = (uint32_t)xh, x1 = (uint32_t)(xh >> 32);
+    const uint32_t y0 = (uint32_t)yh, y1 = (uint32_t)(yh >> 32);
+    uint32_t t, nxl, nx0, nx1, nyl, ny0, ny1;
+    asm("v_sub_co_u32 %[t], vcc, %[yl], %[xl]\n\t"
+        "v_subb_co_u32 %[t], vcc, %[y0], %[x0], vcc\n\t"
+        "v_subb_co_u32 %[t], vcc, %[y1], %[x1], vcc\n\t"
+        "v_cndmask_b32_e64 %[t], 0, 1, vcc\n\t"
+        "v_cmp_ne_u32 vcc, %[t], %[flip]\n\t"
+        "v_cndmask_b32 %[nxl], %[xl], %[yl], vcc\n\t"
+        "v_cndmask_b32 %[nx0], %[x0], %[y0], vcc\n\t"
+        "v_cndmask_b32 %[nx1], %[x1], %[y1], vcc\n\t"
+        "v_cndmask_b32 %[nyl], %[yl], %[xl], vcc\n\t"
+        "v_cndmask_b32 %[ny0], %[y0], %[x0], vcc\n\t"
+        "v_cndmask_b32 %[ny1], %[y1], %[x1], vcc"
+        : [t] "=&v"(t), [nxl] "=&v"(nxl), [nx0] "=&v"(nx0), [nx1] "=&v"(nx1),
+          [nyl] "=&v"(nyl), [ny0] "=&v"(ny0), [ny1] "=&v"(ny1)
+        : [xl] "v"(xl), [x0] "v"(x0), [x1] "v"(x1), [yl] "v"(yl), [y0] "v"(y0), [y1] "v"(y1),
+          [flip] "v"(flip)
+        : "vcc");
+    xl = nxl;
+    xh = ((uint64_t)nx1 << 32) | nx0;
+    yl = nyl;
+    yh = ((uint64_t)ny1 << 32) | ny0;
+}
+
+// bitonic direction: 1 where element e keeps the larger of its pair in the
+// stage (j, kk), i.e. where ((e & j) == 0) != ((e & kk) == 0)
+__device__ __forceinline__ uint32_t bitonic_flip(uint32_t e, uint32_t j, uint32_t kk) {
+    return ((e & j) ? 1u : 0u) ^ ((e & kk) ? 1u : 0u);
 }
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
@@ -1082,18 +1142,17 @@ __device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
 // Bitonic sort of one element per lane over the wavefront.
 __device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& a) {
     const uint32_t lane = lane_id();
+    uint64_t h;
+    uint32_t l;
+    pack96(k, a, h, l);
     for (uint32_t kk = 2; kk <= 64; kk <<= 1) {
         for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
-            const uint64_t pk = shfl_xor64(k, (int)j);
-            const uint32_t pa = __shfl_xor(a, (int)j);
-            const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
-            const bool pl = elem_less(pk, pa, k, a);
-            if (keep_min ? pl : !pl) {
-                k = pk;
-                a = pa;
-            }
+            const uint64_t ph = shfl_xor64(h, (int)j);
+            const uint32_t pl = __shfl_xor(l, (int)j);
+            take96(h, l, ph, pl, bitonic_flip(lane, j, kk));
         }
     }
+    unpack96(h, l, k, a);
 }
 
 // Rounds of decide / re-key / sort inside one wavefront.  Lane r owns output
@@ -1190,17 +1249,13 @@ __global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_
 }
 
 template <int E, int J>
-__device__ __forceinline__ void cex_local(uint64_t (&k)[E], uint32_t (&a)[E], uint32_t t,
+__device__ __forceinline__ void cex_local(uint64_t (&h)[E], uint32_t (&l)[E], uint32_t t,
                                           uint32_t kk) {
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         if ((s & J) == 0) {
             const int s2 = s | J;
-            const bool up = (((uint32_t)(t * E + s)) & kk) == 0;
-            if (elem_less(k[s2], a[s2], k[s], a[s]) == up) {
-                uint64_t tk = k[s]; k[s] = k[s2]; k[s2] = tk;
-                uint32_t ta = a[s]; a[s] = a[s2]; a[s2] = ta;
-            }
+            cex96(h[s], l[s], h[s2], l[s2], ((t * E + s) & kk) ? 1u : 0u);
         }
     }
 }
@@ -1213,30 +1268,27 @@ template <int E, int NT>
 __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
-    uint64_t k[E];
-    uint32_t a[E];
+    // packed elements (see pack96); the partner of an active thread is active,
+    // so inactive threads may run the network on padding
+    uint64_t h[E];
+    uint32_t l[E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
-        k[s] = act ? SK[t * E + s] : 0ull;
-        a[s] = act ? SA[t * E + s] : 0u;
+        if (act)
+            pack96(SK[t * E + s], SA[t * E + s], h[s], l[s]);
+        else
+            h[s] = ~0ull, l[s] = ~0u;
     }
     for (uint32_t kk = 2; kk <= P; kk <<= 1) {
         for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
             if (j >= (uint32_t)E && j / E < 64u) {
-                // partner thread t ^ (j / E) is in this wavefront (every lane
-                // takes part in the shuffles; inactive lanes hold padding)
+                // partner thread t ^ (j / E) is in this wavefront
                 const uint32_t m = j / E;
 #pragma unroll
                 for (int s = 0; s < E; ++s) {
-                    const uint64_t pk = shfl_xor64(k[s], (int)m);
-                    const uint32_t pa = __shfl_xor(a[s], (int)m);
-                    const uint32_t e = t * E + s;
-                    const bool keep_min = ((e & j) == 0) == ((e & kk) == 0);
-                    const bool pl = elem_less(pk, pa, k[s], a[s]);
-                    if (act && (keep_min ? pl : !pl)) {
-                        k[s] = pk;
-                        a[s] = pa;
-                    }
+                    const uint64_t ph = shfl_xor64(h[s], (int)m);
+                    const uint32_t pl = __shfl_xor(l[s], (int)m);
+                    take96(h[s], l[s], ph, pl, bitonic_flip(t * E + s, j, kk));
                 }
             } else if (j >= (uint32_t)E) {
                 // exchange through LDS; slot s of thread t lives at t*E + ((s + t) mod E)
@@ -1245,8 +1297,8 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
                 if (act) {
 #pragma unroll
                     for (int s = 0; s < E; ++s) {
-                        SK[t * E + ((s + t) & (E - 1))] = k[s];
-                        SA[t * E + ((s + t) & (E - 1))] = a[s];
+                        SK[t * E + ((s + t) & (E - 1))] = h[s];
+                        SA[t * E + ((s + t) & (E - 1))] = l[s];
                     }
                 }
                 __syncthreads();
@@ -1254,32 +1306,23 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
                     const uint32_t tp = t ^ (j / E);
 #pragma unroll
                     for (int s = 0; s < E; ++s) {
-                        const uint64_t pk = SK[tp * E + ((s + tp) & (E - 1))];
-                        const uint32_t pa = SA[tp * E + ((s + tp) & (E - 1))];
-                        const uint32_t e = t * E + s;
-                        const bool keep_min = ((e & j) == 0) == ((e & kk) == 0);
-                        const bool pl = elem_less(pk, pa, k[s], a[s]);
-                        if (keep_min ? pl : !pl) {
-                            k[s] = pk;
-                            a[s] = pa;
-                        }
+                        const uint64_t ph = SK[tp * E + ((s + tp) & (E - 1))];
+                        const uint32_t pl = SA[tp * E + ((s + tp) & (E - 1))];
+                        take96(h[s], l[s], ph, pl, bitonic_flip(t * E + s, j, kk));
                     }
                 }
-            } else if (act) {
-                if constexpr (E >= 2) { if (j == 1) cex_local<E, 1>(k, a, t, kk); }
-                if constexpr (E >= 4) { if (j == 2) cex_local<E, 2>(k, a, t, kk); }
-                if constexpr (E >= 8) { if (j == 4) cex_local<E, 4>(k, a, t, kk); }
-                if constexpr (E >= 16) { if (j == 8) cex_local<E, 8>(k, a, t, kk); }
+            } else {
+                if constexpr (E >= 2) { if (j == 1) cex_local<E, 1>(h, l, t, kk); }
+                if constexpr (E >= 4) { if (j == 2) cex_local<E, 2>(h, l, t, kk); }
+                if constexpr (E >= 8) { if (j == 4) cex_local<E, 4>(h, l, t, kk); }
+                if constexpr (E >= 16) { if (j == 8) cex_local<E, 8>(h, l, t, kk); }
             }
         }
     }
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int s = 0; s < E; ++s) {
-            SK[t * E + s] = k[s];
-            SA[t * E + s] = a[s];
-        }
+        for (int s = 0; s < E; ++s) unpack96(h[s], l[s], SK[t * E + s], SA[t * E + s]);
     }
     __syncthreads();
 }
