@@ -1572,7 +1572,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
 }
 
 template <int EMAX, bool G, int NT>
-__global__ __launch_bounds__(NT) void k_base_block(const Seg* items, const uint64_t* key0,
+__global__ __launch_bounds__(NT, EMAX <= 4 ? 4 : 1) void k_base_block(const Seg* items, const uint64_t* key0,
                                                     const uint64_t* key1, const uint32_t* idx0,
                                                     const uint32_t* idx1, const uint8_t* chars,
                                                     const uint64_t* offsets, uint32_t* out_perm,
