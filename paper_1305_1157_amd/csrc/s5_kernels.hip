@@ -1282,13 +1282,14 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     for (uint32_t kk = 2; kk <= P; kk <<= 1) {
         for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
             if (j >= (uint32_t)E && j / E < 64u) {
-                // partner thread t ^ (j / E) is in this wavefront
-                const uint32_t m = j / E;
+                // partner thread t ^ (j / E) is in this wavefront; with j >= E
+                // the direction is the same for the thread's E elements
+                const uint32_t m = j / E, fl = bitonic_flip(t * E, j, kk);
 #pragma unroll
                 for (int s = 0; s < E; ++s) {
                     const uint64_t ph = shfl_xor64(h[s], (int)m);
                     const uint32_t pl = __shfl_xor(l[s], (int)m);
-                    take96(h[s], l[s], ph, pl, bitonic_flip(t * E + s, j, kk));
+                    take96(h[s], l[s], ph, pl, fl);
                 }
             } else if (j >= (uint32_t)E) {
                 // exchange through LDS; slot s of thread t lives at t*E + ((s + t) mod E)
@@ -1303,12 +1304,12 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
                 }
                 __syncthreads();
                 if (act) {
-                    const uint32_t tp = t ^ (j / E);
+                    const uint32_t tp = t ^ (j / E), fl = bitonic_flip(t * E, j, kk);
 #pragma unroll
                     for (int s = 0; s < E; ++s) {
                         const uint64_t ph = SK[tp * E + ((s + tp) & (E - 1))];
                         const uint32_t pl = SA[tp * E + ((s + tp) & (E - 1))];
-                        take96(h[s], l[s], ph, pl, bitonic_flip(t * E + s, j, kk));
+                        take96(h[s], l[s], ph, pl, fl);
                     }
                 }
             } else {
