@@ -578,7 +578,6 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
     const uint64_t tb = (uint64_t)row * g.tile_len;
     const uint32_t start = g.begin + (uint32_t)(tb < g.size ? tb : g.size);
     const uint32_t end = g.begin + (uint32_t)(tb + g.tile_len < g.size ? tb + g.tile_len : g.size);
-    const uint32_t nbits = g.d + 1;
     for (uint32_t c = start + w * 64 * U; c < end; c += kWG * U) {
         uint64_t kk[U];
         uint32_t b[U];
@@ -595,10 +594,16 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
             const uint32_t pos = c + q * 64 + lane;
             if (valid[q]) bid[pos] = (uint16_t)b[q];
             const uint64_t act = __ballot(valid[q]);
-            if (act) {
-                const uint64_t m = match_bucket(b[q], nbits, act);
-                if (valid[q] && lane == (uint32_t)(__ffsll((long long)m) - 1))
-                    h[b[q]] += (uint32_t)__popcll(m);
+            if (!act) continue;
+            // the wavefront's own histogram: one add when every key of the
+            // chunk falls into one bucket (skewed inputs), else an LDS add per
+            // key (spread buckets rarely collide within an instruction)
+            const int lead = __ffsll((long long)act) - 1;
+            const uint32_t b0 = (uint32_t)__builtin_amdgcn_readlane((int)b[q], lead);
+            if (__ballot(valid[q] && b[q] == b0) == act) {
+                if (lane == (uint32_t)lead) h[b0] += (uint32_t)__popcll(act);
+            } else if (valid[q]) {
+                atomicAdd(&h[b[q]], 1u);
             }
         }
     }
