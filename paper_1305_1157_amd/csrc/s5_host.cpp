@@ -76,7 +76,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
-    size_t key[2], key2[2], idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
+    size_t key[2], key2[2], key3, idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
         bstart, base_list, learn, learn_seg, set_tune, counters[2], glob, total;
     uint32_t learn_cap, tune_sets;
     Caps caps;
@@ -115,6 +115,7 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     };
     for (int b = 0; b < 2; ++b) L.key[b] = take(n * 8);
     for (int b = 0; b < 2; ++b) L.key2[b] = take(n * 8);
+    L.key3 = take(n * 8);
     for (int b = 0; b < 2; ++b) L.idx[b] = take(n * 4);
     L.bid = take(n * 2);
     for (int b = 0; b < 2; ++b) L.lseg[b] = take((size_t)cp.large * sizeof(LSeg));
@@ -279,6 +280,7 @@ struct SortArgs {
 struct Ptrs {
     uint64_t* key[2];
     uint64_t* key2[2];  // the 8 bytes after key, or kKeyUnknown
+    uint64_t* key3;     // the 8 bytes after those, for the first pass only
     uint32_t* idx[2];
     uint16_t* bid;
     LSeg* lseg[2];
@@ -297,6 +299,7 @@ Ptrs make_ptrs(const Layout& L, char* W) {
     for (int b = 0; b < 2; ++b) {
         P.key[b] = (uint64_t*)(W + L.key[b]);
         P.key2[b] = (uint64_t*)(W + L.key2[b]);
+        P.key3 = (uint64_t*)(W + L.key3);
         P.idx[b] = (uint32_t*)(W + L.idx[b]);
         P.lseg[b] = (LSeg*)(W + L.lseg[b]);
         P.cnt[b] = (Counters*)(W + L.counters[b]);
@@ -428,7 +431,7 @@ void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
                        P.key2[buf], P.idx[buf], P.key[buf ^ 1], P.key2[buf ^ 1], P.idx[buf ^ 1],
                        P.cm, P.cs, P.bstart,
                        P.tree_in, P.tree_lcp, a.chars, a.offsets, a.perm, a.lcp, S.vmax, S.kmax,
-                       P.glob, S.tile, level == 0 ? 1u : 0u, st);
+                       P.glob, S.tile, level == 0 ? P.key3 : nullptr, st);
     });
 }
 
@@ -439,7 +442,7 @@ void clear_counters(const Ptrs& P, hipStream_t st) {
 void start_sort(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P, hipStream_t st) {
     clear_counters(P, st);
     timed(K_INIT, a.n, st, [&] {
-        launch_init_keys(a.chars, a.offsets, a.n, P.key[0], P.key2[0], P.idx[0], st);
+        launch_init_keys(a.chars, a.offsets, a.n, P.key[0], P.key2[0], P.key3, P.idx[0], st);
     });
     timed(K_ROOTS, a.num_sets, st, [&] {
         launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, plan_ctx(P, L, c, a, 0), st);

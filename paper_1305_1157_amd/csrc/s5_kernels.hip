@@ -352,14 +352,17 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
 
 __global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, const uint64_t* offsets,
                                                    uint32_t n, uint64_t* key, uint64_t* key2,
-                                                   uint32_t* idx) {
+                                                   uint64_t* key3, uint32_t* idx) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     idx[i] = i;
-    uint64_t k0, k1;
-    load_key16(chars, offsets[i], &k0, &k1);
-    key[i] = k0;
-    key2[i] = k1;
+    uint64_t w[3];
+    load_key_run<3>(chars, offsets[i], w);
+    key[i] = w[0];
+    key2[i] = w[1];
+    // the third word is all zero (and never read) unless the string
+    // continues past its first 16 bytes
+    if (!has_zero(w[1])) key3[i] = w[2];
 }
 
 __global__ __launch_bounds__(256) void k_prefix_keys(const uint8_t* chars, const uint64_t* offsets,
@@ -859,12 +862,13 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
     return pre + inc - v;
 }
 
+template <bool K3>
 __device__ __forceinline__ void scatter_body(
     uint32_t tile, const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid,
     const uint64_t* key_in, const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out,
     uint64_t* key2_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in,
     const uint8_t* tree_lcp, const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
-    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, bool fresh) {
+    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const uint64_t* key3) {
     extern __shared__ uint64_t dyn[];
     uint64_t* SK = dyn;                                   // kSubTile staged keys
     uint32_t* SI = (uint32_t*)(SK + kSubTile);            // kSubTile staged indices
@@ -920,7 +924,7 @@ __device__ __forceinline__ void scatter_body(
         const uint32_t se = sub + kSubTile < end ? sub + kSubTile : end;
         const uint32_t pw = sub + w * kPerWave + lane;
         // A: load, refresh, rank inside the wavefront
-        uint64_t nk[kChunks], n2[kChunks];
+        uint64_t nk[kChunks], n2[kChunks], n3[kChunks];
         uint32_t id[kChunks], bb[kChunks];
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
@@ -929,6 +933,7 @@ __device__ __forceinline__ void scatter_body(
             bb[c] = valid ? bid[p] : kNoString;
             nk[c] = valid ? key_in[p] : 0ull;
             n2[c] = valid ? key2_in[p] : 0ull;
+            n3[c] = K3 && valid && !has_zero(n2[c]) ? key3[p] : 0ull;
             id[c] = valid ? idx_in[p] : 0u;
         }
 #pragma unroll
@@ -937,9 +942,11 @@ __device__ __forceinline__ void scatter_body(
             const uint32_t info = binfo[bb[c]];
             const uint32_t delta = info & 15u;
             if ((info >> 4) != kModeLive || delta == 0) continue;
-            // the first pass reads strings in input order, where a gather is
-            // cheap: it gathers whenever the second word would become unknown
-            if (!advance_key16(&nk[c], &n2[c], delta) || (fresh && n2[c] == kKeyUnknown))
+            // the first pass has the third word too (from init): both words
+            // stay exact without a gather
+            if (K3)
+                advance_key24(&nk[c], &n2[c], n3[c], delta);
+            else if (!advance_key16(&nk[c], &n2[c], delta))
                 load_key16(chars, offsets[id[c]] + g.depth + delta, &nk[c], &n2[c]);
         }
 #pragma unroll
@@ -1028,25 +1035,27 @@ __device__ __forceinline__ void scatter_body(
     }
 }
 
-template <bool G>
+// K3: the first pass, which also reads the third key word (a separate
+// instantiation, so that the other passes keep their smaller register budget)
+template <bool G, bool K3>
 __global__ __launch_bounds__(256) void k_scatter(
     const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
     const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out, uint64_t* key2_out,
     uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart,
     const uint64_t* tree_in, const uint8_t* tree_lcp, const uint8_t* chars,
     const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp, uint32_t vmax, uint32_t kmax,
-    const uint32_t* wcnt, uint32_t cap, const Globals* glob, uint32_t fresh) {
+    const uint32_t* wcnt, uint32_t cap, const Globals* glob, const uint64_t* key3) {
     if (!G) {
-        scatter_body(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out,
+        scatter_body<K3>(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out,
                      idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp,
-                     vmax, kmax, fresh != 0);
+                     vmax, kmax, key3);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        scatter_body(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out,
+        scatter_body<K3>(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out,
                      cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax,
-                     kmax, fresh != 0);
+                     kmax, key3);
         __syncthreads();
     }
 }
@@ -1699,10 +1708,10 @@ static inline uint32_t dyn_grid(const Dyn& dy, uint32_t host_units) {
 }
 
 void launch_init_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint64_t* key,
-                      uint64_t* key2, uint32_t* idx, hipStream_t st) {
+                      uint64_t* key2, uint64_t* key3, uint32_t* idx, hipStream_t st) {
     if (!n) return;
     S5_LAUNCH(k_init_keys, dim3((n + 255) / 256), dim3(256), 0, st, chars, offsets, n, key, key2,
-              idx);
+              key3, idx);
 }
 
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
@@ -1801,18 +1810,26 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, uint32_t fresh, hipStream_t st) {
+                    const Dyn& dy, const uint64_t* key3, hipStream_t st) {
     (void)unroll;
     const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
                        (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
-    if (dy.cnt)
-        S5_LAUNCH(k_scatter<true>, dim3(dy.grid), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,
-                  key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
-                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob, fresh);
-    else
-        S5_LAUNCH(k_scatter<false>, dim3(tiles), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,
-                  key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
-                  out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob, fresh);
+#define S5_SCATTER(GG, KK, GRID)                                                               \
+    S5_LAUNCH((k_scatter<GG, KK>), dim3(GRID), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,  \
+              key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp,    \
+              chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob, key3)
+    if (dy.cnt) {
+        if (key3)
+            S5_SCATTER(true, true, dy.grid);
+        else
+            S5_SCATTER(true, false, dy.grid);
+    } else {
+        if (key3)
+            S5_SCATTER(false, true, tiles);
+        else
+            S5_SCATTER(false, false, tiles);
+    }
+#undef S5_SCATTER
 }
 
 // Host-driven: n_items[q] items of class q.  Graph mode (dy[q].cnt set): the

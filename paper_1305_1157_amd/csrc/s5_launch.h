@@ -11,7 +11,7 @@
 namespace s5 {
 
 void launch_init_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint64_t* key,
-                      uint64_t* key2, uint32_t* idx, hipStream_t st);
+                      uint64_t* key2, uint64_t* key3, uint32_t* idx, hipStream_t st);
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                         uint32_t depth, uint64_t* key, hipStream_t st);
 void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
@@ -41,7 +41,7 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, uint32_t fresh, hipStream_t st);
+                    const Dyn& dy, const uint64_t* key3, hipStream_t st);
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
                       const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,

@@ -143,6 +143,21 @@ S5_HD bool advance_key16(uint64_t* k0, uint64_t* k1, uint32_t delta) {
     return true;
 }
 
+// The two key words of a string advanced by `delta` bytes (1..8) when the
+// 24 bytes k0, k1, k2 that follow the current depth are all known (zero past
+// the terminator): both new words are exact.
+S5_HD void advance_key24(uint64_t* k0, uint64_t* k1, uint64_t k2, uint32_t delta) {
+    const uint64_t x = *k0, y = *k1;
+    if (delta >= 8) {
+        *k0 = y;
+        *k1 = k2;
+        return;
+    }
+    const uint32_t s = 8 * delta;
+    *k0 = (x << s) | (y >> (64 - s));
+    *k1 = (y << s) | (k2 >> (64 - s));
+}
+
 S5_HD uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

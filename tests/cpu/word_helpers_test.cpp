@@ -125,6 +125,20 @@ static void test_advance_key16(std::mt19937_64& rng) {
         }
     }
     CHECK(gathers < steps, "some steps need no gather (%d of %d)", gathers, steps);
+    // three known words: both advanced words exact, for every step 1..8
+    for (int t = 0; t < 2000; ++t) {
+        const int len = (int)(rng() % 40);
+        for (int i = 0; i < len; ++i) s[i] = (uint8_t)(1 + rng() % 255);
+        for (int i = len; i < 80; ++i) s[i] = 0;
+        uint64_t w[3];
+        load_key_run<3>(s.data(), 0, w);
+        for (uint32_t delta = 1; delta <= 8; ++delta) {
+            uint64_t a0 = w[0], a1 = w[1];
+            advance_key24(&a0, &a1, w[2], delta);
+            CHECK(a0 == ref_key(&s[delta]) && a1 == ref_key(&s[delta + 8]),
+                  "advance_key24 len %d delta %u", len, delta);
+        }
+    }
 }
 
 static void test_load_key_random(std::mt19937_64& rng) {
