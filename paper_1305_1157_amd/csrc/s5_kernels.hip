@@ -776,27 +776,24 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
         }
         return g.depth + ((j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j]);
     };
-    // the buckets of this thread are b = tid + e * kWG, e < kPlanPer
-    constexpr int kPlanPer = (int)((2u << kDMax) / kWG);
-    static_assert(kPlanPer * kWG >= (int)(2u << kDMax) - 1, "buckets per thread");
-    uint32_t nd[kPlanPer];
+    // every thread counts, then emits, its buckets b = tid, tid + kWG, ... in
+    // the same order (their new depths kept in LDS: loops stay rolled)
+    __shared__ uint32_t ndl[1u << (kDMax + 1)];
     PlanAcc acc;
     acc_clear(acc);
-#pragma unroll
-    for (int e = 0; e < kPlanPer; ++e) {
-        const uint32_t b = threadIdx.x + e * kWG;
-        nd[e] = b < k ? next_depth(b) : 0xFFFFFFFFu;
-        if (nd[e] != 0xFFFFFFFFu) plan_count(tot[b], ctx, sp, acc);
+    for (uint32_t b = threadIdx.x; b < k; b += kWG) {
+        const uint32_t nd = next_depth(b);
+        ndl[b] = nd;
+        if (nd != 0xFFFFFFFFu) plan_count(tot[b], ctx, sp, acc);
     }
     plan_scan(acc, &T);
     if (threadIdx.x < 64) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
-#pragma unroll
-    for (int e = 0; e < kPlanPer; ++e) {
-        const uint32_t b = threadIdx.x + e * kWG;
-        if (nd[e] != 0xFFFFFFFFu)
-            plan_emit(g.begin + st[b], tot[b], nd[e], g.base, next_buf, ctx, sp, &T, acc);
+    for (uint32_t b = threadIdx.x; b < k; b += kWG) {
+        const uint32_t nd = ndl[b];
+        if (nd != 0xFFFFFFFFu)
+            plan_emit(g.begin + st[b], tot[b], nd, g.base, next_buf, ctx, sp, &T, acc);
     }
 }
 
