@@ -1389,6 +1389,44 @@ __device__ uint32_t block_scan_max_add(uint32_t& mx, uint32_t& ad, uint32_t* wl)
     return total;
 }
 
+// (key, a) < (key2, a2) in (group, key, local index) order
+__device__ __forceinline__ bool elem_lt(uint64_t k1, uint32_t a1, uint64_t k2, uint32_t a2) {
+    uint64_t h1, h2;
+    uint32_t l1, l2;
+    pack96(k1, a1, h1, l1);
+    pack96(k2, a2, h2, l2);
+    return h1 < h2 || (h1 == h2 && l1 < l2);
+}
+
+// Merge the sorted runs X = (XK, XA)[0..na) and Y = (YK, YA)[0..nb) (distinct
+// elements) into (OK, OA)[0..na+nb).  Thread t writes a contiguous stretch of
+// the output, found by a binary search along the merge path.  All NT threads call.
+template <int NT>
+__device__ void merge_runs(const uint64_t* XK, const uint32_t* XA, uint32_t na,
+                           const uint64_t* YK, const uint32_t* YA, uint32_t nb, uint64_t* OK,
+                           uint32_t* OA) {
+    const uint32_t n = na + nb, per = (n + NT - 1) / NT;
+    uint32_t o = threadIdx.x * per < n ? threadIdx.x * per : n;
+    const uint32_t oe = o + per < n ? o + per : n;
+    // i = elements of X among the first o outputs
+    uint32_t lo = o > nb ? o - nb : 0u, hi = o < na ? o : na;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (elem_lt(XK[mid], XA[mid], YK[o - mid - 1], YA[o - mid - 1]))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    uint32_t i = lo, j = o - lo;
+    for (; o < oe; ++o) {
+        const bool fx = j >= nb || (i < na && elem_lt(XK[i], XA[i], YK[j], YA[j]));
+        OK[o] = fx ? XK[i] : YK[j];
+        OA[o] = fx ? XA[i] : YA[j];
+        i += fx ? 1u : 0u;
+        j += fx ? 0u : 1u;
+    }
+}
+
 template <int EMAX, int NT>
 __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
                                                 const uint64_t* key0, const uint64_t* key1,
@@ -1422,7 +1460,26 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         if (i < n) IDX[i] = iin[i];
     }
     __syncthreads();
-    sort_pow2<EMAX, NT>(K, A, P);
+    if (P >= 128 && n <= (P >> 1) + (P >> 2)) {
+        // n just above a power of two: sort the first P/2 and the rest (padded
+        // to a smaller power of two) apart and merge them, instead of sorting
+        // P mostly padded elements; K/A and SK/SA swap roles
+        const uint32_t half = P >> 1, nb = n - half;
+        uint32_t PB = 1;
+        while (PB < nb) PB <<= 1;
+        sort_pow2<EMAX, NT>(K, A, half);
+        sort_pow2<EMAX, NT>(K + half, A + half, PB);
+        merge_runs<NT>(K, A, half, K + half, A + half, nb, SK, SA);
+        __syncthreads();
+        uint64_t* tk = K;
+        K = SK;
+        SK = tk;
+        uint32_t* ta = A;
+        A = SA;
+        SA = ta;
+    } else {
+        sort_pow2<EMAX, NT>(K, A, P);
+    }
     // each thread owns positions [c0, c1)
     const uint32_t per = (n + NT - 1) / NT;
     const uint32_t c0 = tid * per < n ? tid * per : n;
