@@ -18,15 +18,16 @@
 //   k_sample_tree  one workgroup per segment: sample, sort, recursive
 //                  splitter selection, level-order/in-order arrays, splitter LCPs
 //   k_classify     one wavefront per unit of a segment: unrolled, interleaved
-//                  descents over coalesced keys; bucket ids; per-unit histogram
-//                  built with wavefront ballots (no atomics)
+//                  descents over coalesced keys; bucket ids; per-wavefront
+//                  histograms in LDS summed into the unit's row
 //   k_colscan      exclusive scan down each bucket column of the count matrix,
 //                  within chunks of 64 unit rows
 //   k_bucket_plan  one workgroup per segment: chunk prefixes, bucket starts,
 //                  and the plan of every bucket (finished / base case / next pass)
-//   k_scatter      stable redistribution of (key, index); keys of buckets whose
-//                  depth grows are refreshed from the arena on the way; buckets
-//                  that are finished write their final output directly
+//   k_scatter      stable redistribution of (key, second key word, index); keys
+//                  of buckets whose depth grows are advanced from the carried
+//                  words or refreshed from the arena on the way; buckets that
+//                  are finished write their final output directly
 // followed, once every bucket is small, by k_base_sort (LDS sorter that emits
 // LCPs) and k_lcp_fix (LCPs at bucket boundaries).
 #include "s5_internal.h"
@@ -818,9 +819,10 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
 // K5: stable redistribution (Section 3.1, out-of-place into the second work
 // array).  A tile is processed in sub-tiles of kSubTile strings:
 //   A. every wavefront loads its 512 strings (8 chunks of 64, in order),
-//      refreshes the keys of buckets whose depth grows (shift when the key
-//      holds the terminator, else an 8-byte gather from the arena), and ranks
-//      them by bucket with ballots into its own LDS counters;
+//      advances the two key words of buckets whose depth grows (from the words
+//      themselves when they hold the bytes -- in the first pass always, with
+//      the third word from init -- else a 16-byte gather from the arena), and
+//      ranks them by bucket with ballots into its own LDS counters;
 //   B. per bucket: prefix over the wavefronts and the bucket's start inside the
 //      sub-tile (block-wide scan over the buckets);
 //   C. every string is staged in LDS at its rank in bucket order;
