@@ -70,8 +70,8 @@ struct Counters {
 // Device-global state that survives the whole sort.
 // Base-case items go to one of four lists by size: <= 64 strings (one
 // wavefront each, in registers), <= 256 (a one-wavefront workgroup), <= 512
-// (two wavefronts) and <= T (four wavefronts), so that small items hold little
-// LDS and many of them are in flight on a compute unit.
+// (two wavefronts) and <= T (four wavefronts, eight for T > 1024), so that
+// small items hold little LDS and many of them are in flight on a compute unit.
 constexpr int kBaseClasses = 4;
 constexpr uint32_t kBaseWave = 64, kBaseSmall = 256, kBaseMid = 512;
 __host__ __device__ inline int base_class(uint32_t size) {

@@ -1917,16 +1917,16 @@ static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const u
                   st, items[2], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P,
                   dy[2].cnt, dy[2].cap, glob, guard);
     }
-    if ((G || n_items[3]) && PT > kBaseMid) {  // <= T strings: four wavefronts
+    if ((G || n_items[3]) && PT > kBaseMid) {  // <= T strings: four (or eight) wavefronts
         const dim3 g(G ? dy[3].grid : n_items[3]);
         if (PT <= 4u * kWG)
             S5_LAUNCH((k_base_block<4, G, kWG>), g, dim3(kWG), per * PT, st, items[3], key0, key1,
                       idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt, dy[3].cap,
                       glob, guard);
-        else
-            S5_LAUNCH((k_base_block<8, G, kWG>), g, dim3(kWG), per * PT, st, items[3], key0, key1,
-                      idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt, dy[3].cap,
-                      glob, guard);
+        else  // <= 2048 strings: eight wavefronts, four strings each
+            S5_LAUNCH((k_base_block<4, G, 2 * kWG>), g, dim3(2 * kWG), per * PT, st, items[3], key0,
+                      key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
+                      dy[3].cap, glob, guard);
     }
 }
 
