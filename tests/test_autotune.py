@@ -40,3 +40,10 @@ def test_committed_table_is_valid():
         assert _valid_row(c["splitters"], c["base_threshold"], c["tile"])
     sizes = np.random.default_rng(0).integers(100, 1_000_000, size=1000)
     assert all(_valid_row(*r) for r in autotune.tuning_for(sizes, t))
+
+
+def test_unroll_needs_a_clear_win():
+    # a faster U replaces the default only when it wins by 2 %
+    assert autotune.pick_unroll({2: 1.0, 4: 1.01, 8: 1.02}) == 4
+    assert autotune.pick_unroll({2: 0.9, 4: 1.0, 8: 1.0}) == 2
+    assert autotune.pick_unroll({2: 1.1, 4: 1.0, 8: 0.985}) == 4
