@@ -5,8 +5,9 @@ The paper fixes its thresholds by hand for its machines (Section 3.1,
 same parameters are measured on the device instead: for every class of set
 sizes the tuner times the HIP sort on a synthetic probe batch of that class
 and keeps the fastest splitter count v, base-case threshold T and tile, by
-coordinate descent from the defaults; the interleaved descents per lane U
-(one value per launch) are tuned last on a batch that mixes all classes.  The
+coordinate descent from the defaults; the table is kept only if it also wins
+on a batch that mixes all classes, and the interleaved descents per lane U
+(one value per launch) are tuned last on that batch.  The
 result is a JSON table; ``tuning_for`` maps set sizes to per-set parameters
 for ``s5.sort_batched(..., tuning=...)``.
 
@@ -151,9 +152,18 @@ def tune(kinds=("random", "url", "dna"), target=3_000_000, rounds=2, seed=0x70E,
         table["classes"].append(dict(lo=lo, hi=hi, **best, ms=t, default_ms=t0, sets=len(b.sizes),
                                      strings=b.n))
         del b
-    # one unroll for the launch, on a batch mixing every class
+    # the table must also win on a batch mixing every class, else the defaults stay
     mix = _Batch(*_probe(SIZE_CLASSES[0][0], SIZE_CLASSES[-1][1], kinds, target, seed + 99))
     rows = tuning_for(mix.sizes, table)
+    t_tab = mix.time(rows, DEFAULT_UNROLL)
+    t_def = mix.time(tuning_for(mix.sizes, default_table()), DEFAULT_UNROLL)
+    table["mix_check"] = {"table_ms": t_tab, "defaults_ms": t_def, "kept": t_tab < t_def * 0.98}
+    log(f"mixed batch: table {t_tab:.3f} ms, defaults {t_def:.3f} ms")
+    if not table["mix_check"]["kept"]:
+        for c in table["classes"]:
+            c.update(DEFAULT)
+        rows = tuning_for(mix.sizes, table)
+    # one unroll for the launch, on the same batch
     ut = {u: mix.time(rows, u) for u in UNROLLS}
     table["unroll"] = pick_unroll(ut)
     table["unroll_ms"] = ut
