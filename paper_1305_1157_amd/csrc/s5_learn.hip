@@ -33,7 +33,7 @@ constexpr uint32_t kNPS = 1408;       // stride of one parameter vector
 constexpr uint32_t oW1 = 0, oB1 = 256, oW2 = 288, oB2 = 1312, oW3 = 1344, oB3 = 1376;
 constexpr float kB1 = 0.9f, kB2 = 0.999f, kEps = 1e-8f;
 constexpr uint32_t kS = kH + 1;       // LDS row stride of per-sample vectors
-constexpr uint32_t kS4 = kH + 4;      // same, 16-byte aligned rows (read four at a time)
+constexpr uint32_t kS1 = kH + 8;      // first hidden layer and features, 16-byte aligned rows
 
 __device__ __forceinline__ float* wbuf(const LearnCtx& c, uint32_t slot, uint32_t b) {
     return c.W + ((size_t)slot * 2 + b) * kNPS;
@@ -161,12 +161,10 @@ __device__ __forceinline__ float summed_grad(const LearnCtx& c, uint32_t slot, u
 
 __device__ __forceinline__ void learn_step_body(const LearnCtx& c, uint32_t slot, uint32_t step,
                                                 float lr) {
+    // 80 KB in all, so that two workgroups fit on one compute unit
     __shared__ float w[kNPS];
-    __shared__ float sx[kGrp * 8];
-    __shared__ __align__(16) float sh1[kGrp * kS4];
-    __shared__ float sh2[kGrp * kS];  // later reused for the first layer's deltas
-    __shared__ float sd2[kGrp * kS];
-    __shared__ float sd3[kGrp];
+    __shared__ __align__(16) float sh1[kGrp * kS1];  // per sample: h1, then the 8 features
+    __shared__ float sv[kGrp * kS];  // per sample: h2 and d3, then d2, then d1
     const uint32_t grp = blockIdx.x, tid = threadIdx.x;
     const uint32_t prev = (step + 1) & 1u, cur = step & 1u;
     const float* wp = wbuf(c, slot, prev);
@@ -196,36 +194,54 @@ __device__ __forceinline__ void learn_step_body(const LearnCtx& c, uint32_t slot
     const float y = mlp_forward(w, x, h1, h2);
     const float t = ((float)i + 0.5f) / (float)c.m;
     const float d3 = (2.0f / (float)c.m) * (y - t) * y * (1.0f - y);
+#pragma unroll
+    for (int j = 0; j < kH; ++j) {
+        sv[tid * kS + j] = h2[j];
+        sh1[tid * kS1 + j] = h1[j];
+    }
+    sv[tid * kS + kH] = d3;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sh1[tid * kS1 + kH + j] = x[j];
+    __syncthreads();
+    float* out = pbuf(c, slot, cur, grp);
+    // third layer (every sample's h2 and d3, read before d2 replaces them):
+    // thread 32 + j owns w3[j], thread 64 owns b3
+    if (tid >= 32 && tid < 64) {
+        float g = 0.0f;
+#pragma unroll 8
+        for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sv[b * kS + kH], sv[b * kS + tid - 32], g);
+        out[oW3 + tid - 32] = g;
+    } else if (tid == 64) {
+        float g = 0.0f;
+#pragma unroll 8
+        for (uint32_t b = 0; b < kGrp; ++b) g += sv[b * kS + kH];
+        out[oB3] = g;
+    }
+    // back-propagation to both hidden layers, in registers (d2 is formed
+    // again from h2 once the third layer's sums are done with h2)
     float d1[kH];
 #pragma unroll
     for (int j = 0; j < kH; ++j) d1[j] = 0.0f;
 #pragma unroll 4
     for (int r = 0; r < kH; ++r) {
         const float d2 = h2[r] > 0.0f ? d3 * w[oW3 + r] : 0.0f;
-        sd2[tid * kS + r] = d2;
 #pragma unroll
         for (int j = 0; j < kH; ++j) d1[j] = fmaf(d2, w[oW2 + r * kH + j], d1[j]);
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) sx[tid * 8 + j] = x[j];
-#pragma unroll
-    for (int j = 0; j < kH; ++j) {
-        sh1[tid * kS4 + j] = h1[j];
-        sh2[tid * kS + j] = h2[j];
-        d1[j] = h1[j] > 0.0f ? d1[j] : 0.0f;
-    }
-    sd3[tid] = d3;
+    for (int j = 0; j < kH; ++j) d1[j] = h1[j] > 0.0f ? d1[j] : 0.0f;
     __syncthreads();
-    float* out = pbuf(c, slot, cur, grp);
-    // second and third layer: thread t owns W2[t / 8][4 (t % 8) .. +3] and one
-    // of b2, w3, b3 (t < 65)
+#pragma unroll
+    for (int r = 0; r < kH; ++r) sv[tid * kS + r] = h2[r] > 0.0f ? d3 * w[oW3 + r] : 0.0f;
+    __syncthreads();
+    // second layer: thread t owns W2[t / 8][4 (t % 8) .. +3], and b2[t] for t < 32
     {
         const uint32_t r = tid >> 3, jq = (tid & 7u) << 2;
         float g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, g3 = 0.0f;
 #pragma unroll 8
         for (uint32_t b = 0; b < kGrp; ++b) {
-            const float d = sd2[b * kS + r];
-            const float4 h = *reinterpret_cast<const float4*>(&sh1[b * kS4 + jq]);
+            const float d = sv[b * kS + r];
+            const float4 h = *reinterpret_cast<const float4*>(&sh1[b * kS1 + jq]);
             g0 = fmaf(d, h.x, g0);
             g1 = fmaf(d, h.y, g1);
             g2 = fmaf(d, h.z, g2);
@@ -239,36 +255,25 @@ __device__ __forceinline__ void learn_step_body(const LearnCtx& c, uint32_t slot
         if (tid < 32) {
             float g = 0.0f;
 #pragma unroll 8
-            for (uint32_t b = 0; b < kGrp; ++b) g += sd2[b * kS + tid];
+            for (uint32_t b = 0; b < kGrp; ++b) g += sv[b * kS + tid];
             out[oB2 + tid] = g;
-        } else if (tid < 64) {
-            float g = 0.0f;
-#pragma unroll 8
-            for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd3[b], sh2[b * kS + tid - 32], g);
-            out[oW3 + tid - 32] = g;
-        } else if (tid == 64) {
-            float g = 0.0f;
-#pragma unroll 8
-            for (uint32_t b = 0; b < kGrp; ++b) g += sd3[b];
-            out[oB3] = g;
         }
     }
     __syncthreads();
-    float* sd1 = sh2;
 #pragma unroll
-    for (int j = 0; j < kH; ++j) sd1[tid * kS + j] = d1[j];
+    for (int j = 0; j < kH; ++j) sv[tid * kS + j] = d1[j];
     __syncthreads();
     // first layer: thread t owns W1[t / 8][t % 8], and b1[t] for t < 32
     {
         const uint32_t r = tid >> 3, j = tid & 7u;
         float g = 0.0f;
 #pragma unroll 8
-        for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sd1[b * kS + r], sx[b * 8 + j], g);
+        for (uint32_t b = 0; b < kGrp; ++b) g = fmaf(sv[b * kS + r], sh1[b * kS1 + kH + j], g);
         out[oW1 + tid] = g;
         if (tid < 32) {
             float gb = 0.0f;
 #pragma unroll 8
-            for (uint32_t b = 0; b < kGrp; ++b) gb += sd1[b * kS + tid];
+            for (uint32_t b = 0; b < kGrp; ++b) gb += sv[b * kS + tid];
             out[oB1 + tid] = gb;
         }
     }
