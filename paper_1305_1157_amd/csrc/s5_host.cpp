@@ -249,6 +249,26 @@ void timed(int k, uint64_t items, hipStream_t st, F&& fn) {
     if (a && b) g_pending.push_back({k, a, b, items});
 }
 
+// Same for a launcher that takes the two events itself and lets the kernel's
+// dispatch stamp them (a single kernel; no marker packets around it).
+template <class F>
+void timed_dispatch(int k, uint64_t items, hipStream_t st, F&& fn) {
+    if (!g_prof_on || (g_prof_only >= 0 && k != g_prof_only)) {
+        fn(nullptr, nullptr);
+        return;
+    }
+    (void)st;
+    hipEvent_t a = prof_event(), b = prof_event();
+    if (!a || !b) {
+        fn(nullptr, nullptr);
+        if (a) g_event_pool.push_back(a);
+        if (b) g_event_pool.push_back(b);
+        return;
+    }
+    fn(a, b);
+    g_pending.push_back({k, a, b, items});
+}
+
 // After the stream has been synchronized: fold pending events into totals.
 void prof_collect() {
     for (auto& p : g_pending) {
@@ -426,12 +446,12 @@ void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
         launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp, x,
                            (uint32_t)(buf ^ 1), S.seg, st);
     });
-    timed(K_SCATTER, S.now.moved, st, [&] {
+    timed_dispatch(K_SCATTER, S.now.moved, st, [&](hipEvent_t e0, hipEvent_t e1) {
         launch_scatter(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.bid, P.key[buf],
                        P.key2[buf], P.idx[buf], P.key[buf ^ 1], P.key2[buf ^ 1], P.idx[buf ^ 1],
                        P.cm, P.cs, P.bstart,
                        P.tree_in, P.tree_lcp, a.chars, a.offsets, a.perm, a.lcp, S.vmax, S.kmax,
-                       P.glob, S.tile, level == 0 ? P.key3 : nullptr, st);
+                       P.glob, S.tile, level == 0 ? P.key3 : nullptr, st, e0, e1);
     });
 }
 

@@ -30,6 +30,8 @@
 //                  are finished write their final output directly
 // followed, once every bucket is small, by k_base_sort (LDS sorter that emits
 // LCPs) and k_lcp_fix (LCPs at bucket boundaries).
+#include <hip/hip_ext.h>
+
 #include "s5_internal.h"
 #include "s5_launch.h"
 #include "s5_word.h"
@@ -1866,14 +1868,28 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, const uint64_t* key3, hipStream_t st) {
+                    const Dyn& dy, const uint64_t* key3, hipStream_t st, hipEvent_t ev_start,
+                    hipEvent_t ev_stop) {
     (void)unroll;
     const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
                        (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
-#define S5_SCATTER(GG, KK, GRID)                                                               \
-    S5_LAUNCH((k_scatter<GG, KK>), dim3(GRID), dim3(kWG), lds, st, lseg, tile_tab, bid, key_in,  \
-              key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp,    \
-              chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap, glob, key3)
+    // with events (instrumentation, host-driven passes only) the dispatch
+    // itself stamps them: their interval is the kernel's execution, with no
+    // marker packets around it
+#define S5_SCATTER(GG, KK, GRID)                                                                  \
+    do {                                                                                          \
+        if (ev_start || ev_stop)                                                                  \
+            hipExtLaunchKernelGGL((k_scatter<GG, KK>), dim3(GRID), dim3(kWG), lds, st, ev_start,  \
+                                  ev_stop, 0u, lseg, tile_tab, bid, key_in, key2_in, idx_in,      \
+                                  key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp,  \
+                                  chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap,  \
+                                  glob, key3);                                                    \
+        else                                                                                      \
+            S5_LAUNCH((k_scatter<GG, KK>), dim3(GRID), dim3(kWG), lds, st, lseg, tile_tab, bid,   \
+                      key_in, key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart,        \
+                      tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt,   \
+                      dy.cap, glob, key3);                                                        \
+    } while (0)
     if (dy.cnt) {
         if (key3)
             S5_SCATTER(true, true, dy.grid);

@@ -41,7 +41,8 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, const uint64_t* key3, hipStream_t st);
+                    const Dyn& dy, const uint64_t* key3, hipStream_t st,
+                    hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
                       const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
