@@ -1,0 +1,88 @@
+"""Register, scratch and occupancy budgets of the gfx950 kernels, read from the
+compiler's resource-usage remarks (a device-only compile; no GPU needed).
+
+The occupancy figures are design choices: the redistribution and the
+workgroup base case keep four waves per SIMD, the training step fits two
+workgroups per compute unit, and no kernel spills vector registers to scratch
+except the host-driven workgroup base case (four registers, the price of its
+four waves per SIMD).
+"""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_1305_1157_amd import build
+
+HIPCC = build.HIPCC
+pytestmark = pytest.mark.skipif(not (os.path.exists(HIPCC) or shutil.which(HIPCC)),
+                                reason="hipcc not available")
+
+
+def resource_usage(src):
+    """{mangled kernel name: {field: int}} for one source file."""
+    out = subprocess.run(
+        [HIPCC, "-x", "hip", *build.DEVICE_FLAGS, "--offload-device-only", "-c",
+         os.path.join(build.CSRC, src), "-o", os.devnull, "-Rpass-analysis=kernel-resource-usage"],
+        stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, check=True).stdout
+    kernels, cur = {}, None
+    for line in out.splitlines():
+        m = re.search(r"remark: Function Name: (\S+)", line)
+        if m:
+            cur = kernels.setdefault(m.group(1), {})
+            continue
+        m = re.search(r"remark:\s+([A-Za-z ]+?)(?: \[[^\]]*\])?: (\d+) \[", line)
+        if m and cur is not None:
+            cur[m.group(1)] = int(m.group(2))
+    return kernels
+
+
+@pytest.fixture(scope="module")
+def usage():
+    u = resource_usage("s5_kernels.hip")
+    u.update(resource_usage("s5_learn.hip"))
+    return u
+
+
+def pick(usage, fragment):
+    found = {k: v for k, v in usage.items() if fragment in k}
+    assert found, f"no kernel matching {fragment}"
+    return found
+
+
+def test_every_kernel_reported(usage):
+    for name in ("k_init_keys", "k_sample_tree", "k_classify", "k_colscan", "k_bucket_plan",
+                 "k_scatter", "k_base_wave", "k_base_block", "k_lcp_fix", "k_learn_step",
+                 "k_learn_finish"):
+        pick(usage, name)
+
+
+def test_no_vector_spills(usage):
+    # the one exception: held to 128 registers (four waves per SIMD), the
+    # host-driven workgroup base case spills four registers
+    for name, r in usage.items():
+        if "k_base_blockILi4ELb0E" in name:
+            assert r.get("VGPRs Spill", 0) <= 4 and r.get("ScratchSize", 0) <= 32, (name, r)
+            continue
+        assert r.get("ScratchSize", 0) == 0, f"{name} uses scratch"
+        assert r.get("VGPRs Spill", 0) == 0, f"{name} spills vector registers"
+
+
+def test_redistribution_keeps_four_waves(usage):
+    for name, r in pick(usage, "k_scatter").items():
+        assert r["VGPRs"] <= 128, name
+        assert r["Occupancy"] >= 4, name
+
+
+def test_workgroup_base_case_keeps_four_waves(usage):
+    for name, r in pick(usage, "k_base_blockILi4E").items():
+        assert r["VGPRs"] <= 128, name
+        assert r["Occupancy"] >= 4, name
+
+
+def test_training_step_fits_two_workgroups(usage):
+    (name, r), = pick(usage, "k_learn_step").items()
+    assert r["LDS Size"] <= 160 * 1024 // 2, r
+    assert r["Occupancy"] >= 2, r
