@@ -214,7 +214,7 @@ def batched_main(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
+def arg_parser():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -229,7 +229,11 @@ def main():
                     help="also run one plain device copy of this size (PMC calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the learned-splitter and batched measurements")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = arg_parser().parse_args()
     if args.gpus != 1:
         print(f"bench.py: the sort runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design note only)", file=sys.stderr)
