@@ -2,7 +2,8 @@
 
 * exhaustive brute force over all permutations of tiny inputs (exactly one
   order satisfies "non-descending, equal strings by ascending index");
-* Python's ``sorted`` on ``(bytes, index)`` (a library routine);
+* Python's ``sorted`` on ``(bytes, index)`` (a library routine), on fixed
+  alphabets and on property-based random inputs;
 * ``os.path.commonprefix`` for every LCP entry (a library routine);
 * pairwise brute force for D (a string's distinguishing prefix is one more
   than its longest common prefix with any other string, capped at |s|);
@@ -241,3 +242,24 @@ def test_check_pairs_tie_break_by_index():
     bad = perm.copy()
     bad[1], bad[2] = bad[2], bad[1]  # same strings, indices descending
     assert oracle.check_pairs(chars, offs, bad, lcp, np.arange(4, dtype=np.uint64)) == 1
+
+
+# property-based: arbitrary byte strings (no zero byte), including empty
+# strings, duplicates and strings that are prefixes of others
+try:
+    from hypothesis import given, settings, strategies as st
+except ImportError:  # pragma: no cover
+    given = None
+
+if given is not None:
+    _strings = st.lists(
+        st.one_of(st.binary(max_size=24), st.sampled_from([b"", b"a", b"ab", b"abc", b"\xff"]))
+        .map(lambda b: b.replace(b"\x00", b"\x01")),
+        max_size=60)
+
+    @settings(max_examples=300, deadline=None)
+    @given(_strings)
+    def test_property_vs_library_sort(strings):
+        perm, lcp = run_oracle(strings)
+        assert perm == lib_sorted_perm(strings)
+        assert lcp == lib_lcp(strings, perm)
