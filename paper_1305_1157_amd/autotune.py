@@ -73,6 +73,18 @@ def pick_unroll(ms: dict) -> int:
     return best if ms[best] < ms[DEFAULT_UNROLL] * 0.98 else DEFAULT_UNROLL
 
 
+def apply_mix_check(table: dict, table_ms: float, defaults_ms: float) -> dict:
+    """Keep the per-class choices only if the whole table is clearly (2 %)
+    faster than the defaults on the mixed batch; otherwise every class goes
+    back to the defaults.  Records both times in ``table["mix_check"]``."""
+    kept = table_ms < defaults_ms * 0.98
+    table["mix_check"] = {"table_ms": table_ms, "defaults_ms": defaults_ms, "kept": kept}
+    if not kept:
+        for c in table["classes"]:
+            c.update(DEFAULT)
+    return table
+
+
 # ---------------------------------------------------------------------------
 # measurement (needs the GPU)
 
@@ -157,12 +169,9 @@ def tune(kinds=("random", "url", "dna"), target=3_000_000, rounds=2, seed=0x70E,
     rows = tuning_for(mix.sizes, table)
     t_tab = mix.time(rows, DEFAULT_UNROLL)
     t_def = mix.time(tuning_for(mix.sizes, default_table()), DEFAULT_UNROLL)
-    table["mix_check"] = {"table_ms": t_tab, "defaults_ms": t_def, "kept": t_tab < t_def * 0.98}
     log(f"mixed batch: table {t_tab:.3f} ms, defaults {t_def:.3f} ms")
-    if not table["mix_check"]["kept"]:
-        for c in table["classes"]:
-            c.update(DEFAULT)
-        rows = tuning_for(mix.sizes, table)
+    apply_mix_check(table, t_tab, t_def)
+    rows = tuning_for(mix.sizes, table)
     # one unroll for the launch, on the same batch
     ut = {u: mix.time(rows, u) for u in UNROLLS}
     table["unroll"] = pick_unroll(ut)

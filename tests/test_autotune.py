@@ -47,3 +47,28 @@ def test_unroll_needs_a_clear_win():
     assert autotune.pick_unroll({2: 1.0, 4: 1.01, 8: 1.02}) == 4
     assert autotune.pick_unroll({2: 0.9, 4: 1.0, 8: 1.0}) == 2
     assert autotune.pick_unroll({2: 1.1, 4: 1.0, 8: 0.985}) == 4
+
+
+def test_mix_check_keeps_only_a_clear_win():
+    def table():
+        t = autotune.default_table()
+        t["classes"][1].update(splitters=63, base_threshold=512)
+        return t
+    won = autotune.apply_mix_check(table(), 0.95, 1.0)
+    assert won["mix_check"]["kept"] and won["classes"][1]["splitters"] == 63
+    lost = autotune.apply_mix_check(table(), 0.99, 1.0)
+    assert not lost["mix_check"]["kept"]
+    assert [(c["splitters"], c["base_threshold"], c["tile"]) for c in lost["classes"]] == \
+        [(c["splitters"], c["base_threshold"], c["tile"]) for c in autotune.default_table()["classes"]]
+    assert lost["mix_check"] == {"table_ms": 0.99, "defaults_ms": 1.0, "kept": False}
+
+
+def test_committed_table_passed_its_mix_check():
+    t = autotune.load_table()
+    mc = t["mix_check"]
+    defaults = autotune.default_table()["classes"]
+    if not mc["kept"]:
+        assert [(c["splitters"], c["base_threshold"], c["tile"]) for c in t["classes"]] == \
+            [(c["splitters"], c["base_threshold"], c["tile"]) for c in defaults]
+    else:
+        assert mc["table_ms"] < 0.98 * mc["defaults_ms"]
