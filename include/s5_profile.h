@@ -6,9 +6,8 @@
  * launched on (for the redistribution kernel the dispatch itself stamps the
  * two events, hipExtLaunchKernel, so its interval is the kernel's execution
  * with no marker packets around it); after the sort completes the elapsed
- * times are accumulated per
- * kernel together with the strings the launch processed and the algorithmic
- * bytes that implies (the per-string byte counts of each step, e.g. 24 bytes
+ * times are accumulated per kernel together with the strings the launch
+ * processed and the algorithmic bytes that implies (the per-string byte counts of each step, e.g. 24 bytes
  * of (key, index) read and written per string by a redistribution pass,
  * Section 3.1 "Parallelization": out-of-place redistribution).
  * Instrumentation only: it changes no result.  Process-wide, not thread-safe
