@@ -7,9 +7,10 @@
  * two events, hipExtLaunchKernel, so its interval is the kernel's execution
  * with no marker packets around it); after the sort completes the elapsed
  * times are accumulated per kernel together with the strings the launch
- * processed and the algorithmic bytes that implies (the per-string byte counts of each step, e.g. 24 bytes
- * of (key, index) read and written per string by a redistribution pass,
- * Section 3.1 "Parallelization": out-of-place redistribution).
+ * processed and the algorithmic bytes that implies (the per-string byte
+ * counts of each step, e.g. 24 bytes of (key, index) read and written per
+ * string by a redistribution pass, Section 3.1 "Parallelization":
+ * out-of-place redistribution).
  * Instrumentation only: it changes no result.  Process-wide, not thread-safe
  * with respect to concurrent sorts.
  */
