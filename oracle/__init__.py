@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", _SRC, "-o", tmp])
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-shared", "-fPIC", _SRC, "-o", tmp])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -54,6 +54,9 @@ def _load():
         lib.oracle_check_pairs.argtypes = [P, P, P, ctypes.c_uint32, ctypes.c_uint64, P, P, P,
                                            ctypes.c_uint64]
         lib.oracle_check_pairs.restype = ctypes.c_uint64
+        lib.oracle_check_all_pairs.argtypes = [P, P, P, ctypes.c_uint32, ctypes.c_uint64, P, P,
+                                               ctypes.c_int]
+        lib.oracle_check_all_pairs.restype = ctypes.c_uint64
         _lib = lib
     return _lib
 
@@ -120,6 +123,21 @@ def dist_prefix(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray,
                                           _ptr(lcp), perm.size))
 
 
+def keys_at(chars: np.ndarray, offsets: np.ndarray, depth: int = 0) -> np.ndarray:
+    """The 8 bytes of every string from byte ``depth`` on, packed big-endian
+    (first byte most significant) and zero from the terminator on, so that
+    unsigned key order is the lexicographic order of those bytes (Section 3.1:
+    a machine word of characters).  Requires depth <= every string's length."""
+    chars, offsets = _check(chars, offsets)
+    padded = np.concatenate([chars, np.zeros(8, dtype=np.uint8)])
+    idx = offsets.astype(np.int64)[:, None] + depth + np.arange(8)[None, :]
+    b = padded[idx].astype(np.uint64)
+    ended = np.maximum.accumulate(b == 0, axis=1)
+    b[ended] = 0
+    shifts = np.arange(56, -8, -8, dtype=np.uint64)
+    return np.bitwise_or.reduce(b << shifts[None, :], axis=1).astype(np.uint64)
+
+
 def check_perm(perm: np.ndarray, set_begin: np.ndarray | None = None) -> bool:
     """True if ``perm`` restricted to every set is a permutation of the set's
     local indices (whole-array check, any size)."""
@@ -146,3 +164,22 @@ def check_pairs(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray, lcp: n
     return int(_load().oracle_check_pairs(_ptr(chars), _ptr(offsets),
                                           None if sb is None else _ptr(sb), ns, perm.size,
                                           _ptr(perm), _ptr(lcp), _ptr(pos), pos.size))
+
+
+def check_all_pairs(chars: np.ndarray, offsets: np.ndarray, perm: np.ndarray, lcp: np.ndarray,
+                    set_begin: np.ndarray | None = None, threads: int | None = None) -> int:
+    """``check_pairs`` at every position: the number of positions whose pair is out
+    of order or whose lcp is wrong.  Together with ``check_perm`` this checks a
+    result completely (the order with ties by index is unique).  Disjoint ranges
+    of positions are checked on ``threads`` host threads (default: all cores,
+    at most 16)."""
+    chars, offsets = _check(chars, offsets)
+    perm = np.ascontiguousarray(perm, dtype=np.uint32)
+    lcp = np.ascontiguousarray(lcp, dtype=np.uint32)
+    sb = None if set_begin is None else np.ascontiguousarray(set_begin, dtype=np.uint64)
+    ns = 1 if sb is None else sb.size - 1
+    if threads is None:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    return int(_load().oracle_check_all_pairs(_ptr(chars), _ptr(offsets),
+                                              None if sb is None else _ptr(sb), ns, perm.size,
+                                              _ptr(perm), _ptr(lcp), threads))

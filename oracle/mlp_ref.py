@@ -26,9 +26,15 @@ a = sqrt(6 / fan_in) for W1, W2 and 0.1 * sqrt(6 / 32) for w3; biases start at 0
 Training: full-batch mean squared error against the empirical CDF of the sorted
 sample, t_i = (i + 0.5) / m, optimised with Adam (Kingma and Ba, 2015).
 
-Proposal: F_i = running maximum of the model over the sorted sample (a monotone
-CDF); splitter j (1 <= j <= v) is the sample key at the first i with
-F_i >= j / (v + 1), or the last sample key if there is none.
+Proposal (all comparisons in float32, the precision the kernels decide in):
+F_i = running maximum of the model's float32 outputs over the sorted sample (a
+monotone CDF).  Heavy hitters first: every run of at least two equal sample keys
+is a candidate; with c(L) the number of runs of length >= L and cap = v // 2,
+the keys of the runs of length >= L* = min{L >= 2 : c(L) <= cap} become
+splitters of their own (equality buckets, Section 3.1).  The other
+vq = v - |heavy| splitters are model quantiles: splitter j (1 <= j <= vq) is the
+sample key at the first i with F_i >= float32(j) / float32(vq + 1), or the last
+sample key if there is none.  The proposal is the sorted union of both lists.
 """
 from __future__ import annotations
 
@@ -165,20 +171,45 @@ def train(sorted_keys: np.ndarray, steps: int, lr: float, seed: int):
 
 
 def quantile_splitters(cdf: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
-    """v splitters from CDF values over the sorted sample: running maximum, then
-    for each j the sample key at the first index whose value reaches j/(v+1)."""
-    f = np.maximum.accumulate(np.asarray(cdf, dtype=np.float64))
-    q = np.arange(1, v + 1, dtype=np.float64) / (v + 1)
+    """v splitters from float32 CDF values over the sorted sample: running
+    maximum, then for each j the sample key at the first index whose value
+    reaches float32(j) / float32(v + 1) (compared in float32)."""
+    f = np.maximum.accumulate(np.asarray(cdf, dtype=np.float32))
+    q = np.arange(1, v + 1, dtype=np.float32) / np.float32(v + 1)
     idx = np.searchsorted(f, q, side="left")
     idx = np.minimum(idx, len(sorted_keys) - 1)
     return np.asarray(sorted_keys, dtype=np.uint64)[idx]
 
 
+def heavy_keys(sorted_keys: np.ndarray, v: int) -> np.ndarray:
+    """Keys of the runs of >= L* equal sample keys, ascending, where L* is the
+    smallest L >= 2 for which at most v // 2 runs are that long (so the heavy
+    hitters take at most half of the v splitters)."""
+    k = np.asarray(sorted_keys, dtype=np.uint64)
+    if k.size == 0:
+        return k
+    starts = np.flatnonzero(np.concatenate([[True], k[1:] != k[:-1]]))
+    lengths = np.diff(np.concatenate([starts, [k.size]]))
+    cap = v // 2
+    L = 2
+    while np.count_nonzero(lengths >= L) > cap:
+        L += 1
+    return k[starts[lengths >= L]]
+
+
+def propose_from_cdf(cdf: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
+    """v splitters (sorted, may repeat): the heavy hitters of the sample, then
+    model quantiles for the remaining slots (float32 CDF values given)."""
+    heavy = heavy_keys(sorted_keys, v)
+    quant = quantile_splitters(cdf, sorted_keys, v - heavy.size)
+    return np.sort(np.concatenate([heavy, quant]))
+
+
 def propose(p: np.ndarray, sorted_keys: np.ndarray, v: int) -> np.ndarray:
-    """v splitters (sorted, may repeat) at the quantiles j/(v+1) of the model's
-    monotone CDF over the sorted sample."""
+    """The proposal of model p for its own training sample (float32 model
+    outputs of the fp64 forward pass)."""
     y, _ = forward(p, features(sorted_keys, *feature_range(sorted_keys)))
-    return quantile_splitters(y, sorted_keys, v)
+    return propose_from_cdf(y.astype(np.float32), sorted_keys, v)
 
 
 def sample_imbalance(splitters: np.ndarray, sorted_keys: np.ndarray) -> int:
@@ -195,8 +226,10 @@ def sample_imbalance(splitters: np.ndarray, sorted_keys: np.ndarray) -> int:
 
 def sample_imbalanced(splitters: np.ndarray, sorted_keys: np.ndarray, v: int, beta: float) -> bool:
     """The proposal is rejected before classification if a range bucket of the
-    sample alone holds more than beta times the ideal share m / (v + 1)."""
-    return sample_imbalance(splitters, sorted_keys) > beta * len(sorted_keys) / (v + 1)
+    sample alone holds more than beta times the ideal share m / (v + 1)
+    (beta as a float32, the product in double)."""
+    b = float(np.float32(beta))
+    return sample_imbalance(splitters, sorted_keys) > b * len(sorted_keys) / (v + 1)
 
 
 def imbalanced(bucket_sizes: np.ndarray, v: int, size: int, beta: float) -> bool:

@@ -218,6 +218,30 @@ int oracle_check_perm(const uint32_t* perm, const uint64_t* set_begin, uint32_t 
     return ok;
 }
 
+/* 1 if the pair (perm[p-1], perm[p]) is out of order or lcp[p] is wrong
+ * (lcp must be 0 at a set's first slot), else 0. */
+static int pair_bad(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,
+                    uint32_t num_sets, uint64_t n, const uint32_t* perm, const uint32_t* lcp,
+                    uint64_t p) {
+    if (p >= n) return 1;
+    uint64_t b = 0, e = n;
+    if (set_begin) { /* last set starting at or before p */
+        uint32_t lo = 0, hi = num_sets - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) / 2;
+            if (set_begin[mid] <= p) lo = mid; else hi = mid - 1;
+        }
+        b = set_begin[lo];
+        e = set_begin[lo + 1];
+    }
+    if (perm[p] >= e - b) return 1;
+    if (p == b) return lcp[p] != 0;
+    if (perm[p - 1] >= e - b) return 1;
+    uint32_t x = (uint32_t)(b + perm[p - 1]), y = (uint32_t)(b + perm[p]);
+    if (!str_less(chars, offsets, x, y, 0)) return 1;
+    return lcp2(chars + offsets[x], chars + offsets[y]) != lcp[p];
+}
+
 /* Number of the given positions whose pair (perm[p-1], perm[p]) is out of
  * order or whose lcp[p] is wrong (lcp must be 0 at a set's first slot). */
 uint64_t oracle_check_pairs(const uint8_t* chars, const uint64_t* offsets,
@@ -225,37 +249,21 @@ uint64_t oracle_check_pairs(const uint8_t* chars, const uint64_t* offsets,
                             const uint32_t* perm, const uint32_t* lcp,
                             const uint64_t* positions, uint64_t count) {
     uint64_t bad = 0;
-    for (uint64_t q = 0; q < count; ++q) {
-        uint64_t p = positions[q];
-        if (p >= n) {
-            ++bad;
-            continue;
-        }
-        uint64_t b = 0, e = n;
-        if (set_begin) { /* last set starting at or before p */
-            uint32_t lo = 0, hi = num_sets - 1;
-            while (lo < hi) {
-                uint32_t mid = (lo + hi + 1) / 2;
-                if (set_begin[mid] <= p) lo = mid; else hi = mid - 1;
-            }
-            b = set_begin[lo];
-            e = set_begin[lo + 1];
-        }
-        if (perm[p] >= e - b) {
-            ++bad;
-            continue;
-        }
-        if (p == b) {
-            if (lcp[p] != 0) ++bad;
-            continue;
-        }
-        if (perm[p - 1] >= e - b) {
-            ++bad;
-            continue;
-        }
-        uint32_t x = (uint32_t)(b + perm[p - 1]), y = (uint32_t)(b + perm[p]);
-        if (!str_less(chars, offsets, x, y, 0)) ++bad;
-        else if (lcp2(chars + offsets[x], chars + offsets[y]) != lcp[p]) ++bad;
-    }
+    for (uint64_t q = 0; q < count; ++q)
+        bad += (uint64_t)pair_bad(chars, offsets, set_begin, num_sets, n, perm, lcp, positions[q]);
+    return bad;
+}
+
+/* The same check at every position 0..n-1.  Positions are independent, so
+ * disjoint ranges of them are checked by `threads` OpenMP threads (a checker
+ * only: the sorting oracle above stays sequential). */
+uint64_t oracle_check_all_pairs(const uint8_t* chars, const uint64_t* offsets,
+                                const uint64_t* set_begin, uint32_t num_sets, uint64_t n,
+                                const uint32_t* perm, const uint32_t* lcp, int threads) {
+    uint64_t bad = 0;
+    int64_t nn = (int64_t)n;
+#pragma omp parallel for num_threads(threads) reduction(+ : bad) schedule(static, 65536)
+    for (int64_t p = 0; p < nn; ++p)
+        bad += (uint64_t)pair_bad(chars, offsets, set_begin, num_sets, n, perm, lcp, (uint64_t)p);
     return bad;
 }

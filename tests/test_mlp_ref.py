@@ -132,3 +132,54 @@ def test_sample_imbalance_brute_force():
         assert mlp_ref.sample_imbalance(s, k) == max(brute)
 
 
+
+
+def test_heavy_keys_by_hand():
+    k = np.array([1, 1, 2, 3, 3, 3, 4, 5, 5], dtype=np.uint64)
+    # v = 7: at most 3 heavy hitters, and there are exactly 3 runs of >= 2
+    assert mlp_ref.heavy_keys(k, 7).tolist() == [1, 3, 5]
+    # v = 3: at most 1, so only runs of >= 3 (the single longest run) count
+    assert mlp_ref.heavy_keys(k, 3).tolist() == [3]
+    assert mlp_ref.heavy_keys(np.arange(10, dtype=np.uint64), 7).size == 0
+    assert mlp_ref.heavy_keys(np.full(10, 7, dtype=np.uint64), 7).tolist() == [7]
+    # two runs of 4, two of 2, cap 1: no length admits a single run except > 4
+    k2 = np.array([1, 1, 1, 1, 2, 2, 2, 2, 3, 3, 4, 4], dtype=np.uint64)
+    assert mlp_ref.heavy_keys(k2, 3).size == 0
+    assert mlp_ref.heavy_keys(k2, 5).tolist() == [1, 2]
+
+
+def test_heavy_keys_brute_force():
+    """The definition counted out: for every L >= 2 the runs of length >= L, the
+    smallest L with at most v // 2 of them, and the keys of those runs."""
+    rng = np.random.default_rng(8)
+    for _ in range(50):
+        m = int(rng.integers(1, 300))
+        k = np.sort(rng.integers(0, int(rng.integers(1, 200)), size=m).astype(np.uint64))
+        v = int(rng.choice([7, 15, 31, 63]))
+        counts = {}
+        for x in k.tolist():
+            counts[x] = counts.get(x, 0) + 1
+        L = 2
+        while sum(1 for c in counts.values() if c >= L) > v // 2:
+            L += 1
+        want = sorted(x for x, c in counts.items() if c >= L)
+        got = mlp_ref.heavy_keys(k, v)
+        assert got.tolist() == want
+        assert got.size <= v // 2
+
+
+def test_propose_from_cdf_by_hand():
+    # distinct keys, ideal CDF: quantiles 1/4, 1/2, 3/4 land on keys 4, 8, 12
+    keys = np.arange(16, dtype=np.uint64)
+    cdf = ((np.arange(16) + 0.5) / 16).astype(np.float32)
+    assert mlp_ref.propose_from_cdf(cdf, keys, 3).tolist() == [4, 8, 12]
+    # a run of three 20s is a heavy hitter (cap 1); the two quantiles 1/3 and
+    # 2/3 land on positions 3 (a 20) and 5 (key 40); the union keeps both 20s
+    keys = np.array([10, 20, 20, 20, 30, 40, 50, 60], dtype=np.uint64)
+    cdf = ((np.arange(8) + 0.5) / 8).astype(np.float32)
+    assert mlp_ref.propose_from_cdf(cdf, keys, 3).tolist() == [20, 20, 40]
+    # the quantile thresholds are float32 divisions: F = 1/3 in float32 reaches
+    # the first quantile exactly
+    keys = np.arange(3, dtype=np.uint64)
+    cdf = np.array([0.0, np.float32(1) / np.float32(3), 1.0], dtype=np.float32)
+    assert mlp_ref.quantile_splitters(cdf, keys, 2).tolist() == [1, 2]

@@ -234,6 +234,43 @@ def test_checkers_catch_planted_mistakes():
     assert oracle.check_pairs(chars, offs, perm, badl, allpos, sb) >= 1
 
 
+def test_check_all_pairs_equals_every_position():
+    """The threaded whole-array check counts exactly what the per-position check
+    counts over every position, on correct and on planted-bad results."""
+    chars, offs, sb, perm, lcp = _batched_case()
+    allpos = np.arange(perm.size, dtype=np.uint64)
+    for threads in (1, 3, 8):
+        assert oracle.check_all_pairs(chars, offs, perm, lcp, sb, threads=threads) == 0
+    rng = np.random.default_rng(2)
+    badl = lcp.copy()
+    hits = rng.choice(perm.size, size=17, replace=False)
+    badl[hits] += 1
+    want = oracle.check_pairs(chars, offs, perm, badl, allpos, sb)
+    assert want == 17
+    for threads in (1, 4):
+        assert oracle.check_all_pairs(chars, offs, perm, badl, sb, threads=threads) == want
+    p1, l1 = oracle.sort(chars, offs)
+    assert oracle.check_all_pairs(chars, offs, p1, l1) == 0
+    bad = p1.copy()
+    bad[[5, 6]] = bad[[6, 5]]
+    assert oracle.check_all_pairs(chars, offs, bad, l1) == \
+        oracle.check_pairs(chars, offs, bad, l1, np.arange(p1.size, dtype=np.uint64)) > 0
+
+
+def test_keys_at_by_bytes():
+    """8-byte big-endian keys written out byte by byte from the definition."""
+    rng = random.Random(4)
+    strings = [bytes(rng.choice([1, 0x41, 0x7F, 0x80, 0xFE, 0xFF]) for _ in range(rng.randint(0, 20)))
+               for _ in range(500)]
+    chars, offs = gen.from_strings(strings)
+    for depth in (0, 3):
+        sel = [i for i, x in enumerate(strings) if len(x) >= depth]
+        keys = oracle.keys_at(chars, offs[sel], depth)
+        for j, i in enumerate(sel):
+            b = strings[i][depth:depth + 8]
+            assert int(keys[j]) == int.from_bytes(b.ljust(8, b"\x00"), "big")
+
+
 def test_check_pairs_tie_break_by_index():
     # equal strings must appear in ascending input order
     chars, offs = gen.from_strings([b"same", b"same", b"other", b"same"])
