@@ -51,6 +51,7 @@ extern "C" {
 #define S5_ERR_NOMEM (-2)   /* workspace missing/too small or allocation failed */
 #define S5_ERR_HIP (-3)     /* HIP runtime error */
 #define S5_ERR_DEVICE (-4)  /* device status word set (a device-side capacity check failed) */
+#define S5_ERR_TOO_LARGE (-5) /* s5_sort_static: the sort needs more than the static scratch array */
 
 /* splitter_mode */
 #define S5_SPLIT_SAMPLED 0u /* splitters from a pseudo-random sample (Section 3.1) */
@@ -111,6 +112,29 @@ int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets
 
 /* Device workspace bytes that a sort of n strings with cfg needs. */
 size_t s5_workspace_bytes(uint32_t n, const s5_config* cfg);
+
+/* Bytes of the static scratch array of s5_sort_static (per device). */
+#define S5_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate (tight serving loops, harnesses that forbid
+ * hipMalloc or pinned host allocations): s5_sort_ex with its workspace taken
+ * from a fixed device array of S5_STATIC_SCRATCH_BYTES that the library
+ * reserves on every device it runs on until the process ends.  Allocates no
+ * device or pinned host memory (counters are read back into static host
+ * memory) and takes no profiling events.  The caller passes the inputs and
+ * the outputs as for s5_sort_ex.
+ *
+ * Limit: s5_workspace_bytes(n, cfg) <= S5_STATIC_SCRATCH_BYTES (at the
+ * defaults about 1.1M strings); a larger sort returns S5_ERR_TOO_LARGE before
+ * any device work.  All calls on one device share its array, which keeps the
+ * last call's contents (a sort clears its counters with a kernel and writes
+ * every other value before reading it).  Two sorts using the array at once
+ * would race; here every call holds the library's lock and finishes on the
+ * device before it returns, so calls from one process never overlap.
+ * Returns what s5_sort_ex returns, or S5_ERR_TOO_LARGE. */
+int s5_sort_static(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
+                   uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg,
+                   hipStream_t stream);
 
 /* Sort num_sets independent sets in one call.  Set s holds the strings
  * offsets[set_begin[s] .. set_begin[s+1]); set_begin (num_sets+1 entries,

@@ -158,8 +158,10 @@ std::unordered_map<int, DevPool> g_pools;
 struct StreamRecord {
     s5_stats stats;
     int status;
+    uint64_t seq;  // order of the sorts that wrote the records
 };
 std::unordered_map<hipStream_t, StreamRecord> g_last;
+uint64_t g_seq = 0;
 
 #define S5_HIP(call)                                   \
     do {                                               \
@@ -219,6 +221,7 @@ struct Pending {
     uint64_t items;
 };
 bool g_prof_on = false;
+thread_local bool t_quiet = false;  // no events (the sort without allocations)
 int g_prof_only = -1;  // time only this kernel (-1: all)
 ProfAcc g_prof[K_COUNT];
 std::vector<hipEvent_t> g_event_pool;
@@ -238,7 +241,7 @@ hipEvent_t prof_event() {
 // Launch `fn` on `st`, bracketed by events when profiling is on.
 template <class F>
 void timed(int k, uint64_t items, hipStream_t st, F&& fn) {
-    if (!g_prof_on || (g_prof_only >= 0 && k != g_prof_only)) {
+    if (!g_prof_on || t_quiet || (g_prof_only >= 0 && k != g_prof_only)) {
         fn();
         return;
     }
@@ -253,7 +256,7 @@ void timed(int k, uint64_t items, hipStream_t st, F&& fn) {
 // dispatch stamp them (a single kernel; no marker packets around it).
 template <class F>
 void timed_dispatch(int k, uint64_t items, hipStream_t st, F&& fn) {
-    if (!g_prof_on || (g_prof_only >= 0 && k != g_prof_only)) {
+    if (!g_prof_on || t_quiet || (g_prof_only >= 0 && k != g_prof_only)) {
         fn(nullptr, nullptr);
         return;
     }
@@ -723,16 +726,78 @@ int run_graph(const SortArgs& a, const Cfg& c, uint32_t levels, void* ws, size_t
     return rc;
 }
 
+// ---- the sort without allocations (s5_sort_static) -------------------------
+// Its workspace is this file-scope device array; each device holds its own
+// copy at its own address, looked up once per device with
+// hipGetSymbolAddress (the array's name in host code is not a device address).
+static __device__ __align__(256) unsigned char scratch[S5_STATIC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (null: not yet)
+// counters of a static sort are read back into static host memory (no pinned block)
+alignas(4096) char g_static_host[3 * kHostSlot];
+// its statistics go to a fixed table instead of the stream map
+constexpr int kStaticRecs = 16;
+struct StaticRecord {
+    hipStream_t stream;
+    StreamRecord rec;
+    bool used;
+};
+StaticRecord g_static_recs[kStaticRecs];
+
+int static_scratch(void** out) {
+    int dev = 0;
+    S5_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return S5_ERR_HIP;
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return S5_ERR_HIP;
+        }
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return S5_OK;
+}
+
+// Record the outcome of a sort for s5_stats_get (caller holds g_mu).
+void record(hipStream_t st, const s5_stats& stats, int rc, bool fixed_table) {
+    StreamRecord r{stats, rc, ++g_seq};
+    if (!fixed_table) {
+        g_last[st] = r;
+        return;
+    }
+    int slot = -1;
+    for (int i = 0; i < kStaticRecs && slot < 0; ++i)
+        if (g_static_recs[i].used && g_static_recs[i].stream == st) slot = i;
+    for (int i = 0; i < kStaticRecs && slot < 0; ++i)
+        if (!g_static_recs[i].used) slot = i;
+    if (slot < 0) {  // replace the oldest
+        slot = 0;
+        for (int i = 1; i < kStaticRecs; ++i)
+            if (g_static_recs[i].rec.seq < g_static_recs[slot].rec.seq) slot = i;
+    }
+    g_static_recs[slot] = StaticRecord{st, r, true};
+}
+
+// Where a sort's workspace comes from.
+enum class WsFrom { Pool, Caller, Static };
+
 int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_bytes,
-                hipStream_t st, bool graph) {
+                hipStream_t st, bool graph, WsFrom from) {
     Cfg c;
     int rc = resolve_cfg(cfg, &c);
     if (rc) return rc;
+    if (from == WsFrom::Static &&
+        make_layout(a.n, c, 0).total > (size_t)S5_STATIC_SCRATCH_BYTES)
+        return S5_ERR_TOO_LARGE;
     if (a.n == 0) {
         std::lock_guard<std::mutex> g(g_mu);
-        StreamRecord& r = g_last[st];
-        memset(&r.stats, 0, sizeof r.stats);
-        r.status = S5_OK;
+        s5_stats z;
+        memset(&z, 0, sizeof z);
+        record(st, z, S5_OK, from == WsFrom::Static);
         return S5_OK;
     }
     // per-set parameters raise the launch-wide limits they must fit in
@@ -748,7 +813,12 @@ int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_byt
     std::lock_guard<std::mutex> g(g_mu);
     const size_t need = make_layout(a.n, c, a.tune_host ? a.num_sets : 0u).total;
     void* host = nullptr;
-    if (!ws) {
+    if (from == WsFrom::Static) {
+        rc = static_scratch(&ws);
+        if (rc) return rc;
+        ws_bytes = S5_STATIC_SCRATCH_BYTES;
+        host = g_static_host;
+    } else if (from == WsFrom::Pool) {
         DevPool* P = nullptr;
         rc = pool_get(need, &P);
         if (rc) return rc;
@@ -762,11 +832,11 @@ int sort_common(const SortArgs& a, const s5_config* cfg, void* ws, size_t ws_byt
         host = P->host;
     }
     s5_stats stats;
+    t_quiet = from == WsFrom::Static;
     rc = graph ? run_graph(a, c, c.graph_levels, ws, ws_bytes, host, st, &stats)
                : run_sort(a, c, ws, ws_bytes, host, st, &stats);
-    StreamRecord& r = g_last[st];
-    r.stats = stats;
-    r.status = rc;
+    t_quiet = false;
+    record(st, stats, rc, from == WsFrom::Static);
     return rc;
 }
 
@@ -781,7 +851,18 @@ int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
     if (n == 0xFFFFFFFFu) return S5_ERR_INVALID;
     SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
-    return sort_common(a, cfg, workspace, workspace_bytes, stream, false);
+    return sort_common(a, cfg, workspace, workspace_bytes, stream, false,
+                       workspace ? WsFrom::Caller : WsFrom::Pool);
+}
+
+int s5_sort_static(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
+                   uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg,
+                   hipStream_t stream) {
+    (void)chars_len;
+    if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
+    if (n == 0xFFFFFFFFu) return S5_ERR_INVALID;
+    SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
+    return sort_common(a, cfg, nullptr, 0, stream, false, WsFrom::Static);
 }
 
 int s5_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t* out_perm,
@@ -832,7 +913,7 @@ int s5_sort_batched_tuned(const uint8_t* chars, uint64_t chars_len, const uint64
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
     SortArgs a{chars, offsets, set_begin, num_sets, n, out_perm, out_lcp,
                set_tuning ? packed.data() : nullptr};
-    return sort_common(a, cfg, nullptr, 0, stream, true);
+    return sort_common(a, cfg, nullptr, 0, stream, true, WsFrom::Pool);
 }
 
 int s5_sort_batched(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
@@ -846,13 +927,17 @@ int s5_stats_get(hipStream_t stream, s5_stats* host_out) {
     if (!host_out) return S5_ERR_INVALID;
     if (hipStreamSynchronize(stream) != hipSuccess) return S5_ERR_HIP;
     std::lock_guard<std::mutex> g(g_mu);
+    const StreamRecord* r = nullptr;
     auto it = g_last.find(stream);
-    if (it == g_last.end()) {
+    if (it != g_last.end()) r = &it->second;
+    for (const StaticRecord& s : g_static_recs)  // the newest record of the stream wins
+        if (s.used && s.stream == stream && (!r || s.rec.seq > r->seq)) r = &s.rec;
+    if (!r) {
         memset(host_out, 0, sizeof *host_out);
         return S5_OK;
     }
-    *host_out = it->second.stats;
-    return it->second.status == S5_ERR_DEVICE ? S5_ERR_DEVICE : S5_OK;
+    *host_out = r->stats;
+    return r->status == S5_ERR_DEVICE ? S5_ERR_DEVICE : S5_OK;
 }
 
 const char* s5_strerror(int status) {
@@ -862,6 +947,7 @@ const char* s5_strerror(int status) {
         case S5_ERR_NOMEM: return "workspace missing, too small, or device allocation failed";
         case S5_ERR_HIP: return "HIP runtime error";
         case S5_ERR_DEVICE: return "device-side capacity check failed";
+        case S5_ERR_TOO_LARGE: return "sort needs more than the static scratch array";
         default: return "unknown status";
     }
 }

@@ -15,9 +15,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libs5.so")
 
 S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP, S5_ERR_DEVICE = 0, -1, -2, -3, -4
+S5_ERR_TOO_LARGE = -5
+STATIC_SCRATCH_BYTES = 64 << 20  # S5_STATIC_SCRATCH_BYTES
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 
-EXPORTS = ("s5_sort", "s5_sort_ex", "s5_workspace_bytes", "s5_sort_batched",
+EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_sort_batched",
            "s5_sort_batched_tuned", "s5_stats_get",
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
            "s5_profile_only",
@@ -73,6 +75,7 @@ def load(path: str = LIB_PATH):
     P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
     lib.s5_sort.argtypes = [P, P, U32, P, P, P]
     lib.s5_sort_ex.argtypes = [P, U64, P, U32, P, P, ctypes.POINTER(Config), P, ctypes.c_size_t, P]
+    lib.s5_sort_static.argtypes = [P, U64, P, U32, P, P, ctypes.POINTER(Config), P]
     lib.s5_workspace_bytes.argtypes = [U32, ctypes.POINTER(Config)]
     lib.s5_workspace_bytes.restype = ctypes.c_size_t
     lib.s5_sort_batched.argtypes = [P, U64, P, P, U32, P, P, ctypes.POINTER(Config), P]
@@ -92,7 +95,7 @@ def load(path: str = LIB_PATH):
     lib.s5_profile_only.argtypes = [ctypes.c_char_p]
     lib.s5_profile_only.restype = ctypes.c_int
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
-    for f in ("s5_sort", "s5_sort_ex", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
+    for f in ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
               "s5_prefix_keys",
               "s5_classify", "s5_profile_enable", "s5_profile_read", "s5_mlp_train", "s5_mlp_grad",
               "s5_mlp_eval"):
@@ -150,6 +153,19 @@ def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,
                         ctypes.byref(cfg) if cfg is not None else None, ws, wsb, _stream(stream))
     _check(rc)
     return out_perm, out_lcp
+
+
+def sort_static(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tensor,
+                out_lcp: torch.Tensor, cfg: Config | None = None, stream=None) -> int:
+    """``s5_sort_static``: the sort with its workspace in the library's static
+    scratch array (no allocation).  The caller passes the outputs; returns the
+    status code (``S5_ERR_TOO_LARGE`` if the sort does not fit the array)."""
+    return int(load().s5_sort_static(_dev(chars, torch.uint8, "chars"), chars.numel(),
+                                     _dev(offsets, torch.uint64, "offsets"), offsets.numel(),
+                                     _dev(out_perm, torch.uint32, "out_perm"),
+                                     _dev(out_lcp, torch.uint32, "out_lcp"),
+                                     ctypes.byref(cfg) if cfg is not None else None,
+                                     _stream(stream)))
 
 
 def sort_plain(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tensor,

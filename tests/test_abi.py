@@ -38,8 +38,8 @@ def test_every_declared_symbol_exported(lib):
 
 
 def test_strerror(lib):
-    for rc in (0, -1, -2, -3, -4):
-        assert lib.s5_strerror(rc)
+    for rc in (0, -1, -2, -3, -4, -5):
+        assert lib.s5_strerror(rc) and lib.s5_strerror(rc) != b"unknown status"
     assert lib.s5_strerror(-99) == b"unknown status"
 
 
@@ -55,3 +55,18 @@ def test_workspace_bytes(lib):
     assert s5.workspace_bytes(1000, s5.make_config(base_threshold=4096)) == 0
     assert s5.workspace_bytes(1000, s5.make_config(unroll=3)) == 0
     assert s5.workspace_bytes(1000, s5.make_config(splitters=1023, unroll=8)) > 0
+
+
+def test_static_sort_size_limit_is_host_logic(lib):
+    """s5_sort_static rejects a sort whose workspace exceeds its static array
+    before any device work (the pointers are never touched, so this runs
+    without a GPU)."""
+    from paper_1305_1157_amd import s5
+    n = 2_000_000
+    assert s5.workspace_bytes(n) > s5.STATIC_SCRATCH_BYTES >= s5.workspace_bytes(1_000_000)
+    fake = 4096  # never dereferenced: the size check comes first
+    assert lib.s5_sort_static(fake, 0, fake, n, fake, fake, None, None) == s5.S5_ERR_TOO_LARGE
+    cfg = s5.make_config(base_threshold=64)
+    assert lib.s5_sort_static(fake, 0, fake, 1_000_000, fake, fake, cfg, None) == \
+        s5.S5_ERR_TOO_LARGE
+    assert lib.s5_sort_static(None, 0, None, 5, None, None, None, None) == s5.S5_ERR_INVALID
