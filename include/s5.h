@@ -26,8 +26,10 @@
  *     out_perm[i-1] and out_perm[i], not counting the terminator.
  *   - Every call is ordered on `stream` (a hipStream_t of the caller's HIP
  *     runtime; 0 = the null stream).  Sorting waits on `stream` between
- *     recursion levels, so a call returns when its results are complete on
- *     the device side of `stream`.
+ *     recursion levels (the host reads one small counter block per level to
+ *     size the next launches), so a sort call returns when its results are
+ *     complete on the device side of `stream`; it cannot be captured into a
+ *     caller's graph (s5_sort_batched captures and replays its own).
  *   - The caller owns every input, output and user workspace; the library
  *     owns only its internal workspace pool, freed by s5_release().
  *   - Inputs are never written.  Outputs may not alias inputs.
@@ -105,7 +107,11 @@ int s5_sort(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t*
 
 /* As s5_sort with explicit tuning and, optionally, a caller workspace of
  * workspace_bytes >= s5_workspace_bytes(n, cfg) (NULL = internal pool).
- * chars_len (bytes in the arena; 0 = unknown) is only used for argument checks. */
+ * chars_len: bytes in the arena, or 0 = unknown.  When it is given, the device
+ * checks that every offsets[i] < chars_len and that chars[chars_len - 1] is a
+ * terminator (so every string ends inside the arena); a failed check stops
+ * the sort before anything is written to out_perm or out_lcp beyond what a
+ * set's first slot receives, and returns S5_ERR_INVALID. */
 int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
                uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg, void* workspace,
                size_t workspace_bytes, hipStream_t stream);
@@ -140,7 +146,10 @@ int s5_sort_static(const uint8_t* chars, uint64_t chars_len, const uint64_t* off
  * offsets[set_begin[s] .. set_begin[s+1]); set_begin (num_sets+1 entries,
  * DEVICE memory, non-decreasing, set_begin[0] = 0) fixes where each set's
  * results go: out_perm holds set-local indices and out_lcp is 0 at every
- * set's first slot.  n = set_begin[num_sets] < 2^32.
+ * set's first slot.  n = set_begin[num_sets] < 2^32.  The device checks the
+ * table (set_begin[s] <= set_begin[s+1] <= n for every s); a set that fails
+ * is not sorted or written, and the call returns S5_ERR_INVALID.  chars_len
+ * is checked as for s5_sort_ex.
  *
  * All sets are sorted together: every distribution pass covers the segments
  * of every set (the segmented form of the level-by-level recursion of

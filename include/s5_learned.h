@@ -58,6 +58,32 @@ int s5_mlp_grad(const float* params, const uint64_t* sorted_keys, uint32_t m, fl
 int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo, uint64_t hi,
                 float* out, hipStream_t stream);
 
+/* The splitter proposal of model `params` for its own sorted training sample
+ * (256 <= m <= 4096, m a multiple of 256; 1 <= v <= 1023; features scaled by
+ * the sample's byte-wise range as in training), the code the sort runs on
+ * every learned segment:
+ *   1. F_i = running maximum of the model outputs over the sample (a monotone
+ *      estimate of the distribution function); out_cdf[i] receives the
+ *      outputs themselves (before the running maximum), m floats;
+ *   2. heavy hitters: the keys of runs of >= L* equal sample keys, L* the
+ *      smallest L >= 2 with at most v/2 such runs, are splitters of their own,
+ *      so each becomes an equality bucket (Section 3.1, equality buckets;
+ *      appendix A, "Adaptivity": inspecting the sample);
+ *   3. the other vq = v - (number of heavy keys) splitters are quantiles:
+ *      splitter j (1 <= j <= vq) is the sample key at the first i with
+ *      F_i >= j / (vq + 1), compared in float32, else the last sample key;
+ *   4. out_splitters (v uint64) = both lists merged in ascending order
+ *      (repeats allowed: equal splitters leave empty range buckets);
+ *   5. *out_reject (one uint32) = 1 if some range bucket of the sample itself
+ *      (keys strictly between neighbouring splitters, or outside them) holds
+ *      more than beta * m / (v + 1) keys, else 0; the sort then uses sampled
+ *      splitters for that segment.
+ * Asynchronous; returns S5_OK, S5_ERR_INVALID (bad m or v, NULL pointer,
+ * beta <= 0) or S5_ERR_HIP. */
+int s5_mlp_propose(const float* params, const uint64_t* sorted_keys, uint32_t m, uint32_t v,
+                   float beta, uint64_t* out_splitters, float* out_cdf, uint32_t* out_reject,
+                   hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,18 +27,34 @@ def _run(cmd):
     return r.stdout
 
 
+# the write-check build: the same library with every output write counted
+# (s5_debug_count_writes); used by the tests only
+OUT_WCHECK = os.path.join(PKG, "libs5_wcheck.so")
+
+
+def _compile(src, extra=(), tag=""):
+    obj = os.path.join(BUILD_DIR, src + tag + ".o")
+    out = _run([HIPCC, "-x", "hip", *DEVICE_FLAGS, *extra, "-c", os.path.join(CSRC, src),
+                "-o", obj])
+    return obj, out
+
+
+def _link(objs, out):
+    tmp = out + ".tmp"
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
+    os.replace(tmp, out)
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    objs = []
-    for src, lang in (("s5_kernels.hip", "hip"), ("s5_learn.hip", "hip"), ("s5_host.cpp", "hip")):
-        obj = os.path.join(BUILD_DIR, src + ".o")
-        out = _run([HIPCC, "-x", lang, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+    objs = {}
+    for src in ("s5_kernels.hip", "s5_learn.hip", "s5_host.cpp"):
+        objs[src], out = _compile(src)
         if verbose and out.strip():
             print(out)
-        objs.append(obj)
-    tmp = OUT + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp])
-    os.replace(tmp, OUT)
+    _link(list(objs.values()), OUT)
+    wc, _ = _compile("s5_kernels.hip", ("-DS5_COUNT_WRITES",), ".wcheck")
+    _link([wc, objs["s5_learn.hip"], objs["s5_host.cpp"]], OUT_WCHECK)
     return OUT
 
 

@@ -20,6 +20,7 @@
 #include "../../include/s5.h"
 #include "../../include/s5_profile.h"
 #include "../../include/s5_learned.h"
+#include "../../include/s5_debug.h"
 #include "s5_internal.h"
 
 #include "s5_launch.h"
@@ -74,6 +75,13 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// test-only limits of device capacities (0 = none), s5_debug_limit_capacity
+uint32_t g_cap_limit[5];
+
+uint32_t limited(uint32_t cap, uint32_t which) {
+    return g_cap_limit[which] ? std::min(cap, g_cap_limit[which]) : cap;
+}
+
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
     size_t key[2], key2[2], key3, idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
@@ -102,6 +110,8 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     cp.base[1] = (uint32_t)(n / (kBaseWave + 1) + 2);
     cp.base[2] = (uint32_t)(n / (kBaseSmall + 1) + 2);
     cp.base[3] = (uint32_t)(n / (kBaseMid + 1) + 2);
+    cp.large = limited(cp.large, S5_CAP_LARGE);
+    for (int q = 0; q < kBaseClasses; ++q) cp.base[q] = limited(cp.base[q], S5_CAP_BASE0 + q);
     // sum over segments of tiles x k: tiles_s <= |S|/tile_min + 1 and
     // k_s <= max(3, min(kmax, 8 |S| / T))
     const uint64_t ksum = 3 * large + 8 * n / c.T_caps + kmax;
@@ -291,6 +301,7 @@ void prof_collect() {
 
 struct SortArgs {
     const uint8_t* chars;
+    uint64_t chars_len;  // 0 = unknown (no device-side argument checks)
     const uint64_t* offsets;
     const uint64_t* set_begin;  // device, or null for a single set
     uint32_t num_sets, n;
@@ -465,7 +476,8 @@ void clear_counters(const Ptrs& P, hipStream_t st) {
 void start_sort(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P, hipStream_t st) {
     clear_counters(P, st);
     timed(K_INIT, a.n, st, [&] {
-        launch_init_keys(a.chars, a.offsets, a.n, P.key[0], P.key2[0], P.key3, P.idx[0], st);
+        launch_init_keys(a.chars, a.chars_len, a.offsets, a.n, P.key[0], P.key2[0], P.key3,
+                         P.idx[0], P.glob, st);
     });
     timed(K_ROOTS, a.num_sets, st, [&] {
         launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, plan_ctx(P, L, c, a, 0), st);
@@ -484,6 +496,12 @@ HostView host_view(void* host) {
                     (Globals*)((char*)host + 2 * kHostSlot)};
 }
 
+// Return code of a device status word: argument checks first.
+int status_rc(uint32_t status) {
+    if (status & kErrArgs) return S5_ERR_INVALID;
+    return status ? S5_ERR_DEVICE : S5_OK;
+}
+
 // Copy a pass's counters together with the globals and wait for them.
 int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
     char* src = which == 0 ? (char*)P.cnt[0] : (char*)P.glob;
@@ -492,7 +510,7 @@ int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
     const char* hb = (const char*)H.host;
     memcpy(H.hc, which == 0 ? hb : hb + sizeof(Globals), sizeof(Counters));
     memcpy(H.hg, which == 0 ? hb + sizeof(Counters) : hb, sizeof(Globals));
-    return H.hg->status ? S5_ERR_DEVICE : S5_OK;
+    return status_rc(H.hg->status);
 }
 
 // Host-driven passes from `level` on (counters of the pass about to run in
@@ -537,7 +555,7 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     });
     timed(K_LCPFIX, a.n, st, [&] {
         launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, nullptr,
-                       st);
+                       P.glob, st);
     });
     S5_HIP(hipGetLastError());
     return S5_OK;
@@ -567,7 +585,7 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
         S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
         S5_HIP(hipStreamSynchronize(st));
         final_stats(H, stats);
-        rc = H.hg->status ? S5_ERR_DEVICE : S5_OK;
+        rc = status_rc(H.hg->status);
     }
     prof_collect();
     return rc;
@@ -583,6 +601,7 @@ int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* h
 struct GraphKey {
     const void *chars, *offsets, *set_begin, *perm, *lcp, *ws;
     size_t ws_bytes;
+    uint64_t chars_len;
     uint32_t num_sets, n, levels, tuned;
     Cfg c;
     int dev;
@@ -627,7 +646,8 @@ void enqueue_graph_body(const SortArgs& a, const Cfg& c, const Layout& L, const 
     const uint32_t zero[kBaseClasses] = {};
     launch_base_sort(zero, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
                      a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard, st);
-    launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, guard, st);
+    launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, guard, P.glob,
+                   st);
 }
 
 int get_graph(const GraphKey& key, const SortArgs& a, const Cfg& c, const Layout& L,
@@ -679,6 +699,7 @@ int run_graph(const SortArgs& a, const Cfg& c, uint32_t levels, void* ws, size_t
     GraphKey key;
     memset(&key, 0, sizeof key);
     key.chars = a.chars;
+    key.chars_len = a.chars_len;
     key.offsets = a.offsets;
     key.set_begin = a.set_begin;
     key.perm = a.perm;
@@ -720,7 +741,7 @@ int run_graph(const SortArgs& a, const Cfg& c, uint32_t levels, void* ws, size_t
         S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
         S5_HIP(hipStreamSynchronize(st));
         final_stats(H, stats);
-        rc = H.hg->status ? S5_ERR_DEVICE : S5_OK;
+        rc = status_rc(H.hg->status);
     }
     prof_collect();
     return rc;
@@ -847,10 +868,9 @@ extern "C" {
 int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
                uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg, void* workspace,
                size_t workspace_bytes, hipStream_t stream) {
-    (void)chars_len;
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
     if (n == 0xFFFFFFFFu) return S5_ERR_INVALID;
-    SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
+    SortArgs a{chars, chars_len, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
     return sort_common(a, cfg, workspace, workspace_bytes, stream, false,
                        workspace ? WsFrom::Caller : WsFrom::Pool);
 }
@@ -858,10 +878,9 @@ int s5_sort_ex(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets
 int s5_sort_static(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets, uint32_t n,
                    uint32_t* out_perm, uint32_t* out_lcp, const s5_config* cfg,
                    hipStream_t stream) {
-    (void)chars_len;
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
     if (n == 0xFFFFFFFFu) return S5_ERR_INVALID;
-    SortArgs a{chars, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
+    SortArgs a{chars, chars_len, offsets, nullptr, 1u, n, out_perm, out_lcp, nullptr};
     return sort_common(a, cfg, nullptr, 0, stream, false, WsFrom::Static);
 }
 
@@ -880,7 +899,6 @@ int s5_sort_batched_tuned(const uint8_t* chars, uint64_t chars_len, const uint64
                           const uint64_t* set_begin, uint32_t num_sets,
                           const s5_set_tuning* set_tuning, uint32_t* out_perm, uint32_t* out_lcp,
                           const s5_config* cfg, hipStream_t stream) {
-    (void)chars_len;
     if (num_sets == 0) return S5_OK;
     if (!set_begin || num_sets == 0xFFFFFFFFu) return S5_ERR_INVALID;
     Cfg base;
@@ -911,7 +929,7 @@ int s5_sort_batched_tuned(const uint8_t* chars, uint64_t chars_len, const uint64
     if (ends[0] != 0 || ends[1] >= 0xFFFFFFFFull) return S5_ERR_INVALID;
     const uint32_t n = (uint32_t)ends[1];
     if (n > 0 && (!chars || !offsets || !out_perm || !out_lcp)) return S5_ERR_INVALID;
-    SortArgs a{chars, offsets, set_begin, num_sets, n, out_perm, out_lcp,
+    SortArgs a{chars, chars_len, offsets, set_begin, num_sets, n, out_perm, out_lcp,
                set_tuning ? packed.data() : nullptr};
     return sort_common(a, cfg, nullptr, 0, stream, true, WsFrom::Pool);
 }
@@ -1071,6 +1089,37 @@ int s5_mlp_grad(const float* params, const uint64_t* sorted_keys, uint32_t m, fl
     launch_mlp_grad(learn_ctx(P->ptr, 1, m), params, sorted_keys, m, out_grad, stream);
     if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
     return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;
+}
+
+int s5_debug_limit_capacity(uint32_t which, uint32_t limit) {
+    if (which > S5_CAP_BASE3) return S5_ERR_INVALID;
+    std::lock_guard<std::mutex> g(g_mu);
+    g_cap_limit[which] = limit;
+    graphs_release();  // their layouts were planned with the old capacities
+    return S5_OK;
+}
+
+int s5_debug_count_writes(uint32_t* perm, uint32_t* lcp, uint64_t n, uint32_t* perm_counts,
+                          uint32_t* lcp_counts, uint32_t* stray) {
+    if (perm_counts && (!perm || !lcp || !lcp_counts || !stray)) return S5_ERR_INVALID;
+    WriteCount w;
+    w.perm_base = perm;
+    w.lcp_base = lcp;
+    w.perm_cnt = perm_counts;
+    w.lcp_cnt = perm_counts ? lcp_counts : nullptr;
+    w.stray = perm_counts ? stray : nullptr;
+    w.n = n;
+    std::lock_guard<std::mutex> g(g_mu);
+    return set_write_count(w) ? S5_OK : S5_ERR_INVALID;
+}
+
+int s5_mlp_propose(const float* params, const uint64_t* sorted_keys, uint32_t m, uint32_t v,
+                   float beta, uint64_t* out_splitters, float* out_cdf, uint32_t* out_reject,
+                   hipStream_t stream) {
+    if (!params || !sorted_keys || !out_splitters || !out_cdf || !out_reject) return S5_ERR_INVALID;
+    if (mlp_check_m(m) || v < 1 || v > 1023 || !(beta > 0.0f)) return S5_ERR_INVALID;
+    launch_mlp_propose(params, sorted_keys, m, v, beta, out_splitters, out_cdf, out_reject, stream);
+    return hipGetLastError() == hipSuccess ? S5_OK : S5_ERR_HIP;
 }
 
 int s5_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo, uint64_t hi,

@@ -23,6 +23,10 @@ constexpr uint32_t kBufBit = 0x80000000u;   // work-buffer bit packed into a dep
 // status-word bits (device side capacity checks)
 constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrTileCap = 4u, kErrCmCap = 8u,
                    kErrTreeCap = 16u;
+// an argument the device checks is invalid (an offset at or past chars_len, an
+// arena whose last byte is not a terminator, a set table that is not
+// non-decreasing or ends past n): reported as S5_ERR_INVALID
+constexpr uint32_t kErrArgs = 32u;
 
 // A bucket that still has to be sorted.
 struct Seg {
@@ -172,6 +176,40 @@ __device__ inline SetP set_params(const PlanCtx& c, uint32_t base) {
     }
     return unpack_set_tune(c.set_tune[lo]);
 }
+
+// Writes of the sort's outputs (out_perm, out_lcp) go through S5_OUT.  The
+// write-check build (S5_COUNT_WRITES) also counts, per output slot, how often
+// it is written, and counts writes that land in neither output; the product
+// build compiles S5_OUT to the plain store.
+struct WriteCount {
+    uint32_t* perm_base;  // the sort's out_perm and out_lcp
+    uint32_t* lcp_base;
+    uint32_t* perm_cnt;   // n counters each (null: counting off)
+    uint32_t* lcp_cnt;
+    uint32_t* stray;      // one counter: writes outside both outputs
+    unsigned long long n;
+};
+#ifdef S5_COUNT_WRITES
+extern __device__ WriteCount g_wc;
+__device__ inline void wc_note(const uint32_t* p) {
+    const WriteCount w = g_wc;
+    if (!w.perm_cnt) return;
+    if (p >= w.perm_base && p < w.perm_base + w.n)
+        atomicAdd(&w.perm_cnt[p - w.perm_base], 1u);
+    else if (p >= w.lcp_base && p < w.lcp_base + w.n)
+        atomicAdd(&w.lcp_cnt[p - w.lcp_base], 1u);
+    else
+        atomicAdd(w.stray, 1u);
+}
+#define S5_OUT(slot, value)                \
+    do {                                   \
+        uint32_t* s5p_ = &(slot);          \
+        *s5p_ = (value);                   \
+        ::s5::wc_note(s5p_);               \
+    } while (0)
+#else
+#define S5_OUT(slot, value) ((slot) = (value))
+#endif
 
 // Work units of one launch.  A host-driven launch sizes its grid to the work
 // (wcnt == nullptr: the grid is the count).  A graph-captured launch reads the

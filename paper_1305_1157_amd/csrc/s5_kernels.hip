@@ -353,14 +353,27 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
 // ---------------------------------------------------------------------------
 // K1: prefix cache at depth 0 (and the building-block entry point)
 
-__global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, const uint64_t* offsets,
-                                                   uint32_t n, uint64_t* key, uint64_t* key2,
-                                                   uint64_t* key3, uint32_t* idx) {
+__global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, uint64_t chars_len,
+                                                   const uint64_t* offsets, uint32_t n,
+                                                   uint64_t* key, uint64_t* key2, uint64_t* key3,
+                                                   uint32_t* idx, Globals* glob) {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     idx[i] = i;
+    const uint64_t off = offsets[i];
+    if (chars_len) {
+        // with the arena's length known: every string starts inside it and the
+        // arena ends with a terminator, so every string ends inside it
+        const bool bad = off >= chars_len || (i == 0 && chars[chars_len - 1] != 0);
+        if (bad) {
+            atomicOr(&glob->status, kErrArgs);
+            key[i] = 0;
+            key2[i] = 0;
+            return;
+        }
+    }
     uint64_t w[3];
-    load_key_run<3>(chars, offsets[i], w);
+    load_key_run<3>(chars, off, w);
     key[i] = w[0];
     key2[i] = w[1];
     // the third word is all zero (and never read) unless the string
@@ -383,11 +396,17 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
     const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t b = 0, e = 0;
     if (s < num_sets) {
-        b = set_begin ? (uint32_t)set_begin[s] : 0u;
-        e = set_begin ? (uint32_t)set_begin[s + 1] : n;
+        const uint64_t b64 = set_begin ? set_begin[s] : 0u, e64 = set_begin ? set_begin[s + 1] : n;
+        if (b64 > e64 || e64 > n) {
+            // not a non-decreasing table within n: nothing of this set is written
+            atomicOr(&ctx.glob->status, kErrArgs);
+        } else {
+            b = (uint32_t)b64;
+            e = (uint32_t)e64;
+        }
         if (e > b) {
-            out_lcp[b] = 0;
-            if (e - b == 1) out_perm[b] = 0;
+            S5_OUT(out_lcp[b], 0u);
+            if (e - b == 1) S5_OUT(out_perm[b], 0u);
         }
     }
     const bool req = e > b + 1;
@@ -1015,14 +1034,14 @@ __device__ __forceinline__ void scatter_body(
             const uint32_t dr = base[b] + s - tstart[b];
             const uint32_t dest = g.begin + dr;
             const uint32_t s0 = bst[b];
-            if (dr == s0 && dr != 0) out_lcp[dest] = kLcpFlag | g.depth;
+            if (dr == s0 && dr != 0) S5_OUT(out_lcp[dest], kLcpFlag | g.depth);
             const uint32_t mode = binfo[b] >> 4;
             if (mode == kModeLive) {
                 key_out[dest] = SK[s];
                 idx_out[dest] = SI[s];
             } else {
-                out_perm[dest] = SI[s] - g.base;
-                if (mode == kModeIdentical && dr != s0) out_lcp[dest] = g.depth + ident[b];
+                S5_OUT(out_perm[dest], SI[s] - g.base);
+                if (mode == kModeIdentical && dr != s0) S5_OUT(out_lcp[dest], g.depth + ident[b]);
             }
         }
         __syncthreads();
@@ -1192,7 +1211,7 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
             if (kp == k && !has_zero(k))
                 und = true;
             else
-                olcp[pos] = h + lcp8(kp, k);
+                S5_OUT(olcp[pos], h + lcp8(kp, k));
         }
         const uint64_t U = __ballot(und);
         if (!U) break;
@@ -1239,7 +1258,7 @@ __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
     wave_sort(k, a);
     const uint32_t fa = wave_rounds(k, a, valid, h, lane, offl[threadIdx.x >> 6], n, iin, chars,
                                     offsets, out_lcp + it.begin);
-    if (valid) out_perm[it.begin + lane] = iin[fa & 0xFFFFu] - it.base;
+    if (valid) S5_OUT(out_perm[it.begin + lane], iin[fa & 0xFFFFu] - it.base);
 }
 
 // One wavefront per item (items are wavefront-uniform; no workgroup barriers).
@@ -1496,7 +1515,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             if (x == y && !has_zero(y))
                 un = 1;
             else
-                olcp[i] = h + lcp8(x, y);
+                S5_OUT(olcp[i], h + lcp8(x, y));
         }
         F[i] = un;
         any |= un;
@@ -1636,12 +1655,12 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
                 any = 1;
             } else {
                 F[i] = 0;
-                olcp[i] = h + lcp8(x, y);
+                S5_OUT(olcp[i], h + lcp8(x, y));
             }
         }
         any = __syncthreads_or(any);
     }
-    for (uint32_t i = tid; i < n; i += NT) out_perm[it.begin + i] = IDX[A[i] & 0xFFFFu] - it.base;
+    for (uint32_t i = tid; i < n; i += NT) S5_OUT(out_perm[it.begin + i], IDX[A[i] & 0xFFFFu] - it.base);
 }
 
 template <int EMAX, bool G, int NT>
@@ -1673,8 +1692,11 @@ __global__ __launch_bounds__(NT, EMAX <= 4 ? 4 : 1) void k_base_block(const Seg*
 __global__ __launch_bounds__(256) void k_lcp_fix(const uint8_t* chars, const uint64_t* offsets,
                                                  const uint64_t* set_begin, uint32_t num_sets,
                                                  uint32_t n, const uint32_t* out_perm,
-                                                 uint32_t* out_lcp, const uint32_t* guard) {
+                                                 uint32_t* out_lcp, const uint32_t* guard,
+                                                 const Globals* glob) {
     if (guard && *guard) return;  // large segments remain: the host finishes them first
+    // after a failed device-side check, perm slots may be unwritten: read none
+    if (glob->status) return;
     uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p == 0 || p >= n) return;
     uint32_t l = out_lcp[p];
@@ -1705,7 +1727,7 @@ __global__ __launch_bounds__(256) void k_lcp_fix(const uint8_t* chars, const uin
         oa += 8;
         ob += 8;
     }
-    out_lcp[p] = h;
+    S5_OUT(out_lcp[p], h);
 }
 
 // ---------------------------------------------------------------------------
@@ -1754,6 +1776,22 @@ __global__ __launch_bounds__(256) void k_classify_plain(const uint64_t* keys, ui
 }
 
 // ---------------------------------------------------------------------------
+// write counting (write-check build only)
+
+#ifdef S5_COUNT_WRITES
+__device__ WriteCount g_wc;
+#endif
+
+bool set_write_count(const WriteCount& w) {
+#ifdef S5_COUNT_WRITES
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_wc), &w, sizeof w) == hipSuccess;
+#else
+    (void)w;
+    return false;
+#endif
+}
+
+// ---------------------------------------------------------------------------
 // host-side launchers.  Dyn selects the launch mode: host-driven (cnt ==
 // nullptr; the grid is the work the host read back) or graph mode (a fixed
 // grid that strides over the count at cnt, clamped to cap).
@@ -1765,11 +1803,12 @@ static inline uint32_t dyn_grid(const Dyn& dy, uint32_t host_units) {
     return dy.cnt ? dy.grid : host_units;
 }
 
-void launch_init_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint64_t* key,
-                      uint64_t* key2, uint64_t* key3, uint32_t* idx, hipStream_t st) {
+void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                      uint32_t n, uint64_t* key, uint64_t* key2, uint64_t* key3, uint32_t* idx,
+                      Globals* glob, hipStream_t st) {
     if (!n) return;
-    S5_LAUNCH(k_init_keys, dim3((n + 255) / 256), dim3(256), 0, st, chars, offsets, n, key, key2,
-              key3, idx);
+    S5_LAUNCH(k_init_keys, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len, offsets, n,
+              key, key2, key3, idx, glob);
 }
 
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
@@ -1963,10 +2002,10 @@ void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t
 
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,
                     uint32_t num_sets, uint32_t n, const uint32_t* out_perm, uint32_t* out_lcp,
-                    const uint32_t* guard, hipStream_t st) {
+                    const uint32_t* guard, const Globals* glob, hipStream_t st) {
     if (n < 2) return;
     S5_LAUNCH(k_lcp_fix, dim3((n + 255) / 256), dim3(256), 0, st, chars, offsets, set_begin,
-              num_sets, n, out_perm, out_lcp, guard);
+              num_sets, n, out_perm, out_lcp, guard, glob);
 }
 
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,

@@ -10,8 +10,9 @@
 
 namespace s5 {
 
-void launch_init_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint64_t* key,
-                      uint64_t* key2, uint64_t* key3, uint32_t* idx, hipStream_t st);
+void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                      uint32_t n, uint64_t* key, uint64_t* key2, uint64_t* key3, uint32_t* idx,
+                      Globals* glob, hipStream_t st);
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                         uint32_t depth, uint64_t* key, hipStream_t st);
 void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
@@ -50,10 +51,14 @@ void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t
                       const uint32_t* guard, hipStream_t st);
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,
                     uint32_t num_sets, uint32_t n, const uint32_t* out_perm, uint32_t* out_lcp,
-                    const uint32_t* guard, hipStream_t st);
+                    const uint32_t* guard, const Globals* glob, hipStream_t st);
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,
                            uint32_t v, uint32_t d, uint64_t* tree_lo, uint64_t* tree_in,
                            uint16_t* out, hipStream_t st);
+
+// Counting of output writes for later sorts (the write-check build; returns
+// false in the product build, where S5_OUT is a plain store).
+bool set_write_count(const WriteCount& w);
 
 size_t learn_bytes(uint32_t slots, uint32_t m);
 LearnCtx learn_ctx(void* mem, uint32_t slots, uint32_t m);
@@ -68,6 +73,9 @@ void launch_mlp_train(const LearnCtx& c, const uint64_t* sorted_keys, uint32_t m
                       float lr, uint64_t seed, float* out, hipStream_t st);
 void launch_mlp_grad(const LearnCtx& c, const float* params, const uint64_t* sorted_keys,
                      uint32_t m, float* out, hipStream_t st);
+void launch_mlp_propose(const float* params, const uint64_t* sorted_keys, uint32_t m, uint32_t v,
+                        float beta, uint64_t* out_spl, float* out_y, uint32_t* out_reject,
+                        hipStream_t st);
 void launch_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo,
                      uint64_t hi, float* out, hipStream_t st);
 

@@ -370,70 +370,157 @@ __device__ __forceinline__ uint32_t bound(const uint64_t* a, uint32_t m, uint64_
     return lo;
 }
 
-// Final update, model CDF over the sorted sample made monotone by a running
-// maximum (256 threads, 16 consecutive values each), splitters at its
-// quantiles, the check on the sample, and the splitter tree.
+// LDS of one proposal (one workgroup of 256 threads).
+struct ProposeLds {
+    uint64_t S[kLearnM];           // the sorted sample
+    float F[kLearnM];              // model outputs made monotone by a running maximum
+    uint64_t Hk[1u << (kDMax - 1)];  // heavy-hitter keys, ascending
+    uint64_t Qk[1u << kDMax];      // quantile splitters, non-decreasing
+    uint64_t spl[1u << kDMax];     // the proposal: both lists merged
+    float tmx[256];
+    uint32_t tsum[256];
+    uint32_t cnt, gmax;
+};
+
+// block-wide sum of one value per thread (256 threads)
+__device__ __forceinline__ uint32_t block_sum256(uint32_t x, ProposeLds& L) {
+    for (uint32_t o = 32; o > 0; o >>= 1) x += __shfl_xor(x, (int)o);
+    __syncthreads();
+    if (threadIdx.x == 0) L.cnt = 0;
+    __syncthreads();
+    if ((threadIdx.x & 63u) == 0) atomicAdd(&L.cnt, x);
+    __syncthreads();
+    return L.cnt;
+}
+
+// Splitter proposal of the model with weights w (LDS) for its sorted sample
+// smp[0..m) (m a multiple of 256, <= kLearnM), feature range (flo, fhi):
+//  1. F_i = running maximum of the model outputs (a monotone CDF); y_out[i]
+//     receives the outputs themselves when given;
+//  2. heavy hitters: the keys of runs of >= L* equal sample keys, L* the
+//     smallest L >= 2 with at most v/2 such runs, get splitters of their own,
+//     so each becomes an equality bucket (Section 3.1);
+//  3. the other vq = v - |heavy| splitters are model quantiles: splitter j
+//     (1 <= j <= vq) is the sample key at the first i with
+//     F_i >= j / (vq + 1) (in float32), or the last sample key;
+//  4. L.spl = both lists merged (sorted, repeats allowed);
+//  5. the check on the sample: the largest number of sample keys strictly
+//     between neighbouring splitters (or outside them) against
+//     beta * m / (v + 1).
+// Returns true (in every thread) if the proposal is rejected.
+__device__ __forceinline__ bool propose_body(const float* w, const uint64_t* smp, uint32_t m, uint32_t v,
+                             float beta, uint64_t flo, uint64_t fhi, float* y_out,
+                             ProposeLds& L) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = m / 256u;  // consecutive samples per thread
+    for (uint32_t i = tid; i < m; i += 256) L.S[i] = smp[i];
+    if (tid == 0) L.gmax = 0;
+    __syncthreads();
+    float run = 0.0f;
+    for (uint32_t e = 0; e < per; ++e) {
+        float x[8];
+        key_features(L.S[tid * per + e], flo, fhi, x);
+        const float y = mlp_forward(w, x, nullptr, nullptr);
+        if (y_out) y_out[tid * per + e] = y;
+        run = y > run ? y : run;
+        L.F[tid * per + e] = run;
+    }
+    L.tmx[tid] = run;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        const float o = tid >= off ? L.tmx[tid - off] : 0.0f;
+        __syncthreads();
+        if (o > L.tmx[tid]) L.tmx[tid] = o;
+        __syncthreads();
+    }
+    const float before = tid ? L.tmx[tid - 1] : 0.0f;
+    for (uint32_t e = 0; e < per; ++e)
+        if (L.F[tid * per + e] < before) L.F[tid * per + e] = before;
+    __syncthreads();
+    // run lengths, recorded at the last key of every run (0 elsewhere)
+    constexpr uint32_t kPer = kLearnM / 256;
+    uint32_t rl[kPer];
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e) {
+        const uint32_t i = tid * per + e;
+        const bool last = e < per && (i + 1 == m || L.S[i + 1] != L.S[i]);
+        rl[e] = last ? i + 1 - bound(L.S, m, L.S[i], false) : 0u;
+    }
+    // L* by bisection: the count of runs of length >= L falls as L grows
+    const uint32_t cap = v / 2;
+    uint32_t lo = 2, hi = m + 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        uint32_t c = 0;
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; ++e) c += rl[e] >= mid ? 1u : 0u;
+        if (block_sum256(c, L) <= cap) hi = mid; else lo = mid + 1;
+    }
+    // heavy keys in sample order: exclusive scan of the flags over the threads
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e) mine += rl[e] >= lo ? 1u : 0u;
+    L.tsum[tid] = mine;
+    __syncthreads();
+    for (uint32_t off = 1; off < 256; off <<= 1) {
+        const uint32_t o = tid >= off ? L.tsum[tid - off] : 0u;
+        __syncthreads();
+        L.tsum[tid] += o;
+        __syncthreads();
+    }
+    const uint32_t nh = L.tsum[255];
+    uint32_t pos = L.tsum[tid] - mine;
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e)
+        if (rl[e] >= lo) L.Hk[pos++] = L.S[tid * per + e];
+    // quantile splitters; j / (vq + 1) is formed in double and rounded once to
+    // float, which equals the correctly rounded float quotient (a quotient of
+    // integers below 2^11 is never within 2^-53 relative of a float midpoint)
+    const uint32_t vq = v - nh;
+    for (uint32_t j = tid + 1; j <= vq; j += 256) {
+        const float q = (float)((double)j / (double)(vq + 1));
+        uint32_t a = 0, b = m;
+        while (a < b) {
+            const uint32_t md = (a + b) >> 1;
+            if (L.F[md] < q) a = md + 1; else b = md;
+        }
+        L.Qk[j - 1] = L.S[a < m ? a : m - 1];
+    }
+    __syncthreads();
+    // merge: a heavy key goes before equal quantile keys
+    for (uint32_t a = tid; a < nh; a += 256) L.spl[a + bound(L.Qk, vq, L.Hk[a], false)] = L.Hk[a];
+    for (uint32_t b = tid; b < vq; b += 256) L.spl[b + bound(L.Hk, nh, L.Qk[b], true)] = L.Qk[b];
+    __syncthreads();
+    // range bucket j (between splitters j-1 and j) counted on the sample
+    uint32_t mx = 0;
+    for (uint32_t j = tid; j <= v; j += 256) {
+        const uint32_t a = j ? bound(L.S, m, L.spl[j - 1], true) : 0u;
+        const uint32_t b = j < v ? bound(L.S, m, L.spl[j], false) : m;
+        const uint32_t n = b > a ? b - a : 0u;
+        mx = n > mx ? n : mx;
+    }
+    atomicMax(&L.gmax, mx);
+    __syncthreads();
+    return (double)L.gmax > (double)beta * (double)m / (double)(v + 1);
+}
+
+// Final update, the proposal, the check on the sample, and the splitter tree.
 __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t slot, LSeg* lseg,
                                                   const uint32_t* learn_seg, uint32_t steps,
                                                   float lr, float beta, Globals* glob,
                                                   uint64_t* tree_lo, uint64_t* tree_in,
                                                   uint8_t* tree_lcp) {
     __shared__ float w[kNPS];
-    __shared__ float F[kLearnM];
-    __shared__ uint64_t spl[1u << kDMax];
-    __shared__ float tmx[256];
-    __shared__ uint32_t gmax;
+    __shared__ ProposeLds L;
     const uint32_t tid = threadIdx.x;
     const uint32_t si = learn_seg[slot];
     const LSeg g = lseg[si];
     learn_final_update(c, slot, steps, lr, w);
-    if (tid == 0) gmax = 0;
     __syncthreads();
     const uint64_t* smp = c.samples + (size_t)slot * kLearnM;
-    const uint64_t flo = c.range[2 * slot], fhi = c.range[2 * slot + 1];
-    constexpr uint32_t per = kLearnM / 256;
-    float run = 0.0f;
-    for (uint32_t e = 0; e < per; ++e) {
-        float x[8];
-        key_features(smp[tid * per + e], flo, fhi, x);
-        const float y = mlp_forward(w, x, nullptr, nullptr);
-        run = y > run ? y : run;
-        F[tid * per + e] = run;
-    }
-    tmx[tid] = run;
-    __syncthreads();
-    for (uint32_t off = 1; off < 256; off <<= 1) {
-        const float o = tid >= off ? tmx[tid - off] : 0.0f;
-        __syncthreads();
-        if (o > tmx[tid]) tmx[tid] = o;
-        __syncthreads();
-    }
-    const float before = tid ? tmx[tid - 1] : 0.0f;
-    for (uint32_t e = 0; e < per; ++e)
-        if (F[tid * per + e] < before) F[tid * per + e] = before;
-    __syncthreads();
-    // splitter j-1 at the first sample whose monotone CDF reaches j / (v + 1)
-    for (uint32_t j = tid + 1; j <= g.v; j += 256) {
-        const float q = (float)j / (float)(g.v + 1);
-        uint32_t lo = 0, hi = kLearnM;
-        while (lo < hi) {
-            const uint32_t md = (lo + hi) >> 1;
-            if (F[md] < q) lo = md + 1; else hi = md;
-        }
-        spl[j - 1] = smp[lo < kLearnM ? lo : kLearnM - 1];
-    }
-    __syncthreads();
-    // range bucket j (between splitters j-1 and j) counted on the sample
-    uint32_t mx = 0;
-    for (uint32_t j = tid; j <= g.v; j += 256) {
-        const uint32_t a = j ? bound(smp, kLearnM, spl[j - 1], true) : 0u;
-        const uint32_t b = j < g.v ? bound(smp, kLearnM, spl[j], false) : kLearnM;
-        const uint32_t n = b > a ? b - a : 0u;
-        mx = n > mx ? n : mx;
-    }
-    atomicMax(&gmax, mx);
-    __syncthreads();
-    if ((double)gmax > (double)beta * (double)kLearnM / (double)(g.v + 1)) {
+    const bool reject = propose_body(w, smp, kLearnM, g.v, beta, c.range[2 * slot],
+                                     c.range[2 * slot + 1], nullptr, L);
+    if (reject) {
         if (tid == 0) {
             lseg[si].pad0 = 0xFFFFFFFFu;  // the sampled tree is built instead
             atomicAdd(&glob->fallbacks, 1u);
@@ -445,12 +532,12 @@ __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t sl
     uint8_t* lcp_out = tree_lcp + g.tree_base;
     for (uint32_t j = tid; j <= g.v; j += 256) {
         if (j < g.v) {
-            const uint64_t x = spl[j];
+            const uint64_t x = L.spl[j];
             lo_out[inorder_node(j, g.d)] = x;
             in_out[j] = x;
             uint8_t l = 0;
-            if (j > 0 && spl[j - 1] != x)
-                l = (uint8_t)(__builtin_clzll((unsigned long long)(spl[j - 1] ^ x)) >> 3);
+            if (j > 0 && L.spl[j - 1] != x)
+                l = (uint8_t)(__builtin_clzll((unsigned long long)(L.spl[j - 1] ^ x)) >> 3);
             lcp_out[j] = l;
         } else {
             lo_out[0] = 0;
@@ -523,6 +610,22 @@ __global__ __launch_bounds__(256) void k_mlp_eval(const float* w, const uint64_t
     float x[8];
     key_features(keys[i], lo, hi, x);
     out[i] = mlp_forward(w, x, nullptr, nullptr);
+}
+
+// the proposal for a caller's model and sorted sample (one workgroup)
+__global__ __launch_bounds__(256) void k_mlp_propose(const float* params, const uint64_t* keys,
+                                                     uint32_t m, uint32_t v, float beta,
+                                                     uint64_t* out_spl, float* out_y,
+                                                     uint32_t* out_reject) {
+    __shared__ float w[kNPS];
+    __shared__ uint64_t range[2];
+    __shared__ ProposeLds L;
+    for (uint32_t p = threadIdx.x; p < kNP; p += 256) w[p] = params[p];
+    sample_range(keys, m, range);
+    __syncthreads();
+    const bool reject = propose_body(w, keys, m, v, beta, range[0], range[1], out_y, L);
+    for (uint32_t j = threadIdx.x; j < v; j += 256) out_spl[j] = L.spl[j];
+    if (threadIdx.x == 0) *out_reject = reject ? 1u : 0u;
 }
 
 __global__ __launch_bounds__(256) void k_learn_sum(LearnCtx c, uint32_t b, float* out) {
@@ -604,6 +707,13 @@ void launch_mlp_grad(const LearnCtx& c, const float* params, const uint64_t* sor
     hipLaunchKernelGGL(k_learn_step, dim3(c.groups, 1), dim3(kGrp), 0, st, c, 0u, 0.0f,
                        (const uint32_t*)nullptr, 0u, (const Globals*)nullptr);
     hipLaunchKernelGGL(k_learn_sum, dim3(8), dim3(256), 0, st, c, 0u, out);
+}
+
+void launch_mlp_propose(const float* params, const uint64_t* sorted_keys, uint32_t m, uint32_t v,
+                        float beta, uint64_t* out_spl, float* out_y, uint32_t* out_reject,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_mlp_propose, dim3(1), dim3(256), 0, st, params, sorted_keys, m, v, beta,
+                       out_spl, out_y, out_reject);
 }
 
 void launch_mlp_eval(const float* params, const uint64_t* keys, uint32_t n, uint64_t lo,

@@ -23,7 +23,8 @@ EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_
            "s5_sort_batched_tuned", "s5_stats_get",
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
            "s5_profile_only",
-           "s5_profile_read", "s5_mlp_train", "s5_mlp_grad", "s5_mlp_eval")
+           "s5_profile_read", "s5_mlp_train", "s5_mlp_grad", "s5_mlp_eval", "s5_mlp_propose",
+           "s5_debug_limit_capacity", "s5_debug_count_writes")
 
 
 class Config(ctypes.Structure):
@@ -61,13 +62,28 @@ class S5Error(RuntimeError):
 
 
 _lib = None
+_wlib = None
+WCHECK_PATH = os.path.join(_PKG, "libs5_wcheck.so")
 
 
 def load(path: str = LIB_PATH):
     """Load ``libs5.so`` (raises if it is missing: there is no fallback path)."""
     global _lib
-    if _lib is not None:
-        return _lib
+    if _lib is None:
+        _lib = _open(path)
+    return _lib
+
+
+def load_wcheck():
+    """The write-check build ``libs5_wcheck.so`` (every output write counted;
+    tests only), with the same entry points."""
+    global _wlib
+    if _wlib is None:
+        _wlib = _open(WCHECK_PATH)
+    return _wlib
+
+
+def _open(path: str):
     if not os.path.exists(path):
         raise S5Error(f"S^5 HIP library not built: {path} is missing "
                       "(run __graft_entry__.build())")
@@ -91,16 +107,19 @@ def load(path: str = LIB_PATH):
     lib.s5_mlp_train.argtypes = [P, U32, U32, ctypes.c_float, U64, P, P]
     lib.s5_mlp_grad.argtypes = [P, P, U32, P, P]
     lib.s5_mlp_eval.argtypes = [P, P, U32, U64, U64, P, P]
+    lib.s5_mlp_propose.argtypes = [P, P, U32, U32, ctypes.c_float, P, P, P, P]
     lib.s5_profile_enable.argtypes = [ctypes.c_int]
     lib.s5_profile_only.argtypes = [ctypes.c_char_p]
     lib.s5_profile_only.restype = ctypes.c_int
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
-    for f in ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
+    lib.s5_debug_limit_capacity.argtypes = [U32, U32]
+    lib.s5_debug_count_writes.argtypes = [P, P, U64, P, P, P]
+    for f in ("s5_debug_limit_capacity", "s5_debug_count_writes", "s5_sort", "s5_sort_ex",
+              "s5_sort_static", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
               "s5_prefix_keys",
               "s5_classify", "s5_profile_enable", "s5_profile_read", "s5_mlp_train", "s5_mlp_grad",
-              "s5_mlp_eval"):
+              "s5_mlp_eval", "s5_mlp_propose"):
         getattr(lib, f).restype = ctypes.c_int
-    _lib = lib
     return lib
 
 
@@ -112,6 +131,11 @@ def _check(rc: int):
 def _stream(stream=None):
     s = torch.cuda.current_stream() if stream is None else stream
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check_out(out_perm: torch.Tensor, out_lcp: torch.Tensor, n: int):
+    if out_perm.numel() < n or out_lcp.numel() < n:
+        raise ValueError(f"out_perm and out_lcp need at least {n} entries")
 
 
 def _dev(t: torch.Tensor, dtype, name: str):
@@ -143,8 +167,11 @@ def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,
         out_perm = torch.empty(n, dtype=torch.uint32, device=dev)
     if out_lcp is None:
         out_lcp = torch.empty(n, dtype=torch.uint32, device=dev)
+    _check_out(out_perm, out_lcp, n)
     ws, wsb = None, 0
     if workspace is not None:
+        # a workspace smaller than workspace_bytes(n, cfg) is rejected by the
+        # library (S5_ERR_NOMEM) before any device work
         ws, wsb = _dev(workspace, torch.uint8, "workspace"), workspace.numel()
     rc = lib.s5_sort_ex(_dev(chars, torch.uint8, "chars"), chars.numel(),
                         _dev(offsets, torch.uint64, "offsets"), n,
@@ -160,6 +187,7 @@ def sort_static(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tens
     """``s5_sort_static``: the sort with its workspace in the library's static
     scratch array (no allocation).  The caller passes the outputs; returns the
     status code (``S5_ERR_TOO_LARGE`` if the sort does not fit the array)."""
+    _check_out(out_perm, out_lcp, offsets.numel())
     return int(load().s5_sort_static(_dev(chars, torch.uint8, "chars"), chars.numel(),
                                      _dev(offsets, torch.uint64, "offsets"), offsets.numel(),
                                      _dev(out_perm, torch.uint32, "out_perm"),
@@ -171,6 +199,7 @@ def sort_static(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tens
 def sort_plain(chars: torch.Tensor, offsets: torch.Tensor, out_perm: torch.Tensor,
                out_lcp: torch.Tensor, stream=None):
     """The 6-argument entry point ``s5_sort`` (internal workspace pool, defaults)."""
+    _check_out(out_perm, out_lcp, offsets.numel())
     _check(load().s5_sort(_dev(chars, torch.uint8, "chars"),
                           _dev(offsets, torch.uint64, "offsets"), offsets.numel(),
                           _dev(out_perm, torch.uint32, "out_perm"),
@@ -200,9 +229,14 @@ def sort_batched(chars: torch.Tensor, offsets: torch.Tensor, set_begin: torch.Te
         out_perm = torch.empty(n, dtype=torch.uint32, device=offsets.device)
     if out_lcp is None:
         out_lcp = torch.empty(n, dtype=torch.uint32, device=offsets.device)
+    _check_out(out_perm, out_lcp, n)
     num_sets = set_begin.numel() - 1
+    if num_sets < 0:
+        raise ValueError("set_begin needs num_sets + 1 entries")
     if tuning is not None and len(tuning) != num_sets:
         raise ValueError("tuning needs one entry per set")
+    if num_sets and int(set_begin[-1]) > n:  # the sets would read past offsets
+        raise ValueError("set_begin[-1] exceeds the number of offsets")
     rc = lib.s5_sort_batched_tuned(_dev(chars, torch.uint8, "chars"), chars.numel(),
                                    _dev(offsets, torch.uint64, "offsets"),
                                    _dev(set_begin, torch.uint64, "set_begin"), num_sets, tuning,
@@ -298,3 +332,20 @@ def mlp_eval(params: torch.Tensor, keys: torch.Tensor, lo: int = 0, hi: int = 2*
                               keys.numel(), lo, hi, _dev(out, torch.float32, "out"),
                               _stream(stream)))
     return out
+
+
+def mlp_propose(params: torch.Tensor, sorted_keys: torch.Tensor, v: int, beta: float = 4.0,
+                stream=None):
+    """The learned splitter proposal for a model and its sorted sample: returns
+    ``(splitters uint64[v], model outputs float32[m], rejected uint32[1])``."""
+    m = sorted_keys.numel()
+    dev = sorted_keys.device
+    spl = torch.empty(v, dtype=torch.uint64, device=dev)
+    y = torch.empty(m, dtype=torch.float32, device=dev)
+    rej = torch.empty(1, dtype=torch.uint32, device=dev)
+    _check(load().s5_mlp_propose(_dev(params, torch.float32, "params"),
+                                 _dev(sorted_keys, torch.uint64, "sorted_keys"), m, v, beta,
+                                 _dev(spl, torch.uint64, "splitters"),
+                                 _dev(y, torch.float32, "cdf"), _dev(rej, torch.uint32, "reject"),
+                                 _stream(stream)))
+    return spl, y, rej

@@ -74,6 +74,55 @@ def test_training_tracks_reference(name):
     assert got_loss < 0.5 * losses[0]
 
 
+def _proposal_vs_reference(params, keys, v, beta):
+    """The kernel's proposal against the reference on the kernel's own float32
+    model outputs (both sides take the quantile decisions in float32 from the
+    same values); the outputs themselves against the fp64 forward pass."""
+    spl, y, rej = s5.mlp_propose(params, to_dev(keys), v, beta)
+    torch.cuda.synchronize()
+    yg = y.cpu().numpy()
+    p64 = params.cpu().numpy().astype(np.float64)
+    y_ref, _ = mlp_ref.forward(p64, mlp_ref.features(keys, *mlp_ref.feature_range(keys)))
+    assert np.all(np.abs(yg - y_ref) <= 3e-5)
+    want = mlp_ref.propose_from_cdf(yg, keys, v)
+    got = spl.cpu().numpy()
+    bad = np.flatnonzero(got != want)
+    assert bad.size == 0, f"v={v}: splitters differ at {bad[:8]}"
+    want_rej = mlp_ref.sample_imbalanced(want, keys, v, beta)
+    assert int(rej.item()) == int(want_rej)
+    return want, mlp_ref.sample_imbalance(want, keys) / (keys.size / (v + 1))
+
+
+@pytest.mark.parametrize("name", ["dna_16M", "words_50M", "url_10M"])
+def test_proposal_matches_reference(name):
+    """The learned splitter proposal (monotone CDF, heavy hitters, quantiles,
+    merge, sample check) bit-exact against the reference, for a model trained
+    by the GPU on the workload's own sample, at the v the sort uses."""
+    keys = sample_keys(name, 4096, seed=4)
+    params = s5.mlp_train(to_dev(keys), 64, 0.03, 5)
+    for v in (127, 255, 1023):
+        for beta in (4.0, 1e9):
+            spl, ratio = _proposal_vs_reference(params, keys, v, beta)
+            print(f"{name} v={v} beta={beta}: heavy {mlp_ref.heavy_keys(keys, v).size}, "
+                  f"largest sample range bucket {ratio:.2f} x ideal", flush=True)
+
+
+def test_proposal_hand_cases():
+    """Heavy hitters from planted duplicate runs, a sample of one repeated key,
+    the smallest sample (m = 256) and untrained weights."""
+    rng = np.random.default_rng(8)
+    p0 = to_dev(mlp_ref.init_params(3).astype(np.float32))
+    base = rng.integers(0, 2**63, size=4096, dtype=np.uint64)
+    runs = np.repeat(rng.integers(0, 2**63, size=40, dtype=np.uint64),
+                     rng.integers(2, 60, size=40))  # 40 runs, at most 2360 keys
+    planted = np.sort(np.concatenate([base[:4096 - runs.size], runs]))
+    cases = [planted, np.full(4096, 0x4142434445464748, dtype=np.uint64),
+             np.sort(base[:256]), np.sort(rng.integers(0, 4, size=512).astype(np.uint64))]
+    for keys in cases:
+        for v in (1, 7, 63, 255, 1023):
+            _proposal_vs_reference(p0, keys, v, 4.0)
+
+
 @pytest.mark.parametrize("name,n", [("dna_16M", 200_000), ("words_50M", 400_000),
                                     ("url_10M", 200_000), ("random_1M", 300_000)])
 def test_learned_sort_parity(name, n):
