@@ -9,11 +9,14 @@ JSON line carries the roofline of the dominant kernel (the redistribution
 pass, timed with HIP events inside the library on its launch stream) and the
 CPU oracle timed on a bounded sample of the same workload.
 
-Beside it (skip with --no-extras): the learned splitter proposal against
-sampled splitters on the DNA and word workloads (their outputs compared), and
-the batched form (4,096 sets in one graph launch, autotuned per-set
-parameters), each with its own strings/s.  Only the CPU baseline uses the
-oracle; the full-size correctness checks are GPU tests.
+Beside it (skip with --no-extras): plain S^5 on the random strings, the
+learned splitter proposal against sampled splitters on the DNA and word
+workloads (their outputs compared), and the batched form (4,096 sets in one
+graph launch, autotuned per-set parameters), each with its strings/s, its
+distinguishing prefix D and its algorithmic HBM bytes and rates (B_min, B_alg,
+% of 8 TB/s and of a measured device copy).  Only the CPU baselines use the
+oracle (one core for the main line, every core over whole sets for the
+batched form); the full-size correctness checks are GPU tests.
 """
 import argparse
 import json
@@ -59,18 +62,141 @@ def pmc_traffic(workload):
     return vals["traffic"], os.path.relpath(path, ROOT)
 
 
-def dist_prefix_from_output(chars, offs, perm, lcp):
+def dist_prefix(d_chars, d_offs, perm, lcp, d_sb=None, chunk=1 << 30):
     """D = sum over strings of min(|s|, max(lcp with sorted neighbours) + 1), |s| with the
-    terminator (Section 2), evaluated on the sort's own output."""
-    import numpy as np
-    zeros = np.flatnonzero(chars == 0)
-    lens = zeros[np.searchsorted(zeros, offs)] - offs.astype(np.int64)  # without terminator
-    l = lcp.astype(np.int64)
-    r = np.empty_like(l)
+    terminator (Section 2), evaluated on the sort's own output (device tensors;
+    batched: set-local perm, lcp 0 at every set start, d_sb the set table)."""
+    import torch
+    # terminator positions, ascending (nonzero over chunks of the arena: one
+    # call over more than 2^31 elements is not supported)
+    zeros = torch.cat([torch.nonzero(d_chars[a:a + chunk] == 0).squeeze(1) + a
+                       for a in range(0, d_chars.numel(), chunk)])
+    offs = d_offs.view(torch.int64)
+    lens = zeros[torch.searchsorted(zeros, offs)] - offs  # bytes before the terminator
+    del zeros
+    p = perm.view(torch.int32).to(torch.int64)
+    if d_sb is not None:
+        sb = d_sb.view(torch.int64)
+        p += torch.repeat_interleave(sb[:-1], sb[1:] - sb[:-1], output_size=p.numel())
+    l = lcp.view(torch.int32).to(torch.int64)
+    r = torch.zeros_like(l)
     r[:-1] = l[1:]
-    r[-1] = 0
-    m = np.maximum(l, r) + 1
-    return int(np.minimum(m, lens[perm.astype(np.int64)] + 1).sum())
+    m = torch.maximum(l, r) + 1
+    return int(torch.minimum(m, lens[p] + 1).sum())
+
+
+def hbm_figures(D, n, moved, sec, copy_gbps):
+    """Algorithmic bytes of one sort and the rates they give: B_min = D + 16 n
+    (offset read, perm and lcp written, distinguishing prefixes), B_alg = B_min +
+    24 M (key and index read and written per string per distribution pass)."""
+    b_min = D + 16 * n
+    b_alg = b_min + 24 * moved
+    g_min, g_alg = b_min / sec / 1e9, b_alg / sec / 1e9
+    out = {"D": D, "moved_M": moved, "B_min_bytes": b_min, "B_alg_bytes": b_alg,
+           "B_min_GBps": g_min, "B_alg_GBps": g_alg,
+           "B_min_pct_peak": 100 * g_min / HBM_PEAK_GBPS,
+           "B_alg_pct_peak": 100 * g_alg / HBM_PEAK_GBPS}
+    if copy_gbps:
+        out["B_alg_pct_copy"] = 100 * g_alg / copy_gbps
+    return out
+
+
+def host_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "usable_cores": len(os.sched_getaffinity(0))}
+
+
+def copy_bandwidth(dev, mib=1024, reps=10):
+    """A plain device copy (torch copy_) of ``mib`` MiB, timed with events on the
+    stream it runs on: bytes read + written per second."""
+    import torch
+    a = torch.empty(mib << 20, dtype=torch.uint8, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    gbps = 2 * (mib << 20) / (ms / 1e3) / 1e9
+    del a, b
+    return {"GBps": gbps, "pct_of_peak": 100 * gbps / HBM_PEAK_GBPS, "bytes_per_copy": 2 * (mib << 20),
+            "how": f"torch copy_ of a {mib} MiB device buffer, {reps} copies timed with HIP events"}
+
+
+def profile_roofline(profile, moved, sorts_key="sorts"):
+    """Roofline of the redistribution kernel (every instantiation) from a
+    committed rocprofv3 summary: average launch duration there, and 24 B per
+    string moved per sort spread over that profile's launches per sort."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    calls, total_us, sorts, sha = 0, 0.0, None, None
+    for line in open(path):
+        parts = [x for x in line.strip().split("  ") if x]
+        if line.startswith(DOMINANT_SYMBOL + "<") and len(parts) >= 3:
+            calls += int(parts[1])
+            total_us += float(parts[2])
+        if line.startswith(sorts_key + " "):
+            sorts = int(line.split()[1])
+        if line.startswith("kernel_source_sha256 "):
+            sha = line.split()[1]
+    if not calls or not sorts:
+        return None
+    src = os.path.join(ROOT, "paper_1305_1157_amd", "csrc", "s5_kernels.hip")
+    fresh = sha == hashlib.sha256(open(src, "rb").read()).hexdigest()
+    per_sort = calls / sorts
+    alg = 24.0 * moved / per_sort
+    avg_us = total_us / calls
+    achieved = alg / (avg_us / 1e6) / 1e9
+    return {"kernel": DOMINANT_SYMBOL, "bound": "hbm", "achieved": achieved,
+            "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None, "avg_launch_us": avg_us, "launches_per_sort": per_sort,
+            "alg_bytes_per_launch": alg, "source": f"profiles/{profile} (rocprofv3)",
+            "profile_matches_kernel_source": fresh}
+
+
+def cpu_baseline_sets(chars, offs, sb, min_seconds=8.0):
+    """The oracle, untuned, on every usable host core: whole sets of the batched
+    workload handed to worker threads (the oracle's C code runs without the
+    interpreter lock), sets taken in a seeded order until the wall clock passes
+    ``min_seconds``."""
+    import concurrent.futures as cf
+    import numpy as np
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    order = np.random.default_rng(5).permutation(sb.size - 1)
+    done_sets, done_strings = 0, 0
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        for lo in range(0, order.size, 4 * cores):
+            chunk = order[lo:lo + 4 * cores]
+            futs = [ex.submit(oracle.sort, chars, offs[int(sb[s]):int(sb[s + 1])]) for s in chunk]
+            for f in futs:
+                f.result()
+            done_sets += chunk.size
+            done_strings += int((sb[chunk + 1] - sb[chunk]).sum())
+            if time.perf_counter() - t0 >= min_seconds:
+                break
+    wall = time.perf_counter() - t0
+    info = host_info()
+    return {"value": done_strings / wall, "unit": "strings/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done_sets} of {sb.size - 1} sets ({done_strings:,} strings) of the same "
+                      f"seeded batched workload, each sorted by the oracle (multikey quicksort + "
+                      f"LCP pass) on one of {cores} worker threads, {wall:.1f} s wall",
+            "cpu_model": info["cpu_model"], "nproc": info["nproc"]}
 
 
 def cpu_baseline(name, n_sample, min_seconds=10.0):
@@ -85,10 +211,12 @@ def cpu_baseline(name, n_sample, min_seconds=10.0):
         oracle.sort(chars, offs)
         total += time.perf_counter() - t0
         reps += 1
+    info = host_info()
     return {"value": n_sample * reps / total, "unit": "strings/s", "cores": 1, "kind": "oracle",
             "sample": f"first {n_sample:,} strings of the same seeded {name} recipe, sorted "
                       f"{reps} times by the oracle (multikey quicksort + LCP pass), "
-                      f"{total:.1f} s total on 1 host core"}
+                      f"{total:.1f} s total on 1 host core",
+            "cpu_model": info["cpu_model"], "nproc": info["nproc"]}
 
 
 def log(msg):
@@ -106,8 +234,9 @@ def _timed_sorts(fn, steps):
     return (time.perf_counter() - t0) / steps
 
 
-def learned_extra(name, steps=3):
-    """Learned vs sampled splitters on one workload (same output, checked)."""
+def learned_extra(name, copy_gbps=None, steps=3):
+    """Learned vs sampled splitters on one workload (same output, checked), each
+    with the metric's HBM figures."""
     import torch
     from paper_1305_1157_amd import gen, s5
     chars, offs = gen.workload(name)
@@ -115,7 +244,7 @@ def learned_extra(name, steps=3):
     dc, do = torch.from_numpy(chars).cuda(), torch.from_numpy(offs).cuda()
     perm = torch.empty(n, dtype=torch.uint32, device="cuda")
     lcp = torch.empty_like(perm)
-    res, ref = {"workload": WORKLOAD_TEXT[name], "name": name, "n": n}, None
+    res, ref, D = {"workload": WORKLOAD_TEXT[name], "name": name, "n": n}, None, None
     variants = [("sampled", s5.make_config()),
                 ("learned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED)),
                 ("learned_no_fallback", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
@@ -134,20 +263,50 @@ def learned_extra(name, steps=3):
         s5.profile_enable(False)
         if ref is None:
             ref = (perm.clone(), lcp.clone())
+            D = dist_prefix(dc, do, perm, lcp)
         same = bool(torch.equal(ref[0], perm) and torch.equal(ref[1], lcp))
         res[label] = {"value": n / sec, "ms": sec * 1e3, "passes": st["passes"],
                       "moved_M": st["moved_M"], "fallbacks": st["fallbacks"],
                       "entropy_bits_first_pass": st["entropy_bits"],
                       "max_bucket_first_pass": st["max_bucket"],
                       "learn_ms": prof.get("learn_splitters", {}).get("total_ms", 0.0),
+                      "hbm": hbm_figures(D, n, st["moved_M"], sec, copy_gbps),
                       "output_identical_to_sampled": same}
         del ws
     return res
 
 
-def batched_extra(steps=3, learned=None):
+def plain_extra(name, copy_gbps=None, steps=10):
+    """Plain S^5 with sampled splitters on another workload: strings/s and the
+    metric's HBM figures."""
+    import torch
+    from paper_1305_1157_amd import gen, s5
+    chars, offs = gen.workload(name)
+    n = int(offs.size)
+    dc, do = torch.from_numpy(chars).cuda(), torch.from_numpy(offs).cuda()
+    perm = torch.empty(n, dtype=torch.uint32, device="cuda")
+    lcp = torch.empty_like(perm)
+    ws = torch.empty(s5.workspace_bytes(n), dtype=torch.uint8, device="cuda")
+    run = lambda: s5.sort(dc, do, out_perm=perm, out_lcp=lcp, workspace=ws)  # noqa
+    for _ in range(3):
+        run()
+    sec = _timed_sorts(run, steps)
+    st = s5.stats()
+    D = dist_prefix(dc, do, perm, lcp)
+    return {"workload": WORKLOAD_TEXT[name], "name": name, "n": n, "value": n / sec,
+            "ms": sec * 1e3, "steps": steps, "passes": st["passes"],
+            "hbm": hbm_figures(D, n, st["moved_M"], sec, copy_gbps)}
+
+
+BATCHED_PROFILES = {"sampled_tuned": "kernels_sets_4096.txt",
+                    "learned_tuned": "kernels_sets_4096_learned.txt"}
+
+
+def batched_extra(steps=3, learned=None, copy_gbps=None, cpu_sample=True):
     """The batched form on 4,096 sets in one graph launch (learned: only that
-    variant, else all three)."""
+    variant, else all three), with the metric's HBM figures, the redistribution
+    kernel's roofline from the committed rocprofv3 summary of the same workload,
+    and the oracle on every host core over a sample of the sets."""
     import numpy as np
     import torch
     from paper_1305_1157_amd import autotune, gen, s5
@@ -175,6 +334,7 @@ def batched_extra(steps=3, learned=None):
                 ("sampled_defaults", s5.make_config(), None)]
     if learned is not None:
         variants = [v for v in variants if v[0] == ("learned_tuned" if learned else "sampled_tuned")]
+    D = None
     for label, cfg, tun in variants:
         log(f"batched: {label}")
         run = lambda: s5.sort_batched(dc, do, ds, cfg=cfg, tuning=tun, out_perm=perm,  # noqa
@@ -182,18 +342,29 @@ def batched_extra(steps=3, learned=None):
         run()  # capture
         sec = _timed_sorts(run, steps)
         st = s5.stats()
+        if D is None:
+            D = dist_prefix(dc, do, perm, lcp, ds)
         res[label] = {"value": n / sec, "ms": sec * 1e3, "passes": st["passes"],
                       "moved_M": st["moved_M"], "fallbacks": st["fallbacks"],
-                      "segments": st["segments"], "base_items": st["base_items"]}
+                      "segments": st["segments"], "base_items": st["base_items"],
+                      "hbm": hbm_figures(D, n, st["moved_M"], sec, copy_gbps)}
+        if label in BATCHED_PROFILES:
+            res[label]["roofline"] = profile_roofline(BATCHED_PROFILES[label], st["moved_M"])
     res["check"] = ("tests/test_gpu_fullsize.py checks this workload at full size "
-                    "(permutation per set, sampled neighbour pairs, whole small sets)")
+                    "(permutation per set and every neighbour pair, whole small sets)")
+    if cpu_sample:
+        log("batched: cpu baseline (oracle, all cores)")
+        res["cpu_baseline"] = cpu_baseline_sets(chars, offs, sb)
     return res
 
 
 def batched_main(args):
     """The batched workload as the main line: whole-job strings/s of one graph
     launch per sort (autotuned per-set parameters)."""
-    res = batched_extra(steps=args.steps, learned=args.learned)
+    import torch
+    copy = copy_bandwidth(torch.device("cuda:0"))
+    res = batched_extra(steps=args.steps, learned=args.learned, copy_gbps=copy["GBps"],
+                        cpu_sample=bool(args.cpu_sample))
     label = "learned_tuned" if args.learned else "sampled_tuned"
     r = res[label]
     out = {
@@ -206,11 +377,17 @@ def batched_main(args):
                    "variant": "batched S^5 in one hipGraph, " +
                    ("learned splitters per set with sampled fallback" if args.learned
                     else "sampled splitters") + ", autotuned per-set parameters"},
-        "roofline": None,
-        "roofline_note": "kernels inside one graph launch are not bracketed by events; "
-                         "per-kernel durations come from rocprofv3 (profiles/)",
+        "hbm": r["hbm"],
+        "roofline": r.get("roofline"),
+        "roofline_note": "kernels inside one graph launch are not bracketed by events; the "
+                         "redistribution kernel's average duration comes from the committed "
+                         "rocprofv3 summary of this workload",
+        "copy_bandwidth": copy,
+        "host": host_info(),
         "batched": res,
     }
+    if "cpu_baseline" in res:
+        out["cpu_baseline"] = res["cpu_baseline"]
     print(json.dumps(out), flush=True)
 
 
@@ -264,6 +441,8 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy = None if args.copy_probe_mib else copy_bandwidth(dev)
+    copy_gbps = copy["GBps"] if copy else None
 
     for _ in range(args.warmup):
         s5.sort(d_chars, d_offs, cfg=cfg, out_perm=perm, out_lcp=lcp, workspace=ws)
@@ -291,10 +470,7 @@ def main():
 
     ms_per_step = dt * 1e3 / args.steps
     value = n * args.steps / dt
-    h_perm, h_lcp = perm.cpu().numpy(), lcp.cpu().numpy()
-    D = dist_prefix_from_output(chars, offs, h_perm, h_lcp)
-    b_min = D + 16 * n
-    b_alg = b_min + 24 * st["moved_M"]
+    D = dist_prefix(d_chars, d_offs, perm, lcp)
     sec = ms_per_step / 1e3
     dom = prof_dom
     avg_ms = dom["total_ms"] / dom["launches"]
@@ -323,10 +499,7 @@ def main():
                    "variant": "S^5, learned splitter proposal with sampled fallback" if args.learned
                    else "plain S^5, sampled splitters",
                    "splitters_max": 255, "base_threshold": 1024},
-        "hbm": {"B_min_bytes": b_min, "B_alg_bytes": b_alg, "moved_M": st["moved_M"],
-                "passes": st["passes"], "B_min_GBps": b_min / sec / 1e9,
-                "B_alg_GBps": b_alg / sec / 1e9,
-                "B_alg_pct_peak": 100 * b_alg / sec / 1e9 / HBM_PEAK_GBPS},
+        "hbm": dict(hbm_figures(D, n, st["moved_M"], sec, copy_gbps), passes=st["passes"]),
         "roofline": {"kernel": DOMINANT_SYMBOL, "bound": "hbm", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic, "traffic_source": traffic_src,
@@ -335,6 +508,8 @@ def main():
                      "alg_bytes_per_launch": dom["alg_bytes"] / dom["launches"]},
         "kernels": kernels,
         "stats": st,
+        "copy_bandwidth": copy,
+        "host": host_info(),
     }
     log(f"{args.workload}: {value / 1e9:.3f} G strings/s, {ms_per_step:.3f} ms per sort")
     if args.cpu_sample:
@@ -343,16 +518,21 @@ def main():
     if not args.no_extras:
         del d_chars, d_offs, perm, lcp, ws
         torch.cuda.empty_cache()
+        try:
+            out["plain"] = {"random_1M": plain_extra("random_1M", copy_gbps)}
+        except Exception as e:  # reported, never hides the main line
+            out["plain"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
         extras = {}
         for name in ("dna_16M", "words_50M"):
             try:
-                extras[name] = learned_extra(name)
-            except Exception as e:  # reported, never hides the main line
+                extras[name] = learned_extra(name, copy_gbps)
+            except Exception as e:
                 extras[name] = {"error": repr(e)}
             torch.cuda.empty_cache()
         out["learned"] = extras
         try:
-            out["batched"] = batched_extra()
+            out["batched"] = batched_extra(copy_gbps=copy_gbps, cpu_sample=bool(args.cpu_sample))
         except Exception as e:
             out["batched"] = {"error": repr(e)}
     print(json.dumps(out), flush=True)

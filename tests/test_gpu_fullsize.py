@@ -1,7 +1,12 @@
 """The workloads at their full sizes, in the configurations the benchmark times,
-checked through the oracle's checkers: the permutation of every set, and the
-order and LCP of sampled neighbour pairs (too large for the oracle to re-sort).
-Smaller cases of the same recipes are checked element by element elsewhere."""
+checked completely through the oracle's checkers: the permutation of every set
+(check_perm) and, at EVERY position, the order of the neighbour pair (bytes,
+then input index) and its LCP recomputed from the bytes (check_all_pairs).
+The order with ties by index is unique, so the two checks together pin the
+whole result.  Smaller cases of the same recipes are compared element by
+element with the oracle's own sort elsewhere."""
+import time
+
 import numpy as np
 import pytest
 
@@ -15,23 +20,20 @@ import oracle  # noqa: E402
 from gpu_util import to_dev  # noqa: E402
 from paper_1305_1157_amd import autotune, gen, s5  # noqa: E402
 
-PAIRS = 2_000_000
+LEARNED = s5.make_config(splitter_mode=s5.SPLIT_LEARNED)
 
 
 def _check(chars, offs, perm, lcp, sb=None, label=""):
     hp, hl = perm.cpu().numpy(), lcp.cpu().numpy()
-    print(f"{label}: checking {hp.size:,} strings", flush=True)
+    t0 = time.time()
+    print(f"{label}: checking all {hp.size:,} positions", flush=True)
     assert oracle.check_perm(hp, sb), f"{label}: not a permutation"
-    rng = np.random.default_rng(hash(label) & 0xFFFF)
-    pos = rng.integers(0, hp.size, size=min(PAIRS, hp.size)).astype(np.uint64)
-    bad = oracle.check_pairs(chars, offs, hp, hl, pos, sb)
-    assert bad == 0, f"{label}: {bad} of {pos.size} sampled neighbour pairs wrong"
-    # the first and last positions of the output too
-    ends = np.concatenate([np.arange(min(1000, hp.size)), np.arange(max(0, hp.size - 1000), hp.size)])
-    assert oracle.check_pairs(chars, offs, hp, hl, ends.astype(np.uint64), sb) == 0
+    bad = oracle.check_all_pairs(chars, offs, hp, hl, sb)
+    assert bad == 0, f"{label}: {bad} of {hp.size} neighbour pairs wrong"
+    print(f"{label}: complete check {time.time() - t0:.1f} s", flush=True)
 
 
-@pytest.mark.parametrize("name", ["url_10M", "words_50M"])
+@pytest.mark.parametrize("name", ["random_1M", "url_10M", "words_50M", "dna_16M"])
 def test_full_plain(name):
     chars, offs = gen.workload(name)
     perm, lcp = s5.sort(to_dev(chars), to_dev(offs))
@@ -39,27 +41,33 @@ def test_full_plain(name):
     _check(chars, offs, perm, lcp, label=name)
 
 
-def test_full_dna_learned_equals_sampled():
-    chars, offs = gen.workload("dna_16M")
+@pytest.mark.parametrize("name", ["dna_16M", "words_50M"])
+def test_full_learned(name):
+    """Learned splitters at full size (the benchmark's learned lines): checked
+    completely, and equal to the sampled-splitter result."""
+    chars, offs = gen.workload(name)
     dc, do = to_dev(chars), to_dev(offs)
+    p2, l2 = s5.sort(dc, do, cfg=LEARNED)
+    torch.cuda.synchronize()
+    _check(chars, offs, p2, l2, label=f"{name} learned")
     p1, l1 = s5.sort(dc, do)
-    p2, l2 = s5.sort(dc, do, cfg=s5.make_config(splitter_mode=s5.SPLIT_LEARNED))
     torch.cuda.synchronize()
     assert torch.equal(p1, p2) and torch.equal(l1, l2)
-    _check(chars, offs, p1, l1, label="dna_16M")
 
 
-def test_full_batched_graph():
+@pytest.mark.parametrize("learned", [False, True], ids=["sampled", "learned"])
+def test_full_batched_graph(learned):
     spec = gen.BATCHED["sets_4096"]
     chars, offs, sb = gen.batched(**spec)
     sizes = np.diff(sb).astype(np.int64)
     table = autotune.load_table()
-    cfg = s5.make_config(unroll=table["unroll"])
+    cfg = s5.make_config(unroll=table["unroll"],
+                         splitter_mode=s5.SPLIT_LEARNED if learned else s5.SPLIT_SAMPLED)
     perm, lcp = s5.sort_batched(to_dev(chars), to_dev(offs), to_dev(sb), cfg=cfg,
                                 tuning=s5.make_tuning(autotune.tuning_for(sizes, table)))
     torch.cuda.synchronize()
-    _check(chars, offs, perm, lcp, sb=sb, label="sets_4096")
-    # whole small sets against the oracle, element by element
+    _check(chars, offs, perm, lcp, sb=sb, label=f"sets_4096 {'learned' if learned else ''}")
+    # whole small sets against the oracle's own sort, element by element
     hp, hl = perm.cpu().numpy(), lcp.cpu().numpy()
     rng = np.random.default_rng(7)
     for s_ in rng.choice(np.flatnonzero((sizes > 1) & (sizes <= 100_000)), size=6, replace=False):

@@ -51,7 +51,12 @@ def test_oracle_callers():
         if any(m == "oracle" or m.startswith("oracle.") for m in mods):
             assert path in allowed, path
     bench = open(os.path.join(ROOT, "bench.py")).read()
-    uses = [m.start() for m in re.finditer(r"\boracle\.", bench)]
-    start = bench.index("def cpu_baseline")
-    end = bench.index("\ndef ", start + 1)
-    assert all(start < u < end for u in uses), "bench.py uses the oracle outside cpu_baseline"
+    # calls into the oracle and its imports
+    uses = [m.start() for m in re.finditer(r"\boracle\.|import oracle\b", bench)]
+    spans = []  # the CPU-baseline functions: cpu_baseline and cpu_baseline_sets
+    for m in re.finditer(r"\ndef cpu_baseline\w*\(", bench):
+        end = bench.index("\ndef ", m.start() + 1)
+        spans.append((m.start(), end))
+    assert len(spans) == 2 and uses
+    assert all(any(a < u < b for a, b in spans) for u in uses), \
+        "bench.py uses the oracle outside its CPU baselines"
