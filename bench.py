@@ -246,6 +246,7 @@ def learned_extra(name, copy_gbps=None, steps=3):
     lcp = torch.empty_like(perm)
     res, ref, D = {"workload": WORKLOAD_TEXT[name], "name": name, "n": n}, None, None
     variants = [("sampled", s5.make_config()),
+                ("sampled_equal", s5.make_config(classifier=s5.CLASSIFY_EQUAL)),
                 ("learned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED)),
                 ("learned_no_fallback", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
                                                        imbalance_bound=1e9))]
@@ -270,6 +271,7 @@ def learned_extra(name, copy_gbps=None, steps=3):
                       "entropy_bits_first_pass": st["entropy_bits"],
                       "max_bucket_first_pass": st["max_bucket"],
                       "learn_ms": prof.get("learn_splitters", {}).get("total_ms", 0.0),
+                      "classify_ms": prof.get("classify", {}).get("total_ms", 0.0),
                       "hbm": hbm_figures(D, n, st["moved_M"], sec, copy_gbps),
                       "output_identical_to_sampled": same}
         del ws
@@ -326,11 +328,12 @@ def batched_extra(steps=3, learned=None, copy_gbps=None, cpu_sample=True):
                        f"[{spec['min_size']:,}, {spec['max_size']:,}], each from one of the "
                        f"{'/'.join(spec['kinds'])} generators", "n": n, "sets": len(sizes),
            "arena_bytes": int(chars.size), "generate_s": gen_s, "tuning": table.get("source"),
-           "unroll": table["unroll"], "launches": "one hipGraph per sort (host reads back "
+           "unroll": table["unroll"], "classifier": table.get("classifier", "unroll"),
+           "launches": "one hipGraph per sort (host reads back "
            "set_begin ends and the final counters)"}
-    variants = [("learned_tuned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
-                                                  unroll=table["unroll"]), tuned),
-                ("sampled_tuned", s5.make_config(unroll=table["unroll"]), tuned),
+    variants = [("learned_tuned", autotune.launch_config(table, splitter_mode=s5.SPLIT_LEARNED),
+                 tuned),
+                ("sampled_tuned", autotune.launch_config(table), tuned),
                 ("sampled_defaults", s5.make_config(), None)]
     if learned is not None:
         variants = [v for v in variants if v[0] == ("learned_tuned" if learned else "sampled_tuned")]
@@ -512,6 +515,26 @@ def main():
         "host": host_info(),
     }
     log(f"{args.workload}: {value / 1e9:.3f} G strings/s, {ms_per_step:.3f} ms per sort")
+    if not args.no_extras:
+        # the other classification variant (Section 3.1) on the same workload
+        other = s5.CLASSIFY_EQUAL if cfg.classifier == s5.CLASSIFY_UNROLL else s5.CLASSIFY_UNROLL
+        c2 = s5.make_config(splitter_mode=cfg.splitter_mode, classifier=other)
+        ws2 = torch.empty(s5.workspace_bytes(n, c2), dtype=torch.uint8, device=dev)
+        run2 = lambda: s5.sort(d_chars, d_offs, cfg=c2, out_perm=perm, out_lcp=lcp,  # noqa
+                               workspace=ws2)
+        run2()
+        sec2 = _timed_sorts(run2, args.steps)
+        s5.profile_enable(True)
+        run2()
+        torch.cuda.synchronize()
+        cl2 = s5.profile_read().get("classify", {}).get("total_ms", 0.0)
+        s5.profile_enable(False)
+        names = {s5.CLASSIFY_UNROLL: "unroll", s5.CLASSIFY_EQUAL: "equal"}
+        out["classifier_variants"] = {
+            names[cfg.classifier]: {"ms": ms_per_step, "value": value,
+                                   "classify_ms": kernels.get("classify", {}).get("ms_per_step")},
+            names[other]: {"ms": sec2 * 1e3, "value": n / sec2, "classify_ms": cl2}}
+        del ws2
     if args.cpu_sample:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, min(args.cpu_sample, n))

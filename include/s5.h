@@ -55,6 +55,16 @@ extern "C" {
 #define S5_ERR_DEVICE (-4)  /* device status word set (a device-side capacity check failed) */
 #define S5_ERR_TOO_LARGE (-5) /* s5_sort_static: the sort needs more than the static scratch array */
 
+/* classifier: the descent through the splitter tree (Section 3.1,
+ * "Implementation Details"; the output never depends on it) */
+#define S5_CLASSIFY_UNROLL 0u /* branch-free descent of every level, one equality
+                                 test at the leaf against the in-order splitter */
+#define S5_CLASSIFY_EQUAL 1u  /* an equality test at every node; a descent stops at
+                                 the first splitter equal to its key (the bucket
+                                 index follows from the node's level-order index
+                                 by bit operations) and a wavefront leaves the tree
+                                 once all its descents have stopped */
+
 /* splitter_mode */
 #define S5_SPLIT_SAMPLED 0u /* splitters from a pseudo-random sample (Section 3.1) */
 #define S5_SPLIT_LEARNED 1u /* splitters proposed by a small learned CDF model */
@@ -83,7 +93,7 @@ typedef struct s5_config {
     uint32_t graph_levels;   /* batched sorts: distribution levels captured in the
                                 sort's hipGraph (0 = 12, at most 64); deeper inputs
                                 finish with host-driven passes after the graph */
-    uint32_t reserved;       /* must be 0 */
+    uint32_t classifier;     /* S5_CLASSIFY_UNROLL (default) or S5_CLASSIFY_EQUAL */
 } s5_config;
 
 /* Counters of the last completed sort on a stream. */
@@ -212,6 +222,16 @@ int s5_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, ui
  * 2j + 1 if splitter j equals the key, else 2j.  Buckets 0..2v. */
 int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
                 uint16_t* out_bucket, hipStream_t stream);
+
+/* s5_classify with the descent `variant` (S5_CLASSIFY_UNROLL or
+ * S5_CLASSIFY_EQUAL).  With repeated splitters the Equal variant may name a
+ * different one of the equal splitters' equality buckets than 2j + 1 (j the
+ * first equal splitter): every key equal to a splitter x_j still lands in an
+ * equality bucket of a splitter equal to it, and every other key in the range
+ * bucket between its neighbouring splitters, so the partition and its order
+ * are the same.  With distinct splitters both variants agree. */
+int s5_classify_ex(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
+                   uint32_t variant, uint16_t* out_bucket, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -7,7 +7,8 @@ sizes the tuner times the HIP sort on a synthetic probe batch of that class
 and keeps the fastest splitter count v, base-case threshold T and tile, by
 coordinate descent from the defaults; the table is kept only if it also wins
 on a batch that mixes all classes, and the interleaved descents per lane U
-(one value per launch) are tuned last on that batch.  The
+and the classification variant (Unroll or Equal, Section 3.1; one value of
+each per launch) are tuned last on that batch.  The
 result is a JSON table; ``tuning_for`` maps set sizes to per-set parameters
 for ``s5.sort_batched(..., tuning=...)``.
 
@@ -33,13 +34,22 @@ CANDIDATES = {
     "tile": [1024, 2048, 4096],
 }
 UNROLLS = [2, 4, 8]
+CLASSIFIERS = {"unroll": 0, "equal": 1}  # s5.CLASSIFY_UNROLL, s5.CLASSIFY_EQUAL
 DEFAULT = {"splitters": 255, "base_threshold": 1024, "tile": 2048}
 DEFAULT_UNROLL = 4
+DEFAULT_CLASSIFIER = "unroll"
 
 
 def default_table() -> dict:
     return {"classes": [dict(lo=lo, hi=hi, **DEFAULT) for lo, hi in SIZE_CLASSES],
-            "unroll": DEFAULT_UNROLL, "source": "defaults"}
+            "unroll": DEFAULT_UNROLL, "classifier": DEFAULT_CLASSIFIER, "source": "defaults"}
+
+
+def launch_config(table: dict, **kw):
+    """The launch-wide s5 config of a table: its U and classification variant."""
+    from . import s5
+    return s5.make_config(unroll=table.get("unroll", DEFAULT_UNROLL),
+                          classifier=CLASSIFIERS[table.get("classifier", DEFAULT_CLASSIFIER)], **kw)
 
 
 def load_table(path: str = TABLE_PATH) -> dict:
@@ -66,11 +76,19 @@ def tuning_for(set_sizes, table: dict):
     return rows
 
 
-def pick_unroll(ms: dict) -> int:
-    """The fastest U from {U: ms}, but the default unless another is clearly
-    (2 %) faster, as for the other parameters."""
+def pick_clearly_faster(ms: dict, default):
+    """The fastest choice from {choice: ms}, but the default unless another is
+    clearly (2 %) faster, as for the other parameters."""
     best = min(ms, key=ms.get)
-    return best if ms[best] < ms[DEFAULT_UNROLL] * 0.98 else DEFAULT_UNROLL
+    return best if ms[best] < ms[default] * 0.98 else default
+
+
+def pick_unroll(ms: dict) -> int:
+    return pick_clearly_faster(ms, DEFAULT_UNROLL)
+
+
+def pick_classifier(ms: dict) -> str:
+    return pick_clearly_faster(ms, DEFAULT_CLASSIFIER)
 
 
 def apply_mix_check(table: dict, table_ms: float, defaults_ms: float) -> dict:
@@ -106,12 +124,12 @@ class _Batch:
         self.perm = torch.empty(self.n, dtype=torch.uint32, device="cuda")
         self.lcp = torch.empty(self.n, dtype=torch.uint32, device="cuda")
 
-    def time(self, rows, unroll, reps=3):
+    def time(self, rows, unroll, reps=3, classifier=DEFAULT_CLASSIFIER):
         """Median wall time (ms) of the batched sort with per-set rows."""
         import torch
 
         from . import s5
-        cfg = s5.make_config(unroll=unroll)
+        cfg = s5.make_config(unroll=unroll, classifier=CLASSIFIERS[classifier])
         tun = s5.make_tuning(rows)
         s5.sort_batched(self.chars, self.offs, self.sb, cfg=cfg, tuning=tun, out_perm=self.perm,
                         out_lcp=self.lcp)  # capture / warm-up
@@ -177,6 +195,11 @@ def tune(kinds=("random", "url", "dna"), target=3_000_000, rounds=2, seed=0x70E,
     table["unroll"] = pick_unroll(ut)
     table["unroll_ms"] = ut
     log(f"unroll: {ut} -> {table['unroll']}")
+    # one classification variant for the launch, on the same batch
+    ct = {c: mix.time(rows, table["unroll"], classifier=c) for c in CLASSIFIERS}
+    table["classifier"] = pick_classifier(ct)
+    table["classifier_ms"] = ct
+    log(f"classifier: {ct} -> {table['classifier']}")
     return table
 
 

@@ -34,7 +34,7 @@ constexpr uint32_t kLearnSamples = kLearnM, kLearnSteps = 64;
 constexpr float kLearnRate = 0.03f;
 
 struct Cfg {
-    uint32_t dmax, alpha, unroll, tile_min, T, mode;
+    uint32_t dmax, alpha, unroll, tile_min, T, mode, classifier;
     uint32_t T_caps, tile_caps;  // smallest T and tile of any set: storage capacities
     float beta;
     uint32_t graph_levels;
@@ -70,6 +70,9 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     o->graph_levels = c->graph_levels ? c->graph_levels : kGraphLevels;
     if (o->graph_levels > kGraphLevelsMax) return S5_ERR_INVALID;
     o->seed = c->seed;
+    o->classifier = c->classifier;
+    if (o->classifier != S5_CLASSIFY_UNROLL && o->classifier != S5_CLASSIFY_EQUAL)
+        return S5_ERR_INVALID;
     return S5_OK;
 }
 
@@ -439,8 +442,9 @@ void pass_front(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
                            P.glob, S.seg, redo, st);
     });
     timed(K_CLASSIFY, S.now.moved, st, [&] {
-        launch_classify(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.key[buf], P.tree_lo,
-                        P.tree_in, P.bid, P.cm, S.vmax, S.kmax, P.glob, S.tile, redo, st);
+        launch_classify(S.now.tiles, c.unroll, c.classifier, P.lseg[cur], P.tile_tab, P.key[buf],
+                        P.tree_lo, P.tree_in, P.bid, P.cm, S.vmax, S.kmax, P.glob, S.tile, redo,
+                        st);
     });
     timed(K_COLSCAN, S.now.moved, st, [&] {
         launch_colscan(S.now.chunks, S.kmax, P.lseg[cur], P.chunk_tab, P.cm, P.cs, P.glob,
@@ -1003,6 +1007,12 @@ int s5_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, ui
 
 int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
                 uint16_t* out_bucket, hipStream_t stream) {
+    return s5_classify_ex(keys, n, splitters, v, S5_CLASSIFY_UNROLL, out_bucket, stream);
+}
+
+int s5_classify_ex(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
+                   uint32_t variant, uint16_t* out_bucket, hipStream_t stream) {
+    if (variant != S5_CLASSIFY_UNROLL && variant != S5_CLASSIFY_EQUAL) return S5_ERR_INVALID;
     uint32_t d = 0;
     while (d < 11 && ((1u << d) - 1) < v) ++d;
     if (v < 1 || v > 1023 || ((1u << d) - 1) != v || !splitters) return S5_ERR_INVALID;
@@ -1013,7 +1023,7 @@ int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uin
     if (rc) return rc;
     uint64_t* tlo = (uint64_t*)P->ptr;
     uint64_t* tin = tlo + (v + 1);
-    launch_classify_plain(keys, n, splitters, v, d, tlo, tin, out_bucket, stream);
+    launch_classify_plain(keys, n, splitters, v, d, variant, tlo, tin, out_bucket, stream);
     if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
     // the pool may be reused by the next call: finish before returning
     return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;

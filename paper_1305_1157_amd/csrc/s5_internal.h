@@ -20,6 +20,11 @@ constexpr int kDMax = 10;                // tree depth limit: v <= 1023 splitter
 constexpr uint32_t kLcpFlag = 0x80000000u;  // out_lcp entry still to be completed
 constexpr uint32_t kBufBit = 0x80000000u;   // work-buffer bit packed into a depth
 
+// classification variants (Section 3.1, "Implementation Details"): "Unroll"
+// descends every level without branches and tests equality once at the leaf;
+// "Equal" tests equality at every node and stops at the first equal splitter
+constexpr uint32_t kClassifyUnroll = 0, kClassifyEqual = 1;
+
 // status-word bits (device side capacity checks)
 constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrTileCap = 4u, kErrCmCap = 8u,
                    kErrTreeCap = 16u;

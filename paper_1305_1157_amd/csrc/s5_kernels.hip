@@ -576,7 +576,46 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
 // lowest lane of each group adds).  The per-wavefront histograms are summed
 // into the tile's row of the count matrix.
 
+// The Equal variant for U interleaved keys: level by level, every descent not
+// yet finished tests its node for equality and steps down; the wavefront
+// leaves the tree as soon as none of its descents is still going (so inputs
+// with many keys equal to splitters near the root stop early).
 template <int U>
+__device__ __forceinline__ void classify_equal_u(const uint64_t* t, uint32_t d,
+                                                 const uint64_t (&key)[U], uint32_t (&b)[U]) {
+    uint32_t i[U];
+    bool done[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        i[q] = 1;
+        done[q] = false;
+        b[q] = 0;
+    }
+    for (uint32_t L = 0; L < d; ++L) {
+        bool going = false;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            equal_step(t, d, key[q], i[q], done[q], b[q]);
+            going = going || !done[q];
+        }
+        if (!__ballot(going)) break;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+        if (!done[q]) b[q] = equal_leaf_bucket(i[q], d);
+}
+
+template <int U, bool EQ>
+__device__ __forceinline__ void classify_keys(const uint64_t* t, const uint64_t* tin, uint32_t d,
+                                              uint32_t v, const uint64_t (&kk)[U],
+                                              uint32_t (&b)[U]) {
+    if (EQ)
+        classify_equal_u<U>(t, d, kk, b);
+    else
+        classify_u<U>(t, tin, d, v, kk, b);
+}
+
+template <int U, bool EQ>
 __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, const LSeg* lseg,
                                               const uint32_t* tile_tab, const uint64_t* key_in,
                                               const uint64_t* tree_lo, const uint64_t* tree_in,
@@ -613,7 +652,7 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
             valid[q] = pos < end;
             kk[q] = valid[q] ? key_in[pos] : 0ull;
         }
-        classify_u<U>(t, tin, g.d, g.v, kk, b);
+        classify_keys<U, EQ>(t, tin, g.d, g.v, kk, b);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const uint32_t pos = c + q * 64 + lane;
@@ -642,7 +681,7 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
     }
 }
 
-template <int U, bool G>
+template <int U, bool G, bool EQ>
 __global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32_t* tile_tab,
                                                   const uint64_t* key_in, const uint64_t* tree_lo,
                                                   const uint64_t* tree_in, uint16_t* bid,
@@ -650,13 +689,14 @@ __global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32
                                                   const uint32_t* wcnt, uint32_t cap,
                                                   const Globals* glob, uint32_t redo) {
     if (!G) {
-        classify_body<U>(blockIdx.x, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax,
-                         kmax);
+        classify_body<U, EQ>(blockIdx.x, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm,
+                             vmax, kmax);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        classify_body<U>(u, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax, kmax);
+        classify_body<U, EQ>(u, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax,
+                             kmax);
         __syncthreads();
     }
 }
@@ -1746,7 +1786,7 @@ __global__ __launch_bounds__(256) void k_tree_from_sorted(const uint64_t* splitt
     }
 }
 
-template <int U>
+template <int U, bool EQ>
 __global__ __launch_bounds__(256) void k_classify_plain(const uint64_t* keys, uint32_t n,
                                                         const uint64_t* tree_lo,
                                                         const uint64_t* tree_in, uint32_t v,
@@ -1767,7 +1807,7 @@ __global__ __launch_bounds__(256) void k_classify_plain(const uint64_t* keys, ui
         uint32_t pos = base + q * kWG + threadIdx.x;
         kk[q] = pos < n ? keys[pos] : 0ull;
     }
-    classify_u<U>(t, tin, d, v, kk, b);
+    classify_keys<U, EQ>(t, tin, d, v, kk, b);
 #pragma unroll
     for (int q = 0; q < U; ++q) {
         uint32_t pos = base + q * kWG + threadIdx.x;
@@ -1853,20 +1893,25 @@ void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_
                   dy.cap, glob, redo);
 }
 
-void launch_classify(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
-                     const uint64_t* key_in, const uint64_t* tree_lo, const uint64_t* tree_in,
-                     uint16_t* bid, uint32_t* cm, uint32_t vmax, uint32_t kmax,
-                     const Globals* glob, const Dyn& dy, uint32_t redo, hipStream_t st) {
+void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LSeg* lseg,
+                     const uint32_t* tile_tab, const uint64_t* key_in, const uint64_t* tree_lo,
+                     const uint64_t* tree_in, uint16_t* bid, uint32_t* cm, uint32_t vmax,
+                     uint32_t kmax, const Globals* glob, const Dyn& dy, uint32_t redo,
+                     hipStream_t st) {
     size_t lds = (size_t)(vmax + 1) * 16 + (size_t)kWaves * kmax * 4;
     dim3 grid(dyn_grid(dy, tiles));
+#define S5_CLASSIFY_GE(U, GG, EE)                                                            \
+    S5_LAUNCH((k_classify<U, GG, EE>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in,       \
+              tree_lo, tree_in, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo)
 #define S5_CLASSIFY(U)                                                                       \
     do {                                                                                     \
-        if (dy.cnt)                                                                          \
-            S5_LAUNCH((k_classify<U, true>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in,  \
-                      tree_lo, tree_in, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo);     \
-        else                                                                                 \
-            S5_LAUNCH((k_classify<U, false>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in, \
-                      tree_lo, tree_in, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo);     \
+        if (dy.cnt) {                                                                        \
+            if (variant == kClassifyEqual) S5_CLASSIFY_GE(U, true, true);                    \
+            else S5_CLASSIFY_GE(U, true, false);                                             \
+        } else {                                                                             \
+            if (variant == kClassifyEqual) S5_CLASSIFY_GE(U, false, true);                   \
+            else S5_CLASSIFY_GE(U, false, false);                                            \
+        }                                                                                    \
     } while (0)
     switch (unroll) {
         case 1: S5_CLASSIFY(1); break;
@@ -1875,6 +1920,7 @@ void launch_classify(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const ui
         default: S5_CLASSIFY(4); break;
     }
 #undef S5_CLASSIFY
+#undef S5_CLASSIFY_GE
 }
 
 void launch_colscan(uint32_t chunks, uint32_t kmax, const LSeg* lseg, const uint32_t* chunk_tab,
@@ -2009,12 +2055,17 @@ void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_
 }
 
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,
-                           uint32_t v, uint32_t d, uint64_t* tree_lo, uint64_t* tree_in,
-                           uint16_t* out, hipStream_t st) {
+                           uint32_t v, uint32_t d, uint32_t variant, uint64_t* tree_lo,
+                           uint64_t* tree_in, uint16_t* out, hipStream_t st) {
     S5_LAUNCH(k_tree_from_sorted, dim3(1), dim3(kWG), 0, st, splitters, v, d, tree_lo, tree_in);
     if (!n) return;
-    S5_LAUNCH(k_classify_plain<4>, dim3((n + kWG * 4 - 1) / (kWG * 4)), dim3(kWG),
-              (size_t)(v + 1) * 16, st, keys, n, tree_lo, tree_in, v, d, out);
+    const dim3 grid((n + kWG * 4 - 1) / (kWG * 4));
+    if (variant == kClassifyEqual)
+        S5_LAUNCH((k_classify_plain<4, true>), grid, dim3(kWG), (size_t)(v + 1) * 16, st, keys, n,
+                  tree_lo, tree_in, v, d, out);
+    else
+        S5_LAUNCH((k_classify_plain<4, false>), grid, dim3(kWG), (size_t)(v + 1) * 16, st, keys,
+                  n, tree_lo, tree_in, v, d, out);
 }
 
 }  // namespace s5

@@ -25,10 +25,11 @@ void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_
                         uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* tile_tab,
                         uint32_t* chunk_tab, Counters* next_cnt, const Globals* glob,
                         const Dyn& dy, uint32_t redo, hipStream_t st);
-void launch_classify(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
-                     const uint64_t* key_in, const uint64_t* tree_lo, const uint64_t* tree_in,
-                     uint16_t* bid, uint32_t* cm, uint32_t vmax, uint32_t kmax,
-                     const Globals* glob, const Dyn& dy, uint32_t redo, hipStream_t st);
+void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LSeg* lseg,
+                     const uint32_t* tile_tab, const uint64_t* key_in, const uint64_t* tree_lo,
+                     const uint64_t* tree_in, uint16_t* bid, uint32_t* cm, uint32_t vmax,
+                     uint32_t kmax, const Globals* glob, const Dyn& dy, uint32_t redo,
+                     hipStream_t st);
 void launch_colscan(uint32_t chunks, uint32_t kmax, const LSeg* lseg, const uint32_t* chunk_tab,
                     uint32_t* cm, uint32_t* cs, const Globals* glob, const Dyn& dy, uint32_t redo,
                     hipStream_t st);
@@ -53,8 +54,8 @@ void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_
                     uint32_t num_sets, uint32_t n, const uint32_t* out_perm, uint32_t* out_lcp,
                     const uint32_t* guard, const Globals* glob, hipStream_t st);
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,
-                           uint32_t v, uint32_t d, uint64_t* tree_lo, uint64_t* tree_in,
-                           uint16_t* out, hipStream_t st);
+                           uint32_t v, uint32_t d, uint32_t variant, uint64_t* tree_lo,
+                           uint64_t* tree_in, uint16_t* out, hipStream_t st);
 
 // Counting of output writes for later sorts (the write-check build; returns
 // false in the product build, where S5_OUT is a plain store).

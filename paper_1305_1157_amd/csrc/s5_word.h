@@ -171,6 +171,30 @@ S5_HD uint32_t inorder_node(uint32_t j, uint32_t d) {
     return (1u << L) + (t >> (d - L));
 }
 
+// in-order index of the splitter at level-order node i (1-based heap index,
+// 1 <= i < 2^d) of a perfect tree of depth d: the inverse of inorder_node
+S5_HD uint32_t node_inorder(uint32_t i, uint32_t d) {
+    const uint32_t L = 31u - (uint32_t)__builtin_clz(i);
+    return ((2u * (i - (1u << L)) + 1u) << (d - 1u - L)) - 1u;
+}
+
+// One level of the "Equal" descent (Section 3.1, the variant that tests for
+// equality at every node and leaves the tree at the first splitter equal to
+// the key): at node i, a key equal to its splitter is done, in the equality
+// bucket 2j + 1 of the node's in-order index j (bit operations on i, no
+// in-order array); otherwise i = 2i + [key > x_i].  Branch-free: a finished
+// descent keeps its node.  After d levels, an unfinished descent sits at leaf
+// i and its bucket is equal_leaf_bucket(i, d).
+S5_HD void equal_step(const uint64_t* t, uint32_t d, uint64_t key, uint32_t& i, bool& done,
+                      uint32_t& b) {
+    const uint64_t x = t[i];
+    const bool eq = !done && key == x;
+    b = eq ? 2u * node_inorder(i, d) + 1u : b;
+    done = done || eq;
+    i = done ? i : 2u * i + (key > x ? 1u : 0u);
+}
+S5_HD uint32_t equal_leaf_bucket(uint32_t i, uint32_t d) { return 2u * (i - (1u << d)); }
+
 // U interleaved branch-free descents followed by one equality test each
 // (Section 3.1: the "unrolled" variant that only uses <= comparisons on the
 // way down).  t: level order, t[1..v]; tin: in order, tin[0..v).

@@ -18,8 +18,10 @@ S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP, S5_ERR_DEVICE = 0, -1, -2, -3, 
 S5_ERR_TOO_LARGE = -5
 STATIC_SCRATCH_BYTES = 64 << 20  # S5_STATIC_SCRATCH_BYTES
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
+CLASSIFY_UNROLL, CLASSIFY_EQUAL = 0, 1
 
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_sort_batched",
+           "s5_classify_ex",
            "s5_sort_batched_tuned", "s5_stats_get",
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
            "s5_profile_only",
@@ -32,7 +34,7 @@ class Config(ctypes.Structure):
                 ("unroll", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("base_threshold", ctypes.c_uint32), ("splitter_mode", ctypes.c_uint32),
                 ("imbalance_bound", ctypes.c_float), ("seed", ctypes.c_uint64),
-                ("graph_levels", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("graph_levels", ctypes.c_uint32), ("classifier", ctypes.c_uint32)]
 
 
 class SetTuning(ctypes.Structure):
@@ -104,6 +106,7 @@ def _open(path: str):
     lib.s5_release.restype = None
     lib.s5_prefix_keys.argtypes = [P, P, U32, U32, P, P]
     lib.s5_classify.argtypes = [P, U32, P, U32, P, P]
+    lib.s5_classify_ex.argtypes = [P, U32, P, U32, U32, P, P]
     lib.s5_mlp_train.argtypes = [P, U32, U32, ctypes.c_float, U64, P, P]
     lib.s5_mlp_grad.argtypes = [P, P, U32, P, P]
     lib.s5_mlp_eval.argtypes = [P, P, U32, U64, U64, P, P]
@@ -115,7 +118,7 @@ def _open(path: str):
     lib.s5_debug_limit_capacity.argtypes = [U32, U32]
     lib.s5_debug_count_writes.argtypes = [P, P, U64, P, P, P]
     for f in ("s5_debug_limit_capacity", "s5_debug_count_writes", "s5_sort", "s5_sort_ex",
-              "s5_sort_static", "s5_sort_batched", "s5_sort_batched_tuned", "s5_stats_get",
+              "s5_sort_static", "s5_sort_batched", "s5_classify_ex", "s5_sort_batched_tuned", "s5_stats_get",
               "s5_prefix_keys",
               "s5_classify", "s5_profile_enable", "s5_profile_read", "s5_mlp_train", "s5_mlp_grad",
               "s5_mlp_eval", "s5_mlp_propose"):
@@ -148,9 +151,9 @@ def _dev(t: torch.Tensor, dtype, name: str):
 
 def make_config(splitters=0, oversample=0, unroll=0, tile=0, base_threshold=0,
                 splitter_mode=SPLIT_SAMPLED, imbalance_bound=0.0, seed=0,
-                graph_levels=0) -> Config:
+                graph_levels=0, classifier=CLASSIFY_UNROLL) -> Config:
     return Config(splitters, oversample, unroll, tile, base_threshold, splitter_mode,
-                  imbalance_bound, seed, graph_levels, 0)
+                  imbalance_bound, seed, graph_levels, classifier)
 
 
 def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,
@@ -268,13 +271,14 @@ def prefix_keys(chars: torch.Tensor, offsets: torch.Tensor, depth: int = 0, stre
     return keys
 
 
-def classify(keys: torch.Tensor, splitters: torch.Tensor, stream=None):
+def classify(keys: torch.Tensor, splitters: torch.Tensor, variant: int = CLASSIFY_UNROLL,
+             stream=None):
     """Ternary bucket (uint16) of every key against sorted splitters (2^d - 1 of them)."""
     n = keys.numel()
     out = torch.empty(n, dtype=torch.uint16, device=keys.device)
-    _check(load().s5_classify(_dev(keys, torch.uint64, "keys"), n,
-                              _dev(splitters, torch.uint64, "splitters"), splitters.numel(),
-                              _dev(out, torch.uint16, "out"), _stream(stream)))
+    _check(load().s5_classify_ex(_dev(keys, torch.uint64, "keys"), n,
+                                 _dev(splitters, torch.uint64, "splitters"), splitters.numel(),
+                                 variant, _dev(out, torch.uint16, "out"), _stream(stream)))
     return out
 
 

@@ -262,6 +262,51 @@ static void test_tree_and_classify(std::mt19937_64& rng) {
     }
 }
 
+// the Equal descent run to the end on the host (no early exit: a finished
+// descent keeps its node and its bucket)
+static uint32_t equal_classify(const std::vector<uint64_t>& t, uint32_t d, uint64_t key) {
+    uint32_t i = 1, b = 0;
+    bool done = false;
+    for (uint32_t L = 0; L < d; ++L) equal_step(t.data(), d, key, i, done, b);
+    return done ? b : equal_leaf_bucket(i, d);
+}
+
+static void test_node_inorder() {
+    for (uint32_t d = 1; d <= 10; ++d)
+        for (uint32_t j = 0; j < (1u << d) - 1; ++j)
+            CHECK(node_inorder(inorder_node(j, d), d) == j, "node_inorder d %u j %u", d, j);
+}
+
+static void test_equal_variant(std::mt19937_64& rng) {
+    for (int rep = 0; rep < 300; ++rep) {
+        uint32_t d = 1 + rng() % 10, v = (1u << d) - 1;
+        uint32_t m = 1 + rng() % (4 * (v + 1));
+        uint32_t distinct = 1 + rng() % (2 * m);
+        std::vector<uint64_t> pool(distinct);
+        for (auto& x : pool) x = rng() >> (rng() % 64);
+        std::vector<uint64_t> smp(m);
+        for (auto& x : smp) x = pool[rng() % distinct];
+        std::sort(smp.begin(), smp.end());
+        std::vector<uint64_t> t, tin;
+        build_tree(smp, d, t, tin);
+        const bool unique = std::adjacent_find(tin.begin(), tin.begin() + v) == tin.begin() + v;
+        for (int probe = 0; probe < 200; ++probe) {
+            const uint64_t key = (rng() % 2) ? pool[rng() % distinct] + (rng() % 3) - 1 : rng();
+            const uint32_t b = equal_classify(t, d, key);
+            const uint32_t j = (uint32_t)(std::lower_bound(tin.begin(), tin.begin() + v, key) -
+                                          tin.begin());
+            const bool eq = j < v && tin[j] == key;
+            if (unique) {  // distinct splitters: exactly 2 lower_bound + [equal]
+                CHECK(b == 2 * j + (eq ? 1u : 0u), "equal d %u got %u want %u", d, b, 2 * j + eq);
+            } else if (eq) {  // an equality bucket of a splitter equal to the key
+                CHECK((b & 1u) && b / 2 < v && tin[b / 2] == key, "equal dup d %u b %u", d, b);
+            } else {  // the range bucket between the neighbouring splitters
+                CHECK(b == 2 * j, "equal range d %u got %u want %u", d, b, 2 * j);
+            }
+        }
+    }
+}
+
 static void test_fig1(const char* path) {
     FILE* f = fopen(path, "r");
     CHECK(f != nullptr, "open %s", path);
@@ -299,6 +344,8 @@ static void test_fig1(const char* path) {
         classify_u<1>(t.data(), tin.data(), 2, 3, key, b);
         CHECK(b[0] == pr.second, "fig1 probe %llx got %u want %u", (unsigned long long)pr.first,
               b[0], pr.second);
+        CHECK(equal_classify(t, 2, pr.first) == pr.second, "fig1 equal probe %llx",
+              (unsigned long long)pr.first);
     }
 }
 
@@ -309,6 +356,8 @@ int main(int argc, char** argv) {
     test_advance_key16(rng);
     test_inorder_map();
     test_tree_and_classify(rng);
+    test_node_inorder();
+    test_equal_variant(rng);
     if (argc > 1) test_fig1(argv[1]);
     if (failures) {
         printf("%d failures\n", failures);

@@ -72,3 +72,13 @@ def test_committed_table_passed_its_mix_check():
             [(c["splitters"], c["base_threshold"], c["tile"]) for c in defaults]
     else:
         assert mc["table_ms"] < 0.98 * mc["defaults_ms"]
+
+
+def test_launch_choices_need_a_clear_win():
+    assert autotune.pick_unroll({2: 1.0, 4: 1.01, 8: 1.1}) == 4
+    assert autotune.pick_unroll({2: 0.9, 4: 1.0, 8: 1.1}) == 2
+    assert autotune.pick_classifier({"unroll": 1.0, "equal": 0.99}) == "unroll"
+    assert autotune.pick_classifier({"unroll": 1.0, "equal": 0.97}) == "equal"
+    t = autotune.default_table()
+    assert t["classifier"] in autotune.CLASSIFIERS
+    assert autotune.load_table().get("classifier", "unroll") in autotune.CLASSIFIERS

@@ -61,8 +61,8 @@ def test_full_batched_graph(learned):
     chars, offs, sb = gen.batched(**spec)
     sizes = np.diff(sb).astype(np.int64)
     table = autotune.load_table()
-    cfg = s5.make_config(unroll=table["unroll"],
-                         splitter_mode=s5.SPLIT_LEARNED if learned else s5.SPLIT_SAMPLED)
+    cfg = autotune.launch_config(
+        table, splitter_mode=s5.SPLIT_LEARNED if learned else s5.SPLIT_SAMPLED)
     perm, lcp = s5.sort_batched(to_dev(chars), to_dev(offs), to_dev(sb), cfg=cfg,
                                 tuning=s5.make_tuning(autotune.tuning_for(sizes, table)))
     torch.cuda.synchronize()

@@ -23,6 +23,10 @@ CFGS = {
     "v1023_u8": s5.make_config(splitters=1023, unroll=8, base_threshold=2048),
     "v31_u1_T128": s5.make_config(splitters=31, unroll=1, base_threshold=128, tile=128),
     "v63_u2_a4": s5.make_config(splitters=63, unroll=2, oversample=4, base_threshold=256),
+    "equal": s5.make_config(classifier=s5.CLASSIFY_EQUAL),
+    "equal_v7_u1_T64": s5.make_config(classifier=s5.CLASSIFY_EQUAL, splitters=7, unroll=1,
+                                      base_threshold=64, tile=64),
+    "equal_v1023_u8": s5.make_config(classifier=s5.CLASSIFY_EQUAL, splitters=1023, unroll=8),
 }
 
 
@@ -57,13 +61,41 @@ def test_classify_vs_searchsorted():
         assert np.array_equal(got, want), v
 
 
+def test_classify_equal_variant():
+    """The Equal descent: with distinct splitters exactly 2 lower_bound + [equal];
+    with repeated splitters every key equal to a splitter lands in an equality
+    bucket of a splitter equal to it and every other key in the range bucket
+    between its neighbours."""
+    rng = np.random.default_rng(6)
+    for v in (1, 3, 7, 255, 1023):
+        for dup in (False, True):
+            spl = np.sort(rng.integers(0, 2**63, size=v, dtype=np.uint64))
+            if dup and v > 3:
+                spl[v // 3: v // 3 + 5] = spl[v // 3]  # a run of repeated splitters
+                spl = np.sort(spl)
+            keys = np.concatenate([rng.integers(0, 2**63, size=5000, dtype=np.uint64), spl,
+                                   spl + np.uint64(1), np.array([0, 2**64 - 1], dtype=np.uint64)])
+            got = s5.classify(to_dev(keys), to_dev(spl), s5.CLASSIFY_EQUAL).cpu().numpy()
+            got = got.astype(np.int64)
+            j = np.searchsorted(spl, keys, side="left")
+            eq = (j < v) & (spl[np.minimum(j, v - 1)] == keys)
+            if not dup or v <= 3:
+                assert np.array_equal(got, 2 * j + eq), v
+            else:
+                odd = (got & 1) == 1
+                assert np.array_equal(odd, eq), v
+                assert np.all(spl[np.minimum(got[odd] // 2, v - 1)] == keys[odd])
+                assert np.array_equal(got[~eq], 2 * j[~eq])
+
+
 def test_fig1_tree():
     spl = np.array([0x6161610000000000, 0x6D6D6D0000000000, 0x7878780000000000], dtype=np.uint64)
     keys = np.array([0, 0x6161600000000000, 0x6161610000000000, 0x6161610000000001,
                      0x6A00000000000000, 0x6D6D6D0000000000, 0x6D6D6D6100000000,
                      0x7878780000000000, 0x7878780100000000, 2**64 - 1], dtype=np.uint64)
-    got = s5.classify(to_dev(keys), to_dev(spl)).cpu().numpy().tolist()
-    assert got == [0, 0, 1, 2, 2, 3, 4, 5, 6, 6]
+    for variant in (s5.CLASSIFY_UNROLL, s5.CLASSIFY_EQUAL):
+        got = s5.classify(to_dev(keys), to_dev(spl), variant).cpu().numpy().tolist()
+        assert got == [0, 0, 1, 2, 2, 3, 4, 5, 6, 6]
 
 
 EDGE = {
@@ -101,7 +133,7 @@ EDGE.update({
 
 
 @pytest.mark.parametrize("name", sorted(EDGE))
-@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "v1023_u8"])
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "v1023_u8", "equal_v7_u1_T64"])
 def test_edge_cases(name, cfg):
     strings_parity(EDGE[name], CFGS[cfg], label=f"{name}/{cfg}")
 
@@ -196,7 +228,7 @@ def test_no_writes_outside_outputs_and_workspace(name, n, cfg):
         assert (h[:pad] == fill).all() and (h[pad + n:] == fill).all()
 
 
-@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7"])
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "equal"])
 def test_batched_small(cfg):
     chars, offs, sb = gen.batched(60, 1, 5000, kinds=("random", "url", "dna", "words"), seed=7)
     # include empty sets and single-string sets
