@@ -247,6 +247,7 @@ def learned_extra(name, copy_gbps=None, steps=3):
     res, ref, D = {"workload": WORKLOAD_TEXT[name], "name": name, "n": n}, None, None
     variants = [("sampled", s5.make_config()),
                 ("sampled_equal", s5.make_config(classifier=s5.CLASSIFY_EQUAL)),
+                ("sampled_jump", s5.make_config(classifier=s5.CLASSIFY_JUMP)),
                 ("learned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED)),
                 ("learned_no_fallback", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
                                                        imbalance_bound=1e9))]
@@ -516,25 +517,30 @@ def main():
     }
     log(f"{args.workload}: {value / 1e9:.3f} G strings/s, {ms_per_step:.3f} ms per sort")
     if not args.no_extras:
-        # the other classification variant (Section 3.1) on the same workload
-        other = s5.CLASSIFY_EQUAL if cfg.classifier == s5.CLASSIFY_UNROLL else s5.CLASSIFY_UNROLL
-        c2 = s5.make_config(splitter_mode=cfg.splitter_mode, classifier=other)
-        ws2 = torch.empty(s5.workspace_bytes(n, c2), dtype=torch.uint8, device=dev)
-        run2 = lambda: s5.sort(d_chars, d_offs, cfg=c2, out_perm=perm, out_lcp=lcp,  # noqa
-                               workspace=ws2)
-        run2()
-        sec2 = _timed_sorts(run2, args.steps)
-        s5.profile_enable(True)
-        run2()
-        torch.cuda.synchronize()
-        cl2 = s5.profile_read().get("classify", {}).get("total_ms", 0.0)
-        s5.profile_enable(False)
-        names = {s5.CLASSIFY_UNROLL: "unroll", s5.CLASSIFY_EQUAL: "equal"}
+        # the other classification variants (Section 3.1; appendix A jump
+        # tables) on the same workload
+        names = {s5.CLASSIFY_UNROLL: "unroll", s5.CLASSIFY_EQUAL: "equal",
+                 s5.CLASSIFY_JUMP: "jump"}
         out["classifier_variants"] = {
             names[cfg.classifier]: {"ms": ms_per_step, "value": value,
-                                   "classify_ms": kernels.get("classify", {}).get("ms_per_step")},
-            names[other]: {"ms": sec2 * 1e3, "value": n / sec2, "classify_ms": cl2}}
-        del ws2
+                                   "classify_ms": kernels.get("classify", {}).get("ms_per_step")}}
+        for other in names:
+            if other == cfg.classifier:
+                continue
+            c2 = s5.make_config(splitter_mode=cfg.splitter_mode, classifier=other)
+            ws2 = torch.empty(s5.workspace_bytes(n, c2), dtype=torch.uint8, device=dev)
+            run2 = lambda: s5.sort(d_chars, d_offs, cfg=c2, out_perm=perm, out_lcp=lcp,  # noqa
+                                   workspace=ws2)
+            run2()
+            sec2 = _timed_sorts(run2, args.steps)
+            s5.profile_enable(True)
+            run2()
+            torch.cuda.synchronize()
+            cl2 = s5.profile_read().get("classify", {}).get("total_ms", 0.0)
+            s5.profile_enable(False)
+            out["classifier_variants"][names[other]] = {"ms": sec2 * 1e3, "value": n / sec2,
+                                                        "classify_ms": cl2}
+            del ws2
     if args.cpu_sample:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, min(args.cpu_sample, n))

@@ -64,6 +64,14 @@ extern "C" {
                                  index follows from the node's level-order index
                                  by bit operations) and a wavefront leaves the tree
                                  once all its descents have stopped */
+#define S5_CLASSIFY_JUMP 2u   /* the Unroll descent started from a jump table
+                                 (appendix A, "Jump tables"): the bits of a key
+                                 after the common prefix of the first and last
+                                 splitter (up to d + 2 of them, at most 12) index a
+                                 table, built with the tree, of the node where
+                                 the path stops being the same for all keys
+                                 with those bits; keys outside the splitter
+                                 range take buckets 0 and 2v directly */
 
 /* splitter_mode */
 #define S5_SPLIT_SAMPLED 0u /* splitters from a pseudo-random sample (Section 3.1) */
@@ -93,7 +101,8 @@ typedef struct s5_config {
     uint32_t graph_levels;   /* batched sorts: distribution levels captured in the
                                 sort's hipGraph (0 = 12, at most 64); deeper inputs
                                 finish with host-driven passes after the graph */
-    uint32_t classifier;     /* S5_CLASSIFY_UNROLL (default) or S5_CLASSIFY_EQUAL */
+    uint32_t classifier;     /* S5_CLASSIFY_UNROLL (default), S5_CLASSIFY_EQUAL or
+                                S5_CLASSIFY_JUMP */
 } s5_config;
 
 /* Counters of the last completed sort on a stream. */
@@ -223,8 +232,8 @@ int s5_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n, ui
 int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
                 uint16_t* out_bucket, hipStream_t stream);
 
-/* s5_classify with the descent `variant` (S5_CLASSIFY_UNROLL or
- * S5_CLASSIFY_EQUAL).  With repeated splitters the Equal variant may name a
+/* s5_classify with the descent `variant` (S5_CLASSIFY_UNROLL, S5_CLASSIFY_EQUAL
+ * or S5_CLASSIFY_JUMP; Jump gives exactly the Unroll buckets).  With repeated splitters the Equal variant may name a
  * different one of the equal splitters' equality buckets than 2j + 1 (j the
  * first equal splitter): every key equal to a splitter x_j still lands in an
  * equality bucket of a splitter equal to it, and every other key in the range

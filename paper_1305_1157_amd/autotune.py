@@ -7,8 +7,9 @@ sizes the tuner times the HIP sort on a synthetic probe batch of that class
 and keeps the fastest splitter count v, base-case threshold T and tile, by
 coordinate descent from the defaults; the table is kept only if it also wins
 on a batch that mixes all classes, and the interleaved descents per lane U
-and the classification variant (Unroll or Equal, Section 3.1; one value of
-each per launch) are tuned last on that batch.  The
+and the classification variant (Unroll or Equal, Section 3.1, or Unroll with
+a jump table, appendix A; one value of each per launch) are tuned last on that
+batch.  The
 result is a JSON table; ``tuning_for`` maps set sizes to per-set parameters
 for ``s5.sort_batched(..., tuning=...)``.
 
@@ -34,7 +35,7 @@ CANDIDATES = {
     "tile": [1024, 2048, 4096],
 }
 UNROLLS = [2, 4, 8]
-CLASSIFIERS = {"unroll": 0, "equal": 1}  # s5.CLASSIFY_UNROLL, s5.CLASSIFY_EQUAL
+CLASSIFIERS = {"unroll": 0, "equal": 1, "jump": 2}  # s5.CLASSIFY_UNROLL / _EQUAL / _JUMP
 DEFAULT = {"splitters": 255, "base_threshold": 1024, "tile": 2048}
 DEFAULT_UNROLL = 4
 DEFAULT_CLASSIFIER = "unroll"

@@ -71,7 +71,8 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     if (o->graph_levels > kGraphLevelsMax) return S5_ERR_INVALID;
     o->seed = c->seed;
     o->classifier = c->classifier;
-    if (o->classifier != S5_CLASSIFY_UNROLL && o->classifier != S5_CLASSIFY_EQUAL)
+    if (o->classifier != S5_CLASSIFY_UNROLL && o->classifier != S5_CLASSIFY_EQUAL &&
+        o->classifier != S5_CLASSIFY_JUMP)
         return S5_ERR_INVALID;
     return S5_OK;
 }
@@ -87,9 +88,10 @@ uint32_t limited(uint32_t cap, uint32_t which) {
 
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
-    size_t key[2], key2[2], key3, idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, cm, cs,
+    size_t key[2], key2[2], key3, idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, jump, cm, cs,
         bstart, base_list, learn, learn_seg, set_tune, counters[2], glob, total;
     uint32_t learn_cap, tune_sets;
+    bool has_jump;
     Caps caps;
 };
 
@@ -137,6 +139,9 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     L.tree_lo = take((size_t)cp.tree * 8);
     L.tree_in = take((size_t)cp.tree * 8);
     L.tree_lcp = take((size_t)cp.tree);
+    // jump tables (Jump classification only): kJumpPerTreeSlot entries per tree slot
+    L.has_jump = c.classifier == S5_CLASSIFY_JUMP;
+    L.jump = take(L.has_jump ? (size_t)cp.tree * kJumpPerTreeSlot * 2 : 0);
     L.cm = take((size_t)cp.cm * 4);
     L.cs = take((size_t)cp.cs * 4);
     L.bstart = take((size_t)cp.bstart * 4);
@@ -324,6 +329,7 @@ struct Ptrs {
     uint32_t *tile_tab, *chunk_tab;
     uint64_t *tree_lo, *tree_in;
     uint8_t* tree_lcp;
+    uint16_t* jump;  // jump tables, or null when the classification does not use them
     uint32_t *cm, *cs, *bstart, *learn_seg, *set_tune;
     LearnCtx lctx;
     Seg* base_list[kBaseClasses];
@@ -347,6 +353,7 @@ Ptrs make_ptrs(const Layout& L, char* W) {
     P.tree_lo = (uint64_t*)(W + L.tree_lo);
     P.tree_in = (uint64_t*)(W + L.tree_in);
     P.tree_lcp = (uint8_t*)(W + L.tree_lcp);
+    P.jump = L.has_jump ? (uint16_t*)(W + L.jump) : nullptr;
     P.cm = (uint32_t*)(W + L.cm);
     P.cs = (uint32_t*)(W + L.cs);
     P.bstart = (uint32_t*)(W + L.bstart);
@@ -433,18 +440,18 @@ void pass_front(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
         timed(K_LEARN, S.n_learn, st, [&] {
             launch_learn_sort_trees(P.lctx, S.n_learn, P.lseg[cur], P.learn_seg, P.key[buf],
                                     c.seed, kLearnSteps, kLearnRate, c.beta, P.glob, P.tree_lo,
-                                    P.tree_in, P.tree_lcp, S.learn, st);
+                                    P.tree_in, P.tree_lcp, P.jump, S.learn, st);
         });
     }
     timed(K_SAMPLE, S.now.n_large, st, [&] {
         launch_sample_tree(S.now.n_large, P.lseg[cur], P.key[buf], c.alpha, S.vmax, c.seed,
-                           P.tree_lo, P.tree_in, P.tree_lcp, P.tile_tab, P.chunk_tab, P.cnt[nxt],
-                           P.glob, S.seg, redo, st);
+                           P.tree_lo, P.tree_in, P.tree_lcp, P.jump, P.tile_tab, P.chunk_tab,
+                           P.cnt[nxt], P.glob, S.seg, redo, st);
     });
     timed(K_CLASSIFY, S.now.moved, st, [&] {
         launch_classify(S.now.tiles, c.unroll, c.classifier, P.lseg[cur], P.tile_tab, P.key[buf],
-                        P.tree_lo, P.tree_in, P.bid, P.cm, S.vmax, S.kmax, P.glob, S.tile, redo,
-                        st);
+                        P.tree_lo, P.tree_in, P.jump, P.bid, P.cm, S.vmax, S.kmax, P.glob, S.tile,
+                        redo, st);
     });
     timed(K_COLSCAN, S.now.moved, st, [&] {
         launch_colscan(S.now.chunks, S.kmax, P.lseg[cur], P.chunk_tab, P.cm, P.cs, P.glob,
@@ -1012,18 +1019,21 @@ int s5_classify(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uin
 
 int s5_classify_ex(const uint64_t* keys, uint32_t n, const uint64_t* splitters, uint32_t v,
                    uint32_t variant, uint16_t* out_bucket, hipStream_t stream) {
-    if (variant != S5_CLASSIFY_UNROLL && variant != S5_CLASSIFY_EQUAL) return S5_ERR_INVALID;
+    if (variant != S5_CLASSIFY_UNROLL && variant != S5_CLASSIFY_EQUAL &&
+        variant != S5_CLASSIFY_JUMP)
+        return S5_ERR_INVALID;
     uint32_t d = 0;
     while (d < 11 && ((1u << d) - 1) < v) ++d;
     if (v < 1 || v > 1023 || ((1u << d) - 1) != v || !splitters) return S5_ERR_INVALID;
     if (n > 0 && (!keys || !out_bucket)) return S5_ERR_INVALID;
     std::lock_guard<std::mutex> g(g_mu);
     DevPool* P = nullptr;
-    int rc = pool_get((size_t)(v + 1) * 16, &P);
+    int rc = pool_get((size_t)(v + 1) * (16 + 2 * kJumpPerTreeSlot), &P);
     if (rc) return rc;
     uint64_t* tlo = (uint64_t*)P->ptr;
     uint64_t* tin = tlo + (v + 1);
-    launch_classify_plain(keys, n, splitters, v, d, variant, tlo, tin, out_bucket, stream);
+    uint16_t* jt = (uint16_t*)(tin + (v + 1));
+    launch_classify_plain(keys, n, splitters, v, d, variant, tlo, tin, jt, out_bucket, stream);
     if (hipGetLastError() != hipSuccess) return S5_ERR_HIP;
     // the pool may be reused by the next call: finish before returning
     return hipStreamSynchronize(stream) == hipSuccess ? S5_OK : S5_ERR_HIP;

@@ -23,7 +23,10 @@ constexpr uint32_t kBufBit = 0x80000000u;   // work-buffer bit packed into a dep
 // classification variants (Section 3.1, "Implementation Details"): "Unroll"
 // descends every level without branches and tests equality once at the leaf;
 // "Equal" tests equality at every node and stops at the first equal splitter
-constexpr uint32_t kClassifyUnroll = 0, kClassifyEqual = 1;
+// "Jump" is the Unroll descent started from a jump table over the top key
+// bits (appendix A, "Jump tables"); its table has 4 (v + 1) entries per tree
+constexpr uint32_t kClassifyUnroll = 0, kClassifyEqual = 1, kClassifyJump = 2;
+constexpr uint32_t kJumpPerTreeSlot = 4;
 
 // status-word bits (device side capacity checks)
 constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrTileCap = 4u, kErrCmCap = 8u,

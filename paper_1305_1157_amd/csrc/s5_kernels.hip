@@ -450,7 +450,8 @@ __device__ __forceinline__ void sample_tree_body(uint32_t slot, uint32_t redo, c
                                                  const uint64_t* key_in, uint32_t alpha,
                                                  uint64_t seed, uint64_t* tree_lo,
                                                  uint64_t* tree_in, uint8_t* tree_lcp,
-                                                 uint32_t* tile_tab, uint32_t* chunk_tab) {
+                                                 uint16_t* jump, uint32_t* tile_tab,
+                                                 uint32_t* chunk_tab) {
     extern __shared__ uint64_t smp[];  // sample, padded to a power of two
     __shared__ uint32_t ra[1u << kDMax], rb[1u << kDMax];
     __shared__ uint64_t t[1u << kDMax];
@@ -540,6 +541,8 @@ __device__ __forceinline__ void sample_tree_body(uint32_t slot, uint32_t redo, c
             lcp_out[i] = 0;
         }
     }
+    if (jump) build_jump_table(t, g.d, g.v, jump + (uint64_t)g.tree_base * kJumpPerTreeSlot,
+                               threadIdx.x, blockDim.x);
 }
 
 // One workgroup per segment (G: grid-stride over a device count, graph mode).
@@ -548,23 +551,24 @@ template <bool G>
 __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uint64_t* key_in,
                                                      uint32_t alpha, uint64_t seed,
                                                      uint64_t* tree_lo, uint64_t* tree_in,
-                                                     uint8_t* tree_lcp, uint32_t* tile_tab,
-                                                     uint32_t* chunk_tab, Counters* next_cnt,
-                                                     const uint32_t* wcnt, uint32_t cap,
-                                                     const Globals* glob, uint32_t redo) {
+                                                     uint8_t* tree_lcp, uint16_t* jump,
+                                                     uint32_t* tile_tab, uint32_t* chunk_tab,
+                                                     Counters* next_cnt, const uint32_t* wcnt,
+                                                     uint32_t cap, const Globals* glob,
+                                                     uint32_t redo) {
     // the next pass's counters are planned later in this pass: clear them here
     if (!redo && blockIdx.x == 0)
         for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += blockDim.x)
             ((uint32_t*)next_cnt)[i] = 0;
     if (!G) {
         sample_tree_body(blockIdx.x, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp,
-                         tile_tab, chunk_tab);
+                         jump, tile_tab, chunk_tab);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        sample_tree_body(u, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp, tile_tab,
-                         chunk_tab);
+        sample_tree_body(u, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp, jump,
+                         tile_tab, chunk_tab);
         __syncthreads();
     }
 }
@@ -605,31 +609,71 @@ __device__ __forceinline__ void classify_equal_u(const uint64_t* t, uint32_t d,
         if (!done[q]) b[q] = equal_leaf_bucket(i[q], d);
 }
 
-template <int U, bool EQ>
-__device__ __forceinline__ void classify_keys(const uint64_t* t, const uint64_t* tin, uint32_t d,
-                                              uint32_t v, const uint64_t (&kk)[U],
-                                              uint32_t (&b)[U]) {
-    if (EQ)
+// The Jump variant: every descent starts at its jump-table entry (keys outside
+// the splitter range at their leaf), then descends like Unroll; the
+// wavefront stops once all its descents have reached the leaves.
+template <int U>
+__device__ __forceinline__ void classify_jump_u(const uint64_t* t, const uint64_t* tin,
+                                                const uint16_t* jt, uint32_t d, uint32_t v,
+                                                const uint64_t (&key)[U], uint32_t (&b)[U]) {
+    const uint64_t first = tin[0], last = tin[v - 1];
+    const JumpShape js = jump_shape(first, last, d);
+    const uint32_t leaf0 = 1u << d;
+    uint32_t i[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+        i[q] = key[q] < first ? leaf0 : (key[q] > last ? leaf0 + v : jt[jump_index(key[q], js)]);
+    for (uint32_t L = 0; L < d; ++L) {
+        bool going = false;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const bool g = i[q] < leaf0;
+            const uint64_t x = t[g ? i[q] : 0u];
+            i[q] = g ? 2u * i[q] + (key[q] > x ? 1u : 0u) : i[q];
+            going = going || g;
+        }
+        if (!__ballot(going)) break;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        const uint32_t j = i[q] - leaf0;
+        b[q] = 2u * j + ((j < v && tin[j] == key[q]) ? 1u : 0u);
+    }
+}
+
+template <int U, int VAR>
+__device__ __forceinline__ void classify_keys(const uint64_t* t, const uint64_t* tin,
+                                              const uint16_t* jt, uint32_t d, uint32_t v,
+                                              const uint64_t (&kk)[U], uint32_t (&b)[U]) {
+    if (VAR == (int)kClassifyEqual)
         classify_equal_u<U>(t, d, kk, b);
+    else if (VAR == (int)kClassifyJump)
+        classify_jump_u<U>(t, tin, jt, d, v, kk, b);
     else
         classify_u<U>(t, tin, d, v, kk, b);
 }
 
-template <int U, bool EQ>
+template <int U, int VAR>
 __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, const LSeg* lseg,
                                               const uint32_t* tile_tab, const uint64_t* key_in,
                                               const uint64_t* tree_lo, const uint64_t* tree_in,
-                                              uint16_t* bid, uint32_t* cm, uint32_t vmax,
-                                              uint32_t kmax) {
+                                              const uint16_t* jump, uint16_t* bid, uint32_t* cm,
+                                              uint32_t vmax, uint32_t kmax) {
     extern __shared__ uint64_t dyn[];
     uint64_t* t = dyn;
     uint64_t* tin = t + (vmax + 1);
     uint32_t* hist = (uint32_t*)(tin + (vmax + 1));  // kWaves * kmax
+    uint16_t* jt = (uint16_t*)(hist + kWaves * kmax);  // Jump: kJumpPerTreeSlot (vmax + 1)
     const LSeg g = lseg[tile_tab[tile]];
     if (redo && g.pad1 != 1u) return;
     for (uint32_t i = threadIdx.x; i <= g.v; i += kWG) {
         t[i] = tree_lo[g.tree_base + i];
         tin[i] = tree_in[g.tree_base + i];
+    }
+    if (VAR == (int)kClassifyJump) {
+        const JumpShape js = jump_shape(tree_in[g.tree_base], tree_in[g.tree_base + g.v - 1], g.d);
+        const uint16_t* src = jump + (uint64_t)g.tree_base * kJumpPerTreeSlot;
+        for (uint32_t p = threadIdx.x; p < (1u << js.a); p += kWG) jt[p] = src[p];
     }
     for (uint32_t b = threadIdx.x; b < g.k; b += kWG) {
 #pragma unroll
@@ -652,7 +696,7 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
             valid[q] = pos < end;
             kk[q] = valid[q] ? key_in[pos] : 0ull;
         }
-        classify_keys<U, EQ>(t, tin, g.d, g.v, kk, b);
+        classify_keys<U, VAR>(t, tin, jt, g.d, g.v, kk, b);
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const uint32_t pos = c + q * 64 + lane;
@@ -681,22 +725,23 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
     }
 }
 
-template <int U, bool G, bool EQ>
+template <int U, bool G, int VAR>
 __global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32_t* tile_tab,
                                                   const uint64_t* key_in, const uint64_t* tree_lo,
-                                                  const uint64_t* tree_in, uint16_t* bid,
-                                                  uint32_t* cm, uint32_t vmax, uint32_t kmax,
-                                                  const uint32_t* wcnt, uint32_t cap,
-                                                  const Globals* glob, uint32_t redo) {
+                                                  const uint64_t* tree_in, const uint16_t* jump,
+                                                  uint16_t* bid, uint32_t* cm, uint32_t vmax,
+                                                  uint32_t kmax, const uint32_t* wcnt,
+                                                  uint32_t cap, const Globals* glob,
+                                                  uint32_t redo) {
     if (!G) {
-        classify_body<U, EQ>(blockIdx.x, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm,
-                             vmax, kmax);
+        classify_body<U, VAR>(blockIdx.x, redo, lseg, tile_tab, key_in, tree_lo, tree_in, jump,
+                              bid, cm, vmax, kmax);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        classify_body<U, EQ>(u, redo, lseg, tile_tab, key_in, tree_lo, tree_in, bid, cm, vmax,
-                             kmax);
+        classify_body<U, VAR>(u, redo, lseg, tile_tab, key_in, tree_lo, tree_in, jump, bid, cm,
+                              vmax, kmax);
         __syncthreads();
     }
 }
@@ -1775,29 +1820,37 @@ __global__ __launch_bounds__(256) void k_lcp_fix(const uint8_t* chars, const uin
 
 __global__ __launch_bounds__(256) void k_tree_from_sorted(const uint64_t* splitters, uint32_t v,
                                                           uint32_t d, uint64_t* tree_lo,
-                                                          uint64_t* tree_in) {
+                                                          uint64_t* tree_in, uint16_t* jump) {
+    __shared__ uint64_t t[1u << kDMax];
     for (uint32_t j = threadIdx.x; j < v; j += kWG) {
         tree_lo[inorder_node(j, d)] = splitters[j];
+        t[inorder_node(j, d)] = splitters[j];
         tree_in[j] = splitters[j];
     }
     if (threadIdx.x == 0) {
         tree_lo[0] = 0;
         tree_in[v] = 0;
     }
+    __syncthreads();
+    if (jump) build_jump_table(t, d, v, jump, threadIdx.x, blockDim.x);
 }
 
-template <int U, bool EQ>
+template <int U, int VAR>
 __global__ __launch_bounds__(256) void k_classify_plain(const uint64_t* keys, uint32_t n,
                                                         const uint64_t* tree_lo,
-                                                        const uint64_t* tree_in, uint32_t v,
+                                                        const uint64_t* tree_in,
+                                                        const uint16_t* jump, uint32_t v,
                                                         uint32_t d, uint16_t* out) {
     extern __shared__ uint64_t dyn[];
     uint64_t* t = dyn;
     uint64_t* tin = t + (v + 1);
+    uint16_t* jt = (uint16_t*)(tin + (v + 1));
     for (uint32_t i = threadIdx.x; i <= v; i += kWG) {
         t[i] = tree_lo[i];
         tin[i] = tree_in[i];
     }
+    if (VAR == (int)kClassifyJump)
+        for (uint32_t p = threadIdx.x; p < (v + 1) * kJumpPerTreeSlot; p += kWG) jt[p] = jump[p];
     __syncthreads();
     const uint32_t base = blockIdx.x * (kWG * U);
     uint64_t kk[U];
@@ -1807,7 +1860,7 @@ __global__ __launch_bounds__(256) void k_classify_plain(const uint64_t* keys, ui
         uint32_t pos = base + q * kWG + threadIdx.x;
         kk[q] = pos < n ? keys[pos] : 0ull;
     }
-    classify_keys<U, EQ>(t, tin, d, v, kk, b);
+    classify_keys<U, VAR>(t, tin, jt, d, v, kk, b);
 #pragma unroll
     for (int q = 0; q < U; ++q) {
         uint32_t pos = base + q * kWG + threadIdx.x;
@@ -1878,40 +1931,42 @@ void launch_zero_words(void* p, size_t bytes, hipStream_t st) {
 
 void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_in,
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
-                        uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* tile_tab,
+                        uint64_t* tree_in, uint8_t* tree_lcp, uint16_t* jump, uint32_t* tile_tab,
                         uint32_t* chunk_tab, Counters* next_cnt, const Globals* glob,
                         const Dyn& dy, uint32_t redo, hipStream_t st) {
     uint32_t m = alpha * (vmax + 1) - 1, P = 1;
     while (P < m) P <<= 1;
     if (dy.cnt)
         S5_LAUNCH(k_sample_tree<true>, dim3(dy.grid), dim3(kWG), (size_t)P * 8, st, lseg, key_in,
-                  alpha, seed, tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, next_cnt, dy.cnt,
-                  dy.cap, glob, redo);
+                  alpha, seed, tree_lo, tree_in, tree_lcp, jump, tile_tab, chunk_tab, next_cnt,
+                  dy.cnt, dy.cap, glob, redo);
     else
         S5_LAUNCH(k_sample_tree<false>, dim3(n_large), dim3(kWG), (size_t)P * 8, st, lseg, key_in,
-                  alpha, seed, tree_lo, tree_in, tree_lcp, tile_tab, chunk_tab, next_cnt, dy.cnt,
-                  dy.cap, glob, redo);
+                  alpha, seed, tree_lo, tree_in, tree_lcp, jump, tile_tab, chunk_tab, next_cnt,
+                  dy.cnt, dy.cap, glob, redo);
 }
 
 void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LSeg* lseg,
                      const uint32_t* tile_tab, const uint64_t* key_in, const uint64_t* tree_lo,
-                     const uint64_t* tree_in, uint16_t* bid, uint32_t* cm, uint32_t vmax,
-                     uint32_t kmax, const Globals* glob, const Dyn& dy, uint32_t redo,
-                     hipStream_t st) {
+                     const uint64_t* tree_in, const uint16_t* jump, uint16_t* bid, uint32_t* cm,
+                     uint32_t vmax, uint32_t kmax, const Globals* glob, const Dyn& dy,
+                     uint32_t redo, hipStream_t st) {
     size_t lds = (size_t)(vmax + 1) * 16 + (size_t)kWaves * kmax * 4;
+    if (variant == kClassifyJump) lds += (size_t)(vmax + 1) * kJumpPerTreeSlot * 2;
     dim3 grid(dyn_grid(dy, tiles));
-#define S5_CLASSIFY_GE(U, GG, EE)                                                            \
-    S5_LAUNCH((k_classify<U, GG, EE>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in,       \
-              tree_lo, tree_in, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo)
+#define S5_CLASSIFY_GE(U, GG, VV)                                                            \
+    S5_LAUNCH((k_classify<U, GG, VV>), grid, dim3(kWG), lds, st, lseg, tile_tab, key_in,       \
+              tree_lo, tree_in, jump, bid, cm, vmax, kmax, dy.cnt, dy.cap, glob, redo)
+#define S5_CLASSIFY_G(U, GG)                                                                 \
+    do {                                                                                     \
+        if (variant == kClassifyEqual) S5_CLASSIFY_GE(U, GG, 1);                             \
+        else if (variant == kClassifyJump) S5_CLASSIFY_GE(U, GG, 2);                         \
+        else S5_CLASSIFY_GE(U, GG, 0);                                                       \
+    } while (0)
 #define S5_CLASSIFY(U)                                                                       \
     do {                                                                                     \
-        if (dy.cnt) {                                                                        \
-            if (variant == kClassifyEqual) S5_CLASSIFY_GE(U, true, true);                    \
-            else S5_CLASSIFY_GE(U, true, false);                                             \
-        } else {                                                                             \
-            if (variant == kClassifyEqual) S5_CLASSIFY_GE(U, false, true);                   \
-            else S5_CLASSIFY_GE(U, false, false);                                            \
-        }                                                                                    \
+        if (dy.cnt) S5_CLASSIFY_G(U, true);                                                  \
+        else S5_CLASSIFY_G(U, false);                                                        \
     } while (0)
     switch (unroll) {
         case 1: S5_CLASSIFY(1); break;
@@ -1920,6 +1975,7 @@ void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LS
         default: S5_CLASSIFY(4); break;
     }
 #undef S5_CLASSIFY
+#undef S5_CLASSIFY_G
 #undef S5_CLASSIFY_GE
 }
 
@@ -2056,16 +2112,21 @@ void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_
 
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,
                            uint32_t v, uint32_t d, uint32_t variant, uint64_t* tree_lo,
-                           uint64_t* tree_in, uint16_t* out, hipStream_t st) {
-    S5_LAUNCH(k_tree_from_sorted, dim3(1), dim3(kWG), 0, st, splitters, v, d, tree_lo, tree_in);
+                           uint64_t* tree_in, uint16_t* jump, uint16_t* out, hipStream_t st) {
+    S5_LAUNCH(k_tree_from_sorted, dim3(1), dim3(kWG), 0, st, splitters, v, d, tree_lo, tree_in,
+              variant == kClassifyJump ? jump : nullptr);
     if (!n) return;
     const dim3 grid((n + kWG * 4 - 1) / (kWG * 4));
+    const size_t lds = (size_t)(v + 1) * (16 + 2 * kJumpPerTreeSlot);
     if (variant == kClassifyEqual)
-        S5_LAUNCH((k_classify_plain<4, true>), grid, dim3(kWG), (size_t)(v + 1) * 16, st, keys, n,
-                  tree_lo, tree_in, v, d, out);
+        S5_LAUNCH((k_classify_plain<4, 1>), grid, dim3(kWG), lds, st, keys, n, tree_lo, tree_in,
+                  jump, v, d, out);
+    else if (variant == kClassifyJump)
+        S5_LAUNCH((k_classify_plain<4, 2>), grid, dim3(kWG), lds, st, keys, n, tree_lo, tree_in,
+                  jump, v, d, out);
     else
-        S5_LAUNCH((k_classify_plain<4, false>), grid, dim3(kWG), (size_t)(v + 1) * 16, st, keys,
-                  n, tree_lo, tree_in, v, d, out);
+        S5_LAUNCH((k_classify_plain<4, 0>), grid, dim3(kWG), lds, st, keys, n, tree_lo, tree_in,
+                  jump, v, d, out);
 }
 
 }  // namespace s5

@@ -22,14 +22,14 @@ void launch_pass_stats(const Counters* cur, const Counters* next, Globals* glob,
 void launch_zero_words(void* p, size_t bytes, hipStream_t st);
 void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_in,
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
-                        uint64_t* tree_in, uint8_t* tree_lcp, uint32_t* tile_tab,
+                        uint64_t* tree_in, uint8_t* tree_lcp, uint16_t* jump, uint32_t* tile_tab,
                         uint32_t* chunk_tab, Counters* next_cnt, const Globals* glob,
                         const Dyn& dy, uint32_t redo, hipStream_t st);
 void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LSeg* lseg,
                      const uint32_t* tile_tab, const uint64_t* key_in, const uint64_t* tree_lo,
-                     const uint64_t* tree_in, uint16_t* bid, uint32_t* cm, uint32_t vmax,
-                     uint32_t kmax, const Globals* glob, const Dyn& dy, uint32_t redo,
-                     hipStream_t st);
+                     const uint64_t* tree_in, const uint16_t* jump, uint16_t* bid, uint32_t* cm,
+                     uint32_t vmax, uint32_t kmax, const Globals* glob, const Dyn& dy,
+                     uint32_t redo, hipStream_t st);
 void launch_colscan(uint32_t chunks, uint32_t kmax, const LSeg* lseg, const uint32_t* chunk_tab,
                     uint32_t* cm, uint32_t* cs, const Globals* glob, const Dyn& dy, uint32_t redo,
                     hipStream_t st);
@@ -55,7 +55,7 @@ void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_
                     const uint32_t* guard, const Globals* glob, hipStream_t st);
 void launch_classify_plain(const uint64_t* keys, uint32_t n, const uint64_t* splitters,
                            uint32_t v, uint32_t d, uint32_t variant, uint64_t* tree_lo,
-                           uint64_t* tree_in, uint16_t* out, hipStream_t st);
+                           uint64_t* tree_in, uint16_t* jump, uint16_t* out, hipStream_t st);
 
 // Counting of output writes for later sorts (the write-check build; returns
 // false in the product build, where S5_OUT is a plain store).
@@ -67,7 +67,7 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
                              const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
                              uint32_t steps, float lr, float beta, Globals* glob,
                              uint64_t* tree_lo, uint64_t* tree_in, uint8_t* tree_lcp,
-                             const Dyn& dy, hipStream_t st);
+                             uint16_t* jump, const Dyn& dy, hipStream_t st);
 void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,
                         float beta, Globals* glob, const Dyn& dy, hipStream_t st);
 void launch_mlp_train(const LearnCtx& c, const uint64_t* sorted_keys, uint32_t m, uint32_t steps,

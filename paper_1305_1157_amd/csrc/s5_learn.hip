@@ -509,7 +509,7 @@ __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t sl
                                                   const uint32_t* learn_seg, uint32_t steps,
                                                   float lr, float beta, Globals* glob,
                                                   uint64_t* tree_lo, uint64_t* tree_in,
-                                                  uint8_t* tree_lcp) {
+                                                  uint8_t* tree_lcp, uint16_t* jump) {
     __shared__ float w[kNPS];
     __shared__ ProposeLds L;
     const uint32_t tid = threadIdx.x;
@@ -545,18 +545,25 @@ __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t sl
             lcp_out[j] = 0;
         }
     }
+    if (jump) {  // the level-order tree in LDS (the quantile list is done with), then the table
+        uint64_t* t = L.Qk;
+        __syncthreads();
+        for (uint32_t j = tid; j < g.v; j += 256) t[inorder_node(j, g.d)] = L.spl[j];
+        __syncthreads();
+        build_jump_table(t, g.d, g.v, jump + (uint64_t)g.tree_base * kJumpPerTreeSlot, tid, 256);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, LSeg* lseg,
                                                       const uint32_t* learn_seg, uint32_t steps,
                                                       float lr, float beta, Globals* glob,
                                                       uint64_t* tree_lo, uint64_t* tree_in,
-                                                      uint8_t* tree_lcp, const uint32_t* wcnt,
-                                                      uint32_t cap) {
+                                                      uint8_t* tree_lcp, uint16_t* jump,
+                                                      const uint32_t* wcnt, uint32_t cap) {
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t slot = blockIdx.x; slot < units; slot += gridDim.x) {
         learn_finish_body(c, slot, lseg, learn_seg, steps, lr, beta, glob, tree_lo, tree_in,
-                          tree_lcp);
+                          tree_lcp, jump);
         __syncthreads();
     }
 }
@@ -665,7 +672,7 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
                              const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
                              uint32_t steps, float lr, float beta, Globals* glob,
                              uint64_t* tree_lo, uint64_t* tree_in, uint8_t* tree_lcp,
-                             const Dyn& dy, hipStream_t st) {
+                             uint16_t* jump, const Dyn& dy, hipStream_t st) {
     const uint32_t g = dy.cnt ? dy.grid : slots;
     hipLaunchKernelGGL(k_learn_prep, dim3(g), dim3(256), 0, st, c, lseg, learn_seg, key_in, seed,
                        dy.cnt, dy.cap, glob);
@@ -673,7 +680,7 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
         hipLaunchKernelGGL(k_learn_step, dim3(c.groups, g), dim3(kGrp), 0, st, c, s, lr, dy.cnt,
                            dy.cap, glob);
     hipLaunchKernelGGL(k_learn_finish, dim3(g), dim3(256), 0, st, c, lseg, learn_seg, steps, lr,
-                       beta, glob, tree_lo, tree_in, tree_lcp, dy.cnt, dy.cap);
+                       beta, glob, tree_lo, tree_in, tree_lcp, jump, dy.cnt, dy.cap);
 }
 
 void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,

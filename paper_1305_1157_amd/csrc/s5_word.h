@@ -195,6 +195,54 @@ S5_HD void equal_step(const uint64_t* t, uint32_t d, uint64_t key, uint32_t& i, 
 }
 S5_HD uint32_t equal_leaf_bucket(uint32_t i, uint32_t d) { return 2u * (i - (1u << d)); }
 
+// Jump table over the top key bits (appendix A, "Jump tables").  All keys
+// between the first and the last splitter share the top `sh` bits of those
+// two splitters; the next `a` bits index a table whose entry is the node at
+// which the descent (i = 2i + [key > x_i]) stops being the same for every key
+// with those bits.  The descent starts there, so its result is the plain
+// descent's.  Keys below the first or above the last splitter take buckets 0
+// and 2v directly.
+struct JumpShape {
+    uint32_t sh, a;  // common top bits of the splitter range; index bits (a = 0: no table)
+};
+S5_HD JumpShape jump_shape(uint64_t first, uint64_t last, uint32_t d) {
+    JumpShape j;
+    j.sh = first == last ? 64u : (uint32_t)__builtin_clzll((unsigned long long)(first ^ last));
+    uint32_t a = d + 2 < 12 ? d + 2 : 12u;
+    j.a = 64 - j.sh < a ? 64 - j.sh : a;
+    return j;
+}
+S5_HD uint32_t jump_index(uint64_t key, JumpShape j) {
+    return j.a ? (uint32_t)((key << j.sh) >> (64 - j.a)) : 0u;
+}
+// table entry for index p (t: level order, t[1..v], d levels; first is the
+// smallest splitter)
+S5_HD uint32_t jump_entry(const uint64_t* t, uint32_t d, uint64_t first, JumpShape j,
+                          uint32_t p) {
+    const uint64_t top = j.sh >= 64 ? first : (j.sh ? first & ~(~0ull >> j.sh) : 0ull);
+    const uint32_t rest = 64 - j.sh - j.a;  // bits below the index
+    const uint64_t lo = j.a ? top | ((uint64_t)p << rest) : top;
+    const uint64_t hi = lo | (rest >= 64 ? ~0ull : ((1ull << rest) - 1));
+    uint32_t i = 1;
+    for (uint32_t L = 0; L < d; ++L) {
+        const uint64_t x = t[i];
+        if (x < lo) i = 2 * i + 1;       // every key with index p is greater
+        else if (x >= hi) i = 2 * i;     // every key with index p is smaller or equal
+        else break;
+    }
+    return i;
+}
+
+// The jump table of a tree (level order t[1..v]) into jt: entries p0,
+// p0 + step, ... (a workgroup passes its thread index and size).
+S5_HD void build_jump_table(const uint64_t* t, uint32_t d, uint32_t v, uint16_t* jt,
+                            uint32_t p0, uint32_t step) {
+    const uint64_t first = t[inorder_node(0, d)], last = t[inorder_node(v - 1, d)];
+    const JumpShape js = jump_shape(first, last, d);
+    for (uint32_t p = p0; p < (1u << js.a); p += step)
+        jt[p] = (uint16_t)jump_entry(t, d, first, js, p);
+}
+
 // U interleaved branch-free descents followed by one equality test each
 // (Section 3.1: the "unrolled" variant that only uses <= comparisons on the
 // way down).  t: level order, t[1..v]; tin: in order, tin[0..v).

@@ -18,7 +18,7 @@ S5_OK, S5_ERR_INVALID, S5_ERR_NOMEM, S5_ERR_HIP, S5_ERR_DEVICE = 0, -1, -2, -3, 
 S5_ERR_TOO_LARGE = -5
 STATIC_SCRATCH_BYTES = 64 << 20  # S5_STATIC_SCRATCH_BYTES
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
-CLASSIFY_UNROLL, CLASSIFY_EQUAL = 0, 1
+CLASSIFY_UNROLL, CLASSIFY_EQUAL, CLASSIFY_JUMP = 0, 1, 2
 
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_sort_batched",
            "s5_classify_ex",

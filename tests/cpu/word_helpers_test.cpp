@@ -307,6 +307,55 @@ static void test_equal_variant(std::mt19937_64& rng) {
     }
 }
 
+// the Jump variant on the host: table, start node, descent, leaf test
+static uint32_t jump_classify(const std::vector<uint64_t>& t, const std::vector<uint64_t>& tin,
+                              const std::vector<uint16_t>& jt, uint32_t d, uint32_t v,
+                              uint64_t key) {
+    const uint64_t first = tin[0], last = tin[v - 1];
+    const JumpShape js = jump_shape(first, last, d);
+    uint32_t i = key < first ? (1u << d) : (key > last ? (1u << d) + v : jt[jump_index(key, js)]);
+    while (i < (1u << d)) i = 2 * i + (key > t[i] ? 1u : 0u);
+    const uint32_t j = i - (1u << d);
+    return 2 * j + ((j < v && tin[j] == key) ? 1u : 0u);
+}
+
+static void test_jump_table(std::mt19937_64& rng) {
+    for (int rep = 0; rep < 400; ++rep) {
+        uint32_t d = 1 + rng() % 10, v = (1u << d) - 1;
+        uint32_t m = 1 + rng() % (4 * (v + 1));
+        uint32_t distinct = 1 + rng() % (2 * m);
+        // pools near one value (long common prefixes) or spread over all 64 bits
+        const uint64_t base = rng(), spread = rng() % 3 == 0 ? (1ull << (rng() % 40)) : ~0ull;
+        std::vector<uint64_t> pool(distinct);
+        for (auto& x : pool) x = spread == ~0ull ? rng() >> (rng() % 64) : base + rng() % spread;
+        std::vector<uint64_t> smp(m);
+        for (auto& x : smp) x = pool[rng() % distinct];
+        std::sort(smp.begin(), smp.end());
+        std::vector<uint64_t> t, tin;
+        build_tree(smp, d, t, tin);
+        const JumpShape js = jump_shape(tin[0], tin[v - 1], d);
+        CHECK(js.a <= 12 && js.a <= d + 2 && js.sh + js.a <= 64, "jump shape d %u", d);
+        std::vector<uint16_t> jt(1u << js.a);
+        build_jump_table(t.data(), d, v, jt.data(), 0, 1);
+        for (uint32_t p = 0; p < jt.size(); ++p) CHECK(jt[p] >= 1 && jt[p] < (2u << d), "entry");
+        for (int probe = 0; probe < 300; ++probe) {
+            uint64_t key;
+            switch (rng() % 4) {
+                case 0: key = pool[rng() % distinct]; break;
+                case 1: key = pool[rng() % distinct] + (rng() % 5) - 2; break;
+                case 2: key = tin[rng() % v] + (rng() % 3) - 1; break;
+                default: key = rng(); break;
+            }
+            uint64_t kk[1] = {key};
+            uint32_t want[1];
+            classify_u<1>(t.data(), tin.data(), d, v, kk, want);
+            const uint32_t got = jump_classify(t, tin, jt, d, v, key);
+            CHECK(got == want[0], "jump d %u key %llx got %u want %u", d, (unsigned long long)key,
+                  got, want[0]);
+        }
+    }
+}
+
 static void test_fig1(const char* path) {
     FILE* f = fopen(path, "r");
     CHECK(f != nullptr, "open %s", path);
@@ -358,6 +407,7 @@ int main(int argc, char** argv) {
     test_tree_and_classify(rng);
     test_node_inorder();
     test_equal_variant(rng);
+    test_jump_table(rng);
     if (argc > 1) test_fig1(argv[1]);
     if (failures) {
         printf("%d failures\n", failures);

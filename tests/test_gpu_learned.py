@@ -131,6 +131,15 @@ def test_learned_sort_parity(name, n):
     assert st["passes"] >= 1
 
 
+def test_learned_jump_tables_parity():
+    # learned trees build their jump tables in the proposal kernel
+    chars, offs = gen.workload("words_50M", 300_000)
+    cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED, imbalance_bound=1e9,
+                         classifier=s5.CLASSIFY_JUMP)
+    st = assert_parity(chars, offs, cfg, label="learned jump")
+    assert st["fallbacks"] == 0
+
+
 def test_forced_fallback_parity():
     chars, offs = gen.workload("words_50M", 300_000)
     cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED, imbalance_bound=1e-6)

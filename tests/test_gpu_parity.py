@@ -27,6 +27,10 @@ CFGS = {
     "equal_v7_u1_T64": s5.make_config(classifier=s5.CLASSIFY_EQUAL, splitters=7, unroll=1,
                                       base_threshold=64, tile=64),
     "equal_v1023_u8": s5.make_config(classifier=s5.CLASSIFY_EQUAL, splitters=1023, unroll=8),
+    "jump": s5.make_config(classifier=s5.CLASSIFY_JUMP),
+    "jump_v7_u2_T64": s5.make_config(classifier=s5.CLASSIFY_JUMP, splitters=7, unroll=2,
+                                     base_threshold=64, tile=64),
+    "jump_v1023_u8": s5.make_config(classifier=s5.CLASSIFY_JUMP, splitters=1023, unroll=8),
 }
 
 
@@ -46,19 +50,27 @@ def test_prefix_keys_vs_bytes():
             assert int(keys[j]) == want, (depth, i)
 
 
-def test_classify_vs_searchsorted():
+@pytest.mark.parametrize("variant", ["unroll", "jump"])
+def test_classify_vs_searchsorted(variant):
+    """2 lower_bound + [equal]: the Unroll descent, and the same descent
+    started from the jump table (splitters spread over 64 bits, and packed
+    close together so that they share a long common prefix)."""
     rng = np.random.default_rng(5)
+    var = {"unroll": s5.CLASSIFY_UNROLL, "jump": s5.CLASSIFY_JUMP}[variant]
     for v in (1, 3, 7, 255, 1023):
-        spl = np.sort(rng.integers(0, 2**63, size=v, dtype=np.uint64))
-        if v > 3:
-            spl[v // 2] = spl[v // 2 - 1]  # a duplicate splitter
-        keys = np.concatenate([rng.integers(0, 2**63, size=5000, dtype=np.uint64), spl,
-                               np.array([0, 2**64 - 1], dtype=np.uint64)])
-        got = s5.classify(to_dev(keys), to_dev(spl)).cpu().numpy().astype(np.int64)
-        j = np.searchsorted(spl, keys, side="left")
-        eq = (j < v) & (spl[np.minimum(j, v - 1)] == keys)
-        want = 2 * j + eq
-        assert np.array_equal(got, want), v
+        for spread in (2**63, 2**20):
+            base = np.uint64(0x6162636465000000)
+            spl = np.sort(base + rng.integers(0, spread, size=v, dtype=np.uint64))
+            if v > 3:
+                spl[v // 2] = spl[v // 2 - 1]  # a duplicate splitter
+            keys = np.concatenate([base + rng.integers(0, spread, size=5000, dtype=np.uint64),
+                                   rng.integers(0, 2**64 - 1, size=500, dtype=np.uint64), spl,
+                                   spl - np.uint64(1), np.array([0, 2**64 - 1], dtype=np.uint64)])
+            got = s5.classify(to_dev(keys), to_dev(spl), var).cpu().numpy().astype(np.int64)
+            j = np.searchsorted(spl, keys, side="left")
+            eq = (j < v) & (spl[np.minimum(j, v - 1)] == keys)
+            want = 2 * j + eq
+            assert np.array_equal(got, want), (v, spread)
 
 
 def test_classify_equal_variant():
@@ -93,7 +105,7 @@ def test_fig1_tree():
     keys = np.array([0, 0x6161600000000000, 0x6161610000000000, 0x6161610000000001,
                      0x6A00000000000000, 0x6D6D6D0000000000, 0x6D6D6D6100000000,
                      0x7878780000000000, 0x7878780100000000, 2**64 - 1], dtype=np.uint64)
-    for variant in (s5.CLASSIFY_UNROLL, s5.CLASSIFY_EQUAL):
+    for variant in (s5.CLASSIFY_UNROLL, s5.CLASSIFY_EQUAL, s5.CLASSIFY_JUMP):
         got = s5.classify(to_dev(keys), to_dev(spl), variant).cpu().numpy().tolist()
         assert got == [0, 0, 1, 2, 2, 3, 4, 5, 6, 6]
 
@@ -133,7 +145,8 @@ EDGE.update({
 
 
 @pytest.mark.parametrize("name", sorted(EDGE))
-@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "v1023_u8", "equal_v7_u1_T64"])
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "v1023_u8", "equal_v7_u1_T64",
+                                 "jump_v7_u2_T64"])
 def test_edge_cases(name, cfg):
     strings_parity(EDGE[name], CFGS[cfg], label=f"{name}/{cfg}")
 
@@ -228,7 +241,7 @@ def test_no_writes_outside_outputs_and_workspace(name, n, cfg):
         assert (h[:pad] == fill).all() and (h[pad + n:] == fill).all()
 
 
-@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "equal"])
+@pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "equal", "jump"])
 def test_batched_small(cfg):
     chars, offs, sb = gen.batched(60, 1, 5000, kinds=("random", "url", "dna", "words"), seed=7)
     # include empty sets and single-string sets
