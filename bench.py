@@ -248,6 +248,7 @@ def learned_extra(name, copy_gbps=None, steps=3):
     variants = [("sampled", s5.make_config()),
                 ("sampled_equal", s5.make_config(classifier=s5.CLASSIFY_EQUAL)),
                 ("sampled_jump", s5.make_config(classifier=s5.CLASSIFY_JUMP)),
+                ("sampled_packed", s5.make_config(alphabet=s5.ALPHABET_AUTO)),
                 ("learned", s5.make_config(splitter_mode=s5.SPLIT_LEARNED)),
                 ("learned_no_fallback", s5.make_config(splitter_mode=s5.SPLIT_LEARNED,
                                                        imbalance_bound=1e9))]
@@ -273,6 +274,8 @@ def learned_extra(name, copy_gbps=None, steps=3):
                       "max_bucket_first_pass": st["max_bucket"],
                       "learn_ms": prof.get("learn_splitters", {}).get("total_ms", 0.0),
                       "classify_ms": prof.get("classify", {}).get("total_ms", 0.0),
+                      "base_ms": prof.get("base_sort", {}).get("total_ms", 0.0),
+                      "char_bits": st["char_bits"],
                       "hbm": hbm_figures(D, n, st["moved_M"], sec, copy_gbps),
                       "output_identical_to_sampled": same}
         del ws

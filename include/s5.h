@@ -73,6 +73,17 @@ extern "C" {
                                  with those bits; keys outside the splitter
                                  range take buckets 0 and 2v directly */
 
+/* alphabet: the characters a key holds (appendix A, "Alphabet compression";
+ * the output never depends on it) */
+#define S5_ALPHABET_BYTES 0u /* 8 characters (bytes) per 64-bit key */
+#define S5_ALPHABET_AUTO 1u  /* the bytes of a sample of the strings (up to 65536
+                                strings, up to 256 bytes each) are taken as the
+                                alphabet; with at most 7 byte values (DNA: 4) each
+                                character is sorted as an order-preserving 3-bit
+                                code, 21 characters per key.  Every key load
+                                checks its bytes; a byte outside the alphabet makes
+                                the call sort again with byte keys */
+
 /* splitter_mode */
 #define S5_SPLIT_SAMPLED 0u /* splitters from a pseudo-random sample (Section 3.1) */
 #define S5_SPLIT_LEARNED 1u /* splitters proposed by a small learned CDF model */
@@ -103,6 +114,8 @@ typedef struct s5_config {
                                 finish with host-driven passes after the graph */
     uint32_t classifier;     /* S5_CLASSIFY_UNROLL (default), S5_CLASSIFY_EQUAL or
                                 S5_CLASSIFY_JUMP */
+    uint32_t alphabet;       /* S5_ALPHABET_BYTES (default) or S5_ALPHABET_AUTO */
+    uint32_t reserved;       /* must be 0 */
 } s5_config;
 
 /* Counters of the last completed sort on a stream. */
@@ -116,6 +129,10 @@ typedef struct s5_stats {
     size_t workspace_bytes; /* device workspace the sort used */
     uint64_t base_items;    /* buckets finished by the base-case sorter */
     uint64_t segments;      /* segments distributed, summed over passes */
+    uint32_t char_bits;     /* bits per character of the keys sorted by (8: bytes;
+                               3: alphabet compression) */
+    uint32_t alphabet_retries; /* sorts redone with byte keys after a byte outside
+                                  the sampled alphabet */
 } s5_stats;
 
 /* Sort n strings.  perm and lcp as described above.  Uses the internal

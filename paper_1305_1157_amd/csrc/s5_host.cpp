@@ -35,6 +35,8 @@ constexpr float kLearnRate = 0.03f;
 
 struct Cfg {
     uint32_t dmax, alpha, unroll, tile_min, T, mode, classifier;
+    uint32_t alphabet;  // S5_ALPHABET_*
+    uint32_t b;         // bits per character of this sort's keys (8: bytes; set per call)
     uint32_t T_caps, tile_caps;  // smallest T and tile of any set: storage capacities
     float beta;
     uint32_t graph_levels;
@@ -71,6 +73,10 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     if (o->graph_levels > kGraphLevelsMax) return S5_ERR_INVALID;
     o->seed = c->seed;
     o->classifier = c->classifier;
+    o->alphabet = c->alphabet;
+    o->b = 8;
+    if (o->alphabet != S5_ALPHABET_BYTES && o->alphabet != S5_ALPHABET_AUTO) return S5_ERR_INVALID;
+    if (c->reserved) return S5_ERR_INVALID;
     if (o->classifier != S5_CLASSIFY_UNROLL && o->classifier != S5_CLASSIFY_EQUAL &&
         o->classifier != S5_CLASSIFY_JUMP)
         return S5_ERR_INVALID;
@@ -89,7 +95,8 @@ uint32_t limited(uint32_t cap, uint32_t which) {
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
     size_t key[2], key2[2], key3, idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, jump, cm, cs,
-        bstart, base_list, learn, learn_seg, set_tune, counters[2], glob, total;
+        bstart, base_list, learn, learn_seg, set_tune, code_tab, alpha_bits, counters[2], glob,
+        total;
     uint32_t learn_cap, tune_sets;
     bool has_jump;
     Caps caps;
@@ -155,6 +162,9 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     // packed per-set parameters of a tuned batched sort
     L.tune_sets = tune_sets;
     L.set_tune = take((size_t)tune_sets * 4);
+    // alphabet compression: byte -> code table and the sampled byte bitmap
+    L.code_tab = take(256);
+    L.alpha_bits = take(32);
     // [counters 0 | globals | counters 1] back to back: one copy reads a pass's
     // counters together with the globals
     L.counters[0] = take(sizeof(Counters) + sizeof(Globals) + sizeof(Counters));
@@ -331,6 +341,8 @@ struct Ptrs {
     uint8_t* tree_lcp;
     uint16_t* jump;  // jump tables, or null when the classification does not use them
     uint32_t *cm, *cs, *bstart, *learn_seg, *set_tune;
+    uint8_t* code_tab;
+    uint32_t* alpha_bits;
     LearnCtx lctx;
     Seg* base_list[kBaseClasses];
     Counters* cnt[2];
@@ -359,11 +371,19 @@ Ptrs make_ptrs(const Layout& L, char* W) {
     P.bstart = (uint32_t*)(W + L.bstart);
     P.learn_seg = (uint32_t*)(W + L.learn_seg);
     P.set_tune = L.tune_sets ? (uint32_t*)(W + L.set_tune) : nullptr;
+    P.code_tab = (uint8_t*)(W + L.code_tab);
+    P.alpha_bits = (uint32_t*)(W + L.alpha_bits);
     P.lctx = learn_ctx(W + L.learn, L.learn_cap, kLearnSamples);
     P.base_list[0] = (Seg*)(W + L.base_list);
     for (int q = 1; q < kBaseClasses; ++q) P.base_list[q] = P.base_list[q - 1] + L.caps.base[q - 1];
     P.glob = (Globals*)(W + L.glob);
     return P;
+}
+
+// The key codec of a sort: bytes, or packed codes of c.b bits (the table is
+// in the workspace; a byte outside the alphabet sets the status word).
+KeyCodec codec_of(const Cfg& c, const Ptrs& P) {
+    return make_codec(c.b, P.code_tab, &P.glob->status);
 }
 
 PlanCtx plan_ctx(const Ptrs& P, const Layout& L, const Cfg& c, const SortArgs& a, int next) {
@@ -383,6 +403,7 @@ PlanCtx plan_ctx(const Ptrs& P, const Layout& L, const Cfg& c, const SortArgs& a
     x.learn_cap = L.learn_cap;
     x.learn_seg = P.learn_seg;
     x.stats = 0;
+    x.kc = codec_of(c, P);
     return x;
 }
 
@@ -440,13 +461,13 @@ void pass_front(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
         timed(K_LEARN, S.n_learn, st, [&] {
             launch_learn_sort_trees(P.lctx, S.n_learn, P.lseg[cur], P.learn_seg, P.key[buf],
                                     c.seed, kLearnSteps, kLearnRate, c.beta, P.glob, P.tree_lo,
-                                    P.tree_in, P.tree_lcp, P.jump, S.learn, st);
+                                    P.tree_in, P.tree_lcp, P.jump, codec_of(c, P), S.learn, st);
         });
     }
     timed(K_SAMPLE, S.now.n_large, st, [&] {
         launch_sample_tree(S.now.n_large, P.lseg[cur], P.key[buf], c.alpha, S.vmax, c.seed,
                            P.tree_lo, P.tree_in, P.tree_lcp, P.jump, P.tile_tab, P.chunk_tab,
-                           P.cnt[nxt], P.glob, S.seg, redo, st);
+                           P.cnt[nxt], P.glob, S.seg, redo, codec_of(c, P), st);
     });
     timed(K_CLASSIFY, S.now.moved, st, [&] {
         launch_classify(S.now.tiles, c.unroll, c.classifier, P.lseg[cur], P.tile_tab, P.key[buf],
@@ -476,7 +497,8 @@ void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
                        P.key2[buf], P.idx[buf], P.key[buf ^ 1], P.key2[buf ^ 1], P.idx[buf ^ 1],
                        P.cm, P.cs, P.bstart,
                        P.tree_in, P.tree_lcp, a.chars, a.offsets, a.perm, a.lcp, S.vmax, S.kmax,
-                       P.glob, S.tile, level == 0 ? P.key3 : nullptr, st, e0, e1);
+                       P.glob, S.tile, level == 0 ? P.key3 : nullptr, codec_of(c, P), st, e0,
+                       e1);
     });
 }
 
@@ -488,7 +510,7 @@ void start_sort(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     clear_counters(P, st);
     timed(K_INIT, a.n, st, [&] {
         launch_init_keys(a.chars, a.chars_len, a.offsets, a.n, P.key[0], P.key2[0], P.key3,
-                         P.idx[0], P.glob, st);
+                         P.idx[0], P.glob, codec_of(c, P), st);
     });
     timed(K_ROOTS, a.num_sets, st, [&] {
         launch_plan_roots(a.set_begin, a.num_sets, a.n, a.perm, a.lcp, plan_ctx(P, L, c, a, 0), st);
@@ -508,9 +530,42 @@ HostView host_view(void* host) {
 }
 
 // Return code of a device status word: argument checks first.
+// internal: a packed sort met a byte outside its alphabet; sort again with bytes
+constexpr int kRetryBytes = -100;
+
 int status_rc(uint32_t status) {
     if (status & kErrArgs) return S5_ERR_INVALID;
-    return status ? S5_ERR_DEVICE : S5_OK;
+    if (status & ~kErrAlphabet) return S5_ERR_DEVICE;
+    return status ? kRetryBytes : S5_OK;
+}
+
+// Alphabet compression (appendix A): with S5_ALPHABET_AUTO the bytes of a
+// sample of the strings are the alphabet; with sigma' <= 7 byte values the
+// sort packs order-preserving 3-bit codes, 21 characters per key (code 0 the
+// terminator, 1..sigma' the alphabet's bytes in byte order, 0xFF a byte
+// outside it) and c.b = 3, else c.b stays 8 (byte keys).
+constexpr size_t kAlphaSlot = 3072;  // bitmap readback, inside the raw slot
+static_assert(sizeof(Counters) + sizeof(Globals) <= kAlphaSlot, "readback slot layout");
+
+int choose_alphabet(const SortArgs& a, Cfg& c, const Ptrs& P, void* host, hipStream_t st) {
+    c.b = 8;
+    if (c.alphabet != S5_ALPHABET_AUTO || a.n == 0) return S5_OK;
+    const uint32_t samples = std::min<uint32_t>(a.n, 65536u);
+    launch_alphabet(a.chars, a.offsets, a.n, samples, P.alpha_bits, st);
+    uint32_t* hb = (uint32_t*)((char*)host + kAlphaSlot);
+    S5_HIP(hipMemcpyAsync(hb, P.alpha_bits, 32, hipMemcpyDeviceToHost, st));
+    S5_HIP(hipStreamSynchronize(st));
+    uint8_t tab[256];
+    uint32_t sigma = 0;
+    for (uint32_t ch = 0; ch < 256; ++ch) {
+        const bool in = ch != 0 && ((hb[ch >> 5] >> (ch & 31)) & 1u);
+        tab[ch] = ch == 0 ? 0 : (in ? (uint8_t)(++sigma) : (uint8_t)0xFF);
+    }
+    if (sigma > 7) return S5_OK;  // byte keys
+    S5_HIP(hipMemcpyAsync(P.code_tab, tab, 256, hipMemcpyHostToDevice, st));
+    S5_HIP(hipStreamSynchronize(st));  // `tab` lives on this stack
+    c.b = kPackBits;
+    return S5_OK;
 }
 
 // Copy a pass's counters together with the globals and wait for them.
@@ -562,7 +617,8 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     const Dyn none[kBaseClasses];
     timed(K_BASE, H.hg->base_elems, st, [&] {
         launch_base_sort(n_base, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
-                         a.offsets, a.perm, a.lcp, c.T, P.glob, none, nullptr, st);
+                         a.offsets, a.perm, a.lcp, c.T, P.glob, none, nullptr, codec_of(c, P),
+                         st);
     });
     timed(K_LCPFIX, a.n, st, [&] {
         launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, nullptr,
@@ -580,25 +636,38 @@ void final_stats(const HostView& H, s5_stats* stats) {
 
 // The whole sort on one workspace, host-driven.  `host` is a pinned block of
 // >= 4 KiB.
-int run_sort(const SortArgs& a, const Cfg& c, void* ws, size_t ws_bytes, void* host,
+int run_sort(const SortArgs& a, const Cfg& c0, void* ws, size_t ws_bytes, void* host,
              hipStream_t st, s5_stats* stats) {
     memset(stats, 0, sizeof *stats);
+    Cfg c = c0;
     const Layout L = make_layout(a.n, c, 0);
     if (ws_bytes < L.total) return S5_ERR_NOMEM;
-    stats->workspace_bytes = L.total;
     const Ptrs P = make_ptrs(L, (char*)ws);
     const HostView H = host_view(host);
-    start_sort(a, c, L, P, st);
-    S5_HIP(hipGetLastError());
-    int rc = readback(P, H, 0, st);
-    if (!rc) rc = host_passes(a, c, L, P, H, 0, st, stats);
-    if (!rc) {
-        S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
-        S5_HIP(hipStreamSynchronize(st));
-        final_stats(H, stats);
-        rc = status_rc(H.hg->status);
+    int rc = choose_alphabet(a, c, P, host, st);
+    if (rc) return rc;
+    uint32_t retries = 0;
+    for (;;) {
+        memset(stats, 0, sizeof *stats);
+        stats->workspace_bytes = L.total;
+        start_sort(a, c, L, P, st);
+        S5_HIP(hipGetLastError());
+        rc = readback(P, H, 0, st);
+        if (!rc) rc = host_passes(a, c, L, P, H, 0, st, stats);
+        if (!rc) {
+            S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+            S5_HIP(hipStreamSynchronize(st));
+            final_stats(H, stats);
+            rc = status_rc(H.hg->status);
+        }
+        prof_collect();
+        if (rc != kRetryBytes || c.b == 8) break;
+        S5_HIP(hipStreamSynchronize(st));  // every kernel of the packed attempt is done
+        c.b = 8;  // a byte outside the sampled alphabet: byte keys
+        ++retries;
     }
-    prof_collect();
+    stats->char_bits = c.b;
+    stats->alphabet_retries = retries;
     return rc;
 }
 
@@ -656,7 +725,7 @@ void enqueue_graph_body(const SortArgs& a, const Cfg& c, const Layout& L, const 
     }
     const uint32_t zero[kBaseClasses] = {};
     launch_base_sort(zero, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
-                     a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard, st);
+                     a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard, codec_of(c, P), st);
     launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, guard, P.glob,
                    st);
 }
@@ -698,63 +767,77 @@ int get_graph(const GraphKey& key, const SortArgs& a, const Cfg& c, const Layout
     return S5_OK;
 }
 
-int run_graph(const SortArgs& a, const Cfg& c, uint32_t levels, void* ws, size_t ws_bytes,
+int run_graph(const SortArgs& a, const Cfg& c0, uint32_t levels, void* ws, size_t ws_bytes,
               void* host, hipStream_t st, s5_stats* stats) {
     memset(stats, 0, sizeof *stats);
+    Cfg c = c0;
     const uint32_t tune_sets = a.tune_host ? a.num_sets : 0u;
     const Layout L = make_layout(a.n, c, tune_sets);
     if (ws_bytes < L.total) return S5_ERR_NOMEM;
-    stats->workspace_bytes = L.total;
     const Ptrs P = make_ptrs(L, (char*)ws);
     const HostView H = host_view(host);
-    GraphKey key;
-    memset(&key, 0, sizeof key);
-    key.chars = a.chars;
-    key.chars_len = a.chars_len;
-    key.offsets = a.offsets;
-    key.set_begin = a.set_begin;
-    key.perm = a.perm;
-    key.lcp = a.lcp;
-    key.ws = ws;
-    key.ws_bytes = ws_bytes;
-    key.num_sets = a.num_sets;
-    key.n = a.n;
-    key.levels = levels;
-    key.tuned = tune_sets ? 1u : 0u;
-    key.c = c;
-    S5_HIP(hipGetDevice(&key.dev));
-    if (tune_sets)
-        S5_HIP(hipMemcpyAsync(P.set_tune, a.tune_host, (size_t)tune_sets * 4,
-                              hipMemcpyHostToDevice, st));
-    hipGraphExec_t exec = nullptr;
-    int rc = get_graph(key, a, c, L, P, &exec);
+    int rc = choose_alphabet(a, c, P, host, st);
     if (rc) return rc;
-    timed(K_GRAPH, a.n, st, [&] { (void)hipGraphLaunch(exec, st); });
-    S5_HIP(hipGetLastError());
-    rc = readback(P, H, (int)(levels & 1u), st);
-    if (!rc) {
-        stats->passes = H.hg->passes;
-        stats->moved_M = H.hg->moved;
-        stats->segments = H.hg->segments;
-        stats->max_bucket = H.hg->max_bucket0;
-        stats->entropy_bits = H.hg->moved0 ? H.hg->entropy_sum0 / (double)H.hg->moved0 : 0.0;
-        if (H.hc->n_large > 0) {
-            // deeper than the captured levels: the host finishes the sort
-            s5_stats tail;
-            memset(&tail, 0, sizeof tail);
-            rc = host_passes(a, c, L, P, H, levels, st, &tail);
-            stats->passes = tail.passes;
-            stats->moved_M += tail.moved_M;
-            stats->segments += tail.segments;
+    uint32_t retries = 0;
+    for (;;) {
+        memset(stats, 0, sizeof *stats);
+        stats->workspace_bytes = L.total;
+        GraphKey key;
+        memset(&key, 0, sizeof key);
+        key.chars = a.chars;
+        key.chars_len = a.chars_len;
+        key.offsets = a.offsets;
+        key.set_begin = a.set_begin;
+        key.perm = a.perm;
+        key.lcp = a.lcp;
+        key.ws = ws;
+        key.ws_bytes = ws_bytes;
+        key.num_sets = a.num_sets;
+        key.n = a.n;
+        key.levels = levels;
+        key.tuned = tune_sets ? 1u : 0u;
+        key.c = c;
+        S5_HIP(hipGetDevice(&key.dev));
+        if (tune_sets)
+            S5_HIP(hipMemcpyAsync(P.set_tune, a.tune_host, (size_t)tune_sets * 4,
+                                  hipMemcpyHostToDevice, st));
+        hipGraphExec_t exec = nullptr;
+        rc = get_graph(key, a, c, L, P, &exec);
+        if (rc) return rc;
+        timed(K_GRAPH, a.n, st, [&] { (void)hipGraphLaunch(exec, st); });
+        S5_HIP(hipGetLastError());
+        rc = readback(P, H, (int)(levels & 1u), st);
+        if (!rc) {
+            stats->passes = H.hg->passes;
+            stats->moved_M = H.hg->moved;
+            stats->segments = H.hg->segments;
+            stats->max_bucket = H.hg->max_bucket0;
+            stats->entropy_bits =
+                H.hg->moved0 ? H.hg->entropy_sum0 / (double)H.hg->moved0 : 0.0;
+            if (H.hc->n_large > 0) {
+                // deeper than the captured levels: the host finishes the sort
+                s5_stats tail;
+                memset(&tail, 0, sizeof tail);
+                rc = host_passes(a, c, L, P, H, levels, st, &tail);
+                stats->passes = tail.passes;
+                stats->moved_M += tail.moved_M;
+                stats->segments += tail.segments;
+            }
         }
-    }
-    if (!rc) {
-        S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+        if (!rc) {
+            S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
+            S5_HIP(hipStreamSynchronize(st));
+            final_stats(H, stats);
+            rc = status_rc(H.hg->status);
+        }
+        prof_collect();
+        if (rc != kRetryBytes || c.b == 8) break;
         S5_HIP(hipStreamSynchronize(st));
-        final_stats(H, stats);
-        rc = status_rc(H.hg->status);
+        c.b = 8;  // a byte outside the sampled alphabet: byte keys (another graph)
+        ++retries;
     }
-    prof_collect();
+    stats->char_bits = c.b;
+    stats->alphabet_retries = retries;
     return rc;
 }
 

@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "s5_word.h"
+
 namespace s5 {
 
 // A distribution pass works on "tiles": contiguous runs of a segment that one
@@ -35,6 +37,9 @@ constexpr uint32_t kErrLargeCap = 1u, kErrBaseCap = 2u, kErrTileCap = 4u, kErrCm
 // arena whose last byte is not a terminator, a set table that is not
 // non-decreasing or ends past n): reported as S5_ERR_INVALID
 constexpr uint32_t kErrArgs = 32u;
+// a byte outside the alphabet of a sort with packed keys (alphabet
+// compression): the host sorts again with byte keys
+constexpr uint32_t kErrAlphabet = 64u;
 
 // A bucket that still has to be sorted.
 struct Seg {
@@ -152,6 +157,7 @@ struct PlanCtx {
     uint32_t d_max;       // tree depth limit for this sort
     uint32_t tile_min;    // minimum strings per tile
     uint32_t stats;       // 1: accumulate bucket entropy and max bucket (first pass only)
+    KeyCodec kc;          // characters per key and the end-of-string test
 };
 
 // Per-set parameters of a batched sort, packed in one word: base threshold T

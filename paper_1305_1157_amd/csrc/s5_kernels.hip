@@ -350,13 +350,27 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
     c.lseg[slot] = g;
 }
 
+// the code table of a packed sort in LDS (every thread of the block calls;
+// a barrier follows before first use)
+#define S5_CODE_TABLE(PK, kc, tab)                                  \
+    const uint8_t* tab = nullptr;                                   \
+    if constexpr (PK) {                                             \
+        __shared__ uint8_t ctab_[256];                              \
+        for (uint32_t c_ = threadIdx.x; c_ < 256; c_ += blockDim.x) \
+            ctab_[c_] = (kc).table[c_];                             \
+        tab = ctab_;                                                \
+    }
+
 // ---------------------------------------------------------------------------
 // K1: prefix cache at depth 0 (and the building-block entry point)
 
+template <bool PK>
 __global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, uint64_t chars_len,
                                                    const uint64_t* offsets, uint32_t n,
                                                    uint64_t* key, uint64_t* key2, uint64_t* key3,
-                                                   uint32_t* idx, Globals* glob) {
+                                                   uint32_t* idx, Globals* glob, KeyCodec kc) {
+    S5_CODE_TABLE(PK, kc, tab)
+    if constexpr (PK) __syncthreads();
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     idx[i] = i;
@@ -373,12 +387,18 @@ __global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, uint64_
         }
     }
     uint64_t w[3];
-    load_key_run<3>(chars, off, w);
+    if constexpr (PK) {
+        uint64_t raw[8];
+        load_key_run<8>(chars, off, raw);
+        if (pack3<8, 3>(tab, raw, w)) atomicOr(kc.status, kErrAlphabet);
+    } else {
+        load_key_run<3>(chars, off, w);
+    }
     key[i] = w[0];
     key2[i] = w[1];
     // the third word is all zero (and never read) unless the string
-    // continues past its first 16 bytes
-    if (!has_zero(w[1])) key3[i] = w[2];
+    // continues past its first two keys
+    if (!(PK ? codec_has_end(kc, w[1]) : has_zero(w[1]))) key3[i] = w[2];
 }
 
 __global__ __launch_bounds__(256) void k_prefix_keys(const uint8_t* chars, const uint64_t* offsets,
@@ -451,7 +471,7 @@ __device__ __forceinline__ void sample_tree_body(uint32_t slot, uint32_t redo, c
                                                  uint64_t seed, uint64_t* tree_lo,
                                                  uint64_t* tree_in, uint8_t* tree_lcp,
                                                  uint16_t* jump, uint32_t* tile_tab,
-                                                 uint32_t* chunk_tab) {
+                                                 uint32_t* chunk_tab, const KeyCodec& kc) {
     extern __shared__ uint64_t smp[];  // sample, padded to a power of two
     __shared__ uint32_t ra[1u << kDMax], rb[1u << kDMax];
     __shared__ uint64_t t[1u << kDMax];
@@ -533,7 +553,7 @@ __device__ __forceinline__ void sample_tree_body(uint32_t slot, uint32_t redo, c
             uint8_t l = 0;
             if (i > 0) {
                 uint64_t p = t[inorder_node(i - 1, g.d)];
-                l = p == x ? 0 : (uint8_t)(__builtin_clzll((unsigned long long)(p ^ x)) >> 3);
+                l = p == x ? 0 : (uint8_t)codec_lcp(kc, p, x);
             }
             lcp_out[i] = l;
         } else {
@@ -555,20 +575,20 @@ __global__ __launch_bounds__(256) void k_sample_tree(const LSeg* lseg, const uin
                                                      uint32_t* tile_tab, uint32_t* chunk_tab,
                                                      Counters* next_cnt, const uint32_t* wcnt,
                                                      uint32_t cap, const Globals* glob,
-                                                     uint32_t redo) {
+                                                     uint32_t redo, KeyCodec kc) {
     // the next pass's counters are planned later in this pass: clear them here
     if (!redo && blockIdx.x == 0)
         for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += blockDim.x)
             ((uint32_t*)next_cnt)[i] = 0;
     if (!G) {
         sample_tree_body(blockIdx.x, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp,
-                         jump, tile_tab, chunk_tab);
+                         jump, tile_tab, chunk_tab, kc);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
         sample_tree_body(u, redo, lseg, key_in, alpha, seed, tree_lo, tree_in, tree_lcp, jump,
-                         tile_tab, chunk_tab);
+                         tile_tab, chunk_tab, kc);
         __syncthreads();
     }
 }
@@ -878,8 +898,8 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
         if (sz < 2) return 0xFFFFFFFFu;
         const uint32_t j = b >> 1;
         if (b & 1u) {
-            if (has_zero(tree_in[g.tree_base + j])) return 0xFFFFFFFFu;
-            return g.depth + 8;
+            if (codec_has_end(ctx.kc, tree_in[g.tree_base + j])) return 0xFFFFFFFFu;
+            return g.depth + ctx.kc.w;
         }
         return g.depth + ((j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j]);
     };
@@ -922,6 +942,31 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
 }
 
 // ---------------------------------------------------------------------------
+// Packed keys (alphabet compression): one or two keys of 21 characters at
+// chars[pos], characters mapped through the LDS code table `tab`; a byte
+// outside the alphabet sets kErrAlphabet (the host then sorts again with
+// byte keys).  Reads the same words load_key_run reads.
+struct SchedFence {
+    __device__ void operator()() const { __builtin_amdgcn_sched_barrier(0); }
+};
+__device__ __forceinline__ uint64_t packed_load1(const KeyCodec& kc, const uint8_t* tab,
+                                                 const uint8_t* chars, uint64_t pos) {
+    uint64_t raw[3], k[1];
+    load_key_run<3>(chars, pos, raw);
+    if (pack3<3, 1>(tab, raw, k, SchedFence())) atomicOr(kc.status, kErrAlphabet);
+    return k[0];
+}
+__device__ __forceinline__ void packed_load2(const KeyCodec& kc, const uint8_t* tab,
+                                             const uint8_t* chars, uint64_t pos, uint64_t* k0,
+                                             uint64_t* k1) {
+    uint64_t raw[6], k[2];
+    load_key_run<6>(chars, pos, raw);
+    if (pack3<6, 2>(tab, raw, k, SchedFence())) atomicOr(kc.status, kErrAlphabet);
+    *k0 = k[0];
+    *k1 = k[1];
+}
+
+// ---------------------------------------------------------------------------
 // K5: stable redistribution (Section 3.1, out-of-place into the second work
 // array).  A tile is processed in sub-tiles of kSubTile strings:
 //   A. every wavefront loads its 512 strings (8 chunks of 64, in order),
@@ -943,8 +988,10 @@ constexpr int kChunks = (int)(kPerWave / 64);     // chunks of 64 per wavefront
 // bucket / rank word of a lane that holds no string (never a (bucket << 16 | rank))
 constexpr uint32_t kNoString = 0xFFFFFFFFu;
 
-// per-bucket byte: mode in bits 4..5, depth increase (0..8) in bits 0..3
+// per-bucket byte: mode in bits 5..6, depth increase in characters (0..w,
+// w <= 21) in bits 0..4
 constexpr uint32_t kModeLive = 0, kModeSingle = 1, kModeIdentical = 2;
+constexpr uint32_t kModeShift = 5, kDeltaMask = 31;
 
 // exclusive block-wide sum of one value per thread; `wl` holds kWaves words
 __device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
@@ -967,13 +1014,13 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
     return pre + inc - v;
 }
 
-template <bool K3>
+template <bool K3, bool PK>
 __device__ __forceinline__ void scatter_body(
     uint32_t tile, const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid,
     const uint64_t* key_in, const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out,
     uint64_t* key2_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in,
     const uint8_t* tree_lcp, const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
-    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const uint64_t* key3) {
+    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const uint64_t* key3, const KeyCodec& kc) {
     extern __shared__ uint64_t dyn[];
     uint64_t* SK = dyn;                                   // kSubTile staged keys
     uint32_t* SI = (uint32_t*)(SK + kSubTile);            // kSubTile staged indices
@@ -986,6 +1033,12 @@ __device__ __forceinline__ void scatter_body(
     uint8_t* ident = binfo + kmax;                        // kmax: LCP inside identical buckets
     __shared__ uint32_t wl[kWaves];
     (void)vmax;
+    const uint8_t* tab = nullptr;  // packed keys: the code table in LDS
+    if constexpr (PK) {
+        __shared__ uint8_t ctab[256];
+        ctab[threadIdx.x] = kc.table[threadIdx.x];
+        tab = ctab;
+    }
 
     const LSeg g = lseg[tile_tab[tile]];
     const uint32_t k = g.k, tid = threadIdx.x;
@@ -997,14 +1050,14 @@ __device__ __forceinline__ void scatter_body(
         const uint32_t j = b >> 1;
         uint32_t info;
         if (s1 - s0 == 1) {
-            info = kModeSingle << 4;
+            info = kModeSingle << kModeShift;
         } else if (b & 1u) {
             const uint64_t x = tree_in[g.tree_base + j];
-            if (has_zero(x)) {
-                info = kModeIdentical << 4;
-                ident[b] = (uint8_t)nz_bytes(x);
+            if (PK ? codec_has_end(kc, x) : has_zero(x)) {
+                info = kModeIdentical << kModeShift;
+                ident[b] = (uint8_t)(PK ? codec_before_end(kc, x) : nz_bytes(x));
             } else {
-                info = 8;
+                info = PK ? kc.w : 8u;
             }
         } else {
             info = (j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j];
@@ -1038,21 +1091,34 @@ __device__ __forceinline__ void scatter_body(
             bb[c] = valid ? bid[p] : kNoString;
             nk[c] = valid ? key_in[p] : 0ull;
             n2[c] = valid ? key2_in[p] : 0ull;
-            n3[c] = K3 && valid && !has_zero(n2[c]) ? key3[p] : 0ull;
+            n3[c] = K3 && valid && !(PK ? codec_has_end(kc, n2[c]) : has_zero(n2[c])) ? key3[p]
+                                                                                   : 0ull;
             id[c] = valid ? idx_in[p] : 0u;
         }
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             if (bb[c] == kNoString) continue;
             const uint32_t info = binfo[bb[c]];
-            const uint32_t delta = info & 15u;
-            if ((info >> 4) != kModeLive || delta == 0) continue;
+            const uint32_t delta = info & kDeltaMask;
+            if ((info >> kModeShift) != kModeLive || delta == 0) continue;
             // the first pass has the third word too (from init): both words
             // stay exact without a gather
-            if (K3)
-                advance_key24(&nk[c], &n2[c], n3[c], delta);
-            else if (!advance_key16(&nk[c], &n2[c], delta))
+            if (K3) {
+                if constexpr (PK)
+                    codec_advance3(kc, &nk[c], &n2[c], n3[c], delta);
+                else
+                    advance_key24(&nk[c], &n2[c], n3[c], delta);
+            } else if constexpr (PK) {
+                // a packed gather brings one key (21 characters); the eight
+                // chunks' raw words and lookups would not fit in registers together
+                if (!codec_advance2(kc, &nk[c], &n2[c], delta)) {
+                    nk[c] = packed_load1(kc, tab, chars, offsets[id[c]] + g.depth + delta);
+                    n2[c] = codec_has_end(kc, nk[c]) ? 0ull : kKeyUnknown;
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            } else if (!advance_key16(&nk[c], &n2[c], delta)) {
                 load_key16(chars, offsets[id[c]] + g.depth + delta, &nk[c], &n2[c]);
+            }
         }
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
@@ -1110,7 +1176,8 @@ __device__ __forceinline__ void scatter_body(
             SB[s] = (uint16_t)b;
             // the second key word goes straight to its place (runs of a bucket
             // are consecutive within a chunk)
-            if ((binfo[b] >> 4) == kModeLive) key2_out[g.begin + base[b] + s - tstart[b]] = n2[c];
+            if ((binfo[b] >> kModeShift) == kModeLive)
+                key2_out[g.begin + base[b] + s - tstart[b]] = n2[c];
         }
         __syncthreads();
         // D: write contiguous runs
@@ -1120,7 +1187,7 @@ __device__ __forceinline__ void scatter_body(
             const uint32_t dest = g.begin + dr;
             const uint32_t s0 = bst[b];
             if (dr == s0 && dr != 0) S5_OUT(out_lcp[dest], kLcpFlag | g.depth);
-            const uint32_t mode = binfo[b] >> 4;
+            const uint32_t mode = binfo[b] >> kModeShift;
             if (mode == kModeLive) {
                 key_out[dest] = SK[s];
                 idx_out[dest] = SI[s];
@@ -1142,25 +1209,26 @@ __device__ __forceinline__ void scatter_body(
 
 // K3: the first pass, which also reads the third key word (a separate
 // instantiation, so that the other passes keep their smaller register budget)
-template <bool G, bool K3>
+template <bool G, bool K3, bool PK>
 __global__ __launch_bounds__(256) void k_scatter(
     const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
     const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out, uint64_t* key2_out,
     uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart,
     const uint64_t* tree_in, const uint8_t* tree_lcp, const uint8_t* chars,
     const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp, uint32_t vmax, uint32_t kmax,
-    const uint32_t* wcnt, uint32_t cap, const Globals* glob, const uint64_t* key3) {
+    const uint32_t* wcnt, uint32_t cap, const Globals* glob, const uint64_t* key3,
+    KeyCodec kc) {
     if (!G) {
-        scatter_body<K3>(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out,
-                     idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp,
-                     vmax, kmax, key3);
+        scatter_body<K3, PK>(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out,
+                             key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
+                             out_perm, out_lcp, vmax, kmax, key3, kc);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        scatter_body<K3>(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out,
-                     cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax,
-                     kmax, key3);
+        scatter_body<K3, PK>(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out,
+                             idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,
+                             out_lcp, vmax, kmax, key3, kc);
         __syncthreads();
     }
 }
@@ -1274,6 +1342,36 @@ __device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& a) {
     unpack96(h, l, k, a);
 }
 
+// Key operations of the base case for byte keys (PK = false) or packed keys
+// (alphabet compression).
+template <bool PK>
+__device__ __forceinline__ bool key_ends(const KeyCodec& kc, uint64_t k) {
+    if constexpr (PK) return codec_has_end(kc, k);
+    else return has_zero(k);
+}
+template <bool PK>
+__device__ __forceinline__ uint32_t key_lcp(const KeyCodec& kc, uint64_t a, uint64_t b) {
+    if constexpr (PK) return codec_lcp(kc, a, b);
+    else return lcp8(a, b);
+}
+template <bool PK>
+__device__ __forceinline__ uint32_t key_chars(const KeyCodec& kc) {
+    if constexpr (PK) return kc.w;
+    else return 8u;
+}
+template <bool PK>
+__device__ __forceinline__ uint64_t key_load1(const KeyCodec& kc, const uint8_t* tab,
+                                              const uint8_t* chars, uint64_t pos) {
+    if constexpr (PK) return packed_load1(kc, tab, chars, pos);
+    else return load_key(chars, pos);
+}
+template <bool PK>
+__device__ __forceinline__ void key_load2(const KeyCodec& kc, const uint8_t* tab,
+                                          const uint8_t* chars, uint64_t pos, uint64_t* k0,
+                                          uint64_t* k1) {
+    if constexpr (PK) packed_load2(kc, tab, chars, pos, k0, k1);
+    else load_key16(chars, pos, k0, k1);
+}
 // Rounds of decide / re-key / sort inside one wavefront.  Lane r owns output
 // position pos; lanes are sorted by (group, key, local index) and padding
 // lanes (valid == false) are last.  Returns the final packed element of the lane.
@@ -1282,9 +1380,11 @@ __device__ __forceinline__ void wave_sort(uint64_t& k, uint32_t& a) {
 // with fill_n > 0 it is filled by lanes < fill_n on the first round that needs
 // it.  A round re-keys the undecided members 8 bytes deeper; it re-sorts only
 // if some group's keys now differ (equal keys keep their local-index order).
+template <bool PK>
 __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, uint32_t pos,
                                 uint64_t* offl, uint32_t fill_n, const uint32_t* iin,
-                                const uint8_t* chars, const uint64_t* offsets, uint32_t* olcp) {
+                                const uint8_t* chars, const uint64_t* offsets, uint32_t* olcp,
+                                const KeyCodec& kc, const uint8_t* tab) {
     const uint32_t lane = lane_id();
     const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
     bool filled = fill_n == 0;
@@ -1293,10 +1393,10 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
         const uint32_t ap = __shfl_up(a, 1);
         bool und = false;
         if (valid && lane > 0 && (ap >> 16) == (a >> 16)) {
-            if (kp == k && !has_zero(k))
+            if (kp == k && !key_ends<PK>(kc, k))
                 und = true;
             else
-                S5_OUT(olcp[pos], h + lcp8(kp, k));
+                S5_OUT(olcp[pos], h + key_lcp<PK>(kc, kp, k));
         }
         const uint64_t U = __ballot(und);
         if (!U) break;
@@ -1309,9 +1409,9 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
         }
         const bool member = ((U >> lane) & 1ull) || (lane < 63 && ((U >> (lane + 1)) & 1ull));
         const uint32_t st = 63u - (uint32_t)__builtin_clzll((unsigned long long)(~U & upto));
-        h += 8;
+        h += key_chars<PK>(kc);
         if (member) {
-            k = load_key(chars, offl[a & 0xFFFFu] + h);
+            k = key_load1<PK>(kc, tab, chars, offl[a & 0xFFFFu] + h);
             a = (st << 16) | (a & 0xFFFFu);
         } else if (valid) {
             a = (lane << 16) | (a & 0xFFFFu);
@@ -1324,11 +1424,13 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
     return a;
 }
 
+template <bool PK>
 __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
                                                const uint64_t* key0, const uint64_t* key1,
                                                const uint32_t* idx0, const uint32_t* idx1,
                                                const uint8_t* chars, const uint64_t* offsets,
-                                               uint32_t* out_perm, uint32_t* out_lcp) {
+                                               uint32_t* out_perm, uint32_t* out_lcp,
+                                               const KeyCodec& kc, const uint8_t* tab) {
     __shared__ uint64_t offl[kWaves][64];  // string starts, by local index
     const uint32_t lane = lane_id();
     const Seg it = items[item];
@@ -1341,30 +1443,35 @@ __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
     uint64_t k = valid ? kin[lane] : ~0ull;
     uint32_t a = valid ? lane : 0xFFFFFFFFu;
     wave_sort(k, a);
-    const uint32_t fa = wave_rounds(k, a, valid, h, lane, offl[threadIdx.x >> 6], n, iin, chars,
-                                    offsets, out_lcp + it.begin);
+    const uint32_t fa = wave_rounds<PK>(k, a, valid, h, lane, offl[threadIdx.x >> 6], n, iin,
+                                        chars, offsets, out_lcp + it.begin, kc, tab);
     if (valid) S5_OUT(out_perm[it.begin + lane], iin[fa & 0xFFFFu] - it.base);
 }
 
 // One wavefront per item (items are wavefront-uniform; no workgroup barriers).
-template <bool G>
+template <bool G, bool PK>
 __global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_items,
                                                    const uint64_t* key0, const uint64_t* key1,
                                                    const uint32_t* idx0, const uint32_t* idx1,
                                                    const uint8_t* chars, const uint64_t* offsets,
                                                    uint32_t* out_perm, uint32_t* out_lcp,
                                                    const uint32_t* wcnt, uint32_t cap,
-                                                   const Globals* glob, const uint32_t* guard) {
+                                                   const Globals* glob, const uint32_t* guard,
+                                                   KeyCodec kc) {
+    S5_CODE_TABLE(PK, kc, tab)
+    if constexpr (PK) __syncthreads();
     if (!G) {
         const uint32_t it = blockIdx.x * kWaves + (threadIdx.x >> 6);
         if (it < n_items)  // uniform per wavefront
-            base_wave_body(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp);
+            base_wave_body<PK>(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+                               out_lcp, kc, tab);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, n_items, guard);
     for (uint32_t it = blockIdx.x * kWaves + (threadIdx.x >> 6); it < units;
          it += gridDim.x * kWaves)
-        base_wave_body(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp);
+        base_wave_body<PK>(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                           kc, tab);
 }
 
 template <int E, int J>
@@ -1535,13 +1642,14 @@ __device__ void merge_runs(const uint64_t* XK, const uint32_t* XA, uint32_t na,
     }
 }
 
-template <int EMAX, int NT>
+template <int EMAX, int NT, bool PK>
 __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
                                                 const uint64_t* key0, const uint64_t* key1,
                                                 const uint32_t* idx0, const uint32_t* idx1,
                                                 const uint8_t* chars, const uint64_t* offsets,
                                                 uint32_t* out_perm, uint32_t* out_lcp,
-                                                uint32_t pmax) {
+                                                uint32_t pmax, const KeyCodec& kc,
+                                                const uint8_t* tab) {
     extern __shared__ uint64_t dyn[];
     uint64_t* K = dyn;                          // pmax keys, by position
     uint64_t* SK = K + pmax;                    // pmax keys, compacted members
@@ -1597,10 +1705,10 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         uint8_t un = 0;
         if (i > 0) {
             const uint64_t x = K[i - 1], y = K[i];
-            if (x == y && !has_zero(y))
+            if (x == y && !key_ends<PK>(kc, y))
                 un = 1;
             else
-                S5_OUT(olcp[i], h + lcp8(x, y));
+                S5_OUT(olcp[i], h + key_lcp<PK>(kc, x, y));
         }
         F[i] = un;
         any |= un;
@@ -1640,16 +1748,16 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             if (tid < 64) {
                 const bool valid = tid < m;
                 const uint32_t pos = valid ? POS[tid] : 0u;
-                const uint32_t fa = wave_rounds(valid ? SK[tid] : ~0ull, valid ? SA[tid] : 0xFFFFFFFFu,
-                                                valid, h, pos, OFFL, 0u, iin, chars, offsets,
-                                                olcp);
+                const uint32_t fa = wave_rounds<PK>(valid ? SK[tid] : ~0ull,
+                                                    valid ? SA[tid] : 0xFFFFFFFFu, valid, h, pos,
+                                                    OFFL, 0u, iin, chars, offsets, olcp, kc, tab);
                 if (valid) A[pos] = fa;
             }
             __syncthreads();
             break;
         }
-        // re-key the members 8 bytes deeper and sort them by (group, key, local index)
-        h += 8;
+        // re-key the members one key deeper and sort them by (group, key, local index)
+        h += key_chars<PK>(kc);
         uint32_t Pm = 1;
         while (Pm < m) Pm <<= 1;
         // up to pmax / NT members per thread: all their gathers in flight at once
@@ -1677,11 +1785,17 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
 #pragma unroll
             for (int e = 0; e < G; ++e) {
                 const uint32_t q = tid + e * NT;
-                if (need[e] && (differs(q) || has_zero(SK[q]))) prog = 1;
+                if (need[e] && (differs(q) || key_ends<PK>(kc, SK[q]))) prog = 1;
             }
             return __syncthreads_or(prog);
         };
-        {
+        if constexpr (PK) {
+#pragma unroll
+            for (int e = 0; e < G; ++e) {
+                if (need[e]) nkey[e] = packed_load1(kc, tab, chars, pos[e] + h);
+                __builtin_amdgcn_sched_barrier(0);  // one member's raw words at a time
+            }
+        } else {
             uint64_t at[G];
 #pragma unroll
             for (int e = 0; e < G; ++e) at[e] = pos[e] + h;
@@ -1692,18 +1806,28 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             if (need[e]) SK[tid + e * NT] = nkey[e];
         __syncthreads();
         while (!progress()) {
-            // a run of equal bytes: from here on 16 bytes per gather
-            h += 8;
+            // a run of equal characters: from here on two keys per gather
+            // (packed keys: one key of 21 characters per gather)
+            h += key_chars<PK>(kc);
+            if constexpr (PK) {
+#pragma unroll
+                for (int e = 0; e < G; ++e) {
+                    if (need[e]) SK[tid + e * NT] = packed_load1(kc, tab, chars, pos[e] + h);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                __syncthreads();
+                continue;
+            }
             uint64_t k2[G];
 #pragma unroll
             for (int e = 0; e < G; ++e)
-                if (need[e]) load_key16(chars, pos[e] + h, &nkey[e], &k2[e]);
+                if (need[e]) key_load2<PK>(kc, tab, chars, pos[e] + h, &nkey[e], &k2[e]);
 #pragma unroll
             for (int e = 0; e < G; ++e)
                 if (need[e]) SK[tid + e * NT] = nkey[e];
             __syncthreads();
             if (progress()) break;
-            h += 8;
+            h += key_chars<PK>(kc);
 #pragma unroll
             for (int e = 0; e < G; ++e)
                 if (need[e]) SK[tid + e * NT] = k2[e];
@@ -1736,11 +1860,11 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         for (uint32_t i = c0; i < c1; ++i) {
             if (!F[i]) continue;
             const uint64_t x = K[i - 1], y = K[i];
-            if (x == y && !has_zero(y)) {
+            if (x == y && !key_ends<PK>(kc, y)) {
                 any = 1;
             } else {
                 F[i] = 0;
-                S5_OUT(olcp[i], h + lcp8(x, y));
+                S5_OUT(olcp[i], h + key_lcp<PK>(kc, x, y));
             }
         }
         any = __syncthreads_or(any);
@@ -1748,23 +1872,25 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     for (uint32_t i = tid; i < n; i += NT) S5_OUT(out_perm[it.begin + i], IDX[A[i] & 0xFFFFu] - it.base);
 }
 
-template <int EMAX, bool G, int NT>
+template <int EMAX, bool G, int NT, bool PK>
 __global__ __launch_bounds__(NT, EMAX <= 4 ? 4 : 1) void k_base_block(const Seg* items, const uint64_t* key0,
                                                     const uint64_t* key1, const uint32_t* idx0,
                                                     const uint32_t* idx1, const uint8_t* chars,
                                                     const uint64_t* offsets, uint32_t* out_perm,
                                                     uint32_t* out_lcp, uint32_t pmax,
                                                     const uint32_t* wcnt, uint32_t cap,
-                                                    const Globals* glob, const uint32_t* guard) {
+                                                    const Globals* glob, const uint32_t* guard,
+                                                    KeyCodec kc) {
+    S5_CODE_TABLE(PK, kc, tab)
     if (!G) {
-        base_block_body<EMAX, NT>(blockIdx.x, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
-                              out_lcp, pmax);
+        base_block_body<EMAX, NT, PK>(blockIdx.x, items, key0, key1, idx0, idx1, chars, offsets,
+                                      out_perm, out_lcp, pmax, kc, tab);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x, guard);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        base_block_body<EMAX, NT>(u, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
-                              pmax);
+        base_block_body<EMAX, NT, PK>(u, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+                                      out_lcp, pmax, kc, tab);
         __syncthreads();
     }
 }
@@ -1898,10 +2024,47 @@ static inline uint32_t dyn_grid(const Dyn& dy, uint32_t host_units) {
 
 void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
                       uint32_t n, uint64_t* key, uint64_t* key2, uint64_t* key3, uint32_t* idx,
-                      Globals* glob, hipStream_t st) {
+                      Globals* glob, const KeyCodec& kc, hipStream_t st) {
     if (!n) return;
-    S5_LAUNCH(k_init_keys, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len, offsets, n,
-              key, key2, key3, idx, glob);
+    if (kc.b != 8)
+        S5_LAUNCH(k_init_keys<true>, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len,
+                  offsets, n, key, key2, key3, idx, glob, kc);
+    else
+        S5_LAUNCH(k_init_keys<false>, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len,
+                  offsets, n, key, key2, key3, idx, glob, kc);
+}
+
+// Bytes that occur in a sample of the strings (alphabet compression): string
+// i = (j * n) / samples for j < samples, read key by key to its terminator
+// (at most 32 keys); bit c of bitmap[c / 32] is set for every byte value c != 0.
+__global__ __launch_bounds__(256) void k_alphabet(const uint8_t* chars, const uint64_t* offsets,
+                                                  uint32_t n, uint32_t samples,
+                                                  uint32_t* bitmap) {
+    __shared__ uint32_t bm[8];
+    if (threadIdx.x < 8) bm[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < samples) {
+        const uint64_t pos = offsets[(uint32_t)(((uint64_t)j * n) / samples)];
+        for (uint32_t q = 0; q < 32; ++q) {
+            const uint64_t k = load_key(chars, pos + 8ull * q);
+            for (int b = 0; b < 8; ++b) {
+                const uint32_t c = (uint32_t)(k >> (56 - 8 * b)) & 0xFFu;
+                if (c) atomicOr(&bm[c >> 5], 1u << (c & 31));
+            }
+            if (has_zero(k)) break;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 8 && bm[threadIdx.x]) atomicOr(&bitmap[threadIdx.x], bm[threadIdx.x]);
+}
+
+void launch_alphabet(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t samples,
+                     uint32_t* bitmap, hipStream_t st) {
+    S5_LAUNCH(k_zero_words, dim3(1), dim3(256), 0, st, bitmap, 8u);
+    if (!n || !samples) return;
+    S5_LAUNCH(k_alphabet, dim3((samples + 255) / 256), dim3(256), 0, st, chars, offsets, n,
+              samples, bitmap);
 }
 
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
@@ -1933,17 +2096,17 @@ void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
                         uint64_t* tree_in, uint8_t* tree_lcp, uint16_t* jump, uint32_t* tile_tab,
                         uint32_t* chunk_tab, Counters* next_cnt, const Globals* glob,
-                        const Dyn& dy, uint32_t redo, hipStream_t st) {
+                        const Dyn& dy, uint32_t redo, const KeyCodec& kc, hipStream_t st) {
     uint32_t m = alpha * (vmax + 1) - 1, P = 1;
     while (P < m) P <<= 1;
     if (dy.cnt)
         S5_LAUNCH(k_sample_tree<true>, dim3(dy.grid), dim3(kWG), (size_t)P * 8, st, lseg, key_in,
                   alpha, seed, tree_lo, tree_in, tree_lcp, jump, tile_tab, chunk_tab, next_cnt,
-                  dy.cnt, dy.cap, glob, redo);
+                  dy.cnt, dy.cap, glob, redo, kc);
     else
         S5_LAUNCH(k_sample_tree<false>, dim3(n_large), dim3(kWG), (size_t)P * 8, st, lseg, key_in,
                   alpha, seed, tree_lo, tree_in, tree_lcp, jump, tile_tab, chunk_tab, next_cnt,
-                  dy.cnt, dy.cap, glob, redo);
+                  dy.cnt, dy.cap, glob, redo, kc);
 }
 
 void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LSeg* lseg,
@@ -2009,27 +2172,32 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, const uint64_t* key3, hipStream_t st, hipEvent_t ev_start,
-                    hipEvent_t ev_stop) {
+                    const Dyn& dy, const uint64_t* key3, const KeyCodec& kc, hipStream_t st,
+                    hipEvent_t ev_start, hipEvent_t ev_stop) {
     (void)unroll;
     const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
                        (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
     // with events (instrumentation, host-driven passes only) the dispatch
     // itself stamps them: their interval is the kernel's execution, with no
     // marker packets around it
-#define S5_SCATTER(GG, KK, GRID)                                                                  \
+#define S5_SCATTER_P(GG, KK, PP, GRID)                                                            \
     do {                                                                                          \
         if (ev_start || ev_stop)                                                                  \
-            hipExtLaunchKernelGGL((k_scatter<GG, KK>), dim3(GRID), dim3(kWG), lds, st, ev_start,  \
-                                  ev_stop, 0u, lseg, tile_tab, bid, key_in, key2_in, idx_in,      \
-                                  key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp,  \
-                                  chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt, dy.cap,  \
-                                  glob, key3);                                                    \
+            hipExtLaunchKernelGGL((k_scatter<GG, KK, PP>), dim3(GRID), dim3(kWG), lds, st,        \
+                                  ev_start, ev_stop, 0u, lseg, tile_tab, bid, key_in, key2_in,    \
+                                  idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in,    \
+                                  tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax,        \
+                                  dy.cnt, dy.cap, glob, key3, kc);                                \
         else                                                                                      \
-            S5_LAUNCH((k_scatter<GG, KK>), dim3(GRID), dim3(kWG), lds, st, lseg, tile_tab, bid,   \
-                      key_in, key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart,        \
+            S5_LAUNCH((k_scatter<GG, KK, PP>), dim3(GRID), dim3(kWG), lds, st, lseg, tile_tab,    \
+                      bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart,   \
                       tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt,   \
-                      dy.cap, glob, key3);                                                        \
+                      dy.cap, glob, key3, kc);                                                    \
+    } while (0)
+#define S5_SCATTER(GG, KK, GRID)                                                                  \
+    do {                                                                                          \
+        if (kc.b != 8) S5_SCATTER_P(GG, KK, true, GRID);                                          \
+        else S5_SCATTER_P(GG, KK, false, GRID);                                                   \
     } while (0)
     if (dy.cnt) {
         if (key3)
@@ -2043,47 +2211,48 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
             S5_SCATTER(false, false, tiles);
     }
 #undef S5_SCATTER
+#undef S5_SCATTER_P
 }
 
 // Host-driven: n_items[q] items of class q.  Graph mode (dy[q].cnt set): the
 // counts are read on the device, and nothing runs while *guard != 0.
-template <bool G>
+template <bool G, bool PK>
 static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
                              const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                              const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                              uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
-                             const uint32_t* guard, hipStream_t st) {
+                             const uint32_t* guard, const KeyCodec& kc, hipStream_t st) {
     if (G || n_items[0]) {
         const uint32_t g = G ? dy[0].grid : (n_items[0] + kWaves - 1) / kWaves;
-        S5_LAUNCH(k_base_wave<G>, dim3(g), dim3(kWG), 0, st, items[0], n_items[0], key0, key1,
-                  idx0, idx1, chars, offsets, out_perm, out_lcp, dy[0].cnt, dy[0].cap, glob,
-                  guard);
+        S5_LAUNCH((k_base_wave<G, PK>), dim3(g), dim3(kWG), 0, st, items[0], n_items[0], key0,
+                  key1, idx0, idx1, chars, offsets, out_perm, out_lcp, dy[0].cnt, dy[0].cap, glob,
+                  guard, kc);
     }
     uint32_t PT = 1;
     while (PT < T) PT <<= 1;
     const size_t per = 8 + 8 + 8 + 4 + 4 + 4 + 2 + 1;  // K, SK, OFFL, A, SA, IDX, POS, F
     if ((G || n_items[1]) && PT > kBaseWave) {  // <= 256 strings: one wavefront
         const uint32_t P = PT < kBaseSmall ? PT : kBaseSmall;
-        S5_LAUNCH((k_base_block<4, G, 64>), dim3(G ? dy[1].grid : n_items[1]), dim3(64), per * P,
-                  st, items[1], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P,
-                  dy[1].cnt, dy[1].cap, glob, guard);
+        S5_LAUNCH((k_base_block<4, G, 64, PK>), dim3(G ? dy[1].grid : n_items[1]), dim3(64),
+                  per * P, st, items[1], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                  P, dy[1].cnt, dy[1].cap, glob, guard, kc);
     }
     if ((G || n_items[2]) && PT > kBaseSmall) {  // <= 512 strings: two wavefronts
         const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
-        S5_LAUNCH((k_base_block<4, G, 128>), dim3(G ? dy[2].grid : n_items[2]), dim3(128), per * P,
-                  st, items[2], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, P,
-                  dy[2].cnt, dy[2].cap, glob, guard);
+        S5_LAUNCH((k_base_block<4, G, 128, PK>), dim3(G ? dy[2].grid : n_items[2]), dim3(128),
+                  per * P, st, items[2], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                  P, dy[2].cnt, dy[2].cap, glob, guard, kc);
     }
     if ((G || n_items[3]) && PT > kBaseMid) {  // <= T strings: four (or eight) wavefronts
         const dim3 g(G ? dy[3].grid : n_items[3]);
         if (PT <= 4u * kWG)
-            S5_LAUNCH((k_base_block<4, G, kWG>), g, dim3(kWG), per * PT, st, items[3], key0, key1,
-                      idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt, dy[3].cap,
-                      glob, guard);
-        else  // <= 2048 strings: eight wavefronts, four strings each
-            S5_LAUNCH((k_base_block<4, G, 2 * kWG>), g, dim3(2 * kWG), per * PT, st, items[3], key0,
+            S5_LAUNCH((k_base_block<4, G, kWG, PK>), g, dim3(kWG), per * PT, st, items[3], key0,
                       key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
-                      dy[3].cap, glob, guard);
+                      dy[3].cap, glob, guard, kc);
+        else  // <= 2048 strings: eight wavefronts, four strings each
+            S5_LAUNCH((k_base_block<4, G, 2 * kWG, PK>), g, dim3(2 * kWG), per * PT, st, items[3],
+                      key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
+                      dy[3].cap, glob, guard, kc);
     }
 }
 
@@ -2093,13 +2262,23 @@ void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t
                       const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                       uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
-                      const uint32_t* guard, hipStream_t st) {
-    if (dy[0].cnt)
-        base_sort_launch<true>(n_items, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
-                               out_lcp, T, glob, dy, guard, st);
-    else
-        base_sort_launch<false>(n_items, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
-                                out_lcp, T, glob, dy, guard, st);
+                      const uint32_t* guard, const KeyCodec& kc, hipStream_t st) {
+    const bool pk = kc.b != 8;
+    if (dy[0].cnt) {
+        if (pk)
+            base_sort_launch<true, true>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+                                         out_perm, out_lcp, T, glob, dy, guard, kc, st);
+        else
+            base_sort_launch<true, false>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+                                          out_perm, out_lcp, T, glob, dy, guard, kc, st);
+    } else {
+        if (pk)
+            base_sort_launch<false, true>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+                                          out_perm, out_lcp, T, glob, dy, guard, kc, st);
+        else
+            base_sort_launch<false, false>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+                                           out_perm, out_lcp, T, glob, dy, guard, kc, st);
+    }
 }
 
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,

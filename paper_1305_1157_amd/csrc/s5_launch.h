@@ -12,7 +12,9 @@ namespace s5 {
 
 void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
                       uint32_t n, uint64_t* key, uint64_t* key2, uint64_t* key3, uint32_t* idx,
-                      Globals* glob, hipStream_t st);
+                      Globals* glob, const KeyCodec& kc, hipStream_t st);
+void launch_alphabet(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t samples,
+                     uint32_t* bitmap, hipStream_t st);
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                         uint32_t depth, uint64_t* key, hipStream_t st);
 void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
@@ -24,7 +26,7 @@ void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
                         uint64_t* tree_in, uint8_t* tree_lcp, uint16_t* jump, uint32_t* tile_tab,
                         uint32_t* chunk_tab, Counters* next_cnt, const Globals* glob,
-                        const Dyn& dy, uint32_t redo, hipStream_t st);
+                        const Dyn& dy, uint32_t redo, const KeyCodec& kc, hipStream_t st);
 void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LSeg* lseg,
                      const uint32_t* tile_tab, const uint64_t* key_in, const uint64_t* tree_lo,
                      const uint64_t* tree_in, const uint16_t* jump, uint16_t* bid, uint32_t* cm,
@@ -43,13 +45,13 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint32_t* bstart, const uint64_t* tree_in, const uint8_t* tree_lcp,
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
-                    const Dyn& dy, const uint64_t* key3, hipStream_t st,
+                    const Dyn& dy, const uint64_t* key3, const KeyCodec& kc, hipStream_t st,
                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
                       const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                       uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
-                      const uint32_t* guard, hipStream_t st);
+                      const uint32_t* guard, const KeyCodec& kc, hipStream_t st);
 void launch_lcp_fix(const uint8_t* chars, const uint64_t* offsets, const uint64_t* set_begin,
                     uint32_t num_sets, uint32_t n, const uint32_t* out_perm, uint32_t* out_lcp,
                     const uint32_t* guard, const Globals* glob, hipStream_t st);
@@ -67,7 +69,7 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
                              const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
                              uint32_t steps, float lr, float beta, Globals* glob,
                              uint64_t* tree_lo, uint64_t* tree_in, uint8_t* tree_lcp,
-                             uint16_t* jump, const Dyn& dy, hipStream_t st);
+                             uint16_t* jump, const KeyCodec& kc, const Dyn& dy, hipStream_t st);
 void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,
                         float beta, Globals* glob, const Dyn& dy, hipStream_t st);
 void launch_mlp_train(const LearnCtx& c, const uint64_t* sorted_keys, uint32_t m, uint32_t steps,

@@ -509,7 +509,8 @@ __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t sl
                                                   const uint32_t* learn_seg, uint32_t steps,
                                                   float lr, float beta, Globals* glob,
                                                   uint64_t* tree_lo, uint64_t* tree_in,
-                                                  uint8_t* tree_lcp, uint16_t* jump) {
+                                                  uint8_t* tree_lcp, uint16_t* jump,
+                                                  const KeyCodec& kc) {
     __shared__ float w[kNPS];
     __shared__ ProposeLds L;
     const uint32_t tid = threadIdx.x;
@@ -536,8 +537,7 @@ __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t sl
             lo_out[inorder_node(j, g.d)] = x;
             in_out[j] = x;
             uint8_t l = 0;
-            if (j > 0 && L.spl[j - 1] != x)
-                l = (uint8_t)(__builtin_clzll((unsigned long long)(L.spl[j - 1] ^ x)) >> 3);
+            if (j > 0 && L.spl[j - 1] != x) l = (uint8_t)codec_lcp(kc, L.spl[j - 1], x);
             lcp_out[j] = l;
         } else {
             lo_out[0] = 0;
@@ -559,11 +559,12 @@ __global__ __launch_bounds__(256) void k_learn_finish(LearnCtx c, LSeg* lseg,
                                                       float lr, float beta, Globals* glob,
                                                       uint64_t* tree_lo, uint64_t* tree_in,
                                                       uint8_t* tree_lcp, uint16_t* jump,
-                                                      const uint32_t* wcnt, uint32_t cap) {
+                                                      const uint32_t* wcnt, uint32_t cap,
+                                                      KeyCodec kc) {
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t slot = blockIdx.x; slot < units; slot += gridDim.x) {
         learn_finish_body(c, slot, lseg, learn_seg, steps, lr, beta, glob, tree_lo, tree_in,
-                          tree_lcp, jump);
+                          tree_lcp, jump, kc);
         __syncthreads();
     }
 }
@@ -672,7 +673,7 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
                              const uint32_t* learn_seg, const uint64_t* key_in, uint64_t seed,
                              uint32_t steps, float lr, float beta, Globals* glob,
                              uint64_t* tree_lo, uint64_t* tree_in, uint8_t* tree_lcp,
-                             uint16_t* jump, const Dyn& dy, hipStream_t st) {
+                             uint16_t* jump, const KeyCodec& kc, const Dyn& dy, hipStream_t st) {
     const uint32_t g = dy.cnt ? dy.grid : slots;
     hipLaunchKernelGGL(k_learn_prep, dim3(g), dim3(256), 0, st, c, lseg, learn_seg, key_in, seed,
                        dy.cnt, dy.cap, glob);
@@ -680,7 +681,7 @@ void launch_learn_sort_trees(const LearnCtx& c, uint32_t slots, LSeg* lseg,
         hipLaunchKernelGGL(k_learn_step, dim3(c.groups, g), dim3(kGrp), 0, st, c, s, lr, dy.cnt,
                            dy.cap, glob);
     hipLaunchKernelGGL(k_learn_finish, dim3(g), dim3(256), 0, st, c, lseg, learn_seg, steps, lr,
-                       beta, glob, tree_lo, tree_in, tree_lcp, jump, dy.cnt, dy.cap);
+                       beta, glob, tree_lo, tree_in, tree_lcp, jump, dy.cnt, dy.cap, kc);
 }
 
 void launch_learn_check(uint32_t slots, LSeg* lseg, const uint32_t* learn_seg, const uint32_t* cs,

@@ -158,6 +158,120 @@ S5_HD void advance_key24(uint64_t* k0, uint64_t* k1, uint64_t k2, uint32_t delta
     *k1 = (y << s) | (k2 >> (64 - s));
 }
 
+// ---------------------------------------------------------------------------
+// Alphabet compression (appendix A, "Alphabet compression"): when only sigma'
+// byte values occur, each character becomes an order-preserving code of b
+// bits (code 0 is the terminator, the alphabet's bytes get 1..sigma' in byte
+// order), and one 64-bit key holds w = floor(64 / b) characters, packed from
+// the most significant bit down; the 64 - b w lowest bits stay zero.  Unsigned
+// key order is again the lexicographic order of the characters, and a zero
+// field is the end of the string (every field after it is zero too).  Bytes
+// are the case b = 8, w = 8.  Depths and LCPs count characters (= bytes of
+// the string) either way.
+struct KeyCodec {
+    uint32_t b;            // bits per character (8: plain bytes)
+    uint32_t w;            // characters per key
+    uint64_t hi;           // top bit of every character field
+    uint64_t lo;           // the other bits of every character field
+    uint32_t inv_b;        // ceil(2^16 / b): q / b = (q * inv_b) >> 16 for q <= 64
+    uint32_t pad;
+    const uint8_t* table;  // packed: byte -> code, 0xFF for a byte outside the alphabet
+    uint32_t* status;      // packed: status word that a byte outside the alphabet sets
+};
+
+S5_HD KeyCodec make_codec(uint32_t b, const uint8_t* table, uint32_t* status) {
+    KeyCodec c;
+    c.b = b;
+    c.w = 64 / b;
+    c.hi = 0;
+    c.lo = 0;
+    for (uint32_t f = 0; f < c.w; ++f) {
+        const uint32_t top = 63 - f * b;  // field f occupies bits [top, top - b + 1]
+        c.hi |= 1ull << top;
+        c.lo |= ((1ull << (b - 1)) - 1) << (top - b + 1);
+    }
+    c.inv_b = (65536u + b - 1) / b;
+    c.pad = 0;
+    c.table = table;
+    c.status = status;
+    return c;
+}
+S5_HD uint32_t codec_div(const KeyCodec& c, uint32_t q) { return (q * c.inv_b) >> 16; }
+// top bit of every zero field of x (exact, as zero_byte_mask)
+S5_HD uint64_t codec_zero_mask(const KeyCodec& c, uint64_t x) {
+    const uint64_t t = ((x & c.lo) + c.lo) | x;
+    return ~(t | c.lo) & c.hi;
+}
+S5_HD bool codec_has_end(const KeyCodec& c, uint64_t x) { return codec_zero_mask(c, x) != 0; }
+// characters before the end of the string inside the key (w if it does not end)
+S5_HD uint32_t codec_before_end(const KeyCodec& c, uint64_t x) {
+    const uint64_t z = codec_zero_mask(c, x);
+    return z ? codec_div(c, (uint32_t)__builtin_clzll((unsigned long long)z)) : c.w;
+}
+// common leading characters of two keys (for two distinct keys: the fields
+// before the first that differs)
+S5_HD uint32_t codec_lcp(const KeyCodec& c, uint64_t a, uint64_t b) {
+    return a == b ? codec_before_end(c, a)
+                  : codec_div(c, (uint32_t)__builtin_clzll((unsigned long long)(a ^ b)));
+}
+// the key `delta` characters (1 <= delta <= w) further on, from the key x and
+// the key y that follows it
+S5_HD uint64_t codec_shift_in(const KeyCodec& c, uint64_t x, uint64_t y, uint32_t delta) {
+    if (delta >= c.w) return y;
+    const uint32_t s = c.b * delta, spare = 64 - c.b * c.w;
+    return (x << s) | ((y >> (c.b * (c.w - delta))) & ~((1ull << spare) - 1ull));
+}
+// advance_key16 for the codec: both key words advanced by delta characters
+// from what is known (k1 exact or kKeyUnknown); false when a gather is needed
+S5_HD bool codec_advance2(const KeyCodec& c, uint64_t* k0, uint64_t* k1, uint32_t delta) {
+    const uint64_t x = *k0, y = *k1;
+    if (codec_has_end(c, x)) {
+        *k0 = delta < c.w ? x << (c.b * delta) : 0ull;
+        *k1 = 0;
+        return true;
+    }
+    if (y == kKeyUnknown) return false;
+    *k0 = codec_shift_in(c, x, y, delta);
+    *k1 = codec_has_end(c, y) ? (delta < c.w ? y << (c.b * delta) : 0ull) : kKeyUnknown;
+    return true;
+}
+// advance_key24 for the codec (k0, k1, k2 all known)
+S5_HD void codec_advance3(const KeyCodec& c, uint64_t* k0, uint64_t* k1, uint64_t k2,
+                          uint32_t delta) {
+    const uint64_t x = *k0, y = *k1;
+    *k0 = codec_shift_in(c, x, y, delta);
+    *k1 = codec_shift_in(c, y, k2, delta);
+}
+// Packed keys are 3-bit codes (alphabets of at most 7 byte values, such as
+// DNA), 21 characters per key: field f of a key occupies bits 63-3f..61-3f.
+constexpr uint32_t kPackBits = 3, kPackChars = 21;
+
+// NK packed keys (21 characters each) from the raw big-endian words of a
+// string (bytes zero from the terminator on), each byte mapped through
+// `table`.  Returns true if some byte is outside the alphabet (table 0xFF).
+// `fence()` runs after every raw word's eight lookups (on the device a
+// scheduling barrier, so that only one word's lookups are in flight).
+struct NoFence {
+    S5_HD void operator()() const {}
+};
+template <int NR, int NK, class F = NoFence>
+S5_HD bool pack3(const uint8_t* table, const uint64_t (&raw)[NR], uint64_t (&key)[NK],
+                 F fence = F()) {
+    static_assert(8 * NR >= (int)kPackChars * NK, "not enough raw bytes");
+    uint32_t bad = 0;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) key[k] = 0;
+#pragma unroll
+    for (int i = 0; i < (int)kPackChars * NK; ++i) {
+        const uint32_t ch = (uint32_t)(raw[i >> 3] >> (56 - 8 * (i & 7))) & 0xFFu;
+        const uint32_t code = table[ch];
+        bad |= code & 0x80u;
+        key[i / kPackChars] |= (uint64_t)(code & 7u) << (61 - 3 * (i % kPackChars));
+        if ((i & 7) == 7) fence();
+    }
+    return bad != 0;
+}
+
 S5_HD uint64_t mix64(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

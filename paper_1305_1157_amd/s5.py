@@ -19,6 +19,7 @@ S5_ERR_TOO_LARGE = -5
 STATIC_SCRATCH_BYTES = 64 << 20  # S5_STATIC_SCRATCH_BYTES
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 CLASSIFY_UNROLL, CLASSIFY_EQUAL, CLASSIFY_JUMP = 0, 1, 2
+ALPHABET_BYTES, ALPHABET_AUTO = 0, 1
 
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_sort_batched",
            "s5_classify_ex",
@@ -34,7 +35,8 @@ class Config(ctypes.Structure):
                 ("unroll", ctypes.c_uint32), ("tile", ctypes.c_uint32),
                 ("base_threshold", ctypes.c_uint32), ("splitter_mode", ctypes.c_uint32),
                 ("imbalance_bound", ctypes.c_float), ("seed", ctypes.c_uint64),
-                ("graph_levels", ctypes.c_uint32), ("classifier", ctypes.c_uint32)]
+                ("graph_levels", ctypes.c_uint32), ("classifier", ctypes.c_uint32),
+                ("alphabet", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 class SetTuning(ctypes.Structure):
@@ -47,7 +49,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("passes", ctypes.c_uint32), ("fallbacks", ctypes.c_uint32),
                 ("moved_M", ctypes.c_uint64), ("max_bucket", ctypes.c_uint64),
                 ("entropy_bits", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
-                ("base_items", ctypes.c_uint64), ("segments", ctypes.c_uint64)]
+                ("base_items", ctypes.c_uint64), ("segments", ctypes.c_uint64),
+                ("char_bits", ctypes.c_uint32), ("alphabet_retries", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -151,9 +154,9 @@ def _dev(t: torch.Tensor, dtype, name: str):
 
 def make_config(splitters=0, oversample=0, unroll=0, tile=0, base_threshold=0,
                 splitter_mode=SPLIT_SAMPLED, imbalance_bound=0.0, seed=0,
-                graph_levels=0, classifier=CLASSIFY_UNROLL) -> Config:
+                graph_levels=0, classifier=CLASSIFY_UNROLL, alphabet=ALPHABET_BYTES) -> Config:
     return Config(splitters, oversample, unroll, tile, base_threshold, splitter_mode,
-                  imbalance_bound, seed, graph_levels, classifier)
+                  imbalance_bound, seed, graph_levels, classifier, alphabet, 0)
 
 
 def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,

@@ -356,6 +356,107 @@ static void test_jump_table(std::mt19937_64& rng) {
     }
 }
 
+// ---- alphabet compression --------------------------------------------------
+// reference: the codes of the characters of s from depth on (0 from the
+// terminator on), one per character
+static std::vector<uint32_t> ref_codes(const uint8_t* s, const uint8_t* table, int count) {
+    std::vector<uint32_t> c(count, 0);
+    bool ended = false;
+    for (int i = 0; i < count; ++i) {
+        if (!ended && s[i] == 0) ended = true;
+        c[i] = ended ? 0 : table[s[i]];
+    }
+    return c;
+}
+static uint64_t ref_pack(const std::vector<uint32_t>& codes, int first) {
+    uint64_t k = 0;
+    for (int f = 0; f < 21; ++f) k |= (uint64_t)(codes[first + f] & 7) << (61 - 3 * f);
+    return k;
+}
+
+static void test_codec(std::mt19937_64& rng) {
+    // b = 8 is the byte codec exactly
+    const KeyCodec b8 = make_codec(8, nullptr, nullptr);
+    CHECK(b8.w == 8 && b8.hi == 0x8080808080808080ull && b8.lo == 0x7F7F7F7F7F7F7F7Full, "b8");
+    for (int rep = 0; rep < 20000; ++rep) {
+        uint64_t x = rng(), y = rng();
+        if (rng() % 3 == 0) x &= ~(0xFFull << (8 * (rng() % 8)));
+        if (rng() % 3 == 0) y = x ^ (1ull << (rng() % 64));
+        x = clip_at_zero(x);
+        y = clip_at_zero(y);
+        CHECK(codec_has_end(b8, x) == has_zero(x), "b8 has_end");
+        CHECK(codec_before_end(b8, x) == nz_bytes(x), "b8 before_end");
+        CHECK(codec_lcp(b8, x, y) == lcp8(x, y), "b8 lcp");
+        const uint32_t d = 1 + rng() % 8;
+        uint64_t a0 = x, a1 = y, c0 = x, c1 = y;
+        const bool ra = advance_key16(&a0, &a1, d), rc = codec_advance2(b8, &c0, &c1, d);
+        CHECK(ra == rc && (!ra || (a0 == c0 && a1 == c1)), "b8 advance2");
+    }
+    for (uint32_t b = 3; b <= 8; ++b) {
+        const KeyCodec c = make_codec(b, nullptr, nullptr);
+        for (uint32_t q = 0; q <= 64; ++q) CHECK(codec_div(c, q) == q / b, "div b %u q %u", b, q);
+    }
+    // 3-bit codes against the reference: pack3, end test, lcp, advances
+    const KeyCodec c3 = make_codec(3, nullptr, nullptr);
+    CHECK(c3.w == 21 && kPackChars == 21, "w");
+    uint8_t table[256];
+    for (int rep = 0; rep < 3000; ++rep) {
+        const int sigma = 1 + (int)(rng() % 7);
+        std::vector<uint8_t> alpha;
+        while ((int)alpha.size() < sigma) {
+            const uint8_t ch = (uint8_t)(1 + rng() % 255);
+            if (std::find(alpha.begin(), alpha.end(), ch) == alpha.end()) alpha.push_back(ch);
+        }
+        std::sort(alpha.begin(), alpha.end());
+        for (int ch = 0; ch < 256; ++ch) table[ch] = 0xFF;
+        table[0] = 0;
+        for (int i = 0; i < sigma; ++i) table[alpha[i]] = (uint8_t)(i + 1);
+        // two strings sharing a random prefix, lengths up to 80
+        const int la = (int)(rng() % 80), lb = (int)(rng() % 80), common = (int)(rng() % 80);
+        uint8_t sa[160] = {0}, sb[160] = {0};
+        for (int i = 0; i < la; ++i) sa[i] = alpha[rng() % sigma];
+        for (int i = 0; i < lb; ++i) sb[i] = i < common && i < la ? sa[i] : alpha[rng() % sigma];
+        const bool plant = rng() % 10 == 0;  // a byte outside the alphabet
+        if (plant && la > 0) sa[rng() % la] = 0xFF == table[1] ? 1 : (uint8_t)1;
+        const bool bad_expected = plant && la > 0 && table[1] == 0xFF;
+        uint64_t rawa[8], rawb[8];
+        load_key_run<8>(sa, 0, rawa);
+        load_key_run<8>(sb, 0, rawb);
+        uint64_t ka[3], kb[3];
+        const bool bad = pack3<8, 3>(table, rawa, ka);
+        pack3<8, 3>(table, rawb, kb);
+        const auto ca = ref_codes(sa, table, 64), cb = ref_codes(sb, table, 64);
+        bool planted_in_range = false;
+        for (int i = 0; i < 63 && i < la; ++i) planted_in_range |= table[sa[i]] == 0xFF;
+        CHECK(bad == planted_in_range, "pack3 bad flag %d %d", bad, planted_in_range);
+        if (bad_expected) continue;
+        for (int k = 0; k < 3; ++k) {
+            CHECK(ka[k] == ref_pack(ca, 21 * k), "pack3 key %d", k);
+            // order of packed keys = order of the code sequences
+            const auto ea = std::vector<uint32_t>(ca.begin() + 21 * k, ca.begin() + 21 * k + 21);
+            const auto eb = std::vector<uint32_t>(cb.begin() + 21 * k, cb.begin() + 21 * k + 21);
+            CHECK((ka[k] < kb[k]) == (ea < eb), "packed order");
+            int end = 0;
+            while (end < 21 && ea[end]) ++end;
+            CHECK(codec_has_end(c3, ka[k]) == (end < 21), "has_end");
+            CHECK(codec_before_end(c3, ka[k]) == (uint32_t)end, "before_end");
+            int l = 0;
+            while (l < 21 && ea[l] == eb[l] && ea[l]) ++l;
+            CHECK(codec_lcp(c3, ka[k], kb[k]) == (uint32_t)l, "lcp %d", l);
+        }
+        // advancing by delta characters equals packing at depth delta
+        const uint32_t d = 1 + rng() % 21;
+        uint64_t s0 = ka[0], s1 = ka[1], t0 = ka[0], t1 = ka[1];
+        codec_advance3(c3, &s0, &s1, ka[2], d);
+        const bool known = codec_advance2(c3, &t0, &t1, d);
+        const uint64_t want0 = ref_pack(ca, (int)d), want1 = d + 42 <= 64 ? ref_pack(ca, (int)d + 21) : 0;
+        CHECK(s0 == want0 && (d + 42 > 64 || s1 == want1), "advance3 d %u", d);
+        CHECK(known && t0 == want0, "advance2 d %u", d);
+        CHECK(t1 == (codec_has_end(c3, ka[1]) ? (d < 21 ? ka[1] << (3 * d) : 0ull) : kKeyUnknown),
+              "advance2 second word");
+    }
+}
+
 static void test_fig1(const char* path) {
     FILE* f = fopen(path, "r");
     CHECK(f != nullptr, "open %s", path);
@@ -408,6 +509,7 @@ int main(int argc, char** argv) {
     test_node_inorder();
     test_equal_variant(rng);
     test_jump_table(rng);
+    test_codec(rng);
     if (argc > 1) test_fig1(argv[1]);
     if (failures) {
         printf("%d failures\n", failures);
