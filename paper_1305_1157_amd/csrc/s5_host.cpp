@@ -482,8 +482,8 @@ void pass_front(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     (void)L;
 }
 
-// Bucket plan of the next pass, then the redistribution.
-void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
+// Bucket plan of the next pass.
+void pass_plan(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
                const PassShape& S, int cur, int buf, uint32_t level, hipStream_t st) {
     const int nxt = cur ^ 1;
     PlanCtx x = plan_ctx(P, L, c, a, nxt);
@@ -492,6 +492,12 @@ void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
         launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp, x,
                            (uint32_t)(buf ^ 1), S.seg, st);
     });
+}
+
+// The redistribution of the pass.
+void pass_scatter(const SortArgs& a, const Cfg& c, const Ptrs& P, const PassShape& S, int cur,
+                  int buf, uint32_t level, hipStream_t st) {
+    (void)cur;
     timed_dispatch(K_SCATTER, S.now.moved, st, [&](hipEvent_t e0, hipEvent_t e1) {
         launch_scatter(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.bid, P.key[buf],
                        P.key2[buf], P.idx[buf], P.key[buf ^ 1], P.key2[buf ^ 1], P.idx[buf ^ 1],
@@ -500,6 +506,13 @@ void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
                        P.glob, S.tile, level == 0 ? P.key3 : nullptr, codec_of(c, P), st, e0,
                        e1);
     });
+}
+
+// Bucket plan of the next pass, then the redistribution.
+void pass_back(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
+               const PassShape& S, int cur, int buf, uint32_t level, hipStream_t st) {
+    pass_plan(a, c, L, P, S, cur, buf, level, st);
+    pass_scatter(a, c, P, S, cur, buf, level, st);
 }
 
 void clear_counters(const Ptrs& P, hipStream_t st) {
@@ -568,15 +581,41 @@ int choose_alphabet(const SortArgs& a, Cfg& c, const Ptrs& P, void* host, hipStr
     return S5_OK;
 }
 
-// Copy a pass's counters together with the globals and wait for them.
-int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
+// Copy a pass's counters together with the globals (one copy: the two lie
+// next to each other) into the host block.
+int readback_start(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
     char* src = which == 0 ? (char*)P.cnt[0] : (char*)P.glob;
     S5_HIP(hipMemcpyAsync(H.host, src, sizeof(Counters) + sizeof(Globals), hipMemcpyDeviceToHost, st));
-    S5_HIP(hipStreamSynchronize(st));
+    return S5_OK;
+}
+
+// Unpack the host block once the copy has landed.
+int readback_parse(const HostView& H, int which) {
     const char* hb = (const char*)H.host;
     memcpy(H.hc, which == 0 ? hb : hb + sizeof(Globals), sizeof(Counters));
     memcpy(H.hg, which == 0 ? hb + sizeof(Counters) : hb, sizeof(Globals));
     return status_rc(H.hg->status);
+}
+
+// Copy a pass's counters together with the globals and wait for them.
+int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
+    int rc = readback_start(P, H, which, st);
+    if (rc) return rc;
+    S5_HIP(hipStreamSynchronize(st));
+    return readback_parse(H, which);
+}
+
+// An event per device that marks a readback copy, so the host can wait for the
+// copy while the kernels queued after it (the redistribution) still run.
+std::unordered_map<int, hipEvent_t> g_copy_events;
+
+int copy_event(hipEvent_t* out) {
+    int dev = 0;
+    S5_HIP(hipGetDevice(&dev));
+    hipEvent_t& e = g_copy_events[dev];
+    if (!e) S5_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    *out = e;
+    return S5_OK;
 }
 
 // Host-driven passes from `level` on (counters of the pass about to run in
@@ -597,9 +636,23 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
             if (rc) return rc;
             if (H.hg->late_fallbacks != before) pass_front(a, c, L, P, S, cur, buf, 1u, st);
         }
-        pass_back(a, c, L, P, S, cur, buf, level, st);
+        // the plan writes the next pass's counters; they are copied back while
+        // the redistribution runs, and the host waits for the copy only, so the
+        // next pass's launches queue behind the redistribution with no idle gap
+        // (the sort without allocations waits for the whole stream instead)
+        pass_plan(a, c, L, P, S, cur, buf, level, st);
+        rc = readback_start(P, H, nxt, st);
+        if (rc) return rc;
+        hipEvent_t ev = nullptr;
+        if (!t_quiet) {
+            rc = copy_event(&ev);
+            if (rc) return rc;
+            S5_HIP(hipEventRecord(ev, st));
+        }
+        pass_scatter(a, c, P, S, cur, buf, level, st);
         S5_HIP(hipGetLastError());
-        rc = readback(P, H, nxt, st);
+        S5_HIP(ev ? hipEventSynchronize(ev) : hipStreamSynchronize(st));
+        rc = readback_parse(H, nxt);
         if (rc) return rc;
         stats->moved_M += S.now.moved;
         stats->segments += S.now.n_large;
@@ -1078,6 +1131,11 @@ void s5_release(void) {
         if (kv.second) (void)hipStreamDestroy(kv.second);
     }
     g_capture_streams.clear();
+    for (auto& kv : g_copy_events) {
+        (void)hipSetDevice(kv.first);
+        if (kv.second) (void)hipEventDestroy(kv.second);
+    }
+    g_copy_events.clear();
     for (auto& kv : g_pools) {
         (void)hipSetDevice(kv.first);
         (void)hipDeviceSynchronize();
