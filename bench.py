@@ -273,6 +273,9 @@ def learned_extra(name, copy_gbps=None, steps=3):
                       "entropy_bits_first_pass": st["entropy_bits"],
                       "max_bucket_first_pass": st["max_bucket"],
                       "learn_ms": prof.get("learn_splitters", {}).get("total_ms", 0.0),
+                      "learned_proposals": st["learned_proposals"],
+                      "sample_imbalance_mean": st["imbalance_mean"],
+                      "sample_imbalance_max": st["imbalance_max"],
                       "classify_ms": prof.get("classify", {}).get("total_ms", 0.0),
                       "base_ms": prof.get("base_sort", {}).get("total_ms", 0.0),
                       "char_bits": st["char_bits"],

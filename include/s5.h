@@ -133,6 +133,13 @@ typedef struct s5_stats {
                                3: alphabet compression) */
     uint32_t alphabet_retries; /* sorts redone with byte keys after a byte outside
                                   the sampled alphabet */
+    uint32_t learned_proposals; /* learned splitter proposals made (S5_SPLIT_LEARNED) */
+    uint32_t pad;
+    double imbalance_mean;  /* over those proposals: the largest range bucket of the
+                               proposal's own training sample, as a multiple of the
+                               ideal share m / (v + 1) (mean and maximum; a
+                               proposal above imbalance_bound is replaced) */
+    double imbalance_max;
 } s5_stats;
 
 /* Sort n strings.  perm and lcp as described above.  Uses the internal

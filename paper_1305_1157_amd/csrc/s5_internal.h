@@ -106,6 +106,10 @@ struct Globals {
     unsigned long long moved, segments;        // sums over the passes
     unsigned long long moved0, max_bucket0;    // first pass
     double entropy_sum0;
+    // learned proposals: how many, and the largest range bucket of each one's
+    // own sample in thousandths of the ideal share m / (v + 1) (sum and maximum)
+    S5_LINE uint32_t learned_props, imb_max_milli;
+    unsigned long long imb_sum_milli;
 };
 
 // Learned splitters apply to segments of at least this many strings.

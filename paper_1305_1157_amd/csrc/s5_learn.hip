@@ -521,6 +521,13 @@ __device__ __forceinline__ void learn_finish_body(const LearnCtx& c, uint32_t sl
     const uint64_t* smp = c.samples + (size_t)slot * kLearnM;
     const bool reject = propose_body(w, smp, kLearnM, g.v, beta, c.range[2 * slot],
                                      c.range[2 * slot + 1], nullptr, L);
+    if (tid == 0) {  // the proposal's sample imbalance, for the statistics
+        const uint32_t milli =
+            (uint32_t)((1000.0 * L.gmax * (g.v + 1)) / (double)kLearnM + 0.5);
+        atomicAdd(&glob->learned_props, 1u);
+        atomicMax(&glob->imb_max_milli, milli);
+        atomicAdd(&glob->imb_sum_milli, (unsigned long long)milli);
+    }
     if (reject) {
         if (tid == 0) {
             lseg[si].pad0 = 0xFFFFFFFFu;  // the sampled tree is built instead

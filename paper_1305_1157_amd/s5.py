@@ -50,7 +50,9 @@ class Stats(ctypes.Structure):
                 ("moved_M", ctypes.c_uint64), ("max_bucket", ctypes.c_uint64),
                 ("entropy_bits", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
                 ("base_items", ctypes.c_uint64), ("segments", ctypes.c_uint64),
-                ("char_bits", ctypes.c_uint32), ("alphabet_retries", ctypes.c_uint32)]
+                ("char_bits", ctypes.c_uint32), ("alphabet_retries", ctypes.c_uint32),
+                ("learned_proposals", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("imbalance_mean", ctypes.c_double), ("imbalance_max", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -144,7 +144,7 @@ def test_forced_fallback_parity():
     chars, offs = gen.workload("words_50M", 300_000)
     cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED, imbalance_bound=1e-6)
     st = assert_parity(chars, offs, cfg, label="forced fallback")
-    assert st["fallbacks"] >= 1
+    assert st["fallbacks"] >= st["learned_proposals"] >= 1
 
 
 def test_never_fallback_parity():
@@ -153,6 +153,23 @@ def test_never_fallback_parity():
     cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED, imbalance_bound=1e9, base_threshold=64)
     st = assert_parity(chars, offs, cfg, label="never fallback")
     assert st["fallbacks"] == 0
+
+
+def test_sample_imbalance_statistics():
+    """The statistics report each proposal's largest range bucket on its own
+    sample (keys equal to a splitter are not in one), relative to m / (v + 1):
+    positive, the maximum at least the mean; with no bound nothing is replaced."""
+    chars, offs = gen.workload("words_50M", 300_000)
+    for bound in (1e9, 4.0):
+        cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED, imbalance_bound=bound)
+        st = assert_parity(chars, offs, cfg, label=f"imbalance stats, bound {bound}")
+        assert st["learned_proposals"] >= 1
+        assert 0.0 < st["imbalance_mean"] <= st["imbalance_max"] + 1e-9
+        if bound == 1e9:
+            assert st["fallbacks"] == 0
+    sampled = s5.make_config()
+    st = assert_parity(chars, offs, sampled, label="sampled, no proposals")
+    assert st["learned_proposals"] == 0 and st["imbalance_max"] == 0.0
 
 
 def test_batched_learned_parity():
