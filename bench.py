@@ -547,6 +547,28 @@ def main():
             out["classifier_variants"][names[other]] = {"ms": sec2 * 1e3, "value": n / sec2,
                                                         "classify_ms": cl2}
             del ws2
+        # the two-pass distribution (appendix A, multipass data distribution)
+        out["distribution_variants"] = {
+            "one_pass": {"ms": ms_per_step, "value": value,
+                         "scatter_ms": kernels.get("scatter", {}).get("ms_per_step")}}
+        c2 = s5.make_config(splitter_mode=cfg.splitter_mode,
+                            distribution=s5.DISTRIBUTE_TWO_PASS)
+        ws2 = torch.empty(s5.workspace_bytes(n, c2), dtype=torch.uint8, device=dev)
+        run2 = lambda: s5.sort(d_chars, d_offs, cfg=c2, out_perm=perm, out_lcp=lcp,  # noqa
+                               workspace=ws2)
+        run2()
+        sec2 = _timed_sorts(run2, args.steps)
+        s5.profile_enable(True)
+        run2()
+        torch.cuda.synchronize()
+        pr2 = s5.profile_read()
+        s5.profile_enable(False)
+        out["distribution_variants"]["two_pass"] = {
+            "ms": sec2 * 1e3, "value": n / sec2,
+            "scatter_ms": pr2.get("scatter", {}).get("total_ms"),
+            "scatter_launches": pr2.get("scatter", {}).get("launches"),
+            "digit_counts_ms": pr2.get("digit_counts", {}).get("total_ms")}
+        del ws2
     if args.cpu_sample:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, min(args.cpu_sample, n))

@@ -84,6 +84,17 @@ extern "C" {
                                 checks its bytes; a byte outside the alphabet makes
                                 the call sort again with byte keys */
 
+/* distribution: how a level's strings move to their buckets (appendix A,
+ * "Multipass data distribution"; the output never depends on it) */
+#define S5_DISTRIBUTE_ONE_PASS 0u /* one stable move per level, by bucket id */
+#define S5_DISTRIBUTE_TWO_PASS 1u /* two stable moves per level by the two digits of
+                                     the bucket id, low digit first (a least-
+                                     significant-digit radix sort on the ids): each
+                                     move has at most 64 destinations per segment,
+                                     whatever the number of buckets.  Host-driven
+                                     sorts only: s5_sort_batched and
+                                     s5_sort_batched_tuned return S5_ERR_INVALID */
+
 /* splitter_mode */
 #define S5_SPLIT_SAMPLED 0u /* splitters from a pseudo-random sample (Section 3.1) */
 #define S5_SPLIT_LEARNED 1u /* splitters proposed by a small learned CDF model */
@@ -115,7 +126,8 @@ typedef struct s5_config {
     uint32_t classifier;     /* S5_CLASSIFY_UNROLL (default), S5_CLASSIFY_EQUAL or
                                 S5_CLASSIFY_JUMP */
     uint32_t alphabet;       /* S5_ALPHABET_BYTES (default) or S5_ALPHABET_AUTO */
-    uint32_t reserved;       /* must be 0 */
+    uint32_t distribution;   /* S5_DISTRIBUTE_ONE_PASS (default) or
+                                S5_DISTRIBUTE_TWO_PASS */
 } s5_config;
 
 /* Counters of the last completed sort on a stream. */

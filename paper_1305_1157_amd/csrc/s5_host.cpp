@@ -40,6 +40,7 @@ struct Cfg {
     uint32_t T_caps, tile_caps;  // smallest T and tile of any set: storage capacities
     float beta;
     uint32_t graph_levels;
+    uint32_t distribution;  // S5_DISTRIBUTE_*
     uint64_t seed;
 };
 
@@ -76,7 +77,9 @@ int resolve_cfg(const s5_config* c, Cfg* o) {
     o->alphabet = c->alphabet;
     o->b = 8;
     if (o->alphabet != S5_ALPHABET_BYTES && o->alphabet != S5_ALPHABET_AUTO) return S5_ERR_INVALID;
-    if (c->reserved) return S5_ERR_INVALID;
+    o->distribution = c->distribution;
+    if (o->distribution != S5_DISTRIBUTE_ONE_PASS && o->distribution != S5_DISTRIBUTE_TWO_PASS)
+        return S5_ERR_INVALID;
     if (o->classifier != S5_CLASSIFY_UNROLL && o->classifier != S5_CLASSIFY_EQUAL &&
         o->classifier != S5_CLASSIFY_JUMP)
         return S5_ERR_INVALID;
@@ -94,7 +97,7 @@ uint32_t limited(uint32_t cap, uint32_t which) {
 
 // Workspace regions (byte offsets into one device allocation).
 struct Layout {
-    size_t key[2], key2[2], key3, idx[2], bid, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, jump, cm, cs,
+    size_t key[2], key2[2], key3, idx[2], bid, bid2, lseg[2], tile_tab, chunk_tab, tree_lo, tree_in, tree_lcp, jump, cm, cs,
         bstart, base_list, learn, learn_seg, set_tune, code_tab, alpha_bits, counters[2], glob,
         total;
     uint32_t learn_cap, tune_sets;
@@ -140,6 +143,8 @@ Layout make_layout(uint64_t n, const Cfg& c, uint32_t tune_sets) {
     L.key3 = take(n * 8);
     for (int b = 0; b < 2; ++b) L.idx[b] = take(n * 4);
     L.bid = take(n * 2);
+    // two-pass distribution: the bucket ids travel with the first move
+    L.bid2 = take(c.distribution == S5_DISTRIBUTE_TWO_PASS ? n * 2 : 0);
     for (int b = 0; b < 2; ++b) L.lseg[b] = take((size_t)cp.large * sizeof(LSeg));
     L.tile_tab = take((size_t)cp.tiles * 4);
     L.chunk_tab = take((size_t)cp.chunks * 4);
@@ -230,15 +235,16 @@ int pool_get(size_t bytes, DevPool** out) {
 
 // ---- per-kernel event timing (s5_profile.h) --------------------------------
 enum KId { K_INIT, K_ROOTS, K_SAMPLE, K_CLASSIFY, K_COLSCAN, K_PLAN, K_SCATTER, K_BASE, K_LCPFIX,
-           K_LEARN, K_GRAPH, K_COUNT };
+           K_LEARN, K_GRAPH, K_DIGITS, K_COUNT };
 const char* const kKName[K_COUNT] = {"init_keys", "plan_roots",      "sample_tree", "classify",
                                      "colscan",   "bucket_plan",     "scatter",     "base_sort",
-                                     "lcp_fix",   "learn_splitters", "sort_graph"};
+                                     "lcp_fix",   "learn_splitters", "sort_graph",  "digit_counts"};
 // algorithmic bytes per string processed: init reads an offset and 8 key bytes
 // and writes key + index; classify reads a key and writes a bucket id; a
 // redistribution pass reads and writes (key, index); the base case reads
 // (key, index) and writes perm + lcp; the LCP completion reads one lcp word
-const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4, 0, 0};
+// (the two-pass distribution's digit counts read a bucket id)
+const double kKBytes[K_COUNT] = {28, 0, 0, 10, 0, 0, 24, 20, 4, 0, 0, 2};
 struct ProfAcc {
     uint64_t launches = 0, items = 0;
     double ms = 0, bytes = 0;
@@ -335,6 +341,7 @@ struct Ptrs {
     uint64_t* key3;     // the 8 bytes after those, for the first pass only
     uint32_t* idx[2];
     uint16_t* bid;
+    uint16_t* bid2;
     LSeg* lseg[2];
     uint32_t *tile_tab, *chunk_tab;
     uint64_t *tree_lo, *tree_in;
@@ -360,6 +367,7 @@ Ptrs make_ptrs(const Layout& L, char* W) {
         P.cnt[b] = (Counters*)(W + L.counters[b]);
     }
     P.bid = (uint16_t*)(W + L.bid);
+    P.bid2 = (uint16_t*)(W + L.bid2);
     P.tile_tab = (uint32_t*)(W + L.tile_tab);
     P.chunk_tab = (uint32_t*)(W + L.chunk_tab);
     P.tree_lo = (uint64_t*)(W + L.tree_lo);
@@ -489,23 +497,41 @@ void pass_plan(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     PlanCtx x = plan_ctx(P, L, c, a, nxt);
     x.stats = level == 0 ? 1u : 0u;  // the statistics report the first pass only
     timed(K_PLAN, S.now.moved, st, [&] {
+        // the buffer the level leaves its strings in
+        const int out = c.distribution == S5_DISTRIBUTE_TWO_PASS ? buf : buf ^ 1;
         launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp, x,
-                           (uint32_t)(buf ^ 1), S.seg, st);
+                           (uint32_t)out, S.seg, st);
     });
 }
 
-// The redistribution of the pass.
+// The redistribution of the pass: one move from buffer `buf` into the other,
+// or (two-pass distribution) a move by the low digit of the bucket ids into
+// the other buffer and one by the high digit back into `buf`.  Each move
+// first counts its digit per tile, scans the columns and adds the digits'
+// starts (the bucket count matrix is used up by the plan by then).
 void pass_scatter(const SortArgs& a, const Cfg& c, const Ptrs& P, const PassShape& S, int cur,
                   int buf, uint32_t level, hipStream_t st) {
-    (void)cur;
-    timed_dispatch(K_SCATTER, S.now.moved, st, [&](hipEvent_t e0, hipEvent_t e1) {
-        launch_scatter(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, P.bid, P.key[buf],
-                       P.key2[buf], P.idx[buf], P.key[buf ^ 1], P.key2[buf ^ 1], P.idx[buf ^ 1],
-                       P.cm, P.cs, P.bstart,
-                       P.tree_in, P.tree_lcp, a.chars, a.offsets, a.perm, a.lcp, S.vmax, S.kmax,
-                       P.glob, S.tile, level == 0 ? P.key3 : nullptr, codec_of(c, P), st, e0,
-                       e1);
-    });
+    const bool two = c.distribution == S5_DISTRIBUTE_TWO_PASS;
+    for (uint32_t dig = two ? kDigitLow : 0u; dig <= (two ? kDigitHigh : 0u); ++dig) {
+        const int from = dig == kDigitHigh ? buf ^ 1 : buf, to = dig == kDigitHigh ? buf : buf ^ 1;
+        const uint16_t* bid = dig == kDigitHigh ? P.bid2 : P.bid;
+        if (dig) {
+            timed(K_DIGITS, S.now.moved, st, [&] {
+                launch_digit_count(S.now.tiles, P.lseg[cur], P.tile_tab, bid, P.cm, dig, st);
+                launch_colscan(S.now.chunks, S.kmax, P.lseg[cur], P.chunk_tab, P.cm, P.cs, P.glob,
+                               S.chunk, 0u, st, dig);
+                launch_digit_starts(S.now.n_large, P.lseg[cur], P.cs, dig, st);
+            });
+        }
+        timed_dispatch(K_SCATTER, S.now.moved, st, [&](hipEvent_t e0, hipEvent_t e1) {
+            launch_scatter(S.now.tiles, c.unroll, P.lseg[cur], P.tile_tab, bid, P.key[from],
+                           P.key2[from], P.idx[from], P.key[to], P.key2[to], P.idx[to], P.cm,
+                           P.cs, P.bstart, P.tree_in, P.tree_lcp, a.chars, a.offsets, a.perm,
+                           a.lcp, S.vmax, S.kmax, P.glob, S.tile,
+                           level == 0 && dig != kDigitHigh ? P.key3 : nullptr, codec_of(c, P),
+                           st, e0, e1, dig, dig == kDigitLow ? P.bid2 : nullptr);
+        });
+    }
 }
 
 // Bucket plan of the next pass, then the redistribution.
@@ -662,7 +688,7 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
         }
         ++level;
         cur = nxt;
-        buf ^= 1;
+        if (c.distribution != S5_DISTRIBUTE_TWO_PASS) buf ^= 1;
     }
     stats->passes = level;
     uint32_t n_base[kBaseClasses];
@@ -1054,6 +1080,8 @@ int s5_sort_batched_tuned(const uint8_t* chars, uint64_t chars_len, const uint64
     if (!set_begin || num_sets == 0xFFFFFFFFu) return S5_ERR_INVALID;
     Cfg base;
     if (resolve_cfg(cfg, &base)) return S5_ERR_INVALID;
+    // the two-pass distribution runs in host-driven sorts only
+    if (base.distribution != S5_DISTRIBUTE_ONE_PASS) return S5_ERR_INVALID;
     // per-set parameters: validated and packed on the host
     std::vector<uint32_t> packed;
     if (set_tuning) {

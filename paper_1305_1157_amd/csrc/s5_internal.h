@@ -19,6 +19,8 @@ constexpr uint32_t kMaxTiles = 1024;     // tiles per segment, at most
 constexpr uint32_t kSubTile = 2048;      // strings staged at once by the redistribution
 constexpr uint32_t kChunkRows = 64;      // count-matrix rows per column-scan chunk
 constexpr int kDMax = 10;                // tree depth limit: v <= 1023 splitters
+// values of the larger (low) digit of a bucket id in the two-pass distribution
+constexpr uint32_t kDigitMax = 1u << ((kDMax + 2) / 2);
 constexpr uint32_t kLcpFlag = 0x80000000u;  // out_lcp entry still to be completed
 constexpr uint32_t kBufBit = 0x80000000u;   // work-buffer bit packed into a depth
 

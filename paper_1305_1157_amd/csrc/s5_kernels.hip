@@ -28,6 +28,9 @@
 //                  of buckets whose depth grows are advanced from the carried
 //                  words or refreshed from the arena on the way; buckets that
 //                  are finished write their final output directly
+//   (two-pass distribution: k_digit_count, k_colscan and k_digit_starts per
+//   digit of the bucket ids, then k_scatter by the low digit, and the same
+//   by the high digit)
 // followed, once every bucket is small, by k_base_sort (LDS sorter that emits
 // LCPs) and k_lcp_fix (LCPs at bucket boundaries).
 #include <hip/hip_ext.h>
@@ -769,13 +772,16 @@ __global__ __launch_bounds__(256) void k_classify(const LSeg* lseg, const uint32
 // ---------------------------------------------------------------------------
 // K4a: exclusive scan down every bucket column within a chunk of unit rows
 
+// dig: the columns are those of a digit of the bucket ids (two-pass
+// distribution) instead of the buckets
 __device__ __forceinline__ void colscan_body(uint32_t cg, uint32_t redo, const LSeg* lseg,
                                              const uint32_t* chunk_tab, uint32_t* cm,
-                                             uint32_t* cs) {
+                                             uint32_t* cs, uint32_t dig) {
     const LSeg g = lseg[chunk_tab[cg]];
     if (redo && g.pad1 != 1u) return;
     const uint32_t b = blockIdx.y * kWG + threadIdx.x;
-    if (b >= g.k) return;
+    const uint32_t kc = digit_values(g.k, g.d, dig);
+    if (b >= kc) return;
     const uint32_t c = cg - g.chunk_base;
     const uint32_t r0 = c * kChunkRows;
     const uint32_t r1 = r0 + kChunkRows < g.tiles ? r0 + kChunkRows : g.tiles;
@@ -786,31 +792,77 @@ __device__ __forceinline__ void colscan_body(uint32_t cg, uint32_t redo, const L
         const uint32_t m = r1 - r < 16 ? r1 - r : 16u;
         uint32_t x[16];
 #pragma unroll
-        for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(r + i) * g.k] : 0u;
+        for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(r + i) * kc] : 0u;
 #pragma unroll
         for (uint32_t i = 0; i < 16; ++i)
             if (i < m) {
-                col[(uint64_t)(r + i) * g.k] = run;
+                col[(uint64_t)(r + i) * kc] = run;
                 run += x[i];
             }
     }
-    cs[g.cs_base + (uint64_t)c * g.k + b] = run;
+    cs[g.cs_base + (uint64_t)c * kc + b] = run;
 }
 
 template <bool G>
 __global__ __launch_bounds__(256) void k_colscan(const LSeg* lseg, const uint32_t* chunk_tab,
                                                  uint32_t* cm, uint32_t* cs, const uint32_t* wcnt,
-                                                 uint32_t cap, const Globals* glob, uint32_t redo) {
+                                                 uint32_t cap, const Globals* glob, uint32_t redo,
+                                                 uint32_t dig) {
     if (!G) {
-        colscan_body(blockIdx.x, redo, lseg, chunk_tab, cm, cs);
+        colscan_body(blockIdx.x, redo, lseg, chunk_tab, cm, cs, dig);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) colscan_body(u, redo, lseg, chunk_tab, cm, cs);
+    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x)
+        colscan_body(u, redo, lseg, chunk_tab, cm, cs, dig);
 }
 
 // ---------------------------------------------------------------------------
 // K4b: chunk prefixes, bucket starts, and the plan of every bucket
+
+// Column b of a segment's chunk sums (kc columns): the exclusive prefix down
+// the chunks, written back, and the column's total in tot[b].  16 chunks'
+// loads are in flight at once.
+__device__ __forceinline__ void chunk_prefixes(const LSeg& g, uint32_t* cs, uint32_t kc,
+                                               uint32_t* tot) {
+    for (uint32_t b = threadIdx.x; b < kc; b += kWG) {
+        uint32_t run = 0;
+        uint32_t* col = cs + g.cs_base + b;
+        for (uint32_t c = 0; c < g.chunks; c += 16) {
+            const uint32_t m = g.chunks - c < 16 ? g.chunks - c : 16u;
+            uint32_t x[16];
+#pragma unroll
+            for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(c + i) * kc] : 0u;
+#pragma unroll
+            for (uint32_t i = 0; i < 16; ++i)
+                if (i < m) {
+                    col[(uint64_t)(c + i) * kc] = run;
+                    run += x[i];
+                }
+        }
+        tot[b] = run;
+    }
+}
+
+// s0 (the column's start in the segment) added to every chunk prefix of column b
+__device__ __forceinline__ void add_column_start(const LSeg& g, uint32_t* cs, uint32_t kc,
+                                                 uint32_t b, uint32_t s0) {
+    uint32_t* col = cs + g.cs_base + b;
+    for (uint32_t c = 0; c < g.chunks; c += 16) {
+        const uint32_t m = g.chunks - c < 16 ? g.chunks - c : 16u;
+        uint32_t x[16];
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(c + i) * kc] : 0u;
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i)
+            if (i < m) col[(uint64_t)(c + i) * kc] = x[i] + s0;
+    }
+}
+
+__device__ __forceinline__ void add_starts(const LSeg& g, uint32_t* cs, uint32_t kc,
+                                           const uint32_t* st) {
+    for (uint32_t b = threadIdx.x; b < kc; b += kWG) add_column_start(g, cs, kc, b, st[b]);
+}
 
 __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg, uint32_t* cs,
                                                  uint32_t* bstart, const uint64_t* tree_in,
@@ -822,24 +874,7 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     const LSeg g = lseg[seg];
     const SetP sp = set_params(ctx, g.base);
     const uint32_t k = g.k;
-    for (uint32_t b = threadIdx.x; b < k; b += kWG) {
-        // exclusive prefix over the chunk sums, 16 chunks' loads in flight at once
-        uint32_t run = 0;
-        uint32_t* col = cs + g.cs_base + b;
-        for (uint32_t c = 0; c < g.chunks; c += 16) {
-            const uint32_t m = g.chunks - c < 16 ? g.chunks - c : 16u;
-            uint32_t x[16];
-#pragma unroll
-            for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(c + i) * k] : 0u;
-#pragma unroll
-            for (uint32_t i = 0; i < 16; ++i)
-                if (i < m) {
-                    col[(uint64_t)(c + i) * k] = run;
-                    run += x[i];
-                }
-        }
-        tot[b] = run;
-    }
+    chunk_prefixes(g, cs, k, tot);
     __syncthreads();
     block_exclusive_scan(tot, st, k, tmp);
     uint32_t* bs = bstart + g.bstart_base;
@@ -849,16 +884,7 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
         const uint32_t s0 = st[b];
         bs[b] = s0;
-        uint32_t* col = cs + g.cs_base + b;
-        for (uint32_t c = 0; c < g.chunks; c += 16) {
-            const uint32_t m = g.chunks - c < 16 ? g.chunks - c : 16u;
-            uint32_t x[16];
-#pragma unroll
-            for (uint32_t i = 0; i < 16; ++i) x[i] = i < m ? col[(uint64_t)(c + i) * k] : 0u;
-#pragma unroll
-            for (uint32_t i = 0; i < 16; ++i)
-                if (i < m) col[(uint64_t)(c + i) * k] = x[i] + s0;
-        }
+        add_column_start(g, cs, k, b, s0);
         const uint32_t sz = tot[b];
         if (sz == 0 || !ctx.stats) continue;
         ent += (double)sz * log2((double)g.size / (double)sz);
@@ -1014,22 +1040,36 @@ __device__ uint32_t block_excl_add(uint32_t v, uint32_t* wl, uint32_t* total) {
     return pre + inc - v;
 }
 
-template <bool K3, bool PK>
+// Slots are ranked by "rank buckets": the bucket itself (DIG = 0, one move per
+// level), or one digit of it in the two-pass distribution (DIG = kDigitLow:
+// keys advanced and everything moved, bucket ids included, into the other
+// arrays by the low digit; DIG = kDigitHigh: moved back by the high digit,
+// which leaves every bucket in place, and finished there as with DIG = 0).
+// krmax: LDS entries of the rank-bucket counters.
+template <int DIG>
+__host__ __device__ constexpr uint32_t scatter_krmax(uint32_t kmax) {
+    return DIG ? kDigitMax : kmax;
+}
+
+template <bool K3, bool PK, int DIG>
 __device__ __forceinline__ void scatter_body(
     uint32_t tile, const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid,
     const uint64_t* key_in, const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out,
     uint64_t* key2_out, uint32_t* idx_out, const uint32_t* cm, const uint32_t* cs, const uint32_t* bstart, const uint64_t* tree_in,
     const uint8_t* tree_lcp, const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
-    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const uint64_t* key3, const KeyCodec& kc) {
+    uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const uint64_t* key3, const KeyCodec& kc,
+    uint16_t* bid_out) {
+    static_assert(DIG == 0 || !K3 || DIG == (int)kDigitLow, "the third word is read where keys advance");
     extern __shared__ uint64_t dyn[];
+    const uint32_t krmax = scatter_krmax<DIG>(kmax);
     uint64_t* SK = dyn;                                   // kSubTile staged keys
     uint32_t* SI = (uint32_t*)(SK + kSubTile);            // kSubTile staged indices
-    uint32_t* base = SI + kSubTile;                       // kmax: next slot of each bucket
-    uint32_t* bst = base + kmax;                          // kmax: bucket starts in the segment
+    uint32_t* base = SI + kSubTile;                       // krmax: next slot of each rank bucket
+    uint32_t* bst = base + krmax;                         // kmax: bucket starts in the segment
     uint16_t* SB = (uint16_t*)(bst + kmax);               // kSubTile staged buckets
-    uint16_t* whist = SB + kSubTile;                      // kWaves * kmax per-wave counts
-    uint16_t* tstart = whist + kWaves * kmax;             // kmax + 1: starts in the sub-tile
-    uint8_t* binfo = (uint8_t*)(tstart + (kmax + 1));     // kmax: mode | depth increase
+    uint16_t* whist = SB + kSubTile;                      // kWaves * krmax per-wave counts
+    uint16_t* tstart = whist + kWaves * krmax;            // krmax + 1: starts in the sub-tile
+    uint8_t* binfo = (uint8_t*)(tstart + (krmax + 1));    // kmax: mode | depth increase
     uint8_t* ident = binfo + kmax;                        // kmax: LCP inside identical buckets
     __shared__ uint32_t wl[kWaves];
     (void)vmax;
@@ -1042,11 +1082,20 @@ __device__ __forceinline__ void scatter_body(
 
     const LSeg g = lseg[tile_tab[tile]];
     const uint32_t k = g.k, tid = threadIdx.x;
+    const uint32_t kr = digit_values(k, g.d, DIG);  // rank buckets (k when DIG = 0)
     const uint32_t row = tile - g.tile_base, chunk = row / kChunkRows;
+    if (DIG) {
+        for (uint32_t r = tid; r < kr; r += kWG) {
+            base[r] = cs[g.cs_base + (uint64_t)chunk * kr + r] + cm[g.cm_base + (uint64_t)row * kr + r];
+#pragma unroll
+            for (int q = 0; q < kWaves; ++q) whist[q * krmax + r] = 0;
+        }
+    }
     for (uint32_t b = tid; b < k; b += kWG) {
         const uint32_t s0 = bstart[g.bstart_base + b], s1 = bstart[g.bstart_base + b + 1];
         bst[b] = s0;
-        base[b] = cs[g.cs_base + (uint64_t)chunk * k + b] + cm[g.cm_base + (uint64_t)row * k + b];
+        if (!DIG)
+            base[b] = cs[g.cs_base + (uint64_t)chunk * k + b] + cm[g.cm_base + (uint64_t)row * k + b];
         const uint32_t j = b >> 1;
         uint32_t info;
         if (s1 - s0 == 1) {
@@ -1063,19 +1112,21 @@ __device__ __forceinline__ void scatter_body(
             info = (j == 0 || j == g.v) ? 0u : (uint32_t)tree_lcp[g.tree_base + j];
         }
         binfo[b] = (uint8_t)info;
+        if (!DIG) {
 #pragma unroll
-        for (int q = 0; q < kWaves; ++q) whist[q * kmax + b] = 0;
+            for (int q = 0; q < kWaves; ++q) whist[q * krmax + b] = 0;
+        }
     }
     __syncthreads();
 
     const uint32_t w = tid >> 6, lane = lane_id();
-    uint16_t* wh = whist + w * kmax;
+    uint16_t* wh = whist + w * krmax;
     const uint64_t ltmask = (1ull << lane) - 1ull;
-    const uint32_t nbits = g.d + 1;
+    const uint32_t nbits = digit_bits(g.d, DIG);
     const uint64_t tb = (uint64_t)row * g.tile_len;
     const uint32_t start = g.begin + (uint32_t)(tb < g.size ? tb : g.size);
     const uint32_t end = g.begin + (uint32_t)(tb + g.tile_len < g.size ? tb + g.tile_len : g.size);
-    const uint32_t per = (k + kWG - 1) / kWG;  // buckets per thread in phase B (<= 8)
+    const uint32_t per = (kr + kWG - 1) / kWG;  // rank buckets per thread in phase B (<= 8)
     const uint32_t b0 = tid * per;
 
     for (uint32_t sub = start; sub < end; sub += kSubTile) {
@@ -1097,7 +1148,8 @@ __device__ __forceinline__ void scatter_body(
         }
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
-            if (bb[c] == kNoString) continue;
+            // the two-pass distribution advances the keys in its first move
+            if (DIG == (int)kDigitHigh || bb[c] == kNoString) continue;
             const uint32_t info = binfo[bb[c]];
             const uint32_t delta = info & kDeltaMask;
             if ((info >> kModeShift) != kModeLive || delta == 0) continue;
@@ -1127,10 +1179,11 @@ __device__ __forceinline__ void scatter_body(
             const uint64_t act = __ballot(valid);
             if (!act) break;
             const uint32_t b = valid ? bb[c] : 0u;
-            const uint64_t m = match_bucket(b, nbits, act);
-            const uint32_t old = valid ? wh[b] : 0u;
+            const uint32_t rb = digit_of(b, g.d, DIG);
+            const uint64_t m = match_bucket(rb, nbits, act);
+            const uint32_t old = valid ? wh[rb] : 0u;
             if (valid && lane == (uint32_t)(__ffsll((long long)m) - 1))
-                wh[b] = (uint16_t)(old + (uint32_t)__popcll(m));
+                wh[rb] = (uint16_t)(old + (uint32_t)__popcll(m));
             bb[c] = valid ? ((b << 16) | (old + (uint32_t)__popcll(m & ltmask))) : kNoString;
         }
         __syncthreads();
@@ -1141,12 +1194,12 @@ __device__ __forceinline__ void scatter_body(
         for (int e = 0; e < 8; ++e) {
             const uint32_t b = b0 + e;
             tot[e] = 0;
-            if ((uint32_t)e < per && b < k) {
+            if ((uint32_t)e < per && b < kr) {
                 uint32_t r = 0;
 #pragma unroll
                 for (int q = 0; q < kWaves; ++q) {
-                    const uint32_t x = whist[q * kmax + b];
-                    whist[q * kmax + b] = (uint16_t)r;
+                    const uint32_t x = whist[q * krmax + b];
+                    whist[q * krmax + b] = (uint16_t)r;
                     r += x;
                 }
                 tot[e] = r;
@@ -1158,33 +1211,39 @@ __device__ __forceinline__ void scatter_body(
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t b = b0 + e;
-            if ((uint32_t)e < per && b < k) {
+            if ((uint32_t)e < per && b < kr) {
                 tstart[b] = (uint16_t)run;
                 run += tot[e];
             }
         }
-        if (tid == 0) tstart[k] = (uint16_t)nsub;
+        if (tid == 0) tstart[kr] = (uint16_t)nsub;
         __syncthreads();
         // C: stage in bucket order
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
             if (bb[c] == kNoString) continue;
-            const uint32_t b = bb[c] >> 16;
-            const uint32_t s = (uint32_t)tstart[b] + whist[w * kmax + b] + (bb[c] & 0xFFFFu);
+            const uint32_t b = bb[c] >> 16, rb = digit_of(b, g.d, DIG);
+            const uint32_t s = (uint32_t)tstart[rb] + whist[w * krmax + rb] + (bb[c] & 0xFFFFu);
             SK[s] = nk[c];
             SI[s] = id[c];
             SB[s] = (uint16_t)b;
             // the second key word goes straight to its place (runs of a bucket
             // are consecutive within a chunk)
-            if ((binfo[b] >> kModeShift) == kModeLive)
-                key2_out[g.begin + base[b] + s - tstart[b]] = n2[c];
+            if (DIG == (int)kDigitLow || (binfo[b] >> kModeShift) == kModeLive)
+                key2_out[g.begin + base[rb] + s - tstart[rb]] = n2[c];
         }
         __syncthreads();
         // D: write contiguous runs
         for (uint32_t s = tid; s < nsub; s += kWG) {
-            const uint32_t b = SB[s];
-            const uint32_t dr = base[b] + s - tstart[b];
+            const uint32_t b = SB[s], rb = digit_of(b, g.d, DIG);
+            const uint32_t dr = base[rb] + s - tstart[rb];
             const uint32_t dest = g.begin + dr;
+            if (DIG == (int)kDigitLow) {  // everything moves, with its bucket id
+                key_out[dest] = SK[s];
+                idx_out[dest] = SI[s];
+                bid_out[dest] = (uint16_t)b;
+                continue;
+            }
             const uint32_t s0 = bst[b];
             if (dr == s0 && dr != 0) S5_OUT(out_lcp[dest], kLcpFlag | g.depth);
             const uint32_t mode = binfo[b] >> kModeShift;
@@ -1198,10 +1257,10 @@ __device__ __forceinline__ void scatter_body(
         }
         __syncthreads();
         // E: advance the tile's bucket bases, clear the counters
-        for (uint32_t b = tid; b < k; b += kWG) {
+        for (uint32_t b = tid; b < kr; b += kWG) {
             base[b] += (uint32_t)tstart[b + 1] - tstart[b];
 #pragma unroll
-            for (int q = 0; q < kWaves; ++q) whist[q * kmax + b] = 0;
+            for (int q = 0; q < kWaves; ++q) whist[q * krmax + b] = 0;
         }
         __syncthreads();
     }
@@ -1209,7 +1268,7 @@ __device__ __forceinline__ void scatter_body(
 
 // K3: the first pass, which also reads the third key word (a separate
 // instantiation, so that the other passes keep their smaller register budget)
-template <bool G, bool K3, bool PK>
+template <bool G, bool K3, bool PK, int DIG>
 __global__ __launch_bounds__(256) void k_scatter(
     const LSeg* lseg, const uint32_t* tile_tab, const uint16_t* bid, const uint64_t* key_in,
     const uint64_t* key2_in, const uint32_t* idx_in, uint64_t* key_out, uint64_t* key2_out,
@@ -1217,20 +1276,74 @@ __global__ __launch_bounds__(256) void k_scatter(
     const uint64_t* tree_in, const uint8_t* tree_lcp, const uint8_t* chars,
     const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp, uint32_t vmax, uint32_t kmax,
     const uint32_t* wcnt, uint32_t cap, const Globals* glob, const uint64_t* key3,
-    KeyCodec kc) {
+    KeyCodec kc, uint16_t* bid_out) {
     if (!G) {
-        scatter_body<K3, PK>(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out,
-                             key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets,
-                             out_perm, out_lcp, vmax, kmax, key3, kc);
+        scatter_body<K3, PK, DIG>(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in,
+                                  key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp,
+                                  chars, offsets, out_perm, out_lcp, vmax, kmax, key3, kc,
+                                  bid_out);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        scatter_body<K3, PK>(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out,
-                             idx_out, cm, cs, bstart, tree_in, tree_lcp, chars, offsets, out_perm,
-                             out_lcp, vmax, kmax, key3, kc);
+        scatter_body<K3, PK, DIG>(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out,
+                                  key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars,
+                                  offsets, out_perm, out_lcp, vmax, kmax, key3, kc, bid_out);
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------
+// K5a/K5b (two-pass distribution): the histogram of one digit of the bucket
+// ids per tile (the tile's row of the count matrix, kd columns), and after
+// the column scan, every digit's start in its segment added into the chunk
+// prefixes -- the counting half of one least-significant-digit pass.
+__device__ __forceinline__ void digit_count_body(uint32_t tile, const LSeg* lseg,
+                                                 const uint32_t* tile_tab, const uint16_t* bid,
+                                                 uint32_t* cm, uint32_t dig) {
+    __shared__ uint32_t h[kDigitMax];
+    const LSeg g = lseg[tile_tab[tile]];
+    const uint32_t kd = digit_values(g.k, g.d, dig);
+    for (uint32_t r = threadIdx.x; r < kd; r += kWG) h[r] = 0;
+    __syncthreads();
+    const uint32_t row = tile - g.tile_base, lane = lane_id();
+    const uint64_t tb = (uint64_t)row * g.tile_len;
+    const uint32_t start = g.begin + (uint32_t)(tb < g.size ? tb : g.size);
+    const uint32_t end = g.begin + (uint32_t)(tb + g.tile_len < g.size ? tb + g.tile_len : g.size);
+    for (uint32_t p0 = start + (threadIdx.x & ~63u); p0 < end; p0 += kWG) {
+        const uint32_t p = p0 + lane;
+        const bool valid = p < end;
+        const uint32_t r = valid ? digit_of(bid[p], g.d, dig) : 0u;
+        const uint64_t act = __ballot(valid);
+        // one add when the chunk's digits are all equal, else one per string
+        const int lead = __ffsll((long long)act) - 1;
+        const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)r, lead);
+        if (__ballot(valid && r == r0) == act) {
+            if (lane == (uint32_t)lead) atomicAdd(&h[r0], (uint32_t)__popcll(act));
+        } else if (valid) {
+            atomicAdd(&h[r], 1u);
+        }
+    }
+    __syncthreads();
+    uint32_t* out = cm + g.cm_base + (uint64_t)row * kd;
+    for (uint32_t r = threadIdx.x; r < kd; r += kWG) out[r] = h[r];
+}
+
+__global__ __launch_bounds__(256) void k_digit_count(const LSeg* lseg, const uint32_t* tile_tab,
+                                                     const uint16_t* bid, uint32_t* cm,
+                                                     uint32_t dig) {
+    digit_count_body(blockIdx.x, lseg, tile_tab, bid, cm, dig);
+}
+
+__global__ __launch_bounds__(256) void k_digit_starts(const LSeg* lseg, uint32_t* cs,
+                                                      uint32_t dig) {
+    __shared__ uint32_t tot[kDigitMax], st[kDigitMax], tmp[kWG + 1];
+    const LSeg g = lseg[blockIdx.x];
+    const uint32_t kd = digit_values(g.k, g.d, dig);
+    chunk_prefixes(g, cs, kd, tot);
+    __syncthreads();
+    block_exclusive_scan(tot, st, kd, tmp);
+    add_starts(g, cs, kd, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -2144,14 +2257,25 @@ void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LS
 
 void launch_colscan(uint32_t chunks, uint32_t kmax, const LSeg* lseg, const uint32_t* chunk_tab,
                     uint32_t* cm, uint32_t* cs, const Globals* glob, const Dyn& dy, uint32_t redo,
-                    hipStream_t st) {
-    const dim3 grid(dyn_grid(dy, chunks), (kmax + kWG - 1) / kWG);
+                    hipStream_t st, uint32_t dig) {
+    const uint32_t cols = dig ? kDigitMax : kmax;
+    const dim3 grid(dyn_grid(dy, chunks), (cols + kWG - 1) / kWG);
     if (dy.cnt)
         S5_LAUNCH(k_colscan<true>, grid, dim3(kWG), 0, st, lseg, chunk_tab, cm, cs, dy.cnt, dy.cap,
-                  glob, redo);
+                  glob, redo, dig);
     else
         S5_LAUNCH(k_colscan<false>, grid, dim3(kWG), 0, st, lseg, chunk_tab, cm, cs, dy.cnt, dy.cap,
-                  glob, redo);
+                  glob, redo, dig);
+}
+
+void launch_digit_count(uint32_t tiles, const LSeg* lseg, const uint32_t* tile_tab,
+                        const uint16_t* bid, uint32_t* cm, uint32_t dig, hipStream_t st) {
+    if (tiles) S5_LAUNCH(k_digit_count, dim3(tiles), dim3(kWG), 0, st, lseg, tile_tab, bid, cm, dig);
+}
+
+void launch_digit_starts(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t dig,
+                         hipStream_t st) {
+    if (n_large) S5_LAUNCH(k_digit_starts, dim3(n_large), dim3(kWG), 0, st, lseg, cs, dig);
 }
 
 void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t* bstart,
@@ -2173,42 +2297,50 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
                     const Dyn& dy, const uint64_t* key3, const KeyCodec& kc, hipStream_t st,
-                    hipEvent_t ev_start, hipEvent_t ev_stop) {
+                    hipEvent_t ev_start, hipEvent_t ev_stop, uint32_t dig, uint16_t* bid_out) {
     (void)unroll;
-    const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + (size_t)kmax * (4 + 4) +
-                       (size_t)kWaves * kmax * 2 + (size_t)(kmax + 1) * 2 + (size_t)kmax * 2;
+    const size_t krmax = dig ? kDigitMax : kmax;
+    const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + krmax * 4 + (size_t)kmax * 4 +
+                       (size_t)kWaves * krmax * 2 + (krmax + 1) * 2 + (size_t)kmax * 2;
     // with events (instrumentation, host-driven passes only) the dispatch
     // itself stamps them: their interval is the kernel's execution, with no
     // marker packets around it
-#define S5_SCATTER_P(GG, KK, PP, GRID)                                                            \
+#define S5_SCATTER_P(GG, KK, PP, DD, GRID)                                                        \
     do {                                                                                          \
         if (ev_start || ev_stop)                                                                  \
-            hipExtLaunchKernelGGL((k_scatter<GG, KK, PP>), dim3(GRID), dim3(kWG), lds, st,        \
+            hipExtLaunchKernelGGL((k_scatter<GG, KK, PP, DD>), dim3(GRID), dim3(kWG), lds, st,    \
                                   ev_start, ev_stop, 0u, lseg, tile_tab, bid, key_in, key2_in,    \
                                   idx_in, key_out, key2_out, idx_out, cm, cs, bstart, tree_in,    \
                                   tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax,        \
-                                  dy.cnt, dy.cap, glob, key3, kc);                                \
+                                  dy.cnt, dy.cap, glob, key3, kc, bid_out);                       \
         else                                                                                      \
-            S5_LAUNCH((k_scatter<GG, KK, PP>), dim3(GRID), dim3(kWG), lds, st, lseg, tile_tab,    \
-                      bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart,   \
-                      tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax, dy.cnt,   \
-                      dy.cap, glob, key3, kc);                                                    \
+            S5_LAUNCH((k_scatter<GG, KK, PP, DD>), dim3(GRID), dim3(kWG), lds, st, lseg,          \
+                      tile_tab, bid, key_in, key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, \
+                      bstart, tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax, kmax,   \
+                      dy.cnt, dy.cap, glob, key3, kc, bid_out);                                   \
     } while (0)
-#define S5_SCATTER(GG, KK, GRID)                                                                  \
+#define S5_SCATTER(GG, KK, DD, GRID)                                                              \
     do {                                                                                          \
-        if (kc.b != 8) S5_SCATTER_P(GG, KK, true, GRID);                                          \
-        else S5_SCATTER_P(GG, KK, false, GRID);                                                   \
+        if (kc.b != 8) S5_SCATTER_P(GG, KK, true, DD, GRID);                                      \
+        else S5_SCATTER_P(GG, KK, false, DD, GRID);                                               \
     } while (0)
-    if (dy.cnt) {
+    if (dig == kDigitLow) {  // the two-pass distribution runs host-driven only
         if (key3)
-            S5_SCATTER(true, true, dy.grid);
+            S5_SCATTER(false, true, 1, tiles);
         else
-            S5_SCATTER(true, false, dy.grid);
+            S5_SCATTER(false, false, 1, tiles);
+    } else if (dig == kDigitHigh) {
+        S5_SCATTER(false, false, 2, tiles);
+    } else if (dy.cnt) {
+        if (key3)
+            S5_SCATTER(true, true, 0, dy.grid);
+        else
+            S5_SCATTER(true, false, 0, dy.grid);
     } else {
         if (key3)
-            S5_SCATTER(false, true, tiles);
+            S5_SCATTER(false, true, 0, tiles);
         else
-            S5_SCATTER(false, false, tiles);
+            S5_SCATTER(false, false, 0, tiles);
     }
 #undef S5_SCATTER
 #undef S5_SCATTER_P

@@ -32,9 +32,17 @@ void launch_classify(uint32_t tiles, uint32_t unroll, uint32_t variant, const LS
                      const uint64_t* tree_in, const uint16_t* jump, uint16_t* bid, uint32_t* cm,
                      uint32_t vmax, uint32_t kmax, const Globals* glob, const Dyn& dy,
                      uint32_t redo, hipStream_t st);
+// dig != 0: the columns of a digit of the bucket ids (two-pass distribution)
 void launch_colscan(uint32_t chunks, uint32_t kmax, const LSeg* lseg, const uint32_t* chunk_tab,
                     uint32_t* cm, uint32_t* cs, const Globals* glob, const Dyn& dy, uint32_t redo,
-                    hipStream_t st);
+                    hipStream_t st, uint32_t dig = 0);
+// Two-pass distribution (host-driven): per-tile histograms of digit `dig`
+// (kDigitLow / kDigitHigh) of the bucket ids in `bid`, and after the column
+// scan the digits' starts added into the chunk prefixes.
+void launch_digit_count(uint32_t tiles, const LSeg* lseg, const uint32_t* tile_tab,
+                        const uint16_t* bid, uint32_t* cm, uint32_t dig, hipStream_t st);
+void launch_digit_starts(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t dig,
+                         hipStream_t st);
 void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t* bstart,
                         const uint64_t* tree_in, const uint8_t* tree_lcp, const PlanCtx& ctx,
                         uint32_t next_buf, const Dyn& dy, hipStream_t st);
@@ -46,7 +54,8 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                     uint32_t* out_lcp, uint32_t vmax, uint32_t kmax, const Globals* glob,
                     const Dyn& dy, const uint64_t* key3, const KeyCodec& kc, hipStream_t st,
-                    hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
+                    hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
+                    uint32_t dig = 0, uint16_t* bid_out = nullptr);
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
                       const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,

@@ -309,6 +309,29 @@ S5_HD void equal_step(const uint64_t* t, uint32_t d, uint64_t key, uint32_t& i, 
 }
 S5_HD uint32_t equal_leaf_bucket(uint32_t i, uint32_t d) { return 2u * (i - (1u << d)); }
 
+// Two-pass distribution (appendix A, "Multipass data distribution"): a
+// level's strings are moved twice, stably, by the two digits of their bucket
+// id, the low digit first -- a least-significant-digit radix sort on the ids,
+// so each pass has few destinations.  Ids of a tree of depth d have d + 1
+// bits; the low digit takes the lower half, rounded up.
+constexpr uint32_t kDigitLow = 1, kDigitHigh = 2;
+// values of a digit: k for the whole id (dig 0), else 2^bits of that digit
+// (the high digit only up to the largest id k - 1)
+S5_HD uint32_t digit_low_bits(uint32_t d) { return (d + 2u) / 2u; }
+S5_HD uint32_t digit_values(uint32_t k, uint32_t d, uint32_t dig) {
+    const uint32_t r = digit_low_bits(d);
+    return dig == 0 ? k : dig == kDigitLow ? (1u << r) : ((k - 1u) >> r) + 1u;
+}
+S5_HD uint32_t digit_of(uint32_t b, uint32_t d, uint32_t dig) {
+    const uint32_t r = digit_low_bits(d);
+    return dig == 0 ? b : dig == kDigitLow ? (b & ((1u << r) - 1u)) : (b >> r);
+}
+// bits of a digit's values (for the ballot match of equal digits)
+S5_HD uint32_t digit_bits(uint32_t d, uint32_t dig) {
+    const uint32_t r = digit_low_bits(d);
+    return dig == 0 ? d + 1u : dig == kDigitLow ? r : d + 1u - r;
+}
+
 // Jump table over the top key bits (appendix A, "Jump tables").  All keys
 // between the first and the last splitter share the top `sh` bits of those
 // two splitters; the next `a` bits index a table whose entry is the node at

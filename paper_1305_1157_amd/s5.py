@@ -20,6 +20,7 @@ STATIC_SCRATCH_BYTES = 64 << 20  # S5_STATIC_SCRATCH_BYTES
 SPLIT_SAMPLED, SPLIT_LEARNED = 0, 1
 CLASSIFY_UNROLL, CLASSIFY_EQUAL, CLASSIFY_JUMP = 0, 1, 2
 ALPHABET_BYTES, ALPHABET_AUTO = 0, 1
+DISTRIBUTE_ONE_PASS, DISTRIBUTE_TWO_PASS = 0, 1
 
 EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_sort_batched",
            "s5_classify_ex",
@@ -36,7 +37,7 @@ class Config(ctypes.Structure):
                 ("base_threshold", ctypes.c_uint32), ("splitter_mode", ctypes.c_uint32),
                 ("imbalance_bound", ctypes.c_float), ("seed", ctypes.c_uint64),
                 ("graph_levels", ctypes.c_uint32), ("classifier", ctypes.c_uint32),
-                ("alphabet", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("alphabet", ctypes.c_uint32), ("distribution", ctypes.c_uint32)]
 
 
 class SetTuning(ctypes.Structure):
@@ -156,9 +157,10 @@ def _dev(t: torch.Tensor, dtype, name: str):
 
 def make_config(splitters=0, oversample=0, unroll=0, tile=0, base_threshold=0,
                 splitter_mode=SPLIT_SAMPLED, imbalance_bound=0.0, seed=0,
-                graph_levels=0, classifier=CLASSIFY_UNROLL, alphabet=ALPHABET_BYTES) -> Config:
+                graph_levels=0, classifier=CLASSIFY_UNROLL, alphabet=ALPHABET_BYTES,
+                distribution=DISTRIBUTE_ONE_PASS) -> Config:
     return Config(splitters, oversample, unroll, tile, base_threshold, splitter_mode,
-                  imbalance_bound, seed, graph_levels, classifier, alphabet, 0)
+                  imbalance_bound, seed, graph_levels, classifier, alphabet, distribution)
 
 
 def sort(chars: torch.Tensor, offsets: torch.Tensor, cfg: Config | None = None,

@@ -499,6 +499,36 @@ static void test_fig1(const char* path) {
     }
 }
 
+// Two digits of the bucket ids: every id is its digits put back together,
+// both digits stay below their value counts (at most 64), and a stable sort by
+// the low digit and then the high digit (the two moves) orders ids exactly as
+// a stable sort by the id does.
+static void test_bucket_digits(std::mt19937_64& rng) {
+    for (uint32_t d = 1; d <= 10; ++d) {
+        const uint32_t k = (2u << d) - 1u, r = digit_low_bits(d);
+        const uint32_t nlo = digit_values(k, d, kDigitLow), nhi = digit_values(k, d, kDigitHigh);
+        CHECK(digit_values(k, d, 0) == k && nlo <= 64 && nhi <= 64 && nlo * nhi >= k, "d %u", d);
+        CHECK(nlo <= (1u << digit_bits(d, kDigitLow)) && nhi <= (1u << digit_bits(d, kDigitHigh)) &&
+                  digit_bits(d, 0) == d + 1,
+              "bits d %u", d);
+        for (uint32_t b = 0; b < k; ++b) {
+            const uint32_t lo = digit_of(b, d, kDigitLow), hi = digit_of(b, d, kDigitHigh);
+            CHECK(lo < nlo && hi < nhi && ((hi << r) | lo) == b && digit_of(b, d, 0) == b,
+                  "d %u b %u", d, b);
+        }
+        std::vector<std::pair<uint32_t, uint32_t>> ids(3000);  // (bucket, input position)
+        for (uint32_t i = 0; i < ids.size(); ++i) ids[i] = {(uint32_t)(rng() % k), i};
+        std::vector<std::pair<uint32_t, uint32_t>> two = ids, one = ids;
+        for (uint32_t dig : {kDigitLow, kDigitHigh})
+            std::stable_sort(two.begin(), two.end(), [&](const auto& a, const auto& b) {
+                return digit_of(a.first, d, dig) < digit_of(b.first, d, dig);
+            });
+        std::stable_sort(one.begin(), one.end(),
+                         [](const auto& a, const auto& b) { return a.first < b.first; });
+        CHECK(two == one, "two moves d %u", d);
+    }
+}
+
 int main(int argc, char** argv) {
     std::mt19937_64 rng(12345);
     test_load_key_guarded(rng);
@@ -510,6 +540,7 @@ int main(int argc, char** argv) {
     test_equal_variant(rng);
     test_jump_table(rng);
     test_codec(rng);
+    test_bucket_digits(rng);
     if (argc > 1) test_fig1(argv[1]);
     if (failures) {
         printf("%d failures\n", failures);

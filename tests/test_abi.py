@@ -55,6 +55,10 @@ def test_workspace_bytes(lib):
     assert s5.workspace_bytes(1000, s5.make_config(base_threshold=4096)) == 0
     assert s5.workspace_bytes(1000, s5.make_config(unroll=3)) == 0
     assert s5.workspace_bytes(1000, s5.make_config(splitters=1023, unroll=8)) > 0
+    assert s5.workspace_bytes(1000, s5.make_config(distribution=2)) == 0
+    # the two-pass distribution holds a second bucket-id array (2 bytes a string)
+    two = s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS)
+    assert s5.workspace_bytes(1_000_000, two) >= s5.workspace_bytes(1_000_000) + 2_000_000
 
 
 def test_static_sort_size_limit_is_host_logic(lib):
@@ -70,3 +74,14 @@ def test_static_sort_size_limit_is_host_logic(lib):
     assert lib.s5_sort_static(fake, 0, fake, 1_000_000, fake, fake, cfg, None) == \
         s5.S5_ERR_TOO_LARGE
     assert lib.s5_sort_static(None, 0, None, 5, None, None, None, None) == s5.S5_ERR_INVALID
+
+
+def test_batched_sorts_refuse_two_pass_distribution(lib):
+    """The two-pass distribution is host-driven only; batched sorts reject the
+    config before any device work (never-dereferenced pointers, no GPU)."""
+    import ctypes
+    from paper_1305_1157_amd import s5
+    fake = 4096
+    cfg = s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS)
+    assert lib.s5_sort_batched(fake, 0, fake, fake, 1, fake, fake, ctypes.byref(cfg), None) == \
+        s5.S5_ERR_INVALID

@@ -24,6 +24,8 @@ CFGS = {
                                     base_threshold=2048),
     "auto_jump_learned": s5.make_config(alphabet=s5.ALPHABET_AUTO, classifier=s5.CLASSIFY_JUMP,
                                         splitter_mode=s5.SPLIT_LEARNED, imbalance_bound=1e9),
+    "auto_two_pass": s5.make_config(alphabet=s5.ALPHABET_AUTO,
+                                    distribution=s5.DISTRIBUTE_TWO_PASS),
 }
 
 

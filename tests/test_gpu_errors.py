@@ -178,10 +178,14 @@ def _counted(run, n, dev):
 
 CASES = [("url_10M", 200_000, None), ("dna_16M", 100_000, None),
          ("words_50M", 300_000, s5.make_config(base_threshold=128, splitters=31)),
-         ("random_1M", 100_000, s5.make_config(splitter_mode=s5.SPLIT_LEARNED))]
+         ("random_1M", 100_000, s5.make_config(splitter_mode=s5.SPLIT_LEARNED)),
+         ("url_10M", 150_001, s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS, splitters=63,
+                                             base_threshold=128))]
 
 
-@pytest.mark.parametrize("name,n,cfg", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("name,n,cfg", CASES,
+                         ids=[c[0] + ("_two_pass" if c[2] is not None and c[2].distribution else "")
+                              for c in CASES])
 def test_every_output_slot_written_once(name, n, cfg):
     chars, offs = gen.workload(name, n)
     dc, do = to_dev(chars), to_dev(offs)

@@ -172,6 +172,13 @@ def test_sample_imbalance_statistics():
     assert st["learned_proposals"] == 0 and st["imbalance_max"] == 0.0
 
 
+def test_learned_two_pass_parity():
+    # learned trees (some rejected on the exact histogram and redone) with two moves per level
+    chars, offs = gen.workload("words_50M", 300_000)
+    cfg = s5.make_config(splitter_mode=s5.SPLIT_LEARNED, distribution=s5.DISTRIBUTE_TWO_PASS)
+    assert_parity(chars, offs, cfg, label="learned two-pass")
+
+
 def test_batched_learned_parity():
     chars, offs, sb = gen.batched(6, 70_000, 150_000, kinds=("random", "url", "dna"), seed=21)
     perm, lcp = s5.sort_batched(to_dev(chars), to_dev(offs), to_dev(sb), cfg=LEARNED)

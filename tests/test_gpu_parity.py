@@ -31,6 +31,15 @@ CFGS = {
     "jump_v7_u2_T64": s5.make_config(classifier=s5.CLASSIFY_JUMP, splitters=7, unroll=2,
                                      base_threshold=64, tile=64),
     "jump_v1023_u8": s5.make_config(classifier=s5.CLASSIFY_JUMP, splitters=1023, unroll=8),
+    # two moves per level by the digits of the bucket ids (appendix A, multipass)
+    "two_pass": s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS),
+    "two_pass_v7_T64": s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS, splitters=7,
+                                      base_threshold=64, tile=64),
+    "two_pass_v1023_u8": s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS, splitters=1023,
+                                        unroll=8, base_threshold=2048),
+    "two_pass_v31_T128_jump": s5.make_config(distribution=s5.DISTRIBUTE_TWO_PASS, splitters=31,
+                                             base_threshold=128, tile=128,
+                                             classifier=s5.CLASSIFY_JUMP),
 }
 
 
@@ -146,7 +155,7 @@ EDGE.update({
 
 @pytest.mark.parametrize("name", sorted(EDGE))
 @pytest.mark.parametrize("cfg", ["default", "tiny_T_v7", "v1023_u8", "equal_v7_u1_T64",
-                                 "jump_v7_u2_T64"])
+                                 "jump_v7_u2_T64", "two_pass_v7_T64", "two_pass_v1023_u8"])
 def test_edge_cases(name, cfg):
     strings_parity(EDGE[name], CFGS[cfg], label=f"{name}/{cfg}")
 
@@ -184,6 +193,15 @@ def test_random_1M_full():
     chars, offs = gen.workload("random_1M")
     st = assert_parity(chars, offs, None, label="random_1M full")
     assert st["passes"] >= 1 and st["moved_M"] >= 1_000_000
+
+
+def test_two_pass_same_passes_and_moves():
+    """The two-pass distribution moves each level twice but splits the same way:
+    the level count and the strings distributed per level are those of one move."""
+    chars, offs = gen.workload("words_50M", 400_000)
+    one = assert_parity(chars, offs, None, label="one move")
+    two = assert_parity(chars, offs, CFGS["two_pass"], label="two moves")
+    assert one["passes"] == two["passes"] and one["moved_M"] == two["moved_M"]
 
 
 def test_output_independent_of_seed():
