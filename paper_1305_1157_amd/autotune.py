@@ -125,7 +125,9 @@ class _Batch:
         self.perm = torch.empty(self.n, dtype=torch.uint32, device="cuda")
         self.lcp = torch.empty(self.n, dtype=torch.uint32, device="cuda")
 
-    def time(self, rows, unroll, reps=3, classifier=DEFAULT_CLASSIFIER):
+    reps = 3  # timed sorts per measurement (the median is kept)
+
+    def time(self, rows, unroll, reps=None, classifier=DEFAULT_CLASSIFIER):
         """Median wall time (ms) of the batched sort with per-set rows."""
         import torch
 
@@ -135,7 +137,7 @@ class _Batch:
         s5.sort_batched(self.chars, self.offs, self.sb, cfg=cfg, tuning=tun, out_perm=self.perm,
                         out_lcp=self.lcp)  # capture / warm-up
         ts = []
-        for _ in range(reps):
+        for _ in range(reps or self.reps):
             torch.cuda.synchronize()
             t = time.perf_counter()
             s5.sort_batched(self.chars, self.offs, self.sb, cfg=cfg, tuning=tun,
@@ -209,7 +211,9 @@ def main():
     ap.add_argument("--out", default=TABLE_PATH)
     ap.add_argument("--target", type=int, default=3_000_000, help="strings per probe batch")
     ap.add_argument("--rounds", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=3, help="timed sorts per measurement")
     a = ap.parse_args()
+    _Batch.reps = a.reps
     t = tune(target=a.target, rounds=a.rounds, log=lambda s: print(s, flush=True))
     with open(a.out, "w") as f:
         json.dump(t, f, indent=1)
