@@ -695,9 +695,9 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     for (int q = 0; q < kBaseClasses; ++q) n_base[q] = H.hg->n_base[q];
     const Dyn none[kBaseClasses];
     timed(K_BASE, H.hg->base_elems, st, [&] {
-        launch_base_sort(n_base, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
-                         a.offsets, a.perm, a.lcp, c.T, P.glob, none, nullptr, codec_of(c, P),
-                         st);
+        launch_base_sort(n_base, P.base_list, P.key[0], P.key[1], P.key2[0], P.key2[1],
+                         P.idx[0], P.idx[1], a.chars, a.offsets, a.perm, a.lcp, c.T, P.glob,
+                         none, nullptr, codec_of(c, P), st);
     });
     timed(K_LCPFIX, a.n, st, [&] {
         launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, nullptr,
@@ -807,8 +807,9 @@ void enqueue_graph_body(const SortArgs& a, const Cfg& c, const Layout& L, const 
         bd[q] = dyn_of(&P.glob->n_base[q], L.caps.base[q], std::min(units, kGraphBaseGrid));
     }
     const uint32_t zero[kBaseClasses] = {};
-    launch_base_sort(zero, P.base_list, P.key[0], P.key[1], P.idx[0], P.idx[1], a.chars,
-                     a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard, codec_of(c, P), st);
+    launch_base_sort(zero, P.base_list, P.key[0], P.key[1], P.key2[0], P.key2[1], P.idx[0],
+                     P.idx[1], a.chars, a.offsets, a.perm, a.lcp, c.T, P.glob, bd, guard,
+                     codec_of(c, P), st);
     launch_lcp_fix(a.chars, a.offsets, a.set_begin, a.num_sets, a.n, a.perm, a.lcp, guard, P.glob,
                    st);
 }

@@ -1490,17 +1490,21 @@ __device__ __forceinline__ void key_load2(const KeyCodec& kc, const uint8_t* tab
 // lanes (valid == false) are last.  Returns the final packed element of the lane.
 // Refinement rounds of one wavefront (<= 64 elements, sorted by (group, key,
 // local index)).  offl[local] holds the string start of element `local` (LDS);
-// with fill_n > 0 it is filled by lanes < fill_n on the first round that needs
-// it.  A round re-keys the undecided members 8 bytes deeper; it re-sorts only
-// if some group's keys now differ (equal keys keep their local-index order).
+// with fill set, the members fill their own entries (from iin and offsets) on
+// the first round that gathers -- later members are among them.  k2 (or
+// nullptr): the item's second key words by local index, exact or kKeyUnknown,
+// which serve the first re-key without a gather.  A round re-keys the
+// undecided members one key deeper; it re-sorts only if some group's keys now
+// differ (equal keys keep their local-index order).
 template <bool PK>
 __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, uint32_t pos,
-                                uint64_t* offl, uint32_t fill_n, const uint32_t* iin,
-                                const uint8_t* chars, const uint64_t* offsets, uint32_t* olcp,
-                                const KeyCodec& kc, const uint8_t* tab) {
+                                uint64_t* offl, bool fill, const uint64_t* k2,
+                                const uint32_t* iin, const uint8_t* chars,
+                                const uint64_t* offsets, uint32_t* olcp, const KeyCodec& kc,
+                                const uint8_t* tab) {
     const uint32_t lane = lane_id();
     const uint64_t upto = lane == 63 ? ~0ull : ((1ull << (lane + 1)) - 1ull);
-    bool filled = fill_n == 0;
+    bool filled = !fill;
     for (;;) {
         const uint64_t kp = shfl_up64(k, 1);
         const uint32_t ap = __shfl_up(a, 1);
@@ -1513,19 +1517,23 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
         }
         const uint64_t U = __ballot(und);
         if (!U) break;
-        if (!filled) {
-            if (lane < fill_n) offl[lane] = offsets[iin[lane]];
+        const bool member = ((U >> lane) & 1ull) || (lane < 63 && ((U >> (lane + 1)) & 1ull));
+        const uint32_t st = 63u - (uint32_t)__builtin_clzll((unsigned long long)(~U & upto));
+        const uint32_t l = a & 0xFFFFu;
+        const uint64_t x2 = k2 && member ? k2[l] : kKeyUnknown;
+        k2 = nullptr;  // only the first re-key is at the second word's depth
+        const bool gather = member && x2 == kKeyUnknown;
+        if (!filled && __ballot(gather)) {
+            if (member) offl[l] = offsets[iin[l]];
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             filled = true;
         }
-        const bool member = ((U >> lane) & 1ull) || (lane < 63 && ((U >> (lane + 1)) & 1ull));
-        const uint32_t st = 63u - (uint32_t)__builtin_clzll((unsigned long long)(~U & upto));
         h += key_chars<PK>(kc);
         if (member) {
-            k = key_load1<PK>(kc, tab, chars, offl[a & 0xFFFFu] + h);
-            a = (st << 16) | (a & 0xFFFFu);
+            k = gather ? key_load1<PK>(kc, tab, chars, offl[l] + h) : x2;
+            a = (st << 16) | l;
         } else if (valid) {
             a = (lane << 16) | (a & 0xFFFFu);
         }
@@ -1540,6 +1548,7 @@ __device__ uint32_t wave_rounds(uint64_t k, uint32_t a, bool valid, uint32_t h, 
 template <bool PK>
 __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
                                                const uint64_t* key0, const uint64_t* key1,
+                                               const uint64_t* key2_0, const uint64_t* key2_1,
                                                const uint32_t* idx0, const uint32_t* idx1,
                                                const uint8_t* chars, const uint64_t* offsets,
                                                uint32_t* out_perm, uint32_t* out_lcp,
@@ -1551,13 +1560,14 @@ __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
     const uint32_t h = it.depth & ~kBufBit;
     const uint32_t n = it.size;
     const uint64_t* kin = (buf ? key1 : key0) + it.begin;
+    const uint64_t* k2in = (buf ? key2_1 : key2_0) + it.begin;
     const uint32_t* iin = (buf ? idx1 : idx0) + it.begin;
     const bool valid = lane < n;
     uint64_t k = valid ? kin[lane] : ~0ull;
     uint32_t a = valid ? lane : 0xFFFFFFFFu;
     wave_sort(k, a);
-    const uint32_t fa = wave_rounds<PK>(k, a, valid, h, lane, offl[threadIdx.x >> 6], n, iin,
-                                        chars, offsets, out_lcp + it.begin, kc, tab);
+    const uint32_t fa = wave_rounds<PK>(k, a, valid, h, lane, offl[threadIdx.x >> 6], true, k2in,
+                                        iin, chars, offsets, out_lcp + it.begin, kc, tab);
     if (valid) S5_OUT(out_perm[it.begin + lane], iin[fa & 0xFFFFu] - it.base);
 }
 
@@ -1565,6 +1575,7 @@ __device__ __forceinline__ void base_wave_body(uint32_t item, const Seg* items,
 template <bool G, bool PK>
 __global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_items,
                                                    const uint64_t* key0, const uint64_t* key1,
+                                                   const uint64_t* key2_0, const uint64_t* key2_1,
                                                    const uint32_t* idx0, const uint32_t* idx1,
                                                    const uint8_t* chars, const uint64_t* offsets,
                                                    uint32_t* out_perm, uint32_t* out_lcp,
@@ -1576,15 +1587,15 @@ __global__ __launch_bounds__(256) void k_base_wave(const Seg* items, uint32_t n_
     if (!G) {
         const uint32_t it = blockIdx.x * kWaves + (threadIdx.x >> 6);
         if (it < n_items)  // uniform per wavefront
-            base_wave_body<PK>(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
-                               out_lcp, kc, tab);
+            base_wave_body<PK>(it, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
+                               out_perm, out_lcp, kc, tab);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, n_items, guard);
     for (uint32_t it = blockIdx.x * kWaves + (threadIdx.x >> 6); it < units;
          it += gridDim.x * kWaves)
-        base_wave_body<PK>(it, items, key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
-                           kc, tab);
+        base_wave_body<PK>(it, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
+                           out_perm, out_lcp, kc, tab);
 }
 
 template <int E, int J>
@@ -1758,6 +1769,7 @@ __device__ void merge_runs(const uint64_t* XK, const uint32_t* XA, uint32_t na,
 template <int EMAX, int NT, bool PK>
 __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
                                                 const uint64_t* key0, const uint64_t* key1,
+                                                const uint64_t* key2_0, const uint64_t* key2_1,
                                                 const uint32_t* idx0, const uint32_t* idx1,
                                                 const uint8_t* chars, const uint64_t* offsets,
                                                 uint32_t* out_perm, uint32_t* out_lcp,
@@ -1780,6 +1792,7 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
     uint32_t P = 1;
     while (P < n) P <<= 1;
     const uint64_t* kin = (buf ? key1 : key0) + it.begin;
+    const uint64_t* k2in = (buf ? key2_1 : key2_0) + it.begin;  // exact or kKeyUnknown
     const uint32_t* iin = (buf ? idx1 : idx0) + it.begin;
     uint32_t* olcp = out_lcp + it.begin;
     const uint32_t tid = threadIdx.x;
@@ -1827,7 +1840,8 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         any |= un;
     }
     any = __syncthreads_or(any);
-    bool first = true;
+    bool first = true;      // the item's first re-key: second key words serve it where known
+    bool have_off = false;  // OFFL holds the string starts of the current members
     while (any) {
         // group start of every position (running max of decided positions) and
         // the rank of every group member among all members
@@ -1848,22 +1862,31 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
             }
         }
         __syncthreads();
-        if (first) {  // string starts of the undecided strings (later members are among them)
+        // string starts of the members (later members are among them), unless
+        // this is the first re-key and every member's second key word is known
+        auto load_starts = [&]() {
             for (uint32_t q = tid; q < m; q += NT) {
                 const uint32_t l = SA[q] & 0xFFFFu;
                 OFFL[l] = offsets[IDX[l]];
             }
-            first = false;
+            have_off = true;
             __syncthreads();
+        };
+        if (!have_off) {
+            int gat = first ? 0 : 1;
+            if (first)
+                for (uint32_t q = tid; q < m; q += NT)
+                    if (k2in[SA[q] & 0xFFFFu] == kKeyUnknown) gat = 1;
+            if (__syncthreads_or(gat)) load_starts();
         }
         if (m <= 64) {
             // few undecided strings left: wavefront 0 finishes them in registers
             if (tid < 64) {
                 const bool valid = tid < m;
                 const uint32_t pos = valid ? POS[tid] : 0u;
-                const uint32_t fa = wave_rounds<PK>(valid ? SK[tid] : ~0ull,
-                                                    valid ? SA[tid] : 0xFFFFFFFFu, valid, h, pos,
-                                                    OFFL, 0u, iin, chars, offsets, olcp, kc, tab);
+                const uint32_t fa = wave_rounds<PK>(
+                    valid ? SK[tid] : ~0ull, valid ? SA[tid] : 0xFFFFFFFFu, valid, h, pos, OFFL,
+                    !have_off, first ? k2in : nullptr, iin, chars, offsets, olcp, kc, tab);
                 if (valid) A[pos] = fa;
             }
             __syncthreads();
@@ -1876,12 +1899,15 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         // up to pmax / NT members per thread: all their gathers in flight at once
         constexpr int G = EMAX;
         uint64_t pos[G], nkey[G];
-        bool need[G];
+        bool need[G], gat[G];
 #pragma unroll
         for (int e = 0; e < G; ++e) {
             const uint32_t q = tid + e * NT;
             need[e] = q < m;
-            pos[e] = need[e] ? OFFL[SA[q] & 0xFFFFu] : 0ull;
+            const uint32_t l = need[e] ? SA[q] & 0xFFFFu : 0u;
+            nkey[e] = first && need[e] ? k2in[l] : kKeyUnknown;
+            gat[e] = need[e] && nkey[e] == kKeyUnknown;  // then have_off holds
+            pos[e] = need[e] && have_off ? OFFL[l] : 0ull;
         }
         // does member q's key differ from its group predecessor's?
         auto differs = [&](uint32_t q) {
@@ -1905,20 +1931,27 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
         if constexpr (PK) {
 #pragma unroll
             for (int e = 0; e < G; ++e) {
-                if (need[e]) nkey[e] = packed_load1(kc, tab, chars, pos[e] + h);
+                if (gat[e]) nkey[e] = packed_load1(kc, tab, chars, pos[e] + h);
                 __builtin_amdgcn_sched_barrier(0);  // one member's raw words at a time
             }
         } else {
             uint64_t at[G];
 #pragma unroll
             for (int e = 0; e < G; ++e) at[e] = pos[e] + h;
-            load_keys<G>(chars, at, need, nkey);
+            load_keys<G>(chars, at, gat, nkey);
         }
+        first = false;
 #pragma unroll
         for (int e = 0; e < G; ++e)
             if (need[e]) SK[tid + e * NT] = nkey[e];
         __syncthreads();
         while (!progress()) {
+            if (!have_off) {  // the second key words decided nothing: gathers from here on
+                load_starts();
+#pragma unroll
+                for (int e = 0; e < G; ++e)
+                    pos[e] = need[e] ? OFFL[SA[tid + e * NT] & 0xFFFFu] : 0ull;
+            }
             // a run of equal characters: from here on two keys per gather
             // (packed keys: one key of 21 characters per gather)
             h += key_chars<PK>(kc);
@@ -1987,7 +2020,8 @@ __device__ __forceinline__ void base_block_body(uint32_t item, const Seg* items,
 
 template <int EMAX, bool G, int NT, bool PK>
 __global__ __launch_bounds__(NT, EMAX <= 4 ? 4 : 1) void k_base_block(const Seg* items, const uint64_t* key0,
-                                                    const uint64_t* key1, const uint32_t* idx0,
+                                                    const uint64_t* key1, const uint64_t* key2_0,
+                                                    const uint64_t* key2_1, const uint32_t* idx0,
                                                     const uint32_t* idx1, const uint8_t* chars,
                                                     const uint64_t* offsets, uint32_t* out_perm,
                                                     uint32_t* out_lcp, uint32_t pmax,
@@ -1996,13 +2030,13 @@ __global__ __launch_bounds__(NT, EMAX <= 4 ? 4 : 1) void k_base_block(const Seg*
                                                     KeyCodec kc) {
     S5_CODE_TABLE(PK, kc, tab)
     if (!G) {
-        base_block_body<EMAX, NT, PK>(blockIdx.x, items, key0, key1, idx0, idx1, chars, offsets,
+        base_block_body<EMAX, NT, PK>(blockIdx.x, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
                                       out_perm, out_lcp, pmax, kc, tab);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x, guard);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        base_block_body<EMAX, NT, PK>(u, items, key0, key1, idx0, idx1, chars, offsets, out_perm,
+        base_block_body<EMAX, NT, PK>(u, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets, out_perm,
                                       out_lcp, pmax, kc, tab);
         __syncthreads();
     }
@@ -2350,14 +2384,15 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
 // counts are read on the device, and nothing runs while *guard != 0.
 template <bool G, bool PK>
 static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
-                             const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
+                             const uint64_t* key1, const uint64_t* key2_0, const uint64_t* key2_1,
+                             const uint32_t* idx0, const uint32_t* idx1,
                              const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                              uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
                              const uint32_t* guard, const KeyCodec& kc, hipStream_t st) {
     if (G || n_items[0]) {
         const uint32_t g = G ? dy[0].grid : (n_items[0] + kWaves - 1) / kWaves;
         S5_LAUNCH((k_base_wave<G, PK>), dim3(g), dim3(kWG), 0, st, items[0], n_items[0], key0,
-                  key1, idx0, idx1, chars, offsets, out_perm, out_lcp, dy[0].cnt, dy[0].cap, glob,
+                  key1, key2_0, key2_1, idx0, idx1, chars, offsets, out_perm, out_lcp, dy[0].cnt, dy[0].cap, glob,
                   guard, kc);
     }
     uint32_t PT = 1;
@@ -2366,24 +2401,24 @@ static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const u
     if ((G || n_items[1]) && PT > kBaseWave) {  // <= 256 strings: one wavefront
         const uint32_t P = PT < kBaseSmall ? PT : kBaseSmall;
         S5_LAUNCH((k_base_block<4, G, 64, PK>), dim3(G ? dy[1].grid : n_items[1]), dim3(64),
-                  per * P, st, items[1], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                  per * P, st, items[1], key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets, out_perm, out_lcp,
                   P, dy[1].cnt, dy[1].cap, glob, guard, kc);
     }
     if ((G || n_items[2]) && PT > kBaseSmall) {  // <= 512 strings: two wavefronts
         const uint32_t P = PT < kBaseMid ? PT : kBaseMid;
         S5_LAUNCH((k_base_block<4, G, 128, PK>), dim3(G ? dy[2].grid : n_items[2]), dim3(128),
-                  per * P, st, items[2], key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp,
+                  per * P, st, items[2], key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets, out_perm, out_lcp,
                   P, dy[2].cnt, dy[2].cap, glob, guard, kc);
     }
     if ((G || n_items[3]) && PT > kBaseMid) {  // <= T strings: four (or eight) wavefronts
         const dim3 g(G ? dy[3].grid : n_items[3]);
         if (PT <= 4u * kWG)
             S5_LAUNCH((k_base_block<4, G, kWG, PK>), g, dim3(kWG), per * PT, st, items[3], key0,
-                      key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
+                      key1, key2_0, key2_1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
                       dy[3].cap, glob, guard, kc);
         else  // <= 2048 strings: eight wavefronts, four strings each
             S5_LAUNCH((k_base_block<4, G, 2 * kWG, PK>), g, dim3(2 * kWG), per * PT, st, items[3],
-                      key0, key1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
+                      key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets, out_perm, out_lcp, PT, dy[3].cnt,
                       dy[3].cap, glob, guard, kc);
     }
 }
@@ -2391,24 +2426,25 @@ static void base_sort_launch(const uint32_t* n_items, Seg* const* items, const u
 // Host-driven: n_items[q] items of class q.  Graph mode (dy[0].cnt set): the
 // counts are read on the device, and nothing runs while *guard != 0.
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
-                      const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
+                      const uint64_t* key1, const uint64_t* key2_0, const uint64_t* key2_1,
+                      const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                       uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
                       const uint32_t* guard, const KeyCodec& kc, hipStream_t st) {
     const bool pk = kc.b != 8;
     if (dy[0].cnt) {
         if (pk)
-            base_sort_launch<true, true>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+            base_sort_launch<true, true>(n_items, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
                                          out_perm, out_lcp, T, glob, dy, guard, kc, st);
         else
-            base_sort_launch<true, false>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+            base_sort_launch<true, false>(n_items, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
                                           out_perm, out_lcp, T, glob, dy, guard, kc, st);
     } else {
         if (pk)
-            base_sort_launch<false, true>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+            base_sort_launch<false, true>(n_items, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
                                           out_perm, out_lcp, T, glob, dy, guard, kc, st);
         else
-            base_sort_launch<false, false>(n_items, items, key0, key1, idx0, idx1, chars, offsets,
+            base_sort_launch<false, false>(n_items, items, key0, key1, key2_0, key2_1, idx0, idx1, chars, offsets,
                                            out_perm, out_lcp, T, glob, dy, guard, kc, st);
     }
 }

@@ -56,8 +56,11 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
                     const Dyn& dy, const uint64_t* key3, const KeyCodec& kc, hipStream_t st,
                     hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr,
                     uint32_t dig = 0, uint16_t* bid_out = nullptr);
+// key2_0 / key2_1: the second key words of the two work buffers (exact or
+// kKeyUnknown), which serve an item's first refinement round
 void launch_base_sort(const uint32_t* n_items, Seg* const* items, const uint64_t* key0,
-                      const uint64_t* key1, const uint32_t* idx0, const uint32_t* idx1,
+                      const uint64_t* key1, const uint64_t* key2_0, const uint64_t* key2_1,
+                      const uint32_t* idx0, const uint32_t* idx1,
                       const uint8_t* chars, const uint64_t* offsets, uint32_t* out_perm,
                       uint32_t* out_lcp, uint32_t T, const Globals* glob, const Dyn* dy,
                       const uint32_t* guard, const KeyCodec& kc, hipStream_t st);
