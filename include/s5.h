@@ -152,6 +152,8 @@ typedef struct s5_stats {
                                ideal share m / (v + 1) (mean and maximum; a
                                proposal above imbalance_bound is replaced) */
     double imbalance_max;
+    uint64_t moved_one_bucket; /* of moved_M: strings of segments that all fell into
+                                  one bucket (moved only to advance their depth) */
 } s5_stats;
 
 /* Sort n strings.  perm and lcp as described above.  Uses the internal

@@ -710,6 +710,7 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
 void final_stats(const HostView& H, s5_stats* stats) {
     stats->fallbacks = H.hg->fallbacks;
     stats->learned_proposals = H.hg->learned_props;
+    stats->moved_one_bucket = H.hg->one_bucket;
     stats->imbalance_max = H.hg->imb_max_milli / 1000.0;
     stats->imbalance_mean =
         H.hg->learned_props ? H.hg->imb_sum_milli / 1000.0 / H.hg->learned_props : 0.0;

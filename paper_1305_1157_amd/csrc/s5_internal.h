@@ -112,6 +112,9 @@ struct Globals {
     // own sample in thousandths of the ideal share m / (v + 1) (sum and maximum)
     S5_LINE uint32_t learned_props, imb_max_milli;
     unsigned long long imb_sum_milli;
+    // strings of distributed segments that all fell into one bucket (moved
+    // only to advance their depth), summed over the passes
+    S5_LINE unsigned long long one_bucket;
 };
 
 // Learned splitters apply to segments of at least this many strings.

@@ -891,7 +891,12 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
         if (sz > mx) mx = sz;
     }
     if (threadIdx.x == 0) bs[k] = g.size;
-    __syncthreads();
+    {  // a segment whose strings all fell into one bucket
+        int one = 0;
+        for (uint32_t b = threadIdx.x; b < k; b += kWG) one |= tot[b] == g.size ? 1 : 0;
+        if (__syncthreads_or(one) && threadIdx.x == 0)
+            atomicAdd(&ctx.glob->one_bucket, (unsigned long long)g.size);
+    }
     if (ctx.stats) {
         // block-reduce the statistics, then one atomic each per block
         __shared__ double s_ent;
@@ -2055,19 +2060,34 @@ __global__ __launch_bounds__(256) void k_lcp_fix(const uint8_t* chars, const uin
     if (guard && *guard) return;  // large segments remain: the host finishes them first
     // after a failed device-side check, perm slots may be unwritten: read none
     if (glob->status) return;
-    uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    // last set whose first position is <= q, searched in [lo, num_sets)
+    auto set_of = [&](uint32_t q, uint32_t lo) {
+        uint32_t hi = num_sets - 1;
+        while (lo < hi) {
+            uint32_t mid = (lo + hi + 1) >> 1;
+            if (set_begin[mid] <= q) lo = mid; else hi = mid - 1;
+        }
+        return lo;
+    };
+    // batched: one search per workgroup for its first position; a thread then
+    // steps over the few set starts inside the workgroup's 256 positions
+    __shared__ uint32_t s_first;
+    const uint32_t p0 = blockIdx.x * blockDim.x;
+    if (set_begin) {
+        if (threadIdx.x == 0) s_first = set_of(p0 < n ? p0 : n - 1, 0);
+        __syncthreads();
+    }
+    uint32_t p = p0 + threadIdx.x;
     if (p == 0 || p >= n) return;
     uint32_t l = out_lcp[p];
     if (!(l & kLcpFlag)) return;
     uint32_t h = l & ~kLcpFlag;
     uint32_t base = 0;
-    if (set_begin) {  // last set whose first position is <= p
-        uint32_t lo = 0, hi = num_sets - 1;
-        while (lo < hi) {
-            uint32_t mid = (lo + hi + 1) >> 1;
-            if (set_begin[mid] <= p) lo = mid; else hi = mid - 1;
-        }
-        base = (uint32_t)set_begin[lo];
+    if (set_begin) {
+        uint32_t s = s_first;
+        for (int step = 0; step < 8 && s + 1 < num_sets && set_begin[s + 1] <= p; ++step) ++s;
+        if (s + 1 < num_sets && set_begin[s + 1] <= p) s = set_of(p, s);
+        base = (uint32_t)set_begin[s];
     }
     uint64_t oa = offsets[out_perm[p - 1] + base] + h;
     uint64_t ob = offsets[out_perm[p] + base] + h;

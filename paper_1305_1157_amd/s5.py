@@ -53,7 +53,8 @@ class Stats(ctypes.Structure):
                 ("base_items", ctypes.c_uint64), ("segments", ctypes.c_uint64),
                 ("char_bits", ctypes.c_uint32), ("alphabet_retries", ctypes.c_uint32),
                 ("learned_proposals", ctypes.c_uint32), ("pad", ctypes.c_uint32),
-                ("imbalance_mean", ctypes.c_double), ("imbalance_max", ctypes.c_double)]
+                ("imbalance_mean", ctypes.c_double), ("imbalance_max", ctypes.c_double),
+                ("moved_one_bucket", ctypes.c_uint64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
