@@ -500,7 +500,7 @@ void pass_plan(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
         // the buffer the level leaves its strings in
         const int out = c.distribution == S5_DISTRIBUTE_TWO_PASS ? buf : buf ^ 1;
         launch_bucket_plan(S.now.n_large, P.lseg[cur], P.cs, P.bstart, P.tree_in, P.tree_lcp, x,
-                           (uint32_t)out, S.seg, st);
+                           (uint32_t)out, S.kmax, S.seg, st);
     });
 }
 

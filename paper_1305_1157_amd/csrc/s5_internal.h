@@ -59,10 +59,12 @@ struct LSeg {
     uint32_t chunks, chunk_base;    // column-scan chunks and first chunk id
     uint32_t tree_base, bstart_base;
     uint32_t pad0;                  // learned-splitter slot, or 0xFFFFFFFF for sampled splitters
-    uint32_t pad1;
+    uint32_t redo_tune;             // kRedoBit: redo with sampled splitters (exact learned
+                                    // check); the other bits: the set's pack_set_tune word
     unsigned long long cm_base;     // tiles x k count matrix (row-major)
     unsigned long long cs_base;     // chunks x k chunk sums / prefixes
 };
+constexpr uint32_t kRedoBit = 0x80000000u;  // (pack_set_tune leaves bit 31 clear)
 
 // Counters written by one planning step and read back by the host.
 // Every workgroup of the planning step adds to these counters with one atomic
@@ -188,17 +190,16 @@ __host__ __device__ inline SetP default_set_params(const PlanCtx& c) {
     return SetP{c.T, c.d_max, c.tile_min};
 }
 
-// Parameters of the set whose first string is `base` (the last set that
-// starts at or before it: sets starting at the same place before it are empty).
-__device__ inline SetP set_params(const PlanCtx& c, uint32_t base) {
+// Parameters of a segment's set: carried in its record (no search of the sets).
+// The word is kept in a vector register: the planning kernel's scalar
+// registers are all taken.
+__device__ inline SetP seg_set_params(const PlanCtx& c, const LSeg& g) {
     if (!c.set_tune) return default_set_params(c);
-    uint32_t lo = 0, hi = c.num_sets - 1;
-    while (lo < hi) {
-        const uint32_t mid = (lo + hi + 1) >> 1;
-        if (c.set_begin[mid] <= base) lo = mid; else hi = mid - 1;
-    }
-    return unpack_set_tune(c.set_tune[lo]);
+    uint32_t w = g.redo_tune & ~kRedoBit;
+    asm volatile("" : "+v"(w));
+    return unpack_set_tune(w);
 }
+
 
 // Writes of the sort's outputs (out_perm, out_lcp) go through S5_OUT.  The
 // write-check build (S5_COUNT_WRITES) also counts, per output slot, how often

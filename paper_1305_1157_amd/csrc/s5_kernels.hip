@@ -337,7 +337,7 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
     g.bstart_base = g0.u[kPU_Bstart] + off.u[kPU_Bstart];
     off.u[kPU_Bstart] += k + 1;
     g.pad0 = 0xFFFFFFFFu;
-    g.pad1 = 0;
+    g.redo_tune = pack_set_tune(sp.T, sp.d_max, sp.tile_min);
     g.cm_base = g0.q[kPQ_Cm] + off.q[kPQ_Cm];
     off.q[kPQ_Cm] += (unsigned long long)tiles * k;
     g.cs_base = g0.q[kPQ_Cs] + off.q[kPQ_Cs];
@@ -483,7 +483,7 @@ __device__ __forceinline__ void sample_tree_body(uint32_t slot, uint32_t redo, c
     if (!redo) {
         for (uint32_t u = tid; u < g.tiles; u += kWG) tile_tab[g.tile_base + u] = slot;
         for (uint32_t c = tid; c < g.chunks; c += kWG) chunk_tab[g.chunk_base + c] = slot;
-    } else if (g.pad1 != 1u) {
+    } else if (!(g.redo_tune & kRedoBit)) {
         return;  // only segments whose learned splitters failed are redone
     }
     if (g.pad0 != 0xFFFFFFFFu) return;  // learned splitters: the tree comes from the model
@@ -688,7 +688,7 @@ __device__ __forceinline__ void classify_body(uint32_t tile, uint32_t redo, cons
     uint32_t* hist = (uint32_t*)(tin + (vmax + 1));  // kWaves * kmax
     uint16_t* jt = (uint16_t*)(hist + kWaves * kmax);  // Jump: kJumpPerTreeSlot (vmax + 1)
     const LSeg g = lseg[tile_tab[tile]];
-    if (redo && g.pad1 != 1u) return;
+    if (redo && !(g.redo_tune & kRedoBit)) return;
     for (uint32_t i = threadIdx.x; i <= g.v; i += kWG) {
         t[i] = tree_lo[g.tree_base + i];
         tin[i] = tree_in[g.tree_base + i];
@@ -778,7 +778,7 @@ __device__ __forceinline__ void colscan_body(uint32_t cg, uint32_t redo, const L
                                              const uint32_t* chunk_tab, uint32_t* cm,
                                              uint32_t* cs, uint32_t dig) {
     const LSeg g = lseg[chunk_tab[cg]];
-    if (redo && g.pad1 != 1u) return;
+    if (redo && !(g.redo_tune & kRedoBit)) return;
     const uint32_t b = blockIdx.y * kWG + threadIdx.x;
     const uint32_t kc = digit_values(g.k, g.d, dig);
     if (b >= kc) return;
@@ -867,12 +867,15 @@ __device__ __forceinline__ void add_starts(const LSeg& g, uint32_t* cs, uint32_t
 __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg, uint32_t* cs,
                                                  uint32_t* bstart, const uint64_t* tree_in,
                                                  const uint8_t* tree_lcp, const PlanCtx& ctx,
-                                                 uint32_t next_buf) {
-    __shared__ uint32_t tot[1u << (kDMax + 1)];
-    __shared__ uint32_t st[1u << (kDMax + 1)];
+                                                 uint32_t next_buf, uint32_t kmax) {
+    // per bucket (kmax entries each, dynamic LDS): sizes, starts, new depths
+    extern __shared__ uint32_t plan_lds[];
+    uint32_t* tot = plan_lds;
+    uint32_t* st = tot + kmax;
+    uint32_t* ndl = st + kmax;
     __shared__ uint32_t tmp[kWG + 1];
     const LSeg g = lseg[seg];
-    const SetP sp = set_params(ctx, g.base);
+    const SetP sp = seg_set_params(ctx, g);
     const uint32_t k = g.k;
     chunk_prefixes(g, cs, k, tot);
     __syncthreads();
@@ -936,7 +939,6 @@ __device__ __forceinline__ void bucket_plan_body(uint32_t seg, const LSeg* lseg,
     };
     // every thread counts, then emits, its buckets b = tid, tid + kWG, ... in
     // the same order (their new depths kept in LDS: loops stay rolled)
-    __shared__ uint32_t ndl[1u << (kDMax + 1)];
     PlanAcc acc;
     acc_clear(acc);
     for (uint32_t b = threadIdx.x; b < k; b += kWG) {
@@ -960,14 +962,14 @@ __global__ __launch_bounds__(256) void k_bucket_plan(const LSeg* lseg, uint32_t*
                                                      uint32_t* bstart, const uint64_t* tree_in,
                                                      const uint8_t* tree_lcp, PlanCtx ctx,
                                                      uint32_t next_buf, const uint32_t* wcnt,
-                                                     uint32_t cap) {
+                                                     uint32_t cap, uint32_t kmax) {
     if (!G) {
-        bucket_plan_body(blockIdx.x, lseg, cs, bstart, tree_in, tree_lcp, ctx, next_buf);
+        bucket_plan_body(blockIdx.x, lseg, cs, bstart, tree_in, tree_lcp, ctx, next_buf, kmax);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, ctx.glob, gridDim.x);
     for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
-        bucket_plan_body(u, lseg, cs, bstart, tree_in, tree_lcp, ctx, next_buf);
+        bucket_plan_body(u, lseg, cs, bstart, tree_in, tree_lcp, ctx, next_buf, kmax);
         __syncthreads();
     }
 }
@@ -2334,13 +2336,14 @@ void launch_digit_starts(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint3
 
 void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t* bstart,
                         const uint64_t* tree_in, const uint8_t* tree_lcp, const PlanCtx& ctx,
-                        uint32_t next_buf, const Dyn& dy, hipStream_t st) {
+                        uint32_t next_buf, uint32_t kmax, const Dyn& dy, hipStream_t st) {
+    const size_t lds = (size_t)kmax * 3 * 4;
     if (dy.cnt)
-        S5_LAUNCH(k_bucket_plan<true>, dim3(dy.grid), dim3(kWG), 0, st, lseg, cs, bstart, tree_in,
-                  tree_lcp, ctx, next_buf, dy.cnt, dy.cap);
+        S5_LAUNCH(k_bucket_plan<true>, dim3(dy.grid), dim3(kWG), lds, st, lseg, cs, bstart,
+                  tree_in, tree_lcp, ctx, next_buf, dy.cnt, dy.cap, kmax);
     else
-        S5_LAUNCH(k_bucket_plan<false>, dim3(n_large), dim3(kWG), 0, st, lseg, cs, bstart, tree_in,
-                  tree_lcp, ctx, next_buf, dy.cnt, dy.cap);
+        S5_LAUNCH(k_bucket_plan<false>, dim3(n_large), dim3(kWG), lds, st, lseg, cs, bstart,
+                  tree_in, tree_lcp, ctx, next_buf, dy.cnt, dy.cap, kmax);
 }
 
 void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,

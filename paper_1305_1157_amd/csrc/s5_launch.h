@@ -43,9 +43,10 @@ void launch_digit_count(uint32_t tiles, const LSeg* lseg, const uint32_t* tile_t
                         const uint16_t* bid, uint32_t* cm, uint32_t dig, hipStream_t st);
 void launch_digit_starts(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t dig,
                          hipStream_t st);
+// kmax: the most buckets of any segment of the pass (sizes the LDS)
 void launch_bucket_plan(uint32_t n_large, const LSeg* lseg, uint32_t* cs, uint32_t* bstart,
                         const uint64_t* tree_in, const uint8_t* tree_lcp, const PlanCtx& ctx,
-                        uint32_t next_buf, const Dyn& dy, hipStream_t st);
+                        uint32_t next_buf, uint32_t kmax, const Dyn& dy, hipStream_t st);
 void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uint32_t* tile_tab,
                     const uint16_t* bid, const uint64_t* key_in, const uint64_t* key2_in,
                     const uint32_t* idx_in, uint64_t* key_out, uint64_t* key2_out,

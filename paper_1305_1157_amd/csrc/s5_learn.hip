@@ -598,7 +598,7 @@ __device__ __forceinline__ void learn_check_body(uint32_t slot, LSeg* lseg,
     __syncthreads();
     if (threadIdx.x == 0 && (double)smax > (double)beta * g.size / (g.v + 1)) {
         lseg[si].pad0 = 0xFFFFFFFFu;
-        lseg[si].pad1 = 1u;  // redo: sampled tree, classification and column scan again
+        lseg[si].redo_tune |= kRedoBit;  // redo: sampled tree, classification and column scan
         atomicAdd(&glob->fallbacks, 1u);
         atomicAdd(&glob->late_fallbacks, 1u);
     }

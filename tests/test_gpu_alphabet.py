@@ -57,6 +57,22 @@ def test_small_alphabets(alphabet, cfg):
     assert st["char_bits"] == 3
 
 
+@pytest.mark.parametrize("cfg", ["auto", "auto_tiny"])
+def test_duplicate_runs_packed(cfg):
+    """Runs of equal DNA strings beside strings that differ from them only at
+    the end (the base case finishes a run at once only if all its strings are
+    equal)."""
+    rng = random.Random(8)
+    strs = []
+    for _ in range(1200):
+        x = bytes(rng.choice(b"ACGT") for _ in range(rng.randint(30, 110)))
+        strs += [x] * rng.randint(2, 4)
+        strs.append([x[:-1] + b"G", x + b"A", x[:-2]][rng.randrange(3)])
+    rng.shuffle(strs)
+    st = strings_parity(strs, CFGS[cfg], label=f"duplicate runs/{cfg}")
+    assert st["char_bits"] == 3
+
+
 def test_eight_values_use_bytes():
     st = strings_parity(_strings(9, b"ACGTNRYK", 20_000, 60), AUTO, label="8 values")
     assert st["char_bits"] == 8

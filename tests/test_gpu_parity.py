@@ -144,7 +144,31 @@ def _dup_groups(seed, n_distinct, max_rep, length):
     return out
 
 
+def _near_duplicates(seed, n_groups, length):
+    """Runs of equal strings next to strings that differ from them only at
+    the end (last character changed, one character more or less, the byte
+    after a shared 8-byte key), so that a run of equal keys holds equal and
+    unequal pairs: the whole run must be refined, not finished as duplicates."""
+    rng = random.Random(seed)
+    out = []
+    for _ in range(n_groups):
+        x = bytes(rng.choice(b"ACGT") for _ in range(length))
+        kind = rng.randrange(4)
+        out += [x] * rng.randint(2, 5)
+        if kind == 0:
+            out.append(x[:-1] + (b"A" if x[-1:] != b"A" else b"C"))
+        elif kind == 1:
+            out.append(x + b"T")
+        elif kind == 2:
+            out.append(x[:-1])
+        else:
+            out.append(x[:8] + bytes([x[8] ^ 1]) + x[9:])
+    rng.shuffle(out)
+    return out
+
+
 EDGE.update({
+    "near_duplicates": _near_duplicates(5, 1500, 90),
     "dup_groups_long": _dup_groups(1, 400, 20, 120),
     "dup_pairs_dna_like": _dup_groups(2, 3000, 2, 100),
     "bucket_sizes_64_65_512_513": [bytes([65 + g]) + bytes([97 + (i * 7919) % 26]) * 12
