@@ -1146,12 +1146,14 @@ __device__ __forceinline__ void scatter_body(
         for (int c = 0; c < kChunks; ++c) {
             const uint32_t p = pw + c * 64;
             const bool valid = p < se;
-            bb[c] = valid ? bid[p] : kNoString;
-            nk[c] = valid ? key_in[p] : 0ull;
-            n2[c] = valid ? key2_in[p] : 0ull;
-            n3[c] = K3 && valid && !(PK ? codec_has_end(kc, n2[c]) : has_zero(n2[c])) ? key3[p]
-                                                                                   : 0ull;
-            id[c] = valid ? idx_in[p] : 0u;
+            // streamed once per pass: non-temporal, so the cache keeps the gathers' lines
+            bb[c] = valid ? __builtin_nontemporal_load(bid + p) : kNoString;
+            nk[c] = valid ? __builtin_nontemporal_load(key_in + p) : 0ull;
+            n2[c] = valid ? __builtin_nontemporal_load(key2_in + p) : 0ull;
+            n3[c] = K3 && valid && !(PK ? codec_has_end(kc, n2[c]) : has_zero(n2[c]))
+                        ? __builtin_nontemporal_load(key3 + p)
+                        : 0ull;
+            id[c] = valid ? __builtin_nontemporal_load(idx_in + p) : 0u;
         }
 #pragma unroll
         for (int c = 0; c < kChunks; ++c) {
