@@ -219,6 +219,19 @@ def test_random_1M_full():
     assert st["passes"] >= 1 and st["moved_M"] >= 1_000_000
 
 
+def test_one_bucket_statistic():
+    """Strings that share their first 16 bytes fall into one bucket in the first
+    pass (moved only to advance the depth); random strings never do."""
+    rng = random.Random(12)
+    shared = [b"prefix-common-16" + bytes(rng.choice(b"abcdefgh") for _ in range(12))
+              for _ in range(20000)]
+    st = strings_parity(shared, None, label="shared 16-byte prefix")
+    assert st["moved_one_bucket"] >= len(shared)
+    chars, offs = gen.workload("random_1M", 100_000)
+    st = assert_parity(chars, offs, None, label="random")
+    assert st["moved_one_bucket"] == 0
+
+
 def test_two_pass_same_passes_and_moves():
     """The two-pass distribution moves each level twice but splits the same way:
     the level count and the strings distributed per level are those of one move."""
