@@ -1624,7 +1624,7 @@ __device__ __forceinline__ void cex_local(uint64_t (&h)[E], uint32_t (&l)[E], ui
 // partner is another thread of the same wavefront exchanges by cross-lane
 // shuffles; only partners in other wavefronts go through LDS (with barriers).
 template <int E, int NT>
-__device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
+__device__ __forceinline__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
     const uint32_t t = threadIdx.x;
     const bool act = t * E < P;
     // packed elements (see pack96); the partner of an active thread is active,
@@ -1690,7 +1690,7 @@ __device__ void block_bitonic(uint64_t* SK, uint32_t* SA, uint32_t P) {
 // P <= EMAX * NT; only the instantiations up to EMAX are compiled into a kernel,
 // so small-bucket kernels keep a small register footprint.
 template <int EMAX, int NT>
-__device__ void sort_pow2(uint64_t* SK, uint32_t* SA, uint32_t P) {
+__device__ __forceinline__ void sort_pow2(uint64_t* SK, uint32_t* SA, uint32_t P) {
     if (P <= (uint32_t)NT) block_bitonic<1, NT>(SK, SA, P);
     else if constexpr (EMAX >= 2) {
         if (P <= 2u * NT) block_bitonic<2, NT>(SK, SA, P);

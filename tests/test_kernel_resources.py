@@ -4,8 +4,8 @@ compiler's resource-usage remarks (a device-only compile; no GPU needed).
 The occupancy figures are design choices: the redistribution and the
 workgroup base case keep four waves per SIMD, the training step fits two
 workgroups per compute unit, and no kernel spills vector registers to scratch
-except the host-driven workgroup base case (at most eight registers, the
-price of its four waves per SIMD).
+except the workgroup base case (at most eight registers, the price of its
+four waves per SIMD).
 """
 import os
 import re
@@ -61,11 +61,11 @@ def test_every_kernel_reported(usage):
 
 def test_no_vector_spills(usage):
     # the one exception: held to 128 registers (four waves per SIMD), the
-    # host-driven workgroup base case spills up to eight registers (values
-    # stored once per item and reloaded once at its end; byte keys with 256 or
-    # 512 threads: eight)
+    # workgroup base case spills up to eight registers (values stored once per
+    # item and reloaded once at its end; the graph-mode instantiations, which
+    # also hold the grid-stride loop, spill the most)
     for name, r in usage.items():
-        if "k_base_blockILi4ELb0E" in name:
+        if "k_base_blockILi4E" in name:
             assert r.get("VGPRs Spill", 0) <= 8 and r.get("ScratchSize", 0) <= 48, (name, r)
             continue
         assert r.get("ScratchSize", 0) == 0, f"{name} uses scratch"
