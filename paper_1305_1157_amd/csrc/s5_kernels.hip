@@ -1286,15 +1286,19 @@ __global__ __launch_bounds__(256) void k_scatter(
     const uint64_t* offsets, uint32_t* out_perm, uint32_t* out_lcp, uint32_t vmax, uint32_t kmax,
     const uint32_t* wcnt, uint32_t cap, const Globals* glob, const uint64_t* key3,
     KeyCodec kc, uint16_t* bid_out) {
+    // neighbouring tiles write adjacent runs of every bucket: on one XCD the
+    // partial cache lines where their runs meet are merged in its L2
     if (!G) {
-        scatter_body<K3, PK, DIG>(blockIdx.x, lseg, tile_tab, bid, key_in, key2_in, idx_in,
-                                  key_out, key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp,
-                                  chars, offsets, out_perm, out_lcp, vmax, kmax, key3, kc,
-                                  bid_out);
+        scatter_body<K3, PK, DIG>(xcd_unit(blockIdx.x, gridDim.x), lseg, tile_tab, bid, key_in,
+                                  key2_in, idx_in, key_out, key2_out, idx_out, cm, cs, bstart,
+                                  tree_in, tree_lcp, chars, offsets, out_perm, out_lcp, vmax,
+                                  kmax, key3, kc, bid_out);
         return;
     }
     const uint32_t units = block_work_count(wcnt, cap, glob, gridDim.x);
-    for (uint32_t u = blockIdx.x; u < units; u += gridDim.x) {
+    for (uint32_t r0 = 0; r0 + blockIdx.x < units; r0 += gridDim.x) {
+        const uint32_t m = units - r0 < gridDim.x ? units - r0 : gridDim.x;
+        const uint32_t u = r0 + xcd_unit(blockIdx.x, m);
         scatter_body<K3, PK, DIG>(u, lseg, tile_tab, bid, key_in, key2_in, idx_in, key_out,
                                   key2_out, idx_out, cm, cs, bstart, tree_in, tree_lcp, chars,
                                   offsets, out_perm, out_lcp, vmax, kmax, key3, kc, bid_out);

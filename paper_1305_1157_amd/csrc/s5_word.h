@@ -332,6 +332,22 @@ S5_HD uint32_t digit_bits(uint32_t d, uint32_t dig) {
     return dig == 0 ? d + 1u : dig == kDigitLow ? r : d + 1u - r;
 }
 
+// The dispatcher hands workgroups to the chip's 8 XCDs in turn (workgroup b
+// runs on XCD b mod 8), and every XCD has an L2 of its own.  xcd_unit(b, n)
+// renumbers the n workgroups of a launch so that runs of kXcdRun consecutive
+// units go to one XCD (a bijection of [0, n)): neighbouring units then share
+// an L2, while every XCD still takes its turn along the whole launch.  In the
+// last, partial group of 8 runs each XCD takes one contiguous range.
+constexpr uint32_t kXcds = 8, kXcdRun = 16;
+S5_HD uint32_t xcd_unit(uint32_t b, uint32_t n) {
+    constexpr uint32_t S = kXcds * kXcdRun;
+    const uint32_t g0 = b / S * S;
+    if (g0 + S <= n) return g0 + (b % kXcds) * kXcdRun + (b % S) / kXcds;
+    const uint32_t c = b - g0, m = n - g0;
+    const uint32_t x = c % kXcds, j = c / kXcds, q = m / kXcds, r = m % kXcds;
+    return g0 + x * q + (x < r ? x : r) + j;
+}
+
 // Jump table over the top key bits (appendix A, "Jump tables").  All keys
 // between the first and the last splitter share the top `sh` bits of those
 // two splitters; the next `a` bits index a table whose entry is the node at

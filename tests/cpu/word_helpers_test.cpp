@@ -529,6 +529,28 @@ static void test_bucket_digits(std::mt19937_64& rng) {
     }
 }
 
+// xcd_unit renumbers a launch's workgroups: a bijection of [0, n); inside
+// every full group of 8 runs, workgroups b and b + 8 (same XCD) take
+// neighbouring units, and the 8 XCDs take the group's 8 runs.
+static void test_xcd_unit() {
+    const uint32_t S = kXcds * kXcdRun;
+    for (uint32_t n : {0u, 1u, 7u, 8u, 9u, S - 1, S, S + 1, 3 * S + 5, 4883u, 65536u, 100003u}) {
+        std::vector<uint32_t> seen(n, 0);
+        bool ok = true;
+        for (uint32_t b = 0; b < n; ++b) {
+            const uint32_t u = xcd_unit(b, n);
+            if (u >= n || seen[u]++) ok = false;
+        }
+        CHECK(ok, "xcd_unit not a bijection of [0, %u)", n);
+        for (uint32_t b = 0; b + kXcds < n / S * S; ++b)
+            if ((b + kXcds) / S == b / S)
+                CHECK(xcd_unit(b + kXcds, n) == xcd_unit(b, n) + 1, "n %u b %u", n, b);
+        for (uint32_t g = 0; g + S <= n; g += S)
+            for (uint32_t x = 0; x < kXcds; ++x)
+                CHECK(xcd_unit(g + x, n) == g + x * kXcdRun, "n %u run %u", n, x);
+    }
+}
+
 int main(int argc, char** argv) {
     std::mt19937_64 rng(12345);
     test_load_key_guarded(rng);
@@ -541,6 +563,7 @@ int main(int argc, char** argv) {
     test_jump_table(rng);
     test_codec(rng);
     test_bucket_digits(rng);
+    test_xcd_unit();
     if (argc > 1) test_fig1(argv[1]);
     if (failures) {
         printf("%d failures\n", failures);

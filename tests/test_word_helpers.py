@@ -5,7 +5,8 @@ splitter tree are compiled for the host and compared with byte-level
 definitions: key extraction (also next to an inaccessible page, so a read past
 a string's last aligned word would fault), lcp of keys, the level-order /
 in-order index map, recursive splitter selection and classification versus
-``2 * lower_bound + [equal]``, and the worked tree of Figure 1
+``2 * lower_bound + [equal]``, the workgroup renumbering over the XCDs (a
+bijection), and the worked tree of Figure 1
 (``tests/golden/fig1_ternary_v3.txt``).
 """
 import os
