@@ -13,6 +13,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -207,6 +209,12 @@ void graphs_release();
 // Pinned readback block of a device: [raw copy | counters | globals], one slot each.
 constexpr size_t kHostSlot = 4096;
 static_assert(2 * sizeof(Counters) + sizeof(Globals) <= kHostSlot, "readback slot too small");
+// the word of the raw slot that a publish kernel raises once the counters are in
+constexpr size_t kFlagOff = kHostSlot - 64;
+static_assert(sizeof(Counters) + sizeof(Globals) <= kFlagOff, "readback slot layout");
+static_assert((sizeof(Counters) + sizeof(Globals)) % 4 == 0 &&
+                  sizeof(Counters) + sizeof(Globals) <= 4096,
+              "counters are published in at most 1024 words");
 
 // Get the pool of the current device with at least `bytes`.
 int pool_get(size_t bytes, DevPool** out) {
@@ -306,8 +314,10 @@ void timed_dispatch(int k, uint64_t items, hipStream_t st, F&& fn) {
     g_pending.push_back({k, a, b, items});
 }
 
-// After the stream has been synchronized: fold pending events into totals.
+// Fold pending events into totals (each waited for first: a sort's last
+// readback need not wait for its whole stream).
 void prof_collect() {
+    for (auto& p : g_pending) (void)hipEventSynchronize(p.b);
     for (auto& p : g_pending) {
         float ms = 0;
         if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
@@ -561,11 +571,19 @@ struct HostView {
     void* host;
     Counters* hc;
     Globals* hg;
+    char* dev;  // the block's device address: counters are published into it (null: copied)
 };
 
-HostView host_view(void* host) {
-    return HostView{host, (Counters*)((char*)host + kHostSlot),
-                    (Globals*)((char*)host + 2 * kHostSlot)};
+// `mapped`: the block is pinned host memory that kernels can write.
+HostView host_view(void* host, bool mapped) {
+    HostView v{host, (Counters*)((char*)host + kHostSlot), (Globals*)((char*)host + 2 * kHostSlot),
+               nullptr};
+    void* d = nullptr;
+    if (mapped && hipHostGetDevicePointer(&d, host, 0) == hipSuccess && d)
+        v.dev = (char*)d;
+    else
+        (void)hipGetLastError();
+    return v;
 }
 
 // Return code of a device status word: argument checks first.
@@ -607,12 +625,27 @@ int choose_alphabet(const SortArgs& a, Cfg& c, const Ptrs& P, void* host, hipStr
     return S5_OK;
 }
 
-// Copy a pass's counters together with the globals (one copy: the two lie
-// next to each other) into the host block.
+// A pass's counters together with the globals (they lie next to each other).
+const char* readback_src(const Ptrs& P, int which) {
+    return which == 0 ? (const char*)P.cnt[0] : (const char*)P.glob;
+}
+
+// Copy them into the host block.
 int readback_start(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
-    char* src = which == 0 ? (char*)P.cnt[0] : (char*)P.glob;
-    S5_HIP(hipMemcpyAsync(H.host, src, sizeof(Counters) + sizeof(Globals), hipMemcpyDeviceToHost, st));
+    S5_HIP(hipMemcpyAsync(H.host, readback_src(P, which), sizeof(Counters) + sizeof(Globals),
+                          hipMemcpyDeviceToHost, st));
     return S5_OK;
+}
+
+// Or have a kernel write them into the mapped host block and raise its flag
+// to a new sequence number (returned).  Unlike a copy followed by an event,
+// this puts no marker between the kernels of the stream.
+uint32_t g_publish_seq = 0;
+uint32_t publish_start(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
+    if (++g_publish_seq == 0) ++g_publish_seq;  // 0 never marks a publication
+    launch_publish(readback_src(P, which), sizeof(Counters) + sizeof(Globals), H.dev,
+                   (uint32_t*)(H.dev + kFlagOff), g_publish_seq, st);
+    return g_publish_seq;
 }
 
 // Unpack the host block once the copy has landed.
@@ -624,24 +657,45 @@ int readback_parse(const HostView& H, int which) {
 }
 
 // Copy a pass's counters together with the globals and wait for them.
-int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
+int readback_copy(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
     int rc = readback_start(P, H, which, st);
     if (rc) return rc;
     S5_HIP(hipStreamSynchronize(st));
     return readback_parse(H, which);
 }
 
-// An event per device that marks a readback copy, so the host can wait for the
-// copy while the kernels queued after it (the redistribution) still run.
-std::unordered_map<int, hipEvent_t> g_copy_events;
+// Wait until publication `seq` has landed, then unpack it.  The host polls
+// the flag word.  After 2 ms without it, it also asks now and then whether
+// the stream has drained, and if it has while the flag still holds another
+// number, it copies the counters instead, so the wait always ends.  (Not
+// sooner: a stream query puts a marker into the stream, and the kernel after
+// it starts about 5 us later.)
+int publish_wait(const Ptrs& P, const HostView& H, int which, uint32_t seq, hipStream_t st) {
+    const volatile uint32_t* flag = (const volatile uint32_t*)((const char*)H.host + kFlagOff);
+    const auto t0 = std::chrono::steady_clock::now();
+    bool queried = false;
+    for (uint32_t spin = 1; *flag != seq; ++spin) {
+        if (spin % 1024) continue;
+        if (!queried && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2))
+            continue;
+        queried = true;
+        const hipError_t q = hipStreamQuery(st);
+        if (q == hipErrorNotReady) continue;
+        (void)hipGetLastError();
+        if (q != hipSuccess) return S5_ERR_HIP;
+        if (*flag != seq) return readback_copy(P, H, which, st);
+    }
+    if (queried) (void)hipGetLastError();  // a not-ready answer is no error
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return readback_parse(H, which);
+}
 
-int copy_event(hipEvent_t* out) {
-    int dev = 0;
-    S5_HIP(hipGetDevice(&dev));
-    hipEvent_t& e = g_copy_events[dev];
-    if (!e) S5_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    *out = e;
-    return S5_OK;
+// Read a pass's counters together with the globals and wait for them.
+int readback(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
+    if (!H.dev) return readback_copy(P, H, which, st);
+    const uint32_t seq = publish_start(P, H, which, st);
+    S5_HIP(hipGetLastError());
+    return publish_wait(P, H, which, seq, st);
 }
 
 // Host-driven passes from `level` on (counters of the pass about to run in
@@ -662,23 +716,27 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
             if (rc) return rc;
             if (H.hg->late_fallbacks != before) pass_front(a, c, L, P, S, cur, buf, 1u, st);
         }
-        // the plan writes the next pass's counters; they are copied back while
-        // the redistribution runs, and the host waits for the copy only, so the
-        // next pass's launches queue behind the redistribution with no idle gap
-        // (the sort without allocations waits for the whole stream instead)
+        // the plan writes the next pass's counters; they are published to the
+        // host while the redistribution runs, and the host waits for them
+        // only, so the next pass's launches queue behind the redistribution
+        // with no idle gap (the sort without allocations copies them and waits
+        // for the whole stream instead)
         pass_plan(a, c, L, P, S, cur, buf, level, st);
-        rc = readback_start(P, H, nxt, st);
-        if (rc) return rc;
-        hipEvent_t ev = nullptr;
-        if (!t_quiet) {
-            rc = copy_event(&ev);
+        uint32_t seq = 0;
+        if (H.dev) {
+            seq = publish_start(P, H, nxt, st);
+        } else {
+            rc = readback_start(P, H, nxt, st);
             if (rc) return rc;
-            S5_HIP(hipEventRecord(ev, st));
         }
         pass_scatter(a, c, P, S, cur, buf, level, st);
         S5_HIP(hipGetLastError());
-        S5_HIP(ev ? hipEventSynchronize(ev) : hipStreamSynchronize(st));
-        rc = readback_parse(H, nxt);
+        if (seq) {
+            rc = publish_wait(P, H, nxt, seq, st);
+        } else {
+            S5_HIP(hipStreamSynchronize(st));
+            rc = readback_parse(H, nxt);
+        }
         if (rc) return rc;
         stats->moved_M += S.now.moved;
         stats->segments += S.now.n_large;
@@ -727,7 +785,7 @@ int run_sort(const SortArgs& a, const Cfg& c0, void* ws, size_t ws_bytes, void* 
     const Layout L = make_layout(a.n, c, 0);
     if (ws_bytes < L.total) return S5_ERR_NOMEM;
     const Ptrs P = make_ptrs(L, (char*)ws);
-    const HostView H = host_view(host);
+    const HostView H = host_view(host, !t_quiet);
     int rc = choose_alphabet(a, c, P, host, st);
     if (rc) return rc;
     uint32_t retries = 0;
@@ -739,8 +797,8 @@ int run_sort(const SortArgs& a, const Cfg& c0, void* ws, size_t ws_bytes, void* 
         rc = readback(P, H, 0, st);
         if (!rc) rc = host_passes(a, c, L, P, H, 0, st, stats);
         if (!rc) {
-            S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
-            S5_HIP(hipStreamSynchronize(st));
+            // the globals after the last kernel (with counters that are not used)
+            if (readback(P, H, 0, st) == S5_ERR_HIP) return S5_ERR_HIP;
             final_stats(H, stats);
             rc = status_rc(H.hg->status);
         }
@@ -860,7 +918,7 @@ int run_graph(const SortArgs& a, const Cfg& c0, uint32_t levels, void* ws, size_
     const Layout L = make_layout(a.n, c, tune_sets);
     if (ws_bytes < L.total) return S5_ERR_NOMEM;
     const Ptrs P = make_ptrs(L, (char*)ws);
-    const HostView H = host_view(host);
+    const HostView H = host_view(host, !t_quiet);
     int rc = choose_alphabet(a, c, P, host, st);
     if (rc) return rc;
     uint32_t retries = 0;
@@ -910,8 +968,8 @@ int run_graph(const SortArgs& a, const Cfg& c0, uint32_t levels, void* ws, size_
             }
         }
         if (!rc) {
-            S5_HIP(hipMemcpyAsync(H.hg, P.glob, sizeof(Globals), hipMemcpyDeviceToHost, st));
-            S5_HIP(hipStreamSynchronize(st));
+            // the globals after the last kernel (with counters that are not used)
+            if (readback(P, H, 0, st) == S5_ERR_HIP) return S5_ERR_HIP;
             final_stats(H, stats);
             rc = status_rc(H.hg->status);
         }
@@ -1165,11 +1223,6 @@ void s5_release(void) {
         if (kv.second) (void)hipStreamDestroy(kv.second);
     }
     g_capture_streams.clear();
-    for (auto& kv : g_copy_events) {
-        (void)hipSetDevice(kv.first);
-        if (kv.second) (void)hipEventDestroy(kv.second);
-    }
-    g_copy_events.clear();
     for (auto& kv : g_pools) {
         (void)hipSetDevice(kv.first);
         (void)hipDeviceSynchronize();

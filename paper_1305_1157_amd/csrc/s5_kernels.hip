@@ -466,6 +466,30 @@ __global__ void k_zero_words(uint32_t* p, uint32_t n) {
     if (i < n) p[i] = 0;
 }
 
+// Copy `words` words of counters into pinned host memory, release them to
+// the system, then raise *flag to `seq` (one wavefront).  The host polls the
+// flag instead of waiting for a copy and an event, and the kernels queued
+// after this one start at once.
+constexpr uint32_t kPublishWords = 1024;  // at most (all loads in flight together)
+__global__ __launch_bounds__(64) void k_publish(const uint32_t* src, uint32_t words,
+                                                uint32_t* dst, uint32_t* flag, uint32_t seq) {
+    constexpr uint32_t R = kPublishWords / 64;
+    uint32_t v[R];
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + 64 * r;
+        v[r] = i < words ? src[i] : 0u;
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < R; ++r) {
+        const uint32_t i = threadIdx.x + 64 * r;
+        if (i < words) dst[i] = v[r];
+    }
+    // the release orders every lane's stores of this wavefront before the flag
+    if (threadIdx.x == 0)
+        __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // ---------------------------------------------------------------------------
 // K2: sample, sort the sample, select splitters recursively, build the tree
 
@@ -2260,6 +2284,13 @@ void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
 void launch_pass_stats(const Counters* cur, const Counters* next, Globals* glob, uint32_t level,
                        hipStream_t st) {
     S5_LAUNCH(k_pass_stats, dim3(1), dim3(64), 0, st, cur, next, glob, level);
+}
+
+void launch_publish(const void* src, size_t bytes, void* dst, uint32_t* flag, uint32_t seq,
+                    hipStream_t st) {
+    const uint32_t words = (uint32_t)std::min<size_t>(bytes / 4, kPublishWords);
+    S5_LAUNCH(k_publish, dim3(1), dim3(64), 0, st, (const uint32_t*)src, words, (uint32_t*)dst,
+              flag, seq);
 }
 
 void launch_zero_words(void* p, size_t bytes, hipStream_t st) {

@@ -22,6 +22,11 @@ void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,
 void launch_pass_stats(const Counters* cur, const Counters* next, Globals* glob, uint32_t level,
                        hipStream_t st);
 void launch_zero_words(void* p, size_t bytes, hipStream_t st);
+// copy `bytes` (a multiple of 4) from device memory into pinned host memory
+// (its device address `dst`), then store `seq` into the host word `flag`
+void launch_publish(const void* src, size_t bytes, void* dst, uint32_t* flag, uint32_t seq,
+                    hipStream_t st);
+
 void launch_sample_tree(uint32_t n_large, const LSeg* lseg, const uint64_t* key_in,
                         uint32_t alpha, uint32_t vmax, uint64_t seed, uint64_t* tree_lo,
                         uint64_t* tree_in, uint8_t* tree_lcp, uint16_t* jump, uint32_t* tile_tab,
