@@ -4,8 +4,9 @@
  * For roofline reporting: while profiling is enabled, every kernel launch of
  * a sort is bracketed by two HIP events recorded on the stream the kernel is
  * launched on (for the redistribution kernel the dispatch itself stamps the
- * two events, hipExtLaunchKernel, so its interval is the kernel's execution
- * with no marker packets around it); after the sort completes the elapsed
+ * two events, hipExtLaunchKernel, so their interval is the kernel's
+ * execution; the device still idles a few microseconds around each timed
+ * launch while the events are processed); after the sort completes the elapsed
  * times are accumulated per kernel together with the strings the launch
  * processed and the algorithmic bytes that implies (the per-string byte
  * counts of each step, e.g. 24 bytes of (key, index) read and written per

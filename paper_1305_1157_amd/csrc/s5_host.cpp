@@ -295,7 +295,7 @@ void timed(int k, uint64_t items, hipStream_t st, F&& fn) {
 }
 
 // Same for a launcher that takes the two events itself and lets the kernel's
-// dispatch stamp them (a single kernel; no marker packets around it).
+// dispatch stamp them (their interval is the one kernel's execution).
 template <class F>
 void timed_dispatch(int k, uint64_t items, hipStream_t st, F&& fn) {
     if (!g_prof_on || t_quiet || (g_prof_only >= 0 && k != g_prof_only)) {

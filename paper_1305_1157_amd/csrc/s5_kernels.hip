@@ -2397,8 +2397,7 @@ void launch_scatter(uint32_t tiles, uint32_t unroll, const LSeg* lseg, const uin
     const size_t lds = (size_t)kSubTile * (8 + 4 + 2) + krmax * 4 + (size_t)kmax * 4 +
                        (size_t)kWaves * krmax * 2 + (krmax + 1) * 2 + (size_t)kmax * 2;
     // with events (instrumentation, host-driven passes only) the dispatch
-    // itself stamps them: their interval is the kernel's execution, with no
-    // marker packets around it
+    // itself stamps them: their interval is the kernel's execution
 #define S5_SCATTER_P(GG, KK, PP, DD, GRID)                                                        \
     do {                                                                                          \
         if (ev_start || ev_stop)                                                                  \
