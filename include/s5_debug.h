@@ -36,6 +36,13 @@ int s5_debug_limit_capacity(uint32_t which, uint32_t limit);
 int s5_debug_count_writes(uint32_t* perm, uint32_t* lcp, uint64_t n, uint32_t* perm_counts,
                           uint32_t* lcp_counts, uint32_t* stray);
 
+/* With on != 0, the sorts that follow publish their per-level counters into
+ * a word next to the flag the host polls, so the flag never shows them: every
+ * read-back then takes its fallback path (after 2 ms the host finds the
+ * stream drained and copies the counters).  on = 0 restores publication.
+ * Returns S5_OK. */
+int s5_debug_miss_publish(int on);
+
 #ifdef __cplusplus
 }
 #endif

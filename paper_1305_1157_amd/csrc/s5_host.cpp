@@ -641,10 +641,11 @@ int readback_start(const Ptrs& P, const HostView& H, int which, hipStream_t st) 
 // to a new sequence number (returned).  Unlike a copy followed by an event,
 // this puts no marker between the kernels of the stream.
 uint32_t g_publish_seq = 0;
+bool g_miss_publish = false;  // test hook: raise a word next to the flag instead
 uint32_t publish_start(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
     if (++g_publish_seq == 0) ++g_publish_seq;  // 0 never marks a publication
     launch_publish(readback_src(P, which), sizeof(Counters) + sizeof(Globals), H.dev,
-                   (uint32_t*)(H.dev + kFlagOff), g_publish_seq, st);
+                   (uint32_t*)(H.dev + kFlagOff + (g_miss_publish ? 4 : 0)), g_publish_seq, st);
     return g_publish_seq;
 }
 
@@ -1344,6 +1345,12 @@ int s5_debug_limit_capacity(uint32_t which, uint32_t limit) {
     std::lock_guard<std::mutex> g(g_mu);
     g_cap_limit[which] = limit;
     graphs_release();  // their layouts were planned with the old capacities
+    return S5_OK;
+}
+
+int s5_debug_miss_publish(int on) {
+    std::lock_guard<std::mutex> g(g_mu);
+    g_miss_publish = on != 0;
     return S5_OK;
 }
 

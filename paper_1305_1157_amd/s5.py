@@ -28,7 +28,7 @@ EXPORTS = ("s5_sort", "s5_sort_ex", "s5_sort_static", "s5_workspace_bytes", "s5_
            "s5_strerror", "s5_release", "s5_prefix_keys", "s5_classify", "s5_profile_enable",
            "s5_profile_only",
            "s5_profile_read", "s5_mlp_train", "s5_mlp_grad", "s5_mlp_eval", "s5_mlp_propose",
-           "s5_debug_limit_capacity", "s5_debug_count_writes")
+           "s5_debug_limit_capacity", "s5_debug_count_writes", "s5_debug_miss_publish")
 
 
 class Config(ctypes.Structure):
@@ -124,7 +124,9 @@ def _open(path: str):
     lib.s5_profile_read.argtypes = [ctypes.POINTER(KernelProfile), U32, ctypes.POINTER(U32)]
     lib.s5_debug_limit_capacity.argtypes = [U32, U32]
     lib.s5_debug_count_writes.argtypes = [P, P, U64, P, P, P]
-    for f in ("s5_debug_limit_capacity", "s5_debug_count_writes", "s5_sort", "s5_sort_ex",
+    lib.s5_debug_miss_publish.argtypes = [ctypes.c_int]
+    for f in ("s5_debug_limit_capacity", "s5_debug_count_writes", "s5_debug_miss_publish",
+              "s5_sort", "s5_sort_ex",
               "s5_sort_static", "s5_sort_batched", "s5_classify_ex", "s5_sort_batched_tuned", "s5_stats_get",
               "s5_prefix_keys",
               "s5_classify", "s5_profile_enable", "s5_profile_read", "s5_mlp_train", "s5_mlp_grad",

@@ -9,6 +9,10 @@
   same process then sorts correctly again.  The planner writes nothing for a
   workgroup whose allocation failed (it returns before emitting any record),
   and every later kernel exits once the status word is set.
+* Read-back fallback: with the per-level counter publications made to miss the
+  flag the host polls (test hook s5_debug_miss_publish), every read-back waits,
+  finds the stream drained and copies the counters instead; host-driven and
+  batched sorts stay exact.
 * Write counts (the write-check build): every out_perm slot is written exactly
   once, every out_lcp slot once or twice (a bucket boundary is flagged by the
   redistribution, then completed), and no output write lands outside the two
@@ -156,6 +160,31 @@ def test_large_segment_capacity_failure(batched):
 @pytest.mark.parametrize("batched", [False, True])
 def test_base_item_capacity_failure(batched):
     _device_failure(CAP_BASE0, 1, "words_50M", 100_000, batched)
+
+
+def test_read_back_fallback():
+    lib = s5.load()
+    chars, offs = gen.workload("url_10M", 40_000)
+    dc, do = to_dev(chars), to_dev(offs)
+    # tiny trees and base cases: several levels, each read back
+    cfg = s5.make_config(splitters=31, base_threshold=64, tile=64)
+    sb_host = np.array([0, 15_000, 40_000], dtype=np.uint64)
+    bcfg = s5.make_config(splitters=31, base_threshold=64, tile=64, graph_levels=1)
+    assert lib.s5_debug_miss_publish(1) == s5.S5_OK
+    try:
+        print("read-back fallback: url n=40000, host-driven and batched", flush=True)
+        p1, l1 = s5.sort(dc, do, cfg=cfg)
+        torch.cuda.synchronize()
+        passes = s5.stats()["passes"]
+        p2, l2 = s5.sort_batched(dc, do, to_dev(sb_host), cfg=bcfg)
+        torch.cuda.synchronize()
+    finally:
+        assert lib.s5_debug_miss_publish(0) == s5.S5_OK
+    assert passes >= 3
+    rp, rl = oracle.sort(chars, offs)
+    assert np.array_equal(p1.cpu().numpy(), rp) and np.array_equal(l1.cpu().numpy(), rl)
+    bp, bl = oracle.sort_batched(chars, offs, sb_host)
+    assert np.array_equal(p2.cpu().numpy(), bp) and np.array_equal(l2.cpu().numpy(), bl)
 
 
 def _counted(run, n, dev):
