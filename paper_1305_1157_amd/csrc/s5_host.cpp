@@ -766,6 +766,30 @@ int host_passes(const SortArgs& a, const Cfg& c, const Layout& L, const Ptrs& P,
     return S5_OK;
 }
 
+// The counters of the root level.  A single set of more than T strings is one
+// large segment, whose shape the host computes with the planner's own
+// seg_shape, so the first level is launched without waiting for the device.
+// The status word (the key cache's argument checks) then arrives with the
+// first level's counters, before any kernel reads the arena past the three
+// words the key cache loaded: the first level advances keys by at most 8
+// bytes, from those words.  Sets, and a root that goes straight to the base
+// case, read the counters back.
+int root_counters(const SortArgs& a, const Cfg& c, const Ptrs& P, const HostView& H,
+                  hipStream_t st) {
+    if (t_quiet || a.set_begin || a.n <= c.T) return readback(P, H, 0, st);
+    memset(H.hc, 0, sizeof *H.hc);
+    memset(H.hg, 0, sizeof *H.hg);
+    uint32_t d, ulen, tiles, chunks;
+    seg_shape(a.n, SetP{c.T, c.dmax, c.tile_min}, d, ulen, tiles, chunks);
+    H.hc->n_large = 1;
+    H.hc->tiles = tiles;
+    H.hc->chunks = chunks;
+    H.hc->kmax = 2 * ((1u << d) - 1) + 1;
+    H.hc->moved = a.n;
+    H.hc->pad0 = c.mode == S5_SPLIT_LEARNED && a.n >= kLearnMin ? 1u : 0u;
+    return S5_OK;
+}
+
 void final_stats(const HostView& H, s5_stats* stats) {
     stats->fallbacks = H.hg->fallbacks;
     stats->learned_proposals = H.hg->learned_props;
@@ -795,7 +819,7 @@ int run_sort(const SortArgs& a, const Cfg& c0, void* ws, size_t ws_bytes, void* 
         stats->workspace_bytes = L.total;
         start_sort(a, c, L, P, st);
         S5_HIP(hipGetLastError());
-        rc = readback(P, H, 0, st);
+        rc = root_counters(a, c, P, H, st);
         if (!rc) rc = host_passes(a, c, L, P, H, 0, st, stats);
         if (!rc) {
             // the globals after the last kernel (with counters that are not used)

@@ -190,6 +190,18 @@ __host__ __device__ inline SetP default_set_params(const PlanCtx& c) {
     return SetP{c.T, c.d_max, c.tile_min};
 }
 
+// tree depth and tiles of a large segment of `size` strings
+__host__ __device__ __forceinline__ void seg_shape(uint32_t size, const SetP& c, uint32_t& d,
+                                                   uint32_t& ulen, uint32_t& tiles, uint32_t& chunks) {
+    d = 1;
+    while (d < c.d_max && ((uint64_t)c.T << d) < 2ull * size) ++d;  // 2^d * T/2 >= size
+    ulen = (uint32_t)(((uint64_t)size + kMaxTiles - 1) / kMaxTiles);
+    ulen = (ulen + 63u) & ~63u;
+    if (ulen < c.tile_min) ulen = c.tile_min;
+    tiles = (uint32_t)(((uint64_t)size + ulen - 1) / ulen);
+    chunks = (tiles + kChunkRows - 1) / kChunkRows;
+}
+
 // Parameters of a segment's set: carried in its record (no search of the sets).
 // The word is kept in a vector register: the planning kernel's scalar
 // registers are all taken.

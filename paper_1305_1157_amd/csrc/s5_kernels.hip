@@ -124,18 +124,6 @@ __device__ __forceinline__ void acc_clear(PlanAcc& a) {
     a.kmax = 0;
 }
 
-// tree depth and tiles of a large segment of `size` strings
-__device__ __forceinline__ void seg_shape(uint32_t size, const SetP& c, uint32_t& d,
-                                          uint32_t& ulen, uint32_t& tiles, uint32_t& chunks) {
-    d = 1;
-    while (d < c.d_max && ((uint64_t)c.T << d) < 2ull * size) ++d;  // 2^d * T/2 >= size
-    ulen = (uint32_t)(((uint64_t)size + kMaxTiles - 1) / kMaxTiles);
-    ulen = (ulen + 63u) & ~63u;
-    if (ulen < c.tile_min) ulen = c.tile_min;
-    tiles = (uint32_t)(((uint64_t)size + ulen - 1) / ulen);
-    chunks = (tiles + kChunkRows - 1) / kChunkRows;
-}
-
 // Count one request (a bucket of size >= 2 that needs sorting).
 __device__ __forceinline__ void plan_count(uint32_t size, const PlanCtx& c, const SetP& sp,
                                            PlanAcc& a) {
