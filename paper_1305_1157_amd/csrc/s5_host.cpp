@@ -608,7 +608,7 @@ int choose_alphabet(const SortArgs& a, Cfg& c, const Ptrs& P, void* host, hipStr
     c.b = 8;
     if (c.alphabet != S5_ALPHABET_AUTO || a.n == 0) return S5_OK;
     const uint32_t samples = std::min<uint32_t>(a.n, 65536u);
-    launch_alphabet(a.chars, a.offsets, a.n, samples, P.alpha_bits, st);
+    launch_alphabet(a.chars, a.chars_len, a.offsets, a.n, samples, P.alpha_bits, st);
     uint32_t* hb = (uint32_t*)((char*)host + kAlphaSlot);
     S5_HIP(hipMemcpyAsync(hb, P.alpha_bits, 32, hipMemcpyDeviceToHost, st));
     S5_HIP(hipStreamSynchronize(st));

@@ -2224,9 +2224,11 @@ void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* 
 // Bytes that occur in a sample of the strings (alphabet compression): string
 // i = (j * n) / samples for j < samples, read key by key to its terminator
 // (at most 32 keys); bit c of bitmap[c / 32] is set for every byte value c != 0.
-__global__ __launch_bounds__(256) void k_alphabet(const uint8_t* chars, const uint64_t* offsets,
-                                                  uint32_t n, uint32_t samples,
-                                                  uint32_t* bitmap) {
+// With chars_len > 0 only bytes before chars_len are read (a string at or past
+// it is skipped: the key cache rejects the offset afterwards).
+__global__ __launch_bounds__(256) void k_alphabet(const uint8_t* chars, uint64_t chars_len,
+                                                  const uint64_t* offsets, uint32_t n,
+                                                  uint32_t samples, uint32_t* bitmap) {
     __shared__ uint32_t bm[8];
     if (threadIdx.x < 8) bm[threadIdx.x] = 0;
     __syncthreads();
@@ -2234,6 +2236,7 @@ __global__ __launch_bounds__(256) void k_alphabet(const uint8_t* chars, const ui
     if (j < samples) {
         const uint64_t pos = offsets[(uint32_t)(((uint64_t)j * n) / samples)];
         for (uint32_t q = 0; q < 32; ++q) {
+            if (chars_len && pos + 8ull * q >= chars_len) break;
             const uint64_t k = load_key(chars, pos + 8ull * q);
             for (int b = 0; b < 8; ++b) {
                 const uint32_t c = (uint32_t)(k >> (56 - 8 * b)) & 0xFFu;
@@ -2246,12 +2249,12 @@ __global__ __launch_bounds__(256) void k_alphabet(const uint8_t* chars, const ui
     if (threadIdx.x < 8 && bm[threadIdx.x]) atomicOr(&bitmap[threadIdx.x], bm[threadIdx.x]);
 }
 
-void launch_alphabet(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t samples,
-                     uint32_t* bitmap, hipStream_t st) {
+void launch_alphabet(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                     uint32_t n, uint32_t samples, uint32_t* bitmap, hipStream_t st) {
     S5_LAUNCH(k_zero_words, dim3(1), dim3(256), 0, st, bitmap, 8u);
     if (!n || !samples) return;
-    S5_LAUNCH(k_alphabet, dim3((samples + 255) / 256), dim3(256), 0, st, chars, offsets, n,
-              samples, bitmap);
+    S5_LAUNCH(k_alphabet, dim3((samples + 255) / 256), dim3(256), 0, st, chars, chars_len,
+              offsets, n, samples, bitmap);
 }
 
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,

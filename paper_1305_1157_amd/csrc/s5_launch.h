@@ -13,8 +13,8 @@ namespace s5 {
 void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
                       uint32_t n, uint64_t* key, uint64_t* key2, uint64_t* key3, uint32_t* idx,
                       Globals* glob, const KeyCodec& kc, hipStream_t st);
-void launch_alphabet(const uint8_t* chars, const uint64_t* offsets, uint32_t n, uint32_t samples,
-                     uint32_t* bitmap, hipStream_t st);
+void launch_alphabet(const uint8_t* chars, uint64_t chars_len, const uint64_t* offsets,
+                     uint32_t n, uint32_t samples, uint32_t* bitmap, hipStream_t st);
 void launch_prefix_keys(const uint8_t* chars, const uint64_t* offsets, uint32_t n,
                         uint32_t depth, uint64_t* key, hipStream_t st);
 void launch_plan_roots(const uint64_t* set_begin, uint32_t num_sets, uint32_t n,

@@ -65,21 +65,26 @@ def _sort_batched(lib, dc, chars_len, do, sb, perm, lcp, cfg=None):
                                s5._stream())
 
 
-def test_offset_past_arena_is_invalid():
+# byte keys; DNA with the alphabet sampled first (its sample reads no byte at
+# or past chars_len) and packed codes
+@pytest.mark.parametrize("name,cfg", [
+    ("url_10M", None), ("dna_16M", s5.make_config(alphabet=s5.ALPHABET_AUTO))],
+    ids=["bytes", "alphabet_auto"])
+def test_offset_past_arena_is_invalid(name, cfg):
     lib = s5.load()
-    chars, offs = gen.workload("url_10M", 30_000)
+    chars, offs = gen.workload(name, 30_000)
     n = offs.size
     dc = to_dev(chars)
     perm, lcp = _guarded(n, dc.device)
     bad = offs.copy()
     bad[n // 2] = chars.size  # one past the end
-    rc = _sort_ex(lib, dc, chars.size, to_dev(bad), n, perm, lcp)
+    rc = _sort_ex(lib, dc, chars.size, to_dev(bad), n, perm, lcp, cfg)
     torch.cuda.synchronize()
     assert rc == s5.S5_ERR_INVALID
     assert _guard_intact(perm, lcp)
     # the same offsets with the arena length unknown are the caller's
     # responsibility; the valid table sorts
-    rc = _sort_ex(lib, dc, chars.size, to_dev(offs), n, perm, lcp)
+    rc = _sort_ex(lib, dc, chars.size, to_dev(offs), n, perm, lcp, cfg)
     torch.cuda.synchronize()
     assert rc == s5.S5_OK
     rp, rl = oracle.sort(chars, offs)
