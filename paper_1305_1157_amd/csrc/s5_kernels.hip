@@ -156,10 +156,13 @@ __device__ __forceinline__ unsigned long long shfl_up_u64(unsigned long long v, 
 
 // Block-wide: a (this thread's counts) becomes its exclusive prefix over the
 // threads before it; T->a receives the block totals and T->err is cleared.
-// All threads of the block call.
+// All threads of the block call; the block has kWG threads (kWaves
+// wavefronts, a compile-time count, so that every wavefront's totals are
+// read from LDS at once rather than one dependent read after another).
 __device__ void plan_scan(PlanAcc& a, PlanTally* T) {
     __shared__ PlanAcc ws[kWaves];
-    const uint32_t lane = lane_id(), w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const uint32_t lane = lane_id(), w = threadIdx.x >> 6;
+    constexpr uint32_t nw = kWaves;
     PlanAcc inc = a;
     for (uint32_t o = 1; o < 64; o <<= 1) {
 #pragma unroll
@@ -181,6 +184,7 @@ __device__ void plan_scan(PlanAcc& a, PlanTally* T) {
 #pragma unroll
     for (int i = 0; i < kPU; ++i) {
         uint32_t pre = 0, tot = 0;
+#pragma unroll
         for (uint32_t qw = 0; qw < nw; ++qw) {
             const uint32_t x = ws[qw].u[i];
             pre += qw < w ? x : 0u;
@@ -192,6 +196,7 @@ __device__ void plan_scan(PlanAcc& a, PlanTally* T) {
 #pragma unroll
     for (int i = 0; i < kPQ; ++i) {
         unsigned long long pre = 0, tot = 0;
+#pragma unroll
         for (uint32_t qw = 0; qw < nw; ++qw) {
             const unsigned long long x = ws[qw].q[i];
             pre += qw < w ? x : 0ull;
@@ -202,6 +207,7 @@ __device__ void plan_scan(PlanAcc& a, PlanTally* T) {
     }
     if (threadIdx.x == 0) {
         uint32_t mx = 0;
+#pragma unroll
         for (uint32_t qw = 0; qw < nw; ++qw) mx = ws[qw].kmax > mx ? ws[qw].kmax : mx;
         T->a.kmax = mx;
         T->err = 0;
