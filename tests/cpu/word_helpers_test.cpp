@@ -233,6 +233,32 @@ static void build_tree(const std::vector<uint64_t>& smp, uint32_t d, std::vector
     for (uint32_t j = 0; j < v; ++j) tin[j] = t[inorder_node(j, d)];
 }
 
+// select_node against its definition by linear scans: the middle sample of
+// [a, b) and the run [lo, hi) of samples equal to it, clipped to [a, b).
+static void test_select_node(std::mt19937_64& rng) {
+    for (int rep = 0; rep < 400; ++rep) {
+        const uint32_t n = 1 + (uint32_t)(rng() % 600);
+        const uint32_t distinct = 1 + (uint32_t)(rng() % (rep % 3 == 0 ? 4 : 2 * n));
+        std::vector<uint64_t> smp(n);
+        for (auto& x : smp) x = (rng() % distinct) * 0x0100000001ull;
+        std::sort(smp.begin(), smp.end());
+        for (int q = 0; q < 40; ++q) {
+            uint32_t a = (uint32_t)(rng() % n), b = (uint32_t)(rng() % n);
+            if (a > b) std::swap(a, b);
+            ++b;
+            uint64_t x;
+            uint32_t lo, hi;
+            select_node(smp.data(), a, b, &x, &lo, &hi);
+            const uint32_t mid = (a + b) / 2;
+            uint32_t rlo = mid, rhi = mid + 1;
+            while (rlo > a && smp[rlo - 1] == smp[mid]) --rlo;
+            while (rhi < b && smp[rhi] == smp[mid]) ++rhi;
+            CHECK(x == smp[mid] && lo == rlo && hi == rhi, "n %u [%u, %u): %u %u vs %u %u", n, a,
+                  b, lo, hi, rlo, rhi);
+        }
+    }
+}
+
 static void test_tree_and_classify(std::mt19937_64& rng) {
     for (int rep = 0; rep < 300; ++rep) {
         uint32_t d = 1 + rng() % 10, v = (1u << d) - 1;
@@ -557,6 +583,7 @@ int main(int argc, char** argv) {
     test_load_key_random(rng);
     test_advance_key16(rng);
     test_inorder_map();
+    test_select_node(rng);
     test_tree_and_classify(rng);
     test_node_inorder();
     test_equal_variant(rng);
