@@ -40,11 +40,23 @@ WORKLOAD_TEXT = {
 }
 
 
+# device sources of the library's kernels; a committed profile records their
+# hash (kernel_source_sha256) and counts as stale once any of them changes
+KERNEL_SOURCES = ("s5_kernels.hip", "s5_word.h", "s5_internal.h")
+
+
+def kernel_source_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1305_1157_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def pmc_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     PMC summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None if there is
     none for this workload or the kernels changed since it was taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", f"pmc_{DOMINANT_SYMBOL}_{workload}.txt")
     if not os.path.exists(path):
         return None, None
@@ -55,9 +67,7 @@ def pmc_traffic(workload):
             vals["traffic"] = float(parts[2])
         if len(parts) == 2 and parts[0] == "kernel_source_sha256":
             vals["sha"] = parts[1]
-    src = os.path.join(ROOT, "paper_1305_1157_amd", "csrc", "s5_kernels.hip")
-    now = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if "traffic" not in vals or vals.get("sha") != now:
+    if "traffic" not in vals or vals.get("sha") != kernel_source_sha256():
         return None, f"{os.path.relpath(path, ROOT)} is stale (kernel source changed)"
     return vals["traffic"], os.path.relpath(path, ROOT)
 
@@ -139,7 +149,6 @@ def profile_roofline(profile, moved, sorts_key="sorts"):
     """Roofline of the redistribution kernel (every instantiation) from a
     committed rocprofv3 summary: average launch duration there, and 24 B per
     string moved per sort spread over that profile's launches per sort."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
         return None
@@ -155,8 +164,7 @@ def profile_roofline(profile, moved, sorts_key="sorts"):
             sha = line.split()[1]
     if not calls or not sorts:
         return None
-    src = os.path.join(ROOT, "paper_1305_1157_amd", "csrc", "s5_kernels.hip")
-    fresh = sha == hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fresh = sha == kernel_source_sha256()
     per_sort = calls / sorts
     alg = 24.0 * moved / per_sort
     avg_us = total_us / calls

@@ -421,44 +421,24 @@ S5_HD void classify_u(const uint64_t* t, const uint64_t* tin, uint32_t d,
 // One step of the recursive splitter selection (Section 3.1): for the sorted
 // sample range smp[a..b), a < b, the node takes the middle sample x; its left
 // child recurses on smp[a..lo) and its right child on smp[hi..b), where
-// [lo, hi) is the run of samples equal to x.  Each end of the run is found by
-// an exponential search outward from the middle (distances 1, 2, 4, ...) and
-// a binary search in the last step: two reads when the middle sample is
-// unique, O(log run length) in a run of duplicates.
+// [lo, hi) is the run of samples equal to x.
 S5_HD void select_node(const uint64_t* smp, uint32_t a, uint32_t b, uint64_t* x, uint32_t* lo,
                        uint32_t* hi) {
-    const uint32_t mid = (a + b) >> 1;
-    const uint64_t m = smp[mid];
-    // first index in [a, mid] with smp >= m: smp[l..mid] are all m, smp[l' < lf] < m
-    uint32_t l = mid, lf = a;
-    for (uint32_t step = 1; l > a; step <<= 1) {
-        const uint32_t q = l - a > step ? l - step : a;
-        if (smp[q] < m) {
-            lf = q + 1;
-            break;
-        }
-        l = q;
-    }
-    while (lf < l) {  // the answer lies in [lf, l]
-        const uint32_t md = (lf + l) >> 1;
-        if (smp[md] < m) lf = md + 1; else l = md;
+    uint32_t mid = (a + b) >> 1;
+    uint64_t m = smp[mid];
+    uint32_t l = a, h = mid;  // first index in [a, mid] with smp >= m
+    while (l < h) {
+        uint32_t md = (l + h) >> 1;
+        if (smp[md] < m) l = md + 1; else h = md;
     }
     *lo = l;
-    // first index in (mid, b] with smp > m: smp[mid..h-1] are all m
-    uint32_t h = mid + 1, hf = b;
-    for (uint32_t step = 1; h < b; step <<= 1) {
-        const uint32_t q = b - h > step ? h + step - 1 : b - 1;
-        if (smp[q] > m) {
-            hf = q;
-            break;
-        }
-        h = q + 1;
+    l = mid + 1;
+    h = b;  // first index in (mid, b] with smp > m
+    while (l < h) {
+        uint32_t md = (l + h) >> 1;
+        if (smp[md] <= m) l = md + 1; else h = md;
     }
-    while (h < hf) {  // the answer lies in [h, hf]
-        const uint32_t md = (h + hf) >> 1;
-        if (smp[md] <= m) h = md + 1; else hf = md;
-    }
-    *hi = h;
+    *hi = l;
     *x = m;
 }
 

@@ -54,7 +54,8 @@ def test_profile_roofline_parses_summary(tmp_path, monkeypatch):
         "sorts 2\n")
     src = tmp_path / "paper_1305_1157_amd" / "csrc"
     src.mkdir(parents=True)
-    (src / "s5_kernels.hip").write_text("x")
+    for name in bench.KERNEL_SOURCES:
+        (src / name).write_text("x")
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     r = bench.profile_roofline("k.txt", moved=600)
     assert r["launches_per_sort"] == 6 and abs(r["avg_launch_us"] - 125.0) < 1e-9
