@@ -16,6 +16,7 @@
 #include <atomic>
 #include <chrono>
 #include <mutex>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -666,19 +667,25 @@ int readback_copy(const Ptrs& P, const HostView& H, int which, hipStream_t st) {
 }
 
 // Wait until publication `seq` has landed, then unpack it.  The host polls
-// the flag word.  After 2 ms without it, it also asks now and then whether
-// the stream has drained, and if it has while the flag still holds another
+// the flag word, yielding its core between polls once the wait has lasted
+// 200 us.  From 2 ms on it also asks the stream, at most once a millisecond,
+// whether it has drained, and if it has while the flag still holds another
 // number, it copies the counters instead, so the wait always ends.  (Not
-// sooner: a stream query puts a marker into the stream, and the kernel after
-// it starts about 5 us later.)
+// sooner or more often: a stream query puts a marker into the stream, and the
+// kernel after it starts about 5 us later.)
 int publish_wait(const Ptrs& P, const HostView& H, int which, uint32_t seq, hipStream_t st) {
+    using clock = std::chrono::steady_clock;
     const volatile uint32_t* flag = (const volatile uint32_t*)((const char*)H.host + kFlagOff);
-    const auto t0 = std::chrono::steady_clock::now();
-    bool queried = false;
+    const auto t0 = clock::now();
+    auto next_query = t0 + std::chrono::milliseconds(2);
+    bool yielding = false, queried = false;
     for (uint32_t spin = 1; *flag != seq; ++spin) {
-        if (spin % 1024) continue;
-        if (!queried && std::chrono::steady_clock::now() - t0 < std::chrono::milliseconds(2))
-            continue;
+        if (yielding) std::this_thread::yield();
+        if (spin % 256) continue;
+        const auto now = clock::now();
+        yielding = now - t0 >= std::chrono::microseconds(200);
+        if (now < next_query) continue;
+        next_query = now + std::chrono::milliseconds(1);
         queried = true;
         const hipError_t q = hipStreamQuery(st);
         if (q == hipErrorNotReady) continue;
