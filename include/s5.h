@@ -146,7 +146,11 @@ typedef struct s5_stats {
     uint32_t alphabet_retries; /* sorts redone with byte keys after a byte outside
                                   the sampled alphabet */
     uint32_t learned_proposals; /* learned splitter proposals made (S5_SPLIT_LEARNED) */
-    uint32_t pad;
+    uint32_t root_depth;    /* bytes every string was found to share at its start
+                               (byte keys): the common prefix of a sample's
+                               smallest and largest first key, checked for every
+                               string and skipped before the first level (0 when
+                               some string lacks it) */
     double imbalance_mean;  /* over those proposals: the largest range bucket of the
                                proposal's own training sample, as a multiple of the
                                ideal share m / (v + 1) (mean and maximum; a

@@ -801,6 +801,10 @@ void final_stats(const HostView& H, s5_stats* stats) {
     stats->fallbacks = H.hg->fallbacks;
     stats->learned_proposals = H.hg->learned_props;
     stats->moved_one_bucket = H.hg->one_bucket;
+    {  // the depth every root segment started at (as the planner computed it)
+        const unsigned long long mx = H.hg->pre_max, mn = ~H.hg->pre_cmin;
+        stats->root_depth = H.hg->pre_bad || mn > mx ? 0u : lcp8(mn, mx);
+    }
     stats->imbalance_max = H.hg->imb_max_milli / 1000.0;
     stats->imbalance_mean =
         H.hg->learned_props ? H.hg->imb_sum_milli / 1000.0 / H.hg->learned_props : 0.0;

@@ -117,7 +117,26 @@ struct Globals {
     // strings of distributed segments that all fell into one bucket (moved
     // only to advance their depth), summed over the passes
     S5_LINE unsigned long long one_bucket;
+    // the largest first key of a sample of the strings and the complement of
+    // the smallest (both start at zero), and whether the key cache found a
+    // string without their common prefix
+    S5_LINE unsigned long long pre_max, pre_cmin;
+    uint32_t pre_bad, pre_pad;
 };
+
+// Bytes that the sampled strings share at their start (byte keys): the
+// common prefix of the smallest and largest sampled first key (0 without a
+// sample).
+__device__ inline uint32_t sample_prefix(const Globals* g) {
+    const unsigned long long mx = g->pre_max, mn = ~g->pre_cmin;
+    return mn > mx ? 0u : lcp8(mn, mx);
+}
+
+// Depth of every root segment: the sampled common prefix, unless some string
+// lacks it (the key cache then holds keys at depth 0).
+__device__ inline uint32_t root_depth(const Globals* g) {
+    return g->pre_bad ? 0u : sample_prefix(g);
+}
 
 // Learned splitters apply to segments of at least this many strings.
 constexpr uint32_t kLearnMin = 65536;

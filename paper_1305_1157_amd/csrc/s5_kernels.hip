@@ -361,15 +361,59 @@ __device__ void plan_emit(uint32_t begin, uint32_t size, uint32_t depth, uint32_
 // ---------------------------------------------------------------------------
 // K1: prefix cache at depth 0 (and the building-block entry point)
 
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
+    uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// The common start of the strings, estimated from a sample of up to
+// kPrefixSamples strings, one per thread: the largest sampled first key and
+// the complement of the smallest (one atomic each per workgroup).  The key
+// cache checks every string against their common prefix.
+constexpr uint32_t kPrefixSamples = 64 * kWG;
+__global__ __launch_bounds__(256) void k_prefix_sample(const uint8_t* chars, uint64_t chars_len,
+                                                       const uint64_t* offsets, uint32_t n,
+                                                       Globals* glob) {
+    const uint32_t S = n < kPrefixSamples ? n : kPrefixSamples;
+    unsigned long long mx = 0, cmin = 0;
+    for (uint32_t j = blockIdx.x * kWG + threadIdx.x; j < S; j += gridDim.x * kWG) {
+        const uint64_t off = offsets[(uint32_t)(((uint64_t)j * n) / S)];
+        if (chars_len && off >= chars_len) continue;  // rejected by the key cache
+        const uint64_t k = load_key(chars, off);
+        mx = k > mx ? k : mx;
+        cmin = ~k > cmin ? ~k : cmin;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long a = shfl_xor64(mx, o), b = shfl_xor64(cmin, o);
+        mx = a > mx ? a : mx;
+        cmin = b > cmin ? b : cmin;
+    }
+    __shared__ unsigned long long smx[kWaves], scm[kWaves];
+    if (lane_id() == 0) {
+        smx[threadIdx.x >> 6] = mx;
+        scm[threadIdx.x >> 6] = cmin;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWaves; ++w) {
+            mx = smx[w] > mx ? smx[w] : mx;
+            cmin = scm[w] > cmin ? scm[w] : cmin;
+        }
+        if (mx) atomicMax(&glob->pre_max, mx);
+        if (cmin) atomicMax(&glob->pre_cmin, cmin);
+    }
+}
+
+// Key cache of string i with its keys at depth d0 (byte keys only for
+// d0 > 0): the string must start with the first d0 bytes of `pfx`, else the
+// flag pre_bad is raised (the keys of every string are then loaded again at
+// depth 0).  The first d0 + 24 bytes come from one run of aligned words.
 template <bool PK>
-__global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, uint64_t chars_len,
-                                                   const uint64_t* offsets, uint32_t n,
-                                                   uint64_t* key, uint64_t* key2, uint64_t* key3,
-                                                   uint32_t* idx, Globals* glob, KeyCodec kc) {
-    S5_CODE_TABLE(PK, kc, tab)
-    if constexpr (PK) __syncthreads();
-    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+__device__ __forceinline__ void init_one(uint32_t i, const uint8_t* chars, uint64_t chars_len,
+                                         const uint64_t* offsets, uint64_t* key, uint64_t* key2,
+                                         uint64_t* key3, uint32_t* idx, Globals* glob,
+                                         const KeyCodec& kc, const uint8_t* tab, uint32_t d0,
+                                         uint64_t pfx) {
     idx[i] = i;
     const uint64_t off = offsets[i];
     if (chars_len) {
@@ -388,14 +432,52 @@ __global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, uint64_
         uint64_t raw[8];
         load_key_run<8>(chars, off, raw);
         if (pack3<8, 3>(tab, raw, w)) atomicOr(kc.status, kErrAlphabet);
-    } else {
+    } else if (d0 == 0) {
         load_key_run<3>(chars, off, w);
+    } else {
+        uint64_t r[4];
+        load_key_run<4>(chars, off, r);
+        const bool ok = d0 == 8 ? r[0] == pfx : ((r[0] ^ pfx) >> (64 - 8 * d0)) == 0;
+        if (!ok) {
+            atomicOr(&glob->pre_bad, 1u);
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            w[j] = d0 == 8 ? r[j + 1] : (r[j] << (8 * d0)) | (r[j + 1] >> (64 - 8 * d0));
     }
     key[i] = w[0];
     key2[i] = w[1];
     // the third word is all zero (and never read) unless the string
     // continues past its first two keys
     if (!(PK ? codec_has_end(kc, w[1]) : has_zero(w[1]))) key3[i] = w[2];
+}
+
+template <bool PK>
+__global__ __launch_bounds__(256) void k_init_keys(const uint8_t* chars, uint64_t chars_len,
+                                                   const uint64_t* offsets, uint32_t n,
+                                                   uint64_t* key, uint64_t* key2, uint64_t* key3,
+                                                   uint32_t* idx, Globals* glob, KeyCodec kc) {
+    S5_CODE_TABLE(PK, kc, tab)
+    if constexpr (PK) __syncthreads();
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // byte keys start at the sampled common prefix (checked string by string)
+    const uint32_t d0 = PK ? 0u : sample_prefix(glob);
+    init_one<PK>(i, chars, chars_len, offsets, key, key2, key3, idx, glob, kc, tab, d0,
+                 ~glob->pre_cmin);
+}
+
+// Byte keys again at depth 0, only if some string lacked the sampled prefix
+// (grid-stride over the strings; every other launch exits at once).
+__global__ __launch_bounds__(256) void k_init_redo(const uint8_t* chars, uint64_t chars_len,
+                                                   const uint64_t* offsets, uint32_t n,
+                                                   uint64_t* key, uint64_t* key2, uint64_t* key3,
+                                                   uint32_t* idx, Globals* glob, KeyCodec kc) {
+    if (!glob->pre_bad) return;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        init_one<false>(i, chars, chars_len, offsets, key, key2, key3, idx, glob, kc, nullptr, 0u,
+                        0ull);
 }
 
 __global__ __launch_bounds__(256) void k_prefix_keys(const uint8_t* chars, const uint64_t* offsets,
@@ -436,7 +518,8 @@ __global__ __launch_bounds__(256) void k_plan_roots(const uint64_t* set_begin, u
     if (threadIdx.x < 64) plan_allocate(ctx, &T);
     __syncthreads();
     if (T.err) return;
-    if (req) plan_emit(b, e - b, 0, b, 0, ctx, sp, &T, acc);
+    // every string of every set starts with the root depth's bytes
+    if (req) plan_emit(b, e - b, ctx.kc.b == 8 ? root_depth(ctx.glob) : 0u, b, 0, ctx, sp, &T, acc);
 }
 
 // Graph-captured sorts keep their statistics on the device: after each pass,
@@ -1461,10 +1544,6 @@ __device__ __forceinline__ uint32_t bitonic_flip(uint32_t e, uint32_t j, uint32_
     return ((e & j) ? 1u : 0u) ^ ((e & kk) ? 1u : 0u);
 }
 
-__device__ __forceinline__ uint64_t shfl_xor64(uint64_t v, int m) {
-    uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
-    return ((uint64_t)hi << 32) | lo;
-}
 __device__ __forceinline__ uint64_t shfl_up64(uint64_t v, int d) {
     uint32_t lo = __shfl_up((uint32_t)v, d), hi = __shfl_up((uint32_t)(v >> 32), d);
     return ((uint64_t)hi << 32) | lo;
@@ -2219,12 +2298,17 @@ void launch_init_keys(const uint8_t* chars, uint64_t chars_len, const uint64_t* 
                       uint32_t n, uint64_t* key, uint64_t* key2, uint64_t* key3, uint32_t* idx,
                       Globals* glob, const KeyCodec& kc, hipStream_t st) {
     if (!n) return;
-    if (kc.b != 8)
+    if (kc.b != 8) {
         S5_LAUNCH(k_init_keys<true>, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len,
                   offsets, n, key, key2, key3, idx, glob, kc);
-    else
-        S5_LAUNCH(k_init_keys<false>, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len,
-                  offsets, n, key, key2, key3, idx, glob, kc);
+        return;
+    }
+    S5_LAUNCH(k_prefix_sample, dim3((std::min(n, kPrefixSamples) + kWG - 1) / kWG), dim3(kWG), 0,
+              st, chars, chars_len, offsets, n, glob);
+    S5_LAUNCH(k_init_keys<false>, dim3((n + 255) / 256), dim3(256), 0, st, chars, chars_len,
+              offsets, n, key, key2, key3, idx, glob, kc);
+    S5_LAUNCH(k_init_redo, dim3(std::min<uint32_t>((n + 255) / 256, 256)), dim3(256), 0, st,
+              chars, chars_len, offsets, n, key, key2, key3, idx, glob, kc);
 }
 
 // Bytes that occur in a sample of the strings (alphabet compression): string

@@ -52,7 +52,7 @@ class Stats(ctypes.Structure):
                 ("entropy_bits", ctypes.c_double), ("workspace_bytes", ctypes.c_size_t),
                 ("base_items", ctypes.c_uint64), ("segments", ctypes.c_uint64),
                 ("char_bits", ctypes.c_uint32), ("alphabet_retries", ctypes.c_uint32),
-                ("learned_proposals", ctypes.c_uint32), ("pad", ctypes.c_uint32),
+                ("learned_proposals", ctypes.c_uint32), ("root_depth", ctypes.c_uint32),
                 ("imbalance_mean", ctypes.c_double), ("imbalance_max", ctypes.c_double),
                 ("moved_one_bucket", ctypes.c_uint64)]
 

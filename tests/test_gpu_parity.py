@@ -311,3 +311,42 @@ def test_batched_small(cfg):
     rp, rl = oracle.sort_batched(chars, offs2, sb2)
     assert np.array_equal(perm.cpu().numpy(), rp)
     assert np.array_equal(lcp.cpu().numpy(), rl)
+
+
+# Common start of all strings: the key cache starts at the prefix of the
+# smallest and largest sampled first key (at most 8 bytes), after checking
+# every string; one string without it (placed where the sample does not look)
+# sends the key cache back to depth 0.
+def _prefixed(prefix, n, seed, odd=None):
+    rng = random.Random(seed)
+    strings = [prefix + bytes(rng.choice(b"abcxyz") for _ in range(rng.randint(0, 12)))
+               for _ in range(n)]
+    strings[n // 2] = prefix  # a string that is the prefix itself
+    if odd is not None:
+        strings[1] = odd  # index 1 is not among the sampled strings at this n
+    return strings
+
+
+@pytest.mark.parametrize("plen", [3, 7, 8, 11])
+def test_common_prefix_skipped(plen):
+    prefix = b"http://www.example"[:plen]
+    st = strings_parity(_prefixed(prefix, 40_000, plen), label=f"prefix {plen}")
+    assert st["root_depth"] == min(plen, 8)
+
+
+@pytest.mark.parametrize("odd", [b"zz", b"htt", b""], ids=["other", "shorter", "empty"])
+def test_common_prefix_missed_by_the_sample(odd):
+    st = strings_parity(_prefixed(b"http://w", 40_000, 5, odd), label=f"odd {odd!r}")
+    assert st["root_depth"] == 0
+
+
+@pytest.mark.parametrize("odd", [None, b"ab"], ids=["shared", "missed"])
+def test_common_prefix_batched(odd):
+    chars, offs = gen.from_strings(_prefixed(b"abcdef", 40_000, 9, odd))
+    sb = np.array([0, 15_000, 15_001, 40_000], dtype=np.uint64)
+    perm, lcp = s5.sort_batched(to_dev(chars), to_dev(offs), to_dev(sb))
+    torch.cuda.synchronize()
+    rp, rl = oracle.sort_batched(chars, offs, sb)
+    assert np.array_equal(perm.cpu().numpy(), rp)
+    assert np.array_equal(lcp.cpu().numpy(), rl)
+    assert s5.stats()["root_depth"] == (6 if odd is None else 0)
