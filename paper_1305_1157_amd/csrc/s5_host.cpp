@@ -575,15 +575,27 @@ struct HostView {
     char* dev;  // the block's device address: counters are published into it (null: copied)
 };
 
+// Device addresses of the pinned readback blocks, looked up once per block
+// (the caller holds g_mu; s5_release clears them with the pools).
+std::unordered_map<void*, char*> g_host_dev;
+
 // `mapped`: the block is pinned host memory that kernels can write.
 HostView host_view(void* host, bool mapped) {
     HostView v{host, (Counters*)((char*)host + kHostSlot), (Globals*)((char*)host + 2 * kHostSlot),
                nullptr};
+    if (!mapped) return v;
+    auto it = g_host_dev.find(host);
+    if (it != g_host_dev.end()) {
+        v.dev = it->second;
+        return v;
+    }
     void* d = nullptr;
-    if (mapped && hipHostGetDevicePointer(&d, host, 0) == hipSuccess && d)
+    if (hipHostGetDevicePointer(&d, host, 0) == hipSuccess && d) {
         v.dev = (char*)d;
-    else
+        g_host_dev[host] = v.dev;
+    } else {
         (void)hipGetLastError();
+    }
     return v;
 }
 
@@ -1266,6 +1278,7 @@ void s5_release(void) {
         if (kv.second.host) (void)hipHostFree(kv.second.host);
     }
     g_pools.clear();
+    g_host_dev.clear();
     (void)hipSetDevice(cur);
 }
 
